@@ -1,0 +1,572 @@
+/*
+ * Minimod acoustic_iso_cd oracle: a plain, slow, FP64 CPU implementation of
+ * the time-stepping method, written from the paper (Meng, Atle, Calandra,
+ * Araya-Polo, "Minimod: A Finite Difference solver for Seismic Modeling",
+ * arXiv 2007.06048).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the correctness reference for the
+ * GPU library.  Only the test suite, the smoke check and the CPU-baseline leg
+ * of the benchmark may load it.  It shares no code, header, table or helper
+ * with the HIP path; both sides receive the same seeded inputs and nothing
+ * else.
+ *
+ * What is computed (section "Finite Differences", Eq. (acoustic_iso_cd) and
+ * the semi-discretised Eq. (minimod-semidisc), 25-point stencil formula):
+ *
+ *   p^{n+1} - Q p^n + p^{n-1} = dt^2 v^2 f^n,   Q = 2 + dt^2 v^2 Lap,
+ *   Lap p ~ sum_m c_xm [p(i+m)+p(i-m)-2p] + c_ym[...] + c_zm[...],  m=1..4,
+ *
+ * with the 8th-order Taylor coefficients c_m = a_m / h^2,
+ * a = (8/5, -1/5, 8/315, -1/560) (the paper names the order but prints no
+ * values; these are the unique order-8 central weights).  Algorithm 1
+ * ("Minimod high-level description") fixes p^0 = 0 and the loop over time
+ * steps; Algorithm 2 splits the domain into an inner region and damping
+ * slabs at the six faces, which the section "Minimod Description" says use
+ * a PML/CPML boundary.
+ *
+ * Readings where the paper is silent (all listed in the design notes):
+ *  - source:  f^n at the source cell is w(n dt)/(hx hy hz) and enters
+ *             p^{n+1} through dt^2 v^2 (Eq. (minimod-semidisc) right side);
+ *  - ghosts:  values outside the domain are zero (bc none, sponge, CPML);
+ *             bc periodic wraps (a test mode);
+ *  - sponge:  p^{n+1} = G (2 p^n - G p^{n-1} + D (Lap p^n + s^n)),
+ *             G = gx gy gz,  g(k) = exp(-(sigma d_k)^2), d_k = nb - k cells
+ *             inside the layer, 1 elsewhere;
+ *  - CPML:    recursive-convolution CPML for the second-order equation with
+ *             kappa = 1: per damped axis i, psi_i <- b psi_i + a D1_i p^n,
+ *             zeta_i <- b zeta_i + a (D2_i p^n + D1_i psi_i), and the
+ *             Laplacian gains D1_i psi_i + zeta_i inside the layer.
+ *             d(q) = d0 q^2, d0 = -3 vmax ln R / (2 nb h), alpha = pi f0 (1-q),
+ *             b = exp(-(d+alpha) dt), a = d (b-1)/(d+alpha),
+ *             q = (nb-k)/nb in the layer, 0 inside;
+ *  - dt:      dt = cfl * 2 / (vmax sqrt(S (hx^-2+hy^-2+hz^-2))),
+ *             S = 4 (a1 + a3), the symbol maximum of the 1D operator;
+ *  - wavelet: Ricker, w(t) = (1 - 2 pi^2 f0^2 tau^2) exp(-pi^2 f0^2 tau^2),
+ *             tau = t - t0;
+ *  - traces:  traces[n][r] = p^{n+1}(x_r), n = 0..T-1.
+ *
+ * Adjoint and gradient (the inverse problem the paper names as motivation
+ * in "Seismic Modeling"): the exact discrete adjoint of the forward
+ * recursion for bc none / sponge / periodic, written in the scaled variable
+ * eta = D G mu, which obeys the forward recursion run backward in time:
+ *   eta^m = G (2 eta^{m+1} - G eta^{m+2} + D (Lap eta^{m+1} + R^T r^m)),
+ * and the gradient with respect to squared slowness m = 1/v^2:
+ *   dJ/dm = -(1/(dt^2 G)) sum_n eta^{n+1} (p^{n+1} - 2 G p^n + G^2 p^{n-1}).
+ *
+ * Layout of every 3D array: index (k*ny + j)*nx + i, x fastest.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_ERR_ARG 1
+#define ORC_ERR_MEM 2
+#define ORC_ERR_UNSUPPORTED 3
+
+enum { BC_NONE = 0, BC_SPONGE = 1, BC_CPML = 2, BC_PERIODIC = 3 };
+
+typedef struct {
+    int nx, ny, nz;
+    double hx, hy, hz;
+    double dt;
+    int bc;
+    int nb;          /* damping width in cells (sponge and CPML) */
+    double sigma;    /* sponge strength */
+    double R;        /* CPML nominal reflection coefficient */
+    double f0;       /* CPML alpha_max = pi * f0 */
+    double vmax;     /* CPML d0 uses the model maximum velocity */
+} orc_grid;
+
+/* Order-8 central second-derivative weights a_m and first-derivative
+ * weights beta_m, m = 1..4 (index 0 unused). */
+static const double A2[5] = {0.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+static const double B1[5] = {0.0, 4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
+
+static size_t npts(const orc_grid* g) { return (size_t)g->nx * g->ny * g->nz; }
+
+static size_t lin(const orc_grid* g, int i, int j, int k) {
+    return ((size_t)k * g->ny + j) * g->nx + i;
+}
+
+static int wrap(int i, int n) {
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+/* Value of field f at (i,j,k); zero outside the domain unless periodic. */
+static double at(const orc_grid* g, const double* f, int i, int j, int k) {
+    if (g->bc == BC_PERIODIC) {
+        return f[lin(g, wrap(i, g->nx), wrap(j, g->ny), wrap(k, g->nz))];
+    }
+    if (i < 0 || j < 0 || k < 0 || i >= g->nx || j >= g->ny || k >= g->nz) return 0.0;
+    return f[lin(g, i, j, k)];
+}
+
+/* ---------------------------------------------------------------- scalars */
+
+/* Largest stable dt of the leapfrog scheme with this stencil: the checkerboard
+ * mode has symbol 4 (a1 + a3) per axis, and the recursion stays bounded while
+ * dt^2 v^2 * sum_axes S/h^2 <= 4. */
+double orc_dt_stab(double vmax, double hx, double hy, double hz) {
+    double S = 4.0 * (A2[1] + A2[3]);
+    double sum = 1.0 / (hx * hx) + 1.0 / (hy * hy) + 1.0 / (hz * hz);
+    return 2.0 / (vmax * sqrt(S * sum));
+}
+
+void orc_ricker(double f0, double t0, double dt, int n, double* out) {
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i) {
+        double tau = i * dt - t0;
+        double x = pi * pi * f0 * f0 * tau * tau;
+        out[i] = (1.0 - 2.0 * x) * exp(-x);
+    }
+}
+
+/* ------------------------------------------------------- stencil operators */
+
+/* Discrete Laplacian in the paper's form:
+ *   sum_m c_xm [p(i+m)+p(i-m)-2p] + c_ym [...] + c_zm [...]. */
+static double lap_at(const orc_grid* g, const double* p, int i, int j, int k) {
+    double c = at(g, p, i, j, k);
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int m = 1; m <= 4; ++m) {
+        sx += (A2[m] / (g->hx * g->hx)) * (at(g, p, i + m, j, k) + at(g, p, i - m, j, k) - 2.0 * c);
+        sy += (A2[m] / (g->hy * g->hy)) * (at(g, p, i, j + m, k) + at(g, p, i, j - m, k) - 2.0 * c);
+        sz += (A2[m] / (g->hz * g->hz)) * (at(g, p, i, j, k + m) + at(g, p, i, j, k - m) - 2.0 * c);
+    }
+    return sx + sy + sz;
+}
+
+/* One axis of the Laplacian (D2 along axis ax = 0,1,2). */
+static double d2_axis(const orc_grid* g, const double* p, int i, int j, int k, int ax) {
+    int di = ax == 0, dj = ax == 1, dk = ax == 2;
+    double h = ax == 0 ? g->hx : (ax == 1 ? g->hy : g->hz);
+    double c = at(g, p, i, j, k);
+    double s = 0.0;
+    for (int m = 1; m <= 4; ++m)
+        s += (A2[m] / (h * h)) *
+             (at(g, p, i + m * di, j + m * dj, k + m * dk) + at(g, p, i - m * di, j - m * dj, k - m * dk) - 2.0 * c);
+    return s;
+}
+
+/* Centred first derivative along axis ax. */
+static double d1_axis(const orc_grid* g, const double* p, int i, int j, int k, int ax) {
+    int di = ax == 0, dj = ax == 1, dk = ax == 2;
+    double h = ax == 0 ? g->hx : (ax == 1 ? g->hy : g->hz);
+    double s = 0.0;
+    for (int m = 1; m <= 4; ++m)
+        s += (B1[m] / h) * (at(g, p, i + m * di, j + m * dj, k + m * dk) - at(g, p, i - m * di, j - m * dj, k - m * dk));
+    return s;
+}
+
+void orc_laplacian(const orc_grid* g, const double* p, double* out) {
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) out[lin(g, i, j, k)] = lap_at(g, p, i, j, k);
+}
+
+/* ---------------------------------------------------- boundary profiles */
+
+/* Depth of index k inside the damping layer of an axis of n cells, counted
+ * so that the outermost cell has depth nb and the first inner cell 0:
+ * returns nb - k on the low side, nb - (n-1-k) on the high side, 0 inside. */
+static int layer_depth(int k, int n, int nb) {
+    int dl = nb - k;
+    int dh = nb - (n - 1 - k);
+    int d = dl > dh ? dl : dh;
+    return d > 0 ? d : 0;
+}
+
+/* Sponge factor of one axis at index k. */
+static double sponge_g(const orc_grid* g, int k, int n) {
+    int d = layer_depth(k, n, g->nb);
+    if (d == 0) return 1.0;
+    double x = g->sigma * d;
+    return exp(-x * x);
+}
+
+double orc_sponge_G(const orc_grid* g, int i, int j, int k) {
+    if (g->bc != BC_SPONGE) return 1.0;
+    return sponge_g(g, i, g->nx) * sponge_g(g, j, g->ny) * sponge_g(g, k, g->nz);
+}
+
+/* CPML coefficients (a, b) of axis ax at index k along that axis.  Returns 0
+ * if k is outside the layer of that axis (then a = 0 and psi stays zero). */
+static int cpml_ab(const orc_grid* g, int ax, int k, double* a, double* b) {
+    int n = ax == 0 ? g->nx : (ax == 1 ? g->ny : g->nz);
+    double h = ax == 0 ? g->hx : (ax == 1 ? g->hy : g->hz);
+    int d = layer_depth(k, n, g->nb);
+    if (d == 0) {
+        *a = 0.0;
+        *b = 1.0;
+        return 0;
+    }
+    const double pi = 3.14159265358979323846;
+    double q = (double)d / g->nb;
+    double d0 = -3.0 * g->vmax * log(g->R) / (2.0 * g->nb * h);
+    double dq = d0 * q * q;
+    double al = pi * g->f0 * (1.0 - q);
+    double bb = exp(-(dq + al) * g->dt);
+    *b = bb;
+    *a = (dq + al) > 0.0 ? dq * (bb - 1.0) / (dq + al) : 0.0;
+    return 1;
+}
+
+void orc_cpml_coeffs(const orc_grid* g, int ax, int k, double* a, double* b) { cpml_ab(g, ax, k, a, b); }
+
+/* CPML memory: 6 full-grid arrays, psi_x psi_y psi_z zeta_x zeta_y zeta_z. */
+static void cpml_update(const orc_grid* g, const double* p, double* mem, double* Lp, double* scratch) {
+    size_t N = npts(g);
+    for (int ax = 0; ax < 3; ++ax) {
+        double* psi = mem + (size_t)ax * N;
+        double* zeta = mem + (size_t)(3 + ax) * N;
+        /* psi_i <- b psi_i + a D1_i p^n, inside the layer of axis i */
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < g->nz; ++k)
+            for (int j = 0; j < g->ny; ++j)
+                for (int i = 0; i < g->nx; ++i) {
+                    int kk = ax == 0 ? i : (ax == 1 ? j : k);
+                    double a, b;
+                    size_t id = lin(g, i, j, k);
+                    if (cpml_ab(g, ax, kk, &a, &b))
+                        scratch[id] = b * psi[id] + a * d1_axis(g, p, i, j, k, ax);
+                    else
+                        scratch[id] = 0.0;
+                }
+        memcpy(psi, scratch, N * sizeof(double));
+        /* zeta_i <- b zeta_i + a (D2_i p^n + D1_i psi_i); Lap += D1_i psi_i + zeta_i */
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < g->nz; ++k)
+            for (int j = 0; j < g->ny; ++j)
+                for (int i = 0; i < g->nx; ++i) {
+                    int kk = ax == 0 ? i : (ax == 1 ? j : k);
+                    double a, b;
+                    size_t id = lin(g, i, j, k);
+                    if (!cpml_ab(g, ax, kk, &a, &b)) continue;
+                    double dpsi = d1_axis(g, psi, i, j, k, ax);
+                    zeta[id] = b * zeta[id] + a * (d2_axis(g, p, i, j, k, ax) + dpsi);
+                    Lp[id] += dpsi + zeta[id];
+                }
+    }
+}
+
+/* ------------------------------------------------------------- forward */
+
+static int check_grid(const orc_grid* g) {
+    if (!g || g->nx < 1 || g->ny < 1 || g->nz < 1) return ORC_ERR_ARG;
+    if (g->hx <= 0 || g->hy <= 0 || g->hz <= 0 || g->dt <= 0) return ORC_ERR_ARG;
+    if (g->bc < 0 || g->bc > 3) return ORC_ERR_ARG;
+    if ((g->bc == BC_SPONGE || g->bc == BC_CPML) && g->nb < 1) return ORC_ERR_ARG;
+    return ORC_OK;
+}
+
+static int check_pts(const orc_grid* g, int n, const int* ijk) {
+    for (int s = 0; s < n; ++s) {
+        int i = ijk[3 * s], j = ijk[3 * s + 1], k = ijk[3 * s + 2];
+        if (i < 0 || j < 0 || k < 0 || i >= g->nx || j >= g->ny || k >= g->nz) return ORC_ERR_ARG;
+    }
+    return ORC_OK;
+}
+
+/* One leapfrog step.  Reads p_prev = p^{n-1}, p_cur = p^n, writes p_next.
+ * src_term holds s^n on the grid (zero except at sources).  If Lp_out is
+ * given it receives the (CPML-corrected) Laplacian. */
+static void step(const orc_grid* g, const double* D, const double* p_prev, const double* p_cur,
+                 const double* src_term, double* mem, double* Lp, double* scratch, double* p_next) {
+    orc_laplacian(g, p_cur, Lp);
+    if (g->bc == BC_CPML) cpml_update(g, p_cur, mem, Lp, scratch);
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                size_t id = lin(g, i, j, k);
+                double G = orc_sponge_G(g, i, j, k);
+                double s = src_term ? src_term[id] : 0.0;
+                p_next[id] = G * (2.0 * p_cur[id] - G * p_prev[id] + D[id] * (Lp[id] + s));
+            }
+}
+
+static double* alloc_d(size_t n) { return (double*)calloc(n ? n : 1, sizeof(double)); }
+
+static void fill_D(const orc_grid* g, const double* vel, double* D) {
+    size_t N = npts(g);
+    for (size_t id = 0; id < N; ++id) {
+        double v = vel[id];
+        D[id] = g->dt * g->dt * v * v;
+    }
+}
+
+/* Forward modeling for T steps from the state (p_prev, p_cur) = (p^{-1}, p^0)
+ * given on entry (zero for Algorithm 1); on return they hold (p^{T-1}, p^T).
+ * wav is [T][nsrc] raw wavelet samples w(t_n); traces [T][nrec] receives
+ * p^{n+1} at the receivers (may be NULL).  cpml_mem, if not NULL, is the
+ * 6*N CPML memory in/out (psi_x,y,z then zeta_x,y,z); otherwise it starts
+ * at zero. */
+int orc_forward(const orc_grid* g, const double* vel, int nsrc, const int* src, const double* wav, int nrec,
+                const int* rec, int T, double* traces, double* p_prev, double* p_cur, double* cpml_mem) {
+    if (check_grid(g) || T < 0 || nsrc < 0 || nrec < 0) return ORC_ERR_ARG;
+    if (check_pts(g, nsrc, src) || check_pts(g, nrec, rec)) return ORC_ERR_ARG;
+    size_t N = npts(g);
+    double* D = alloc_d(N);
+    double* Lp = alloc_d(N);
+    double* scratch = alloc_d(N);
+    double* nxt = alloc_d(N);
+    double* S = alloc_d(N);
+    double* mem = NULL;
+    int own_mem = 0;
+    if (g->bc == BC_CPML) {
+        if (cpml_mem) mem = cpml_mem;
+        else {
+            mem = alloc_d(6 * N);
+            own_mem = 1;
+        }
+    }
+    if (!D || !Lp || !scratch || !nxt || !S || (g->bc == BC_CPML && !mem)) {
+        free(D); free(Lp); free(scratch); free(nxt); free(S);
+        if (own_mem) free(mem);
+        return ORC_ERR_MEM;
+    }
+    fill_D(g, vel, D);
+    double inv_vol = 1.0 / (g->hx * g->hy * g->hz);
+    for (int n = 0; n < T; ++n) {
+        memset(S, 0, N * sizeof(double));
+        for (int s = 0; s < nsrc; ++s)
+            S[lin(g, src[3 * s], src[3 * s + 1], src[3 * s + 2])] += wav[(size_t)n * nsrc + s] * inv_vol;
+        step(g, D, p_prev, p_cur, S, mem, Lp, scratch, nxt);
+        if (traces)
+            for (int r = 0; r < nrec; ++r)
+                traces[(size_t)n * nrec + r] = nxt[lin(g, rec[3 * r], rec[3 * r + 1], rec[3 * r + 2])];
+        memcpy(p_prev, p_cur, N * sizeof(double));
+        memcpy(p_cur, nxt, N * sizeof(double));
+    }
+    free(D); free(Lp); free(scratch); free(nxt); free(S);
+    if (own_mem) free(mem);
+    return ORC_OK;
+}
+
+/* p^{n+1} at a list of points from a given state: the same step as
+ * orc_forward, evaluated point by point (for sampled checks on grids too
+ * large to step whole).  cpml_mem (6*N, may be NULL when bc != CPML) holds
+ * psi and zeta of step n-1 and is not modified.  src_term_at[q] is s^n at
+ * point q (the caller adds w/(hx hy hz) where a source sits). */
+int orc_step_points(const orc_grid* g, const double* vel, const double* p_prev, const double* p_cur,
+                    const double* cpml_mem, int npt, const int* ijk, const double* src_term_at, double* out) {
+    if (check_grid(g) || check_pts(g, npt, ijk)) return ORC_ERR_ARG;
+    if (g->bc == BC_CPML && !cpml_mem) return ORC_ERR_ARG;
+    size_t N = npts(g);
+    for (int q = 0; q < npt; ++q) {
+        int i = ijk[3 * q], j = ijk[3 * q + 1], k = ijk[3 * q + 2];
+        size_t id = lin(g, i, j, k);
+        double L = lap_at(g, p_cur, i, j, k);
+        if (g->bc == BC_CPML) {
+            for (int ax = 0; ax < 3; ++ax) {
+                int pos[3] = {i, j, k};
+                int n_ax = ax == 0 ? g->nx : (ax == 1 ? g->ny : g->nz);
+                double a, b;
+                if (!cpml_ab(g, ax, pos[ax], &a, &b)) continue;
+                const double* psi = cpml_mem + (size_t)ax * N;
+                const double* zeta = cpml_mem + (size_t)(3 + ax) * N;
+                /* new psi along the axis at offsets -4..4 */
+                double pn[9];
+                for (int m = -4; m <= 4; ++m) {
+                    int p2[3] = {i, j, k};
+                    p2[ax] += m;
+                    double aa, bb;
+                    if (p2[ax] < 0 || p2[ax] >= n_ax || !cpml_ab(g, ax, p2[ax], &aa, &bb)) {
+                        pn[m + 4] = 0.0;
+                        continue;
+                    }
+                    size_t id2 = lin(g, p2[0], p2[1], p2[2]);
+                    pn[m + 4] = bb * psi[id2] + aa * d1_axis(g, p_cur, p2[0], p2[1], p2[2], ax);
+                }
+                double h = ax == 0 ? g->hx : (ax == 1 ? g->hy : g->hz);
+                double dpsi = 0.0;
+                for (int m = 1; m <= 4; ++m) dpsi += (B1[m] / h) * (pn[4 + m] - pn[4 - m]);
+                double zn = b * zeta[id] + a * (d2_axis(g, p_cur, i, j, k, ax) + dpsi);
+                L += dpsi + zn;
+            }
+        }
+        double G = orc_sponge_G(g, i, j, k);
+        double v = vel[id];
+        double D = g->dt * g->dt * v * v;
+        double s = src_term_at ? src_term_at[q] : 0.0;
+        out[q] = G * (2.0 * p_cur[id] - G * p_prev[id] + D * (L + s));
+    }
+    return ORC_OK;
+}
+
+/* Discrete energy between consecutive states p^n and p^{n+1}:
+ *   E^{n+1/2} = sum (p^{n+1}-p^n)^2 / (v^2 dt^2) - sum p^{n+1} Lap p^n. */
+double orc_energy(const orc_grid* g, const double* vel, const double* pn, const double* pn1) {
+    size_t N = npts(g);
+    double* Lp = alloc_d(N);
+    if (!Lp) return NAN;
+    orc_laplacian(g, pn, Lp);
+    double kin = 0.0, pot = 0.0;
+    for (size_t id = 0; id < N; ++id) {
+        double v = vel[id];
+        double d = pn1[id] - pn[id];
+        kin += d * d / (v * v * g->dt * g->dt);
+        pot += pn1[id] * Lp[id];
+    }
+    free(Lp);
+    return kin - pot;
+}
+
+/* ------------------------------------------------------------- adjoint */
+
+static int adjoint_supported(const orc_grid* g) { return g->bc != BC_CPML; }
+
+/* One backward step of the scaled adjoint: eta^m from eta^{m+1}, eta^{m+2}
+ * and the receiver residual r^m.  It is the forward step with the residual
+ * as a source of unit scale at the receivers. */
+static void adj_step(const orc_grid* g, const double* D, const double* e2, const double* e1, const double* rt,
+                     double* Lp, double* out) {
+    orc_laplacian(g, e1, Lp);
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                size_t id = lin(g, i, j, k);
+                double G = orc_sponge_G(g, i, j, k);
+                out[id] = G * (2.0 * e1[id] - G * e2[id] + D[id] * (Lp[id] + rt[id]));
+            }
+}
+
+/* Adjoint run for T steps with residual resid [T][nrec] (resid[n] pairs with
+ * the trace of p^{n+1}).  adj_src [T][nsrc] receives eta^{n+1} at the source
+ * points.  With zero initial adjoint state this is the transpose of the map
+ * (sources s^n) -> (traces), in the sense
+ *   sum_n <R p^{n+1}, r^n> = sum_n <s^n, eta^{n+1}(src)>. */
+int orc_adjoint(const orc_grid* g, const double* vel, int nrec, const int* rec, const double* resid, int T, int nsrc,
+                const int* src, double* adj_src) {
+    if (check_grid(g) || T < 0) return ORC_ERR_ARG;
+    if (!adjoint_supported(g)) return ORC_ERR_UNSUPPORTED;
+    if (check_pts(g, nsrc, src) || check_pts(g, nrec, rec)) return ORC_ERR_ARG;
+    size_t N = npts(g);
+    double *D = alloc_d(N), *Lp = alloc_d(N), *e2 = alloc_d(N), *e1 = alloc_d(N), *en = alloc_d(N),
+           *rt = alloc_d(N);
+    if (!D || !Lp || !e2 || !e1 || !en || !rt) {
+        free(D); free(Lp); free(e2); free(e1); free(en); free(rt);
+        return ORC_ERR_MEM;
+    }
+    fill_D(g, vel, D);
+    for (int m = T; m >= 1; --m) {
+        memset(rt, 0, N * sizeof(double));
+        for (int r = 0; r < nrec; ++r)
+            rt[lin(g, rec[3 * r], rec[3 * r + 1], rec[3 * r + 2])] += resid[(size_t)(m - 1) * nrec + r];
+        adj_step(g, D, e2, e1, rt, Lp, en);
+        if (adj_src)
+            for (int s = 0; s < nsrc; ++s)
+                adj_src[(size_t)(m - 1) * nsrc + s] = en[lin(g, src[3 * s], src[3 * s + 1], src[3 * s + 2])];
+        memcpy(e2, e1, N * sizeof(double));
+        memcpy(e1, en, N * sizeof(double));
+    }
+    free(D); free(Lp); free(e2); free(e1); free(en); free(rt);
+    return ORC_OK;
+}
+
+/* FWI gradient of J = 1/2 sum_n sum_r (d^n_r - dobs^n_r)^2 with respect to
+ * m = 1/v^2, for a forward run from zero state.  The forward wavefields are
+ * regenerated segment by segment from FP64 checkpoints taken every ckpt
+ * steps (ckpt >= T keeps one segment); FP64 replay is exact, so ckpt does
+ * not change the result.  traces [T][nrec] and loss may be NULL. */
+int orc_gradient(const orc_grid* g, const double* vel, int nsrc, const int* src, const double* wav, int nrec,
+                 const int* rec, const double* d_obs, int T, int ckpt, double* grad, double* traces, double* loss) {
+    if (check_grid(g) || T < 1 || ckpt < 1) return ORC_ERR_ARG;
+    if (!adjoint_supported(g)) return ORC_ERR_UNSUPPORTED;
+    if (check_pts(g, nsrc, src) || check_pts(g, nrec, rec)) return ORC_ERR_ARG;
+    size_t N = npts(g);
+    int nseg = (T + ckpt - 1) / ckpt;
+    double* D = alloc_d(N);
+    double* Lp = alloc_d(N);
+    double* S = alloc_d(N);
+    double* a = alloc_d(N);
+    double* b = alloc_d(N);
+    double* c = alloc_d(N);
+    double* ck = alloc_d((size_t)nseg * 2 * N);
+    double* tr = alloc_d((size_t)T * nrec);
+    double* res = alloc_d((size_t)T * nrec);
+    double* seg = alloc_d((size_t)(ckpt + 2) * N);
+    double *e2 = alloc_d(N), *e1 = alloc_d(N), *en = alloc_d(N), *rt = alloc_d(N);
+    int rc = ORC_OK;
+    if (!D || !Lp || !S || !a || !b || !c || !ck || !tr || !res || !seg || !e2 || !e1 || !en || !rt) {
+        rc = ORC_ERR_MEM;
+        goto done;
+    }
+    fill_D(g, vel, D);
+    double inv_vol = 1.0 / (g->hx * g->hy * g->hz);
+    /* forward: a = p^{n-1}, b = p^n, checkpoint (p^{cK-1}, p^{cK}) */
+    for (int n = 0; n < T; ++n) {
+        if (n % ckpt == 0) {
+            memcpy(ck + (size_t)(n / ckpt) * 2 * N, a, N * sizeof(double));
+            memcpy(ck + (size_t)(n / ckpt) * 2 * N + N, b, N * sizeof(double));
+        }
+        memset(S, 0, N * sizeof(double));
+        for (int s = 0; s < nsrc; ++s)
+            S[lin(g, src[3 * s], src[3 * s + 1], src[3 * s + 2])] += wav[(size_t)n * nsrc + s] * inv_vol;
+        step(g, D, a, b, S, NULL, Lp, NULL, c);
+        for (int r = 0; r < nrec; ++r) tr[(size_t)n * nrec + r] = c[lin(g, rec[3 * r], rec[3 * r + 1], rec[3 * r + 2])];
+        double* t = a; a = b; b = c; c = t;
+    }
+    double J = 0.0;
+    for (size_t q = 0; q < (size_t)T * nrec; ++q) {
+        res[q] = tr[q] - d_obs[q];
+        J += 0.5 * res[q] * res[q];
+    }
+    if (traces) memcpy(traces, tr, (size_t)T * nrec * sizeof(double));
+    if (loss) *loss = J;
+    memset(grad, 0, N * sizeof(double));
+    /* backward over segments, last first */
+    for (int cseg = nseg - 1; cseg >= 0; --cseg) {
+        int n0 = cseg * ckpt;
+        int n1 = n0 + ckpt < T ? n0 + ckpt : T;
+        /* seg[t - n0 + 1] = p^t for t = n0-1 .. n1 */
+        memcpy(seg, ck + (size_t)cseg * 2 * N, 2 * N * sizeof(double));
+        for (int n = n0; n < n1; ++n) {
+            memset(S, 0, N * sizeof(double));
+            for (int s = 0; s < nsrc; ++s)
+                S[lin(g, src[3 * s], src[3 * s + 1], src[3 * s + 2])] += wav[(size_t)n * nsrc + s] * inv_vol;
+            step(g, D, seg + (size_t)(n - n0) * N, seg + (size_t)(n - n0 + 1) * N, S, NULL, Lp, NULL,
+                 seg + (size_t)(n - n0 + 2) * N);
+        }
+        for (int m = n1; m >= n0 + 1; --m) {
+            memset(rt, 0, N * sizeof(double));
+            for (int r = 0; r < nrec; ++r)
+                rt[lin(g, rec[3 * r], rec[3 * r + 1], rec[3 * r + 2])] += res[(size_t)(m - 1) * nrec + r];
+            adj_step(g, D, e2, e1, rt, Lp, en);
+            const double* pm = seg + (size_t)(m - n0 + 1) * N;
+            const double* pm1 = seg + (size_t)(m - n0) * N;
+            const double* pm2 = seg + (size_t)(m - n0 - 1) * N;
+#pragma omp parallel for schedule(static)
+            for (int k = 0; k < g->nz; ++k)
+                for (int j = 0; j < g->ny; ++j)
+                    for (int i = 0; i < g->nx; ++i) {
+                        size_t id = lin(g, i, j, k);
+                        double G = orc_sponge_G(g, i, j, k);
+                        double d2p = pm[id] - 2.0 * G * pm1[id] + G * G * pm2[id];
+                        grad[id] -= en[id] * d2p / (g->dt * g->dt * G);
+                    }
+            double* t = e2; e2 = e1; e1 = en; en = t;
+        }
+    }
+done:
+    free(D); free(Lp); free(S); free(a); free(b); free(c); free(ck); free(tr); free(res); free(seg);
+    free(e2); free(e1); free(en); free(rt);
+    return rc;
+}
+
+/* Number of threads the OpenMP runtime will use (for reporting). */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
