@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Benchmark of the acoustic_iso_cd forward propagator on one MI355X.
+
+One bench step = one full forward modelling run of the workload: reset the
+state, then T leapfrog steps with CPML, source injection and recording of
+the receiver plane (all in the HIP library).  Inputs (model, wavelet, trace
+buffer) are resident in HBM before timing starts.
+
+Prints ONE JSON line:
+  value     = grid points x T / wall time of one run (Gpoint-updates/s)
+  roofline  = algorithmic bytes of the stencil kernel per launch / its average
+              launch time (HIP events on the library's stream), vs 8 TB/s
+  cpu_baseline = the FP64 oracle timed on the host cores on a bounded sample
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+ALG_BYTES_STENCIL = 16  # read p^n, p^{n-1}, (dt v)^2; write p^{n+1}  (bytes per grid point)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("mm_kernels.hip", "mm_internal.h"):
+        with open(os.path.join(ROOT, "paper_2007_06048_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_workload(name):
+    from paper_2007_06048_amd import workloads as W
+    if name == "smooth240":
+        return W.smooth_240()
+    if name == "layered1024":
+        return W.layered_1024()
+    if name == "twolayer64":
+        return W.two_layer_64()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def traffic_for(workload_name):
+    """HBM bytes per stencil launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "stencil_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = d.get(workload_name)
+    if not e or e.get("kernel_hash") != kernel_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, budget_s):
+    """Time the FP64 oracle on a bounded sample: the same grid, model,
+    boundary and source, for as many steps as fit in about budget_s."""
+    import numpy as np
+    from oracle import c_oracle as C
+    from paper_2007_06048_amd import minimod as mm
+    s = wl.shots[0]
+    p = mm.default_params(nx=wl.nx, ny=wl.ny, nz=wl.nz, dx=wl.h, dy=wl.h, dz=wl.h, cfl=wl.cfl, bc=wl.bc, nb=wl.nb)
+    vmax = float(s.vel.max())
+    dt = mm.dt_for(p, vmax)
+    g = C.Grid(wl.nx, wl.ny, wl.nz, wl.h, wl.h, wl.h, dt, bc=wl.bc, nb=wl.nb, sigma=wl.sigma, R=wl.cpml_R,
+               f0=wl.f0, vmax=vmax)
+    vel = s.vel.astype(np.float64)
+    w = C.ricker(wl.f0, wl.t0, dt, wl.nsteps)[:, None]
+    t0 = time.perf_counter()
+    _, pm, pc, mem = C.forward(g, vel, s.src, w[:1], s.rec, 1)
+    t1 = time.perf_counter()
+    per = max(t1 - t0, 1e-3)
+    n = int(max(1, min(wl.nsteps - 1, budget_s / per)))
+    t0 = time.perf_counter()
+    C.forward(g, vel, s.src, w[1:1 + n], s.rec, n, p_prev=pm, p_cur=pc, cpml_mem=mem)
+    t1 = time.perf_counter()
+    pts = wl.nx * wl.ny * wl.nz
+    return {"value": pts * n / (t1 - t0) / 1e9, "unit": "Gpt/s", "cores": C.num_threads(), "kind": "oracle",
+            "sample": f"{n} steps (of {wl.nsteps}) of the same {wl.nx}x{wl.ny}x{wl.nz} run, FP64, "
+                      f"after 1 warm-up step"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="smooth240")
+    ap.add_argument("--tile", type=int, default=-1, help="tile variant, -1 = autotune")
+    ap.add_argument("--prof-stride", type=int, default=1)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="launch the step loop as one HIP graph")
+    ap.add_argument("--calib", action="store_true", help="also run a 1 GiB copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (shots and z-slabs would shard "
+              "across GPUs; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2007_06048_amd import minimod as mm
+
+    dev = torch.device("cuda:0")
+    wl = load_workload(args.workload)
+    s = wl.shots[0]
+    T = wl.nsteps
+    p = mm.default_params(nx=wl.nx, ny=wl.ny, nz=wl.nz, dx=wl.h, dy=wl.h, dz=wl.h, cfl=wl.cfl, bc=wl.bc, nb=wl.nb,
+                          sponge_sigma=wl.sigma, cpml_R=wl.cpml_R, cpml_f0=wl.f0, tile=args.tile)
+    vel = torch.from_numpy(s.vel).to(dev)
+    t_init0 = time.perf_counter()
+    ctx = mm.Context.single(p, vel, s.src, s.rec)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t_init0
+    dt = ctx.dt
+    w = torch.from_numpy(mm.ricker(wl.f0, wl.t0, dt, T)).to(dev).reshape(T, 1)
+    traces = torch.empty((T, len(s.rec)), dtype=torch.float32, device=dev)
+
+    def run():
+        ctx.reset()
+        ctx.forward(T, w, traces, graph=args.graph)
+
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    if args.prof_stride > 0 and not args.graph:
+        ctx.profile(args.prof_stride)
+        ctx.profile_read()  # clear
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    k_ms, k_n = (ctx.profile_read() if args.prof_stride > 0 and not args.graph else (0.0, 0))
+    ctx.profile(0)
+    pts = wl.nx * wl.ny * wl.nz
+    value = pts * T / (ms_step / 1e3) / 1e9
+
+    if args.calib:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    roof = None
+    if k_n > 0:
+        avg_ms = k_ms / k_n
+        bytes_launch = ALG_BYTES_STENCIL * pts
+        ach = bytes_launch / (avg_ms / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_for(wl.name),
+                "kernel": "k_step (stencil + sponge/leapfrog update)", "avg_launch_us": round(avg_ms * 1e3, 2),
+                "alg_bytes_per_launch": bytes_launch, "timed_launches": k_n}
+
+    out = {
+        "metric": "Gpoint-updates/s and % HBM roofline (fwd)",
+        "value": round(value, 3),
+        "unit": "Gpt/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid": [wl.nx, wl.ny, wl.nz], "time_steps_per_run": T, "h_m": wl.h,
+                   "bc": {0: "none", 1: "sponge", 2: "cpml"}[wl.bc], "nb": wl.nb, "receivers": len(s.rec),
+                   "tile": mm.tile_name(ctx.info()["tile"]), "graph": bool(args.graph),
+                   "init_s": round(t_init, 3), "dt_s": dt},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

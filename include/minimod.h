@@ -1,0 +1,228 @@
+/*
+ * minimod.h - C ABI of the MI355X (gfx950) acoustic_iso_cd propagator.
+ *
+ * Method (Meng, Atle, Calandra, Araya-Polo, "Minimod: A Finite Difference
+ * solver for Seismic Modeling", arXiv 2007.06048):
+ *  - Eq. (acoustic_iso_cd): (1/v^2) p_tt - Lap p = f, constant density;
+ *  - Eq. (minimod-semidisc): p^{n+1} - Q p^n + p^{n-1} = dt^2 v^2 f^n,
+ *    Q = 2 + dt^2 v^2 Lap (second-order leapfrog in time);
+ *  - the 25-point stencil of section "Finite Differences": radius 4 per axis,
+ *    8th-order Taylor coefficients c_m = a_m/h^2,
+ *    a = (8/5, -1/5, 8/315, -1/560);
+ *  - Algorithm 1 (time loop from p^0 = 0, source added every step) and
+ *    Algorithm 2 (inner region plus damping slabs on the six faces, PML/CPML
+ *    boundary per section "Minimod Description").
+ * Where the paper is silent this library implements the readings below
+ * (they are also the readings of the test oracle):
+ *  - source term: s^n = w(t_n) / (dx dy dz) at the source cell, entering
+ *    p^{n+1} as dt^2 v^2 s^n (a discrete point source);
+ *  - cells outside the grid are zero (radius-4 ghost zone);
+ *  - MM_BC_SPONGE: p^{n+1} = G (2 p^n - G p^{n-1} + D (Lap p^n + s^n)),
+ *    D = (dt v)^2, G = g(i) g(j) g(k), g = exp(-(sigma d)^2) at depth d =
+ *    nb - k cells inside a layer of nb cells, 1 elsewhere;
+ *  - MM_BC_CPML: kappa = 1 recursive-convolution CPML of the second-order
+ *    equation: per damped axis psi <- b psi + a D1 p^n,
+ *    zeta <- b zeta + a (D2 p^n + D1 psi), Lap gains D1 psi + zeta in the
+ *    layer; d = d0 q^2, d0 = -3 vmax ln(R) / (2 nb h), alpha = pi f0 (1 - q),
+ *    b = exp(-(d + alpha) dt), a = d (b - 1)/(d + alpha), q = depth/nb;
+ *  - dt = cfl * 2 / (vmax sqrt(S (dx^-2 + dy^-2 + dz^-2))), S = 4 (a1 + a3):
+ *    cfl is the fraction of the leapfrog stability limit;
+ *  - receivers: traces[n][r] = p^{n+1} at the receiver cell.
+ *
+ * Conventions.
+ *  - All 3D arrays handed to the library are float32, C order [nz][ny][nx]
+ *    (x fastest), in device memory.  Point lists are host int32 triples
+ *    (i, j, k) = (x, y, z), 0-based.
+ *  - Every device buffer belongs to the caller: velocities, wavelets,
+ *    traces, gradients and the workspace.  The library never allocates
+ *    device memory; it owns only small host tables and HIP graph objects,
+ *    released by mm_destroy.
+ *  - All work is enqueued on the stream given to mm_init (NULL = the null
+ *    stream).  Functions return when the work is enqueued, except where
+ *    noted (mm_gradient reads the loss back and synchronises).
+ *  - Time: after k steps the context holds (p^{k-1}, p^k).
+ *    mm_forward_steps(n) produces p^{k+1} .. p^{k+n}; wavelet row j is
+ *    w(t_{k+j}) and enters p^{k+j+1}; traces row j is p^{k+j+1} at the
+ *    receivers.
+ *  - Errors: every function returns an mm_status; on error the context is
+ *    unchanged (no work enqueued) and mm_last_error() describes the
+ *    problem.  A context is not thread-safe; use one per stream.
+ *  - Batches: a context holds one or more shots, each on its own grid
+ *    (sub-volume) with its own sources and receivers; all shots share
+ *    spacing, dt, boundary kind and width.  Wavelet and trace rows
+ *    concatenate the shots' sources / receivers in shot order.  One launch
+ *    per kernel per time step covers every shot.
+ */
+#ifndef MINIMOD_H
+#define MINIMOD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mm_ctx mm_ctx;
+
+typedef enum {
+    MM_OK = 0,
+    MM_ERR_ARG = 1,         /* invalid size, spacing, point, pointer or option */
+    MM_ERR_UNSTABLE = 2,    /* cfl > 1 or dt above the stability limit */
+    MM_ERR_WORKSPACE = 3,   /* workspace too small or misaligned */
+    MM_ERR_DEVICE = 4,      /* a HIP call failed */
+    MM_ERR_STATE = 5,       /* call not valid in the context's current state */
+    MM_ERR_NONFINITE = 6,   /* NaN/Inf or non-positive velocity */
+    MM_ERR_UNSUPPORTED = 7  /* valid request this build does not implement */
+} mm_status;
+
+typedef enum { MM_BC_NONE = 0, MM_BC_SPONGE = 1, MM_BC_CPML = 2 } mm_bc;
+
+/* Snapshot storage of the gradient's checkpoints. */
+typedef enum {
+    MM_SNAP_FP32 = 0, /* lossless */
+    MM_SNAP_BF16 = 1  /* bf16(x / s), s = max |x| of the field (1 if zero), round to nearest even */
+} mm_snap;
+
+typedef struct {
+    int32_t nx, ny, nz;      /* grid points per axis (single-shot contexts) */
+    double dx, dy, dz;       /* spacing, metres */
+    double dt;               /* time step, s; 0 => cfl * stability limit */
+    double cfl;              /* fraction of the stability limit, (0, 1]; used when dt == 0 */
+    double vmax;             /* velocity for dt and CPML d0; 0 => max of the model(s) */
+    int32_t bc;              /* mm_bc */
+    int32_t nb;              /* damping layer width in cells (sponge, CPML); each axis needs n >= 2 nb + 1 */
+    double sponge_sigma;     /* sponge strength (0.015 typical) */
+    double cpml_R;           /* CPML nominal reflection coefficient, (0, 1]; 1 disables damping */
+    double cpml_f0;          /* CPML frequency: alpha_max = pi * cpml_f0, >= 0 */
+    int32_t ckpt_every;      /* gradient checkpoint interval in steps; 0 => no gradient support */
+    int32_t snap;            /* mm_snap for the checkpoints */
+    int32_t nsteps_max;      /* longest gradient / adjoint run the workspace must hold */
+    int32_t tile;            /* stencil tile variant; 0 => library default, -1 => autotune at init */
+} mm_params;
+
+/* One shot of a batched context. */
+typedef struct {
+    int32_t nx, ny, nz;            /* grid of this shot */
+    const float* vel;              /* device [nz][ny][nx] velocity, m/s (read only during init) */
+    const int32_t* src_ijk;        /* host [nsrc][3] */
+    int32_t nsrc;
+    const int32_t* rec_ijk;        /* host [nrec][3] */
+    int32_t nrec;
+} mm_shot;
+
+/* Fill *p with defaults (sponge 0.015, CPML R = 1e-3, cfl 0.5, ...). */
+void mm_default_params(mm_params* p);
+
+/* Stable time step for params p and maximum velocity vmax (host only).
+ * Returns MM_ERR_UNSTABLE if p->dt > 0 exceeds the limit or p->cfl > 1. */
+mm_status mm_dt(const mm_params* p, double vmax, double* dt_out);
+
+/* Ricker wavelet w_i = (1 - 2 pi^2 f0^2 tau^2) exp(-pi^2 f0^2 tau^2),
+ * tau = i dt - t0, i = 0..n-1, computed in FP64 and rounded to float
+ * (host only; the source signature is a reading, the paper gives fmax). */
+mm_status mm_ricker(double f0, double t0, double dt, int32_t n, float* host_out);
+
+/* Device workspace needed by a context with these shots (bytes, multiple
+ * of 256).  Nothing is launched. */
+mm_status mm_workspace_size(const mm_params* p, int32_t nshots, const mm_shot* shots, size_t* bytes);
+
+/* Create a context: validates, derives dt, computes (dt v)^2 and the
+ * boundary tables on the device, zeroes the state (step 0).  workspace is a
+ * caller-owned device buffer of at least mm_workspace_size bytes, 256-byte
+ * aligned, that must outlive the context.  hip_stream is a hipStream_t (or
+ * NULL).  If p->vmax == 0 the models are reduced on the device and read
+ * back (a synchronisation). */
+mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const mm_shot* shots,
+                        void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Single-shot form: the grid is p->nx * p->ny * p->nz, velocity vel_dev. */
+mm_status mm_init(mm_ctx** out, const mm_params* p, const float* vel_dev, const int32_t* src_ijk_host,
+                  int32_t nsrc, const int32_t* rec_ijk_host, int32_t nrec, void* workspace, size_t ws_bytes,
+                  void* hip_stream);
+
+/* Advance nsteps steps.  wavelet: device [nsteps][nsrc_total] raw samples
+ * (may be NULL only if nsrc_total == 0).  traces: device
+ * [nsteps][nrec_total] or NULL.  If the context was made with
+ * ckpt_every > 0 and the run starts at step 0, checkpoints are stored and
+ * the wavelet is kept for the gradient's replay (nsteps <= nsteps_max). */
+mm_status mm_forward_steps(mm_ctx* ctx, int32_t nsteps, const float* wavelet, float* traces);
+
+/* Same result as mm_forward_steps, with the whole step loop captured once
+ * into a HIP graph and launched as one graph (re-used while nsteps and the
+ * pointers are unchanged).  Bitwise identical to mm_forward_steps. */
+mm_status mm_forward_steps_graph(mm_ctx* ctx, int32_t nsteps, const float* wavelet, float* traces);
+
+/* Adjoint (reverse-time) steps, bc none or sponge only (MM_ERR_UNSUPPORTED
+ * for CPML).  The scaled adjoint eta obeys the forward recursion run
+ * backward with the residual injected at the receivers with unit scale:
+ *   eta^m = G (2 eta^{m+1} - G eta^{m+2} + D (Lap eta^{m+1} + R^T r^m)).
+ * The first call starts from eta = 0 at time m = T (the forward step count)
+ * and each call continues downward.  resid: device [nsteps][nrec_total] in
+ * forward time order (row j pairs with the trace of p^{m0+j}, where
+ * m0 = current adjoint time - nsteps + 1).  adj_at_src (device
+ * [nsteps][nsrc_total] or NULL) receives eta^{m} at the sources, same row
+ * order.  grad_m (device [nz][ny][nx] of a single-shot context, or NULL) is
+ * accumulated with -(1/(dt^2 G)) eta^m (p^m - 2 G p^{m-1} + G^2 p^{m-2}),
+ * the imaging condition of the gradient w.r.t. m = 1/v^2; it needs the
+ * checkpoints of a forward run made from step 0 with ckpt_every > 0, and
+ * clobbers the forward state (call mm_reset before a new forward run). */
+mm_status mm_adjoint_steps(mm_ctx* ctx, int32_t nsteps, const float* resid, float* adj_at_src, float* grad_m);
+
+/* FWI gradient of J = 1/2 sum_n sum_r (d^n_r - d_obs^n_r)^2 w.r.t.
+ * m = 1/v^2 for a single-shot context: reset, forward nsteps with
+ * checkpoints, residual, adjoint with imaging.  grad_m is overwritten;
+ * traces (device [nsteps][nrec], may be NULL) receives the modelled data;
+ * loss_host (may be NULL) receives J (this synchronises the stream). */
+mm_status mm_gradient(mm_ctx* ctx, int32_t nsteps, const float* wavelet, const float* d_obs, float* grad_m,
+                      float* traces, double* loss_host);
+
+/* Zero the forward and adjoint state and the CPML memory; step = 0. */
+mm_status mm_reset(mm_ctx* ctx);
+
+/* Size of the state blob of mm_get_state / mm_set_state, in bytes. */
+mm_status mm_state_size(const mm_ctx* ctx, size_t* bytes);
+
+/* Copy the state to / from a caller device buffer.  Layout per shot, in
+ * shot order: p^{k-1} [nz][ny][nx], p^k [nz][ny][nx] (float32), then for
+ * CPML psi_x, psi_y, psi_z, zeta_x, zeta_y, zeta_z in slab layout:
+ * x-slabs [nz][ny][2nb], y-slabs [nz][2nb][nx], z-slabs [2nb][ny][nx],
+ * where slab index s < nb is grid index s and s >= nb is grid index
+ * n - 2nb + s.  mm_set_state also sets the step counter. */
+mm_status mm_get_state(mm_ctx* ctx, void* dst_dev);
+mm_status mm_set_state(mm_ctx* ctx, const void* src_dev, int32_t step);
+
+/* Time step, step counter and launch geometry actually in use. */
+mm_status mm_get_info(const mm_ctx* ctx, double* dt, int32_t* step, int32_t* tile);
+
+/* Pick the stencil tile variant by timing each candidate on this context
+ * (state is zeroed afterwards; synchronises).  Results are cached per
+ * (grid, boundary) for the life of the process.  *tile_out may be NULL. */
+mm_status mm_autotune(mm_ctx* ctx, int32_t steps_per_trial, int32_t* tile_out);
+
+/* Force a tile variant (0 = default).  Returns MM_ERR_ARG if unknown. */
+mm_status mm_set_tile(mm_ctx* ctx, int32_t tile);
+
+/* Number of tile variants and a description of variant t (static string). */
+int32_t mm_num_tiles(void);
+const char* mm_tile_name(int32_t t);
+
+/* Kernel timing on the context's stream: while stride > 0, every stride-th
+ * launch of the stencil kernel (the dominant kernel of a step) is bracketed
+ * by a pair of HIP events.  mm_profile_read synchronises the stream, returns
+ * the summed milliseconds and the number of timed launches, and clears the
+ * record.  stride 0 stops timing.  Graph launches are not timed. */
+mm_status mm_profile(mm_ctx* ctx, int32_t stride);
+mm_status mm_profile_read(mm_ctx* ctx, double* ms, int32_t* launches);
+
+void mm_destroy(mm_ctx* ctx);
+const char* mm_status_str(mm_status s);
+/* Message of the last failed call on ctx (or of the last failed call that
+ * had no context, if ctx is NULL).  Never NULL. */
+const char* mm_last_error(const mm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MINIMOD_H */

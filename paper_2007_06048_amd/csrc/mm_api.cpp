@@ -1,0 +1,1141 @@
+// Host runtime of the acoustic_iso_cd library: argument checks, time step,
+// workspace carving, boundary and point tables, the time loop, the
+// adjoint/gradient with checkpoints, HIP graph capture and the tile
+// autotuner.  Every array operation runs in the kernels of mm_kernels.hip;
+// this file only computes scalars and small 1D tables and enqueues work.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/minimod.h"
+#include "mm_internal.h"
+
+using namespace mm;
+
+namespace {
+
+// Order-8 central weights: second derivative a_m, first derivative beta_m.
+const double kA2[4] = {8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+const double kB1[4] = {4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
+const double kPi = 3.14159265358979323846;
+
+thread_local std::string g_err;  // last error without a context
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct ShotGeom {
+    int nx, ny, nz;
+    long long n() const { return (long long)nx * ny * nz; }
+};
+
+long long slab_points(const ShotGeom& g, int nb) {
+    const long long nb2 = 2LL * nb;
+    return nb2 * g.ny * g.nx + (g.nz - nb2) * nb2 * g.nx + (g.nz - nb2) * (g.ny - nb2) * nb2;
+}
+
+// Tiles of one variant over all shots, in shot-major, z-chunk, y, x order.
+void build_tiles(int variant, const std::vector<ShotGeom>& shots, std::vector<TileEnt>& out) {
+    const TileShape& ts = tile_variant(variant);
+    const int TX = ts.tx, TY = tile_rows(variant);
+    long long xy = 0;
+    for (const auto& g : shots) xy += (long long)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
+    long long nch = xy > 0 ? (ts.target + xy - 1) / xy : 1;
+    if (nch < 1) nch = 1;
+    out.clear();
+    for (size_t s = 0; s < shots.size(); ++s) {
+        const auto& g = shots[s];
+        int zlen = (int)((g.nz + nch - 1) / nch);
+        if (zlen < 4) zlen = 4;
+        for (int z0 = 0; z0 < g.nz; z0 += zlen) {
+            const int z1 = std::min(g.nz, z0 + zlen);
+            for (int y0 = 0; y0 < g.ny; y0 += TY)
+                for (int x0 = 0; x0 < g.nx; x0 += TX) out.push_back(TileEnt{(int)s, x0, y0, z0, z1, 0, 0, 0});
+        }
+    }
+}
+
+struct Layout {
+    size_t total = 0;
+    size_t shots_dev = 0, shots_adj = 0, tiles = 0, scratch = 0;
+    int max_tiles = 0;
+    std::vector<size_t> buf0, buf1, vdt2, prof, ebuf0, ebuf1;
+    std::vector<size_t> psi[3], zeta[3];
+    size_t src_shot = 0, src_off = 0, src_start = 0, src_col = 0, src_g = 0;
+    size_t rin_shot = 0, rin_off = 0, rin_start = 0, rin_col = 0, rin_g = 0;
+    size_t rg_shot = 0, rg_off = 0, sg_shot = 0, sg_off = 0;
+    bool adjoint = false, grad = false;
+    int nseg = 0;
+    size_t seg = 0, ckpt = 0, ckpt_scale = 0, wav_store = 0, tr_store = 0, resid_store = 0;
+    size_t ckpt_field_bytes = 0;
+};
+
+const int kPartials = 2048;  // reduction partial slots
+
+size_t take(Layout& L, size_t bytes) {
+    const size_t off = L.total;
+    L.total += align256(bytes ? bytes : 1);
+    return off;
+}
+
+void compute_layout(const mm_params& p, const std::vector<ShotGeom>& shots, int nsrc, int nrec, Layout& L) {
+    L = Layout();
+    const int S = (int)shots.size();
+    L.shots_dev = take(L, sizeof(ShotDev) * S);
+    L.shots_adj = take(L, sizeof(ShotDev) * S);
+    int mt = 0;
+    std::vector<TileEnt> tmp;
+    for (int v = 0; v < num_tile_variants(); ++v) {
+        build_tiles(v, shots, tmp);
+        mt = std::max(mt, (int)tmp.size());
+    }
+    L.max_tiles = mt;
+    L.tiles = take(L, sizeof(TileEnt) * mt);
+    // scratch: vcheck (2 u32), absmax partials + result, loss partials + loss
+    L.scratch = take(L, 64 + sizeof(float) * (kPartials + 2) + sizeof(double) * (kPartials + 2));
+    L.adjoint = p.ckpt_every > 0;
+    L.grad = L.adjoint && S == 1;
+    for (int s = 0; s < S; ++s) {
+        const auto& g = shots[s];
+        const size_t fb = sizeof(float) * (size_t)g.n();
+        L.buf0.push_back(take(L, fb));
+        L.buf1.push_back(take(L, fb));
+        L.vdt2.push_back(take(L, fb));
+        const int np = p.bc == MM_BC_CPML ? 2 * (g.nx + g.ny + g.nz) : (g.nx + g.ny + g.nz);
+        L.prof.push_back(take(L, sizeof(float) * np));
+        const size_t nb2 = 2 * (size_t)std::max(p.nb, 0);
+        const size_t sl[3] = {(size_t)g.nz * g.ny * nb2, (size_t)g.nz * nb2 * g.nx, nb2 * g.ny * g.nx};
+        for (int a = 0; a < 3; ++a) {
+            const bool c = p.bc == MM_BC_CPML;
+            L.psi[a].push_back(c ? take(L, sizeof(float) * sl[a]) : 0);
+            L.zeta[a].push_back(c ? take(L, sizeof(float) * sl[a]) : 0);
+        }
+        L.ebuf0.push_back(L.adjoint ? take(L, fb) : 0);
+        L.ebuf1.push_back(L.adjoint ? take(L, fb) : 0);
+    }
+    L.src_shot = take(L, sizeof(int) * nsrc);
+    L.src_off = take(L, sizeof(long long) * nsrc);
+    L.src_start = take(L, sizeof(int) * (nsrc + 1));
+    L.src_col = take(L, sizeof(int) * nsrc);
+    L.src_g = take(L, sizeof(float) * nsrc);
+    L.rin_shot = take(L, sizeof(int) * nrec);
+    L.rin_off = take(L, sizeof(long long) * nrec);
+    L.rin_start = take(L, sizeof(int) * (nrec + 1));
+    L.rin_col = take(L, sizeof(int) * nrec);
+    L.rin_g = take(L, sizeof(float) * nrec);
+    L.rg_shot = take(L, sizeof(int) * nrec);
+    L.rg_off = take(L, sizeof(long long) * nrec);
+    L.sg_shot = take(L, sizeof(int) * nsrc);
+    L.sg_off = take(L, sizeof(long long) * nsrc);
+    if (L.grad) {
+        const long long N = shots[0].n();
+        const int K = p.ckpt_every;
+        L.nseg = (p.nsteps_max + K - 1) / K;
+        L.seg = take(L, sizeof(float) * (size_t)K * N);
+        L.ckpt_field_bytes = align256((p.snap == MM_SNAP_BF16 ? 2 : 4) * (size_t)N);
+        L.ckpt = take(L, (size_t)L.nseg * 2 * L.ckpt_field_bytes);
+        L.ckpt_scale = take(L, sizeof(float) * 2 * L.nseg);
+        L.wav_store = take(L, sizeof(float) * (size_t)p.nsteps_max * nsrc);
+        L.tr_store = take(L, sizeof(float) * (size_t)p.nsteps_max * nrec);
+        L.resid_store = take(L, sizeof(float) * (size_t)p.nsteps_max * nrec);
+    }
+}
+
+// Depth of index k inside a layer of nb cells at either end of n cells:
+// nb at the outermost cell, 1 at the innermost layer cell, 0 inside.
+int layer_depth(int k, int n, int nb) {
+    const int d = std::max(nb - k, nb - (n - 1 - k));
+    return d > 0 ? d : 0;
+}
+
+void sponge_table(int n, int nb, double sigma, float* out) {
+    for (int k = 0; k < n; ++k) {
+        const int d = layer_depth(k, n, nb);
+        const double x = sigma * d;
+        out[k] = d > 0 ? (float)std::exp(-x * x) : 1.0f;
+    }
+}
+
+void cpml_table(int n, int nb, double h, double dt, double vmax, double R, double f0, float* a, float* b) {
+    const double d0 = -3.0 * vmax * std::log(R) / (2.0 * nb * h);
+    for (int k = 0; k < n; ++k) {
+        const int dep = layer_depth(k, n, nb);
+        if (dep == 0) {
+            a[k] = 0.0f;
+            b[k] = 1.0f;
+            continue;
+        }
+        const double q = (double)dep / nb;
+        const double d = d0 * q * q;
+        const double al = kPi * f0 * (1.0 - q);
+        const double bb = std::exp(-(d + al) * dt);
+        b[k] = (float)bb;
+        a[k] = (d + al) > 0.0 ? (float)(d * (bb - 1.0) / (d + al)) : 0.0f;
+    }
+}
+
+double dt_stab(const mm_params& p, double vmax) {
+    const double S = 4.0 * (kA2[0] + kA2[2]);
+    const double sum = 1.0 / (p.dx * p.dx) + 1.0 / (p.dy * p.dy) + 1.0 / (p.dz * p.dz);
+    return 2.0 / (vmax * std::sqrt(S * sum));
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+}  // namespace
+
+struct GraphKey {
+    int nsteps = -1;
+    const float* wav = nullptr;
+    float* tr = nullptr;
+    int step = -1;
+    int variant = -1;
+    bool operator==(const GraphKey& o) const {
+        return nsteps == o.nsteps && wav == o.wav && tr == o.tr && step == o.step && variant == o.variant;
+    }
+};
+
+struct mm_ctx {
+    mm_params p{};
+    hipStream_t stream = nullptr;
+    double dt = 0.0, vmax = 0.0;
+    std::vector<ShotGeom> geom;
+    std::vector<ShotDev> shots_h, shots_adj_h;
+    Layout L;
+    char* ws = nullptr;
+    ShotDev* d_shots = nullptr;
+    ShotDev* d_shots_adj = nullptr;
+    TileEnt* d_tiles = nullptr;
+    std::vector<TileEnt> tiles_h;
+    int ntiles = 0, variant = 0;
+    InjTab src_inj{}, rec_inj{};
+    GatherTab rec_gather{}, src_gather{};
+    int nsrc = 0, nrec = 0;
+    int max_slab = 0;
+    Coefs cf{};
+    bool sponge = false, cpml = false;
+    // time state
+    int step = 0;
+    bool fwd_valid = true;
+    // gradient / adjoint
+    bool ckpt_active = false;
+    bool adj_started = false;
+    bool adj_grad = false;
+    int adj_T = 0, adj_j = 0, seg_loaded = -1;
+    // scratch pointers
+    unsigned* vcheck = nullptr;
+    float* absmax_part = nullptr;
+    float* absmax_res = nullptr;
+    double* loss_part = nullptr;
+    double* loss_dev = nullptr;
+    // graph
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    GraphKey gkey;
+    std::string err;
+    // host tables kept alive until their uploads complete
+    std::vector<char> host_tables;
+    // stencil timing
+    int prof_stride = 0;
+    long long prof_count = 0;
+    std::vector<hipEvent_t> prof_ev;
+    size_t prof_used = 0;
+};
+
+namespace {
+
+mm_status fail(mm_ctx* c, mm_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    g_err = msg;
+    return s;
+}
+
+mm_status dev(mm_ctx* c, hipError_t e, const char* what) {
+    if (e == hipSuccess) return MM_OK;
+    return fail(c, MM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define MM_TRY(expr)                 \
+    do {                             \
+        mm_status _s = (expr);       \
+        if (_s != MM_OK) return _s;  \
+    } while (0)
+
+template <class T>
+T* at(char* ws, size_t off) {
+    return reinterpret_cast<T*>(ws + off);
+}
+
+mm_status check_params(const mm_params* p, mm_ctx* c) {
+    if (!p) return fail(c, MM_ERR_ARG, "params is NULL");
+    if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->dz))
+        return fail(c, MM_ERR_ARG, "grid spacing must be finite and > 0");
+    if (p->bc < MM_BC_NONE || p->bc > MM_BC_CPML) return fail(c, MM_ERR_ARG, "unknown boundary kind");
+    if (p->bc != MM_BC_NONE && p->nb < 1) return fail(c, MM_ERR_ARG, "damping width nb must be >= 1");
+    if (p->nb < 0 || p->nb > 4096) return fail(c, MM_ERR_ARG, "damping width nb out of range");
+    if (p->bc == MM_BC_SPONGE && !(std::isfinite(p->sponge_sigma) && p->sponge_sigma >= 0.0))
+        return fail(c, MM_ERR_ARG, "sponge_sigma must be finite and >= 0");
+    if (p->bc == MM_BC_CPML && !(std::isfinite(p->cpml_R) && p->cpml_R > 0.0 && p->cpml_R <= 1.0))
+        return fail(c, MM_ERR_ARG, "cpml_R must be in (0, 1]");
+    if (p->bc == MM_BC_CPML && !(std::isfinite(p->cpml_f0) && p->cpml_f0 >= 0.0))
+        return fail(c, MM_ERR_ARG, "cpml_f0 must be finite and >= 0");
+    if (!(std::isfinite(p->dt) && p->dt >= 0.0)) return fail(c, MM_ERR_ARG, "dt must be finite and >= 0");
+    if (p->dt == 0.0 && !(std::isfinite(p->cfl) && p->cfl > 0.0)) return fail(c, MM_ERR_ARG, "cfl must be > 0");
+    if (!(std::isfinite(p->vmax) && p->vmax >= 0.0)) return fail(c, MM_ERR_ARG, "vmax must be finite and >= 0");
+    if (p->ckpt_every < 0) return fail(c, MM_ERR_ARG, "ckpt_every must be >= 0");
+    if (p->ckpt_every > 0 && p->nsteps_max < 1) return fail(c, MM_ERR_ARG, "nsteps_max must be >= 1");
+    if (p->snap != MM_SNAP_FP32 && p->snap != MM_SNAP_BF16) return fail(c, MM_ERR_ARG, "unknown snapshot kind");
+    if (p->tile < -1 || p->tile >= num_tile_variants()) return fail(c, MM_ERR_ARG, "unknown tile variant");
+    return MM_OK;
+}
+
+mm_status check_shot(const mm_params* p, const mm_shot& s, int idx, bool need_vel, mm_ctx* c) {
+    char buf[160];
+    const int n[3] = {s.nx, s.ny, s.nz};
+    for (int a = 0; a < 3; ++a) {
+        if (n[a] < 1 || n[a] > (1 << 20)) {
+            snprintf(buf, sizeof buf, "shot %d: grid size %d out of range", idx, n[a]);
+            return fail(c, MM_ERR_ARG, buf);
+        }
+        if (p->bc != MM_BC_NONE && n[a] < 2 * p->nb + 1) {
+            snprintf(buf, sizeof buf, "shot %d: grid size %d < 2*nb+1 = %d", idx, n[a], 2 * p->nb + 1);
+            return fail(c, MM_ERR_ARG, buf);
+        }
+    }
+    if ((long long)s.nx * s.ny * s.nz > (1LL << 34)) return fail(c, MM_ERR_ARG, "grid too large");
+    if (need_vel && !s.vel) return fail(c, MM_ERR_ARG, "velocity pointer is NULL");
+    if (s.nsrc < 0 || s.nrec < 0) return fail(c, MM_ERR_ARG, "negative source/receiver count");
+    if ((s.nsrc > 0 && !s.src_ijk) || (s.nrec > 0 && !s.rec_ijk))
+        return fail(c, MM_ERR_ARG, "source/receiver list is NULL");
+    for (int q = 0; q < s.nsrc + s.nrec; ++q) {
+        const int32_t* t = q < s.nsrc ? s.src_ijk + 3 * q : s.rec_ijk + 3 * (q - s.nsrc);
+        if (t[0] < 0 || t[1] < 0 || t[2] < 0 || t[0] >= s.nx || t[1] >= s.ny || t[2] >= s.nz) {
+            snprintf(buf, sizeof buf, "shot %d: %s %d at (%d,%d,%d) outside the %dx%dx%d grid", idx,
+                     q < s.nsrc ? "source" : "receiver", q < s.nsrc ? q : q - s.nsrc, t[0], t[1], t[2], s.nx, s.ny,
+                     s.nz);
+            return fail(c, MM_ERR_ARG, buf);
+        }
+    }
+    return MM_OK;
+}
+
+mm_status totals(const mm_params* p, int32_t nshots, const mm_shot* shots, bool need_vel, std::vector<ShotGeom>& g,
+                 int& nsrc, int& nrec, mm_ctx* c) {
+    if (nshots < 1 || !shots) return fail(c, MM_ERR_ARG, "need at least one shot");
+    g.clear();
+    long long ns = 0, nr = 0;
+    for (int s = 0; s < nshots; ++s) {
+        MM_TRY(check_shot(p, shots[s], s, need_vel, c));
+        g.push_back(ShotGeom{shots[s].nx, shots[s].ny, shots[s].nz});
+        ns += shots[s].nsrc;
+        nr += shots[s].nrec;
+    }
+    if (ns > (1 << 28) || nr > (1 << 28)) return fail(c, MM_ERR_ARG, "too many sources or receivers");
+    nsrc = (int)ns;
+    nrec = (int)nr;
+    return MM_OK;
+}
+
+// CSR of unique cells for point injection.
+struct Csr {
+    std::vector<int> shot, start, col;
+    std::vector<long long> off;
+    std::vector<float> g;
+};
+
+void build_csr(const std::vector<int>& shot, const std::vector<long long>& off, const std::vector<float>& gval,
+               Csr& out) {
+    const int n = (int)shot.size();
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+        return shot[a] != shot[b] ? shot[a] < shot[b] : off[a] < off[b];
+    });
+    out = Csr();
+    for (int q = 0; q < n; ++q) {
+        const int i = idx[q];
+        if (q == 0 || shot[i] != out.shot.back() || off[i] != out.off.back()) {
+            out.shot.push_back(shot[i]);
+            out.off.push_back(off[i]);
+            out.g.push_back(gval[i]);
+            out.start.push_back(q);
+        }
+        out.col.push_back(i);
+    }
+    out.start.push_back(n);
+}
+
+mm_status upload(mm_ctx* c, void* dst, const void* src, size_t bytes) {
+    if (bytes == 0) return MM_OK;
+    return dev(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream), "upload");
+}
+
+mm_status set_variant(mm_ctx* c, int v) {
+    build_tiles(v, c->geom, c->tiles_h);
+    if ((int)c->tiles_h.size() > c->L.max_tiles) return fail(c, MM_ERR_WORKSPACE, "tile table overflow");
+    MM_TRY(dev(c, hipStreamSynchronize(c->stream), "sync"));
+    MM_TRY(upload(c, c->d_tiles, c->tiles_h.data(), sizeof(TileEnt) * c->tiles_h.size()));
+    MM_TRY(dev(c, hipStreamSynchronize(c->stream), "sync"));
+    c->ntiles = (int)c->tiles_h.size();
+    c->variant = v;
+    return MM_OK;
+}
+
+void drop_graph(mm_ctx* c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->gkey = GraphKey();
+}
+
+mm_status zero_state(mm_ctx* c, hipStream_t s) {
+    for (size_t i = 0; i < c->geom.size(); ++i) {
+        const long long n = c->geom[i].n();
+        const ShotDev& sd = c->shots_h[i];
+        MM_TRY(dev(c, launch_fill(sd.buf[0], n, 0.0f, s), "fill"));
+        MM_TRY(dev(c, launch_fill(sd.buf[1], n, 0.0f, s), "fill"));
+        if (c->cpml) {
+            const long long nb2 = 2LL * c->p.nb;
+            const long long sl[3] = {(long long)c->geom[i].nz * c->geom[i].ny * nb2,
+                                     (long long)c->geom[i].nz * nb2 * c->geom[i].nx,
+                                     nb2 * c->geom[i].ny * c->geom[i].nx};
+            for (int a = 0; a < 3; ++a) {
+                MM_TRY(dev(c, launch_fill(sd.psi[a], sl[a], 0.0f, s), "fill"));
+                MM_TRY(dev(c, launch_fill(sd.zeta[a], sl[a], 0.0f, s), "fill"));
+            }
+        }
+    }
+    return MM_OK;
+}
+
+mm_status zero_adjoint(mm_ctx* c, hipStream_t s) {
+    for (size_t i = 0; i < c->geom.size(); ++i) {
+        const long long n = c->geom[i].n();
+        MM_TRY(dev(c, launch_fill(c->shots_adj_h[i].buf[0], n, 0.0f, s), "fill"));
+        MM_TRY(dev(c, launch_fill(c->shots_adj_h[i].buf[1], n, 0.0f, s), "fill"));
+    }
+    return MM_OK;
+}
+
+// One leapfrog step of the forward (or adjoint) field set.
+mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, const StepAux& aux, hipStream_t s) {
+    const bool timed = c->prof_stride > 0 && s == c->stream && (c->prof_count++ % c->prof_stride) == 0;
+    if (timed) {
+        while (c->prof_ev.size() < c->prof_used + 2) {
+            hipEvent_t e;
+            MM_TRY(dev(c, hipEventCreate(&e), "event"));
+            c->prof_ev.push_back(e);
+        }
+        MM_TRY(dev(c, hipEventRecord(c->prof_ev[c->prof_used], s), "event"));
+    }
+    MM_TRY(dev(c, launch_step(c->variant, c->sponge, mode, c->d_tiles, c->ntiles, shots, parity, c->cf, aux, s),
+               "stencil launch"));
+    if (timed) {
+        MM_TRY(dev(c, hipEventRecord(c->prof_ev[c->prof_used + 1], s), "event"));
+        c->prof_used += 2;
+    }
+    if (c->cpml && shots == c->d_shots)
+        MM_TRY(dev(c, launch_cpml(shots, (int)c->geom.size(), c->max_slab, parity, c->cf, s), "cpml launch"));
+    return MM_OK;
+}
+
+float* ckpt_field(mm_ctx* c, int seg, int which) {
+    return reinterpret_cast<float*>(c->ws + c->L.ckpt + ((size_t)seg * 2 + which) * c->L.ckpt_field_bytes);
+}
+
+mm_status save_ckpt(mm_ctx* c, int seg, int parity, hipStream_t s) {
+    const long long N = c->geom[0].n();
+    const ShotDev& sd = c->shots_h[0];
+    const float* f[2] = {sd.buf[parity ^ 1], sd.buf[parity]};  // p^{k-1}, p^k
+    float* scale = at<float>(c->ws, c->L.ckpt_scale) + 2 * seg;
+    for (int w = 0; w < 2; ++w) {
+        if (c->p.snap == MM_SNAP_FP32) {
+            MM_TRY(dev(c, hipMemcpyAsync(ckpt_field(c, seg, w), f[w], sizeof(float) * N, hipMemcpyDeviceToDevice, s),
+                       "checkpoint copy"));
+        } else {
+            MM_TRY(dev(c, launch_absmax(f[w], N, c->absmax_part, kPartials, scale + w, s), "absmax"));
+            MM_TRY(dev(c, launch_pack_bf16(f[w], N, scale + w, reinterpret_cast<uint16_t*>(ckpt_field(c, seg, w)), s),
+                       "pack"));
+        }
+    }
+    return MM_OK;
+}
+
+mm_status restore_ckpt(mm_ctx* c, int seg, int parity, hipStream_t s) {
+    const long long N = c->geom[0].n();
+    const ShotDev& sd = c->shots_h[0];
+    float* f[2] = {sd.buf[parity ^ 1], sd.buf[parity]};
+    const float* scale = at<float>(c->ws, c->L.ckpt_scale) + 2 * seg;
+    for (int w = 0; w < 2; ++w) {
+        if (c->p.snap == MM_SNAP_FP32) {
+            MM_TRY(dev(c, hipMemcpyAsync(f[w], ckpt_field(c, seg, w), sizeof(float) * N, hipMemcpyDeviceToDevice, s),
+                       "checkpoint copy"));
+        } else {
+            MM_TRY(dev(c, launch_unpack_bf16(reinterpret_cast<const uint16_t*>(ckpt_field(c, seg, w)), N, scale + w,
+                                             f[w], s),
+                       "unpack"));
+        }
+    }
+    return MM_OK;
+}
+
+mm_status enqueue_forward(mm_ctx* c, int nsteps, const float* wav, float* traces, hipStream_t s) {
+    const StepAux none{};
+    const bool ck = c->ckpt_active;
+    if (ck && c->nsrc > 0)
+        MM_TRY(dev(c, hipMemcpyAsync(at<float>(c->ws, c->L.wav_store) + (size_t)c->step * c->nsrc, wav,
+                                     sizeof(float) * (size_t)nsteps * c->nsrc, hipMemcpyDeviceToDevice, s),
+                   "wavelet copy"));
+    for (int j = 0; j < nsteps; ++j) {
+        const int k = c->step + j;
+        const int parity = k & 1;
+        if (ck && k % c->p.ckpt_every == 0) MM_TRY(save_ckpt(c, k / c->p.ckpt_every, parity, s));
+        MM_TRY(enqueue_step(c, c->d_shots, parity, MODE_PLAIN, none, s));
+        if (c->nsrc > 0)
+            MM_TRY(dev(c, launch_inject(c->src_inj, c->d_shots, parity, wav + (size_t)j * c->nsrc, c->nsrc, MODE_PLAIN,
+                                        none, s),
+                       "inject"));
+        if (traces && c->nrec > 0)
+            MM_TRY(dev(c, launch_gather(c->rec_gather, c->d_shots, parity, traces + (size_t)j * c->nrec, s), "record"));
+    }
+    return MM_OK;
+}
+
+mm_status check_forward(mm_ctx* c, int nsteps, const float* wav) {
+    if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
+    if (nsteps < 0) return fail(c, MM_ERR_ARG, "nsteps must be >= 0");
+    if (c->nsrc > 0 && nsteps > 0 && !wav) return fail(c, MM_ERR_ARG, "wavelet is NULL");
+    if (!c->fwd_valid) return fail(c, MM_ERR_STATE, "forward state was consumed by a gradient replay; call mm_reset");
+    if ((long long)c->step + nsteps > (1LL << 30)) return fail(c, MM_ERR_ARG, "step counter overflow");
+    return MM_OK;
+}
+
+void begin_forward(mm_ctx* c, int nsteps) {
+    if (c->L.grad) {
+        if (c->step == 0) c->ckpt_active = true;
+        if (c->ckpt_active && c->step + nsteps > c->p.nsteps_max) c->ckpt_active = false;
+    }
+    c->adj_started = false;
+}
+
+// Replay segment sg from its checkpoint, keeping d2p of every step.
+mm_status replay_segment(mm_ctx* c, int sg, hipStream_t s) {
+    const int K = c->p.ckpt_every;
+    const int n0 = sg * K, n1 = std::min(n0 + K, c->adj_T);
+    const long long N = c->geom[0].n();
+    MM_TRY(restore_ckpt(c, sg, n0 & 1, s));
+    float* seg = at<float>(c->ws, c->L.seg);
+    const float* wav = at<float>(c->ws, c->L.wav_store);
+    for (int n = n0; n < n1; ++n) {
+        StepAux aux{};
+        aux.d2p_out = seg + (size_t)(n - n0) * N;
+        MM_TRY(enqueue_step(c, c->d_shots, n & 1, MODE_D2P, aux, s));
+        if (c->nsrc > 0)
+            MM_TRY(dev(c, launch_inject(c->src_inj, c->d_shots, n & 1, wav + (size_t)n * c->nsrc, c->nsrc, MODE_D2P,
+                                        aux, s),
+                       "inject"));
+    }
+    c->seg_loaded = sg;
+    c->fwd_valid = false;
+    return MM_OK;
+}
+
+mm_status enqueue_adjoint(mm_ctx* c, int nsteps, const float* resid, float* adj_src, float* grad, hipStream_t s) {
+    const int mcur = c->adj_T - c->adj_j;
+    const int m0 = mcur - nsteps + 1;
+    const long long N = c->geom[0].n();
+    for (int j = 0; j < nsteps; ++j) {
+        const int jj = c->adj_j + j;
+        const int m = c->adj_T - jj;
+        const int parity = jj & 1;
+        StepAux aux{};
+        int mode = MODE_PLAIN;
+        if (grad) {
+            const int K = c->p.ckpt_every;
+            const int sg = (m - 1) / K;
+            if (c->seg_loaded != sg) MM_TRY(replay_segment(c, sg, s));
+            aux.d2p_in = at<float>(c->ws, c->L.seg) + (size_t)((m - 1) - sg * K) * N;
+            aux.grad = grad;
+            aux.neg_inv_dt2 = (float)(-1.0 / (c->dt * c->dt));
+            mode = MODE_IMAGE;
+        }
+        MM_TRY(enqueue_step(c, c->d_shots_adj, parity, mode, aux, s));
+        const int row = m - m0;
+        if (c->nrec > 0)
+            MM_TRY(dev(c, launch_inject(c->rec_inj, c->d_shots_adj, parity, resid + (size_t)row * c->nrec, c->nrec,
+                                        mode, aux, s),
+                       "adjoint inject"));
+        if (adj_src && c->nsrc > 0)
+            MM_TRY(dev(c, launch_gather(c->src_gather, c->d_shots_adj, parity, adj_src + (size_t)row * c->nsrc, s),
+                       "adjoint record"));
+    }
+    return MM_OK;
+}
+
+std::string tune_key(const mm_ctx* c) {
+    std::string k = std::to_string(c->p.bc) + "/" + std::to_string(c->p.nb);
+    for (const auto& g : c->geom) k += ":" + std::to_string(g.nx) + "x" + std::to_string(g.ny) + "x" + std::to_string(g.nz);
+    return k;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune_cache;
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+void mm_default_params(mm_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->dx = p->dy = p->dz = 10.0;
+    p->cfl = 0.5;
+    p->bc = MM_BC_SPONGE;
+    p->nb = 12;
+    p->sponge_sigma = 0.015;
+    p->cpml_R = 1e-3;
+    p->cpml_f0 = 15.0;
+    p->snap = MM_SNAP_FP32;
+}
+
+const char* mm_status_str(mm_status s) {
+    switch (s) {
+        case MM_OK: return "ok";
+        case MM_ERR_ARG: return "invalid argument";
+        case MM_ERR_UNSTABLE: return "unstable time step";
+        case MM_ERR_WORKSPACE: return "workspace too small or misaligned";
+        case MM_ERR_DEVICE: return "device error";
+        case MM_ERR_STATE: return "invalid state for this call";
+        case MM_ERR_NONFINITE: return "non-finite or non-positive value";
+        case MM_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* mm_last_error(const mm_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+mm_status mm_dt(const mm_params* p, double vmax, double* dt_out) {
+    MM_TRY(check_params(p, nullptr));
+    if (!finite_pos(vmax)) return fail(nullptr, MM_ERR_ARG, "vmax must be finite and > 0");
+    if (!dt_out) return fail(nullptr, MM_ERR_ARG, "dt_out is NULL");
+    const double lim = dt_stab(*p, vmax);
+    if (p->dt > 0.0) {
+        if (p->dt > lim) return fail(nullptr, MM_ERR_UNSTABLE, "dt exceeds the stability limit");
+        *dt_out = p->dt;
+        return MM_OK;
+    }
+    if (p->cfl > 1.0) return fail(nullptr, MM_ERR_UNSTABLE, "cfl > 1 is unstable");
+    *dt_out = p->cfl * lim;
+    return MM_OK;
+}
+
+mm_status mm_ricker(double f0, double t0, double dt, int32_t n, float* out) {
+    if (!(std::isfinite(f0) && f0 > 0) || !std::isfinite(t0) || !finite_pos(dt) || n < 0 || (n > 0 && !out))
+        return fail(nullptr, MM_ERR_ARG, "bad Ricker arguments");
+    for (int i = 0; i < n; ++i) {
+        const double tau = i * dt - t0;
+        const double x = (kPi * f0 * tau) * (kPi * f0 * tau);
+        out[i] = (float)((1.0 - 2.0 * x) * std::exp(-x));
+    }
+    return MM_OK;
+}
+
+mm_status mm_workspace_size(const mm_params* p, int32_t nshots, const mm_shot* shots, size_t* bytes) {
+    MM_TRY(check_params(p, nullptr));
+    if (!bytes) return fail(nullptr, MM_ERR_ARG, "bytes is NULL");
+    std::vector<ShotGeom> g;
+    int ns, nr;
+    MM_TRY(totals(p, nshots, shots, false, g, ns, nr, nullptr));
+    Layout L;
+    compute_layout(*p, g, ns, nr, L);
+    *bytes = L.total;
+    return MM_OK;
+}
+
+mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const mm_shot* shots, void* workspace,
+                        size_t ws_bytes, void* hip_stream) {
+    if (!out) return fail(nullptr, MM_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    MM_TRY(check_params(p, nullptr));
+    std::vector<ShotGeom> geom;
+    int nsrc, nrec;
+    MM_TRY(totals(p, nshots, shots, true, geom, nsrc, nrec, nullptr));
+    if (p->dt == 0.0 && p->cfl > 1.0) return fail(nullptr, MM_ERR_UNSTABLE, "cfl > 1 is unstable");
+    Layout L;
+    compute_layout(*p, geom, nsrc, nrec, L);
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
+        return fail(nullptr, MM_ERR_WORKSPACE, "workspace must be a non-NULL 256-byte aligned device pointer");
+    if (ws_bytes < L.total) {
+        char buf[128];
+        snprintf(buf, sizeof buf, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+        return fail(nullptr, MM_ERR_WORKSPACE, buf);
+    }
+
+    mm_ctx* c = new mm_ctx();
+    c->p = *p;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->geom = geom;
+    c->L = L;
+    c->ws = reinterpret_cast<char*>(workspace);
+    c->nsrc = nsrc;
+    c->nrec = nrec;
+    c->sponge = p->bc == MM_BC_SPONGE;
+    c->cpml = p->bc == MM_BC_CPML;
+    hipStream_t s = c->stream;
+    auto bail = [&](mm_status st) {
+        g_err = c->err;
+        delete c;
+        return st;
+    };
+
+    char* scr = c->ws + L.scratch;
+    c->vcheck = reinterpret_cast<unsigned*>(scr);
+    c->absmax_part = reinterpret_cast<float*>(scr + 64);
+    c->absmax_res = c->absmax_part + kPartials;
+    c->loss_part = reinterpret_cast<double*>(scr + 64 + sizeof(float) * (kPartials + 2));
+    c->loss_dev = c->loss_part + kPartials;
+
+    // velocity check and maximum (one synchronisation)
+    mm_status st = dev(c, launch_fill(reinterpret_cast<float*>(c->vcheck), 2, 0.0f, s), "fill");
+    if (st) return bail(st);
+    for (int i = 0; i < nshots; ++i) {
+        st = dev(c, launch_vcheck(shots[i].vel, geom[i].n(), c->vcheck, s), "velocity check");
+        if (st) return bail(st);
+    }
+    unsigned vres[2] = {0, 0};
+    st = dev(c, hipMemcpyAsync(vres, c->vcheck, sizeof vres, hipMemcpyDeviceToHost, s), "readback");
+    if (!st) st = dev(c, hipStreamSynchronize(s), "sync");
+    if (st) return bail(st);
+    if (vres[1]) return bail(fail(c, MM_ERR_NONFINITE, "velocity has NaN, Inf or non-positive values"));
+    float vmf;
+    std::memcpy(&vmf, &vres[0], sizeof vmf);
+    c->vmax = p->vmax > 0.0 ? p->vmax : (double)vmf;
+    if (p->vmax > 0.0 && p->vmax < (double)vmf) return bail(fail(c, MM_ERR_ARG, "vmax is below the model maximum"));
+    const double lim = dt_stab(*p, c->vmax);
+    if (p->dt > 0.0) {
+        if (p->dt > lim) return bail(fail(c, MM_ERR_UNSTABLE, "dt exceeds the stability limit"));
+        c->dt = p->dt;
+    } else {
+        c->dt = p->cfl * lim;
+    }
+
+    // coefficients
+    const double h[3] = {p->dx, p->dy, p->dz};
+    for (int m = 0; m < 4; ++m) {
+        c->cf.cx[m] = (float)(kA2[m] / (h[0] * h[0]));
+        c->cf.cy[m] = (float)(kA2[m] / (h[1] * h[1]));
+        c->cf.cz[m] = (float)(kA2[m] / (h[2] * h[2]));
+        c->cf.bx[m] = (float)(kB1[m] / h[0]);
+        c->cf.by[m] = (float)(kB1[m] / h[1]);
+        c->cf.bz[m] = (float)(kB1[m] / h[2]);
+    }
+
+    // shot descriptors and 1D boundary tables
+    std::vector<std::vector<float>> prof(nshots);
+    c->max_slab = 0;
+    for (int i = 0; i < nshots; ++i) {
+        const ShotGeom& g = geom[i];
+        ShotDev sd{};
+        sd.buf[0] = at<float>(c->ws, L.buf0[i]);
+        sd.buf[1] = at<float>(c->ws, L.buf1[i]);
+        sd.vdt2 = at<float>(c->ws, L.vdt2[i]);
+        sd.prof = at<float>(c->ws, L.prof[i]);
+        for (int a = 0; a < 3; ++a) {
+            sd.psi[a] = c->cpml ? at<float>(c->ws, L.psi[a][i]) : nullptr;
+            sd.zeta[a] = c->cpml ? at<float>(c->ws, L.zeta[a][i]) : nullptr;
+        }
+        sd.nx = g.nx;
+        sd.ny = g.ny;
+        sd.nz = g.nz;
+        sd.nb = p->nb;
+        c->shots_h.push_back(sd);
+        ShotDev sa = sd;
+        sa.buf[0] = L.adjoint ? at<float>(c->ws, L.ebuf0[i]) : nullptr;
+        sa.buf[1] = L.adjoint ? at<float>(c->ws, L.ebuf1[i]) : nullptr;
+        c->shots_adj_h.push_back(sa);
+        const int n[3] = {g.nx, g.ny, g.nz};
+        std::vector<float>& pr = prof[i];
+        if (c->cpml) {
+            pr.resize(2 * (g.nx + g.ny + g.nz));
+            float* q = pr.data();
+            for (int a = 0; a < 3; ++a) {
+                cpml_table(n[a], p->nb, h[a], c->dt, c->vmax, p->cpml_R, p->cpml_f0, q, q + n[a]);
+                q += 2 * n[a];
+            }
+            c->max_slab = std::max<long long>(c->max_slab, slab_points(g, p->nb));
+        } else {
+            pr.resize(g.nx + g.ny + g.nz);
+            float* q = pr.data();
+            for (int a = 0; a < 3; ++a) {
+                if (c->sponge) sponge_table(n[a], p->nb, p->sponge_sigma, q);
+                else std::fill(q, q + n[a], 1.0f);
+                q += n[a];
+            }
+        }
+    }
+    c->d_shots = at<ShotDev>(c->ws, L.shots_dev);
+    c->d_shots_adj = at<ShotDev>(c->ws, L.shots_adj);
+    c->d_tiles = at<TileEnt>(c->ws, L.tiles);
+
+    // point tables
+    std::vector<int> s_shot, r_shot;
+    std::vector<long long> s_off, r_off;
+    std::vector<float> s_g, r_g;
+    for (int i = 0; i < nshots; ++i) {
+        const ShotGeom& g = geom[i];
+        auto lin = [&](const int32_t* t) { return ((long long)t[2] * g.ny + t[1]) * g.nx + t[0]; };
+        auto gval = [&](const int32_t* t) {
+            if (!c->sponge) return 1.0f;
+            const float* q = prof[i].data();
+            return q[t[0]] * q[g.nx + t[1]] * q[g.nx + g.ny + t[2]];
+        };
+        for (int k = 0; k < shots[i].nsrc; ++k) {
+            s_shot.push_back(i);
+            s_off.push_back(lin(shots[i].src_ijk + 3 * k));
+            s_g.push_back(gval(shots[i].src_ijk + 3 * k));
+        }
+        for (int k = 0; k < shots[i].nrec; ++k) {
+            r_shot.push_back(i);
+            r_off.push_back(lin(shots[i].rec_ijk + 3 * k));
+            r_g.push_back(gval(shots[i].rec_ijk + 3 * k));
+        }
+    }
+    Csr cs, cr;
+    build_csr(s_shot, s_off, s_g, cs);
+    build_csr(r_shot, r_off, r_g, cr);
+
+    // stage every host table in one buffer kept alive in the context
+    size_t hb = 0;
+    auto reserve = [&](size_t bytes) { size_t o = hb; hb += align256(bytes); return o; };
+    const size_t o_shots = reserve(sizeof(ShotDev) * nshots), o_adj = reserve(sizeof(ShotDev) * nshots);
+    std::vector<size_t> o_prof;
+    for (int i = 0; i < nshots; ++i) o_prof.push_back(reserve(sizeof(float) * prof[i].size()));
+    c->host_tables.assign(hb, 0);
+    char* H = c->host_tables.data();
+    std::memcpy(H + o_shots, c->shots_h.data(), sizeof(ShotDev) * nshots);
+    std::memcpy(H + o_adj, c->shots_adj_h.data(), sizeof(ShotDev) * nshots);
+    for (int i = 0; i < nshots; ++i) std::memcpy(H + o_prof[i], prof[i].data(), sizeof(float) * prof[i].size());
+
+    st = upload(c, c->d_shots, H + o_shots, sizeof(ShotDev) * nshots);
+    if (!st) st = upload(c, c->d_shots_adj, H + o_adj, sizeof(ShotDev) * nshots);
+    for (int i = 0; i < nshots && !st; ++i)
+        st = upload(c, const_cast<float*>(c->shots_h[i].prof), H + o_prof[i], sizeof(float) * prof[i].size());
+    // point tables: uploaded from vectors that live until the synchronisation below
+    auto up = [&](size_t off, const void* src, size_t bytes) {
+        if (!st) st = upload(c, c->ws + off, src, bytes);
+    };
+    up(L.src_shot, cs.shot.data(), sizeof(int) * cs.shot.size());
+    up(L.src_off, cs.off.data(), sizeof(long long) * cs.off.size());
+    up(L.src_start, cs.start.data(), sizeof(int) * cs.start.size());
+    up(L.src_col, cs.col.data(), sizeof(int) * cs.col.size());
+    up(L.src_g, cs.g.data(), sizeof(float) * cs.g.size());
+    up(L.rin_shot, cr.shot.data(), sizeof(int) * cr.shot.size());
+    up(L.rin_off, cr.off.data(), sizeof(long long) * cr.off.size());
+    up(L.rin_start, cr.start.data(), sizeof(int) * cr.start.size());
+    up(L.rin_col, cr.col.data(), sizeof(int) * cr.col.size());
+    up(L.rin_g, cr.g.data(), sizeof(float) * cr.g.size());
+    up(L.rg_shot, r_shot.data(), sizeof(int) * r_shot.size());
+    up(L.rg_off, r_off.data(), sizeof(long long) * r_off.size());
+    up(L.sg_shot, s_shot.data(), sizeof(int) * s_shot.size());
+    up(L.sg_off, s_off.data(), sizeof(long long) * s_off.size());
+    for (int i = 0; i < nshots && !st; ++i)
+        st = dev(c, launch_vdt2(shots[i].vel, c->shots_h[i].vdt2, geom[i].n(), c->dt, s), "vdt2");
+    if (!st) st = dev(c, hipStreamSynchronize(s), "sync");
+    if (st) return bail(st);
+
+    c->src_inj = InjTab{at<int>(c->ws, L.src_shot), at<long long>(c->ws, L.src_off), at<int>(c->ws, L.src_start),
+                        at<int>(c->ws, L.src_col), at<float>(c->ws, L.src_g), (int)cs.shot.size(),
+                        (float)(1.0 / (p->dx * p->dy * p->dz))};
+    c->rec_inj = InjTab{at<int>(c->ws, L.rin_shot), at<long long>(c->ws, L.rin_off), at<int>(c->ws, L.rin_start),
+                        at<int>(c->ws, L.rin_col), at<float>(c->ws, L.rin_g), (int)cr.shot.size(), 1.0f};
+    c->rec_gather = GatherTab{at<int>(c->ws, L.rg_shot), at<long long>(c->ws, L.rg_off), nrec};
+    c->src_gather = GatherTab{at<int>(c->ws, L.sg_shot), at<long long>(c->ws, L.sg_off), nsrc};
+
+    st = zero_state(c, s);
+    if (!st && L.adjoint) st = zero_adjoint(c, s);
+    if (st) return bail(st);
+
+    int v = p->tile > 0 ? p->tile : 0;
+    if (p->tile == -1) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(tune_key(c));
+        if (it != g_tune_cache.end()) v = it->second;
+    }
+    st = set_variant(c, v);
+    if (st) return bail(st);
+    if (p->tile == -1 && v == 0) {
+        st = mm_autotune(c, 3, nullptr);
+        if (st) return bail(st);
+    }
+    *out = c;
+    return MM_OK;
+}
+
+mm_status mm_init(mm_ctx** out, const mm_params* p, const float* vel_dev, const int32_t* src, int32_t nsrc,
+                  const int32_t* rec, int32_t nrec, void* workspace, size_t ws_bytes, void* hip_stream) {
+    if (!p) return fail(nullptr, MM_ERR_ARG, "params is NULL");
+    mm_shot s{p->nx, p->ny, p->nz, vel_dev, src, nsrc, rec, nrec};
+    return mm_init_batch(out, p, 1, &s, workspace, ws_bytes, hip_stream);
+}
+
+mm_status mm_forward_steps(mm_ctx* c, int32_t nsteps, const float* wav, float* traces) {
+    MM_TRY(check_forward(c, nsteps, wav));
+    begin_forward(c, nsteps);
+    MM_TRY(enqueue_forward(c, nsteps, wav, traces, c->stream));
+    c->step += nsteps;
+    return MM_OK;
+}
+
+mm_status mm_forward_steps_graph(mm_ctx* c, int32_t nsteps, const float* wav, float* traces) {
+    MM_TRY(check_forward(c, nsteps, wav));
+    if (nsteps == 0) return MM_OK;
+    begin_forward(c, nsteps);
+    GraphKey key;
+    key.nsteps = nsteps;
+    key.wav = wav;
+    key.tr = traces;
+    key.step = c->ckpt_active ? c->step : (c->step & 1);
+    key.variant = c->variant;
+    if (!(c->gexec && c->gkey == key)) {
+        drop_graph(c);
+        if (!c->cap_stream) MM_TRY(dev(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "stream"));
+        MM_TRY(dev(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture"));
+        mm_status st = enqueue_forward(c, nsteps, wav, traces, c->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+        if (st) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        MM_TRY(dev(c, e, "end capture"));
+        c->graph = g;
+        MM_TRY(dev(c, hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0), "graph instantiate"));
+        c->gkey = key;
+    }
+    MM_TRY(dev(c, hipGraphLaunch(c->gexec, c->stream), "graph launch"));
+    c->step += nsteps;
+    return MM_OK;
+}
+
+mm_status mm_adjoint_steps(mm_ctx* c, int32_t nsteps, const float* resid, float* adj_src, float* grad) {
+    if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
+    if (c->cpml) return fail(c, MM_ERR_UNSUPPORTED, "the adjoint is implemented for bc none and sponge only");
+    if (!c->L.adjoint) return fail(c, MM_ERR_STATE, "context was created with ckpt_every = 0 (no adjoint storage)");
+    if (nsteps < 0) return fail(c, MM_ERR_ARG, "nsteps must be >= 0");
+    if (c->nrec > 0 && nsteps > 0 && !resid) return fail(c, MM_ERR_ARG, "residual is NULL");
+    if (grad && !c->L.grad) return fail(c, MM_ERR_UNSUPPORTED, "gradients need a single-shot context");
+    const int T = c->adj_started ? c->adj_T : c->step;
+    const int done = c->adj_started ? c->adj_j : 0;
+    if (done + nsteps > T) return fail(c, MM_ERR_STATE, "adjoint would run past time 0");
+    if (grad && !(c->ckpt_active && T <= c->p.nsteps_max))
+        return fail(c, MM_ERR_STATE, "gradient needs a checkpointed forward run from step 0 (<= nsteps_max steps)");
+    if (grad && c->adj_started && !c->adj_grad)
+        return fail(c, MM_ERR_STATE, "adjoint was started without a gradient; reset and rerun the forward");
+    if (!c->adj_started) {
+        MM_TRY(zero_adjoint(c, c->stream));
+        c->adj_started = true;
+        c->adj_T = c->step;
+        c->adj_j = 0;
+        c->adj_grad = grad != nullptr;
+        c->seg_loaded = -1;
+    }
+    MM_TRY(enqueue_adjoint(c, nsteps, resid, adj_src, grad, c->stream));
+    c->adj_j += nsteps;
+    return MM_OK;
+}
+
+mm_status mm_reset(mm_ctx* c) {
+    if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
+    MM_TRY(zero_state(c, c->stream));
+    if (c->L.adjoint) MM_TRY(zero_adjoint(c, c->stream));
+    c->step = 0;
+    c->fwd_valid = true;
+    c->ckpt_active = false;
+    c->adj_started = false;
+    c->seg_loaded = -1;
+    return MM_OK;
+}
+
+mm_status mm_gradient(mm_ctx* c, int32_t nsteps, const float* wav, const float* d_obs, float* grad, float* traces,
+                      double* loss_host) {
+    if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
+    if (c->cpml) return fail(c, MM_ERR_UNSUPPORTED, "the gradient is implemented for bc none and sponge only");
+    if (!c->L.grad) return fail(c, MM_ERR_STATE, "gradients need a single-shot context with ckpt_every > 0");
+    if (nsteps < 1 || nsteps > c->p.nsteps_max) return fail(c, MM_ERR_ARG, "nsteps must be in [1, nsteps_max]");
+    if (!grad || (c->nrec > 0 && !d_obs) || (c->nsrc > 0 && !wav)) return fail(c, MM_ERR_ARG, "NULL operand");
+    hipStream_t s = c->stream;
+    MM_TRY(mm_reset(c));
+    float* tr = traces ? traces : at<float>(c->ws, c->L.tr_store);
+    begin_forward(c, nsteps);
+    MM_TRY(enqueue_forward(c, nsteps, wav, tr, s));
+    c->step = nsteps;
+    float* resid = at<float>(c->ws, c->L.resid_store);
+    const long long nr = (long long)nsteps * c->nrec;
+    if (nr > 0) MM_TRY(dev(c, launch_residual_loss(tr, d_obs, resid, nr, c->loss_part, kPartials, c->loss_dev, s), "loss"));
+    MM_TRY(dev(c, launch_fill(grad, c->geom[0].n(), 0.0f, s), "fill"));
+    MM_TRY(mm_adjoint_steps(c, nsteps, resid, nullptr, grad));
+    if (loss_host) {
+        if (nr > 0) {
+            MM_TRY(dev(c, hipMemcpyAsync(loss_host, c->loss_dev, sizeof(double), hipMemcpyDeviceToHost, s), "readback"));
+            MM_TRY(dev(c, hipStreamSynchronize(s), "sync"));
+        } else {
+            *loss_host = 0.0;
+        }
+    }
+    return MM_OK;
+}
+
+mm_status mm_state_size(const mm_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return fail(nullptr, MM_ERR_ARG, "NULL argument");
+    size_t b = 0;
+    for (const auto& g : c->geom) {
+        b += 2 * sizeof(float) * (size_t)g.n();
+        if (c->cpml) {
+            const size_t nb2 = 2 * (size_t)c->p.nb;
+            b += 2 * sizeof(float) * ((size_t)g.nz * g.ny * nb2 + (size_t)g.nz * nb2 * g.nx + nb2 * g.ny * g.nx);
+        }
+    }
+    *bytes = b;
+    return MM_OK;
+}
+
+static mm_status state_copy(mm_ctx* c, char* ext, bool to_ext) {
+    size_t o = 0;
+    const int par = c->step & 1;
+    auto cp = [&](void* field, size_t bytes) -> mm_status {
+        void* d = to_ext ? (void*)(ext + o) : field;
+        const void* s = to_ext ? (const void*)field : (const void*)(ext + o);
+        o += bytes;
+        return dev(c, hipMemcpyAsync(d, s, bytes, hipMemcpyDeviceToDevice, c->stream), "state copy");
+    };
+    for (size_t i = 0; i < c->geom.size(); ++i) {
+        const auto& g = c->geom[i];
+        const size_t fb = sizeof(float) * (size_t)g.n();
+        MM_TRY(cp(c->shots_h[i].buf[par ^ 1], fb));
+        MM_TRY(cp(c->shots_h[i].buf[par], fb));
+        if (c->cpml) {
+            const size_t nb2 = 2 * (size_t)c->p.nb;
+            const size_t sl[3] = {(size_t)g.nz * g.ny * nb2, (size_t)g.nz * nb2 * g.nx, nb2 * g.ny * g.nx};
+            for (int a = 0; a < 3; ++a) MM_TRY(cp(c->shots_h[i].psi[a], sizeof(float) * sl[a]));
+            for (int a = 0; a < 3; ++a) MM_TRY(cp(c->shots_h[i].zeta[a], sizeof(float) * sl[a]));
+        }
+    }
+    return MM_OK;
+}
+
+mm_status mm_get_state(mm_ctx* c, void* dst) {
+    if (!c || !dst) return fail(c, MM_ERR_ARG, "NULL argument");
+    if (!c->fwd_valid) return fail(c, MM_ERR_STATE, "forward state was consumed by a gradient replay");
+    return state_copy(c, reinterpret_cast<char*>(dst), true);
+}
+
+mm_status mm_set_state(mm_ctx* c, const void* src, int32_t step) {
+    if (!c || !src) return fail(c, MM_ERR_ARG, "NULL argument");
+    if (step < 0) return fail(c, MM_ERR_ARG, "step must be >= 0");
+    c->step = step;
+    c->fwd_valid = true;
+    c->ckpt_active = false;
+    c->adj_started = false;
+    return state_copy(c, const_cast<char*>(reinterpret_cast<const char*>(src)), false);
+}
+
+mm_status mm_get_info(const mm_ctx* c, double* dt, int32_t* step, int32_t* tile) {
+    if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
+    if (dt) *dt = c->dt;
+    if (step) *step = c->step;
+    if (tile) *tile = c->variant;
+    return MM_OK;
+}
+
+int32_t mm_num_tiles(void) { return num_tile_variants(); }
+
+const char* mm_tile_name(int32_t t) { return (t >= 0 && t < num_tile_variants()) ? tile_variant(t).name : "?"; }
+
+mm_status mm_set_tile(mm_ctx* c, int32_t t) {
+    if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
+    if (t < 0 || t >= num_tile_variants()) return fail(c, MM_ERR_ARG, "unknown tile variant");
+    drop_graph(c);
+    return set_variant(c, t);
+}
+
+mm_status mm_autotune(mm_ctx* c, int32_t steps, int32_t* tile_out) {
+    if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
+    if (steps < 1) return fail(c, MM_ERR_ARG, "steps_per_trial must be >= 1");
+    hipEvent_t e0, e1;
+    MM_TRY(dev(c, hipEventCreate(&e0), "event"));
+    MM_TRY(dev(c, hipEventCreate(&e1), "event"));
+    int best = c->variant;
+    float best_ms = 1e30f;
+    const StepAux none{};
+    mm_status st = MM_OK;
+    for (int v = 0; v < num_tile_variants() && !st; ++v) {
+        st = set_variant(c, v);
+        for (int j = 0; j < 2 && !st; ++j) st = enqueue_step(c, c->d_shots, j & 1, MODE_PLAIN, none, c->stream);
+        if (!st) st = dev(c, hipEventRecord(e0, c->stream), "event");
+        for (int j = 0; j < steps && !st; ++j) st = enqueue_step(c, c->d_shots, j & 1, MODE_PLAIN, none, c->stream);
+        if (!st) st = dev(c, hipEventRecord(e1, c->stream), "event");
+        if (!st) st = dev(c, hipEventSynchronize(e1), "event");
+        float ms = 0.0f;
+        if (!st) st = dev(c, hipEventElapsedTime(&ms, e0, e1), "event");
+        if (!st && ms < best_ms) {
+            best_ms = ms;
+            best = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    drop_graph(c);
+    MM_TRY(set_variant(c, best));
+    MM_TRY(mm_reset(c));
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[tune_key(c)] = best;
+    }
+    if (tile_out) *tile_out = best;
+    return MM_OK;
+}
+
+mm_status mm_profile(mm_ctx* c, int32_t stride) {
+    if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
+    if (stride < 0) return fail(c, MM_ERR_ARG, "stride must be >= 0");
+    c->prof_stride = stride;
+    c->prof_count = 0;
+    return MM_OK;
+}
+
+mm_status mm_profile_read(mm_ctx* c, double* ms, int32_t* launches) {
+    if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
+    MM_TRY(dev(c, hipStreamSynchronize(c->stream), "sync"));
+    double tot = 0.0;
+    for (size_t i = 0; i + 1 < c->prof_used; i += 2) {
+        float m = 0.0f;
+        MM_TRY(dev(c, hipEventElapsedTime(&m, c->prof_ev[i], c->prof_ev[i + 1]), "event"));
+        tot += m;
+    }
+    if (ms) *ms = tot;
+    if (launches) *launches = (int32_t)(c->prof_used / 2);
+    c->prof_used = 0;
+    c->prof_count = 0;
+    return MM_OK;
+}
+
+void mm_destroy(mm_ctx* c) {
+    if (!c) return;
+    for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
+    drop_graph(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// Internal types shared by the host runtime (mm_api.cpp) and the gfx950
+// kernels (mm_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+namespace mm {
+
+// Per-shot device descriptor.  All 3D arrays are [nz][ny][nx], x fastest.
+struct ShotDev {
+    float* buf[2];        // wavefields: after k steps p^k is buf[k&1], p^{k-1} is buf[(k+1)&1]
+    float* vdt2;          // (dt v)^2
+    const float* prof;    // sponge: g_x[nx] g_y[ny] g_z[nz]; CPML: a_x b_x [nx], a_y b_y [ny], a_z b_z [nz]
+    float* psi[3];        // CPML memory, slab layouts (see minimod.h)
+    float* zeta[3];
+    int nx, ny, nz, nb;
+};
+
+// One z-marching tile: an xy rectangle of one shot and a z range [z0, z1).
+struct TileEnt {
+    int shot, x0, y0, z0, z1, pad0, pad1, pad2;
+};
+
+// Stencil weights a_m / h^2 per axis (m = 1..4) and first-derivative weights
+// beta_m / h (CPML).
+struct Coefs {
+    float cx[4], cy[4], cz[4];
+    float bx[4], by[4], bz[4];
+};
+
+// Point injection table in CSR form: unique cells, each with the list of
+// columns of the value row that land on it.
+struct InjTab {
+    const int* cell_shot;
+    const long long* cell_off;
+    const int* start;     // [ncell + 1]
+    const int* col;       // column in the value row
+    const float* cell_g;  // sponge factor G at the cell (1 if no sponge)
+    int ncell;
+    float scale;          // 1/(dx dy dz) for sources, 1 for adjoint residuals
+};
+
+// Point gather table.
+struct GatherTab {
+    const int* shot;
+    const long long* off;
+    int n;
+};
+
+// Extra per-step operands.
+//  mode 1: d2p[x] = G (dt v)^2 Lap p^n  (= p^{n+1} - 2G p^n + G^2 p^{n-1}
+//          before the source term; single shot)
+//  mode 2: grad[x] += neg_inv_dt2 / G * p^{n+1}[x] * d2p[x]  (imaging)
+struct StepAux {
+    float* d2p_out;
+    const float* d2p_in;
+    float* grad;
+    float neg_inv_dt2;
+};
+
+enum { MODE_PLAIN = 0, MODE_D2P = 1, MODE_IMAGE = 2 };
+
+// Tile variants of the stencil kernel.
+struct TileShape {
+    int tx;     // tile width in x (threads per row)
+    int ry;     // rows per thread
+    int target; // desired number of blocks (z-chunking)
+    const char* name;
+};
+int num_tile_variants();
+const TileShape& tile_variant(int t);
+int tile_rows(int t);  // TY of variant t
+
+hipError_t launch_step(int variant, bool sponge, int mode, const TileEnt* tiles, int ntiles,
+                       const ShotDev* shots, int parity, const Coefs& cf, const StepAux& aux,
+                       hipStream_t s);
+hipError_t launch_cpml(const ShotDev* shots, int nshots, int max_slab_pts, int parity, const Coefs& cf,
+                       hipStream_t s);
+hipError_t launch_inject(const InjTab& tab, const ShotDev* shots, int parity, const float* vals, int ncols,
+                         int mode, const StepAux& aux, hipStream_t s);
+hipError_t launch_gather(const GatherTab& tab, const ShotDev* shots, int parity, float* out, hipStream_t s);
+hipError_t launch_vdt2(const float* vel, float* vdt2, long long n, double dt, hipStream_t s);
+hipError_t launch_vcheck(const float* vel, long long n, unsigned* result2, hipStream_t s);
+hipError_t launch_fill(float* p, long long n, float v, hipStream_t s);
+hipError_t launch_copy(float* dst, const float* src, long long n, hipStream_t s);
+hipError_t launch_absmax(const float* x, long long n, float* partial, int nparts, float* result,
+                         hipStream_t s);
+hipError_t launch_pack_bf16(const float* x, long long n, const float* scale, uint16_t* out, hipStream_t s);
+hipError_t launch_unpack_bf16(const uint16_t* in, long long n, const float* scale, float* x, hipStream_t s);
+hipError_t launch_residual_loss(const float* traces, const float* dobs, float* resid, long long n,
+                                double* partial, int nparts, double* loss, hipStream_t s);
+
+}  // namespace mm

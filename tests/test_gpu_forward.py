@@ -1,0 +1,202 @@
+"""GPU forward parity: the HIP library against the FP64 oracle (element by
+element, relative L2), plus exact properties of the GPU path itself.
+
+Tolerance: relative L2 <= 1e-5 over the run for FP32 fields against the FP64
+oracle (the bar stated for the 200-step plain forward); measured values are
+printed."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2007_06048_amd import minimod as mm
+from paper_2007_06048_amd import workloads as W
+
+from .gpu_util import DEV, gpu_forward, oracle_forward, params, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _ricker_rows(f0, t0, dt, T, nsrc=1):
+    w = mm.ricker(f0, t0, dt, T).astype(np.float64)
+    return np.repeat(w[:, None], nsrc, axis=1)
+
+
+@pytest.mark.parametrize("bc", [mm.BC_SPONGE, mm.BC_CPML, mm.BC_NONE])
+def test_two_layer_64_full_run(bc):
+    """64^3 two-layer model, Ricker 15 Hz at the centre, 200 steps at cfl 0.5:
+    final field and the 64 x 64 receiver plane within 1e-5 of the oracle."""
+    wl = W.two_layer_64()
+    s = wl.shots[0]
+    p = params(s.vel.shape, bc=bc, nb=wl.nb, cfl=wl.cfl, f0=wl.f0, sigma=wl.sigma)
+    T = wl.nsteps
+    dt = mm.dt_for(p, float(s.vel.max()))
+    w = _ricker_rows(wl.f0, wl.t0, dt, T)
+    tr, pc, pm, dt_gpu = gpu_forward(p, s.vel, s.src, s.rec, w, T)
+    assert dt_gpu == dt
+    rtr, rpc, rpm = oracle_forward(p, dt, s.vel, s.src, s.rec, w, T)
+    e_tr, e_pc, e_pm = rel(tr, rtr), rel(pc, rpc), rel(pm, rpm)
+    print(f"bc={bc}: traces {e_tr:.2e} p^T {e_pc:.2e} p^(T-1) {e_pm:.2e}")
+    assert e_tr <= 1e-5 and e_pc <= 1e-5 and e_pm <= 1e-5
+
+
+_RAGGED = (23, 29, 37)  # (nz, ny, nx): not a multiple of any tile size
+
+
+def _ragged_case(bc, seed=3):
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = _RAGGED
+    vel = rng.uniform(1500.0, 3200.0, _RAGGED).astype(np.float32)
+    src = np.array([[18, 14, 11], [3, 5, 7], [18, 14, 11], [0, 0, 0], [36, 28, 22]], dtype=np.int32)
+    rec = np.concatenate([W.plane(nx, ny, 2, inc=3), [[18, 14, 11], [36, 28, 22], [0, 28, 0]]]).astype(np.int32)
+    p = params(_RAGGED, h=(10.0, 12.0, 9.0), bc=bc, nb=5, f0=25.0, sigma=0.05)
+    T = 70
+    dt = mm.dt_for(p, float(vel.max()))
+    w = rng.standard_normal((T, len(src)))
+    return p, vel, src, rec, w, T, dt
+
+
+@pytest.mark.parametrize("bc", [mm.BC_NONE, mm.BC_SPONGE, mm.BC_CPML])
+def test_ragged_every_tile_variant(bc):
+    """A ragged grid (partial tiles in x, y and z), duplicate sources,
+    receivers on sources and on corners: every tile variant matches the oracle
+    and all variants agree bitwise (tiling does not change the arithmetic)."""
+    p, vel, src, rec, w, T, dt = _ragged_case(bc)
+    rtr, rpc, _ = oracle_forward(p, dt, vel, src, rec, w, T)
+    first = None
+    for t in range(mm.num_tiles()):
+        tr, pc, pm, _ = gpu_forward(p, vel, src, rec, w, T, tile=t)
+        assert rel(tr, rtr) <= 1e-5, (t, rel(tr, rtr))
+        assert rel(pc, rpc) <= 1e-5, (t, rel(pc, rpc))
+        if first is None:
+            first = (tr, pc, pm)
+        else:
+            assert np.array_equal(first[0], tr) and np.array_equal(first[1], pc) and np.array_equal(first[2], pm), t
+
+
+@pytest.mark.parametrize("bc", [mm.BC_NONE, mm.BC_SPONGE, mm.BC_CPML])
+def test_graph_and_chunked_runs_are_bitwise_equal(bc):
+    p, vel, src, rec, w, T, dt = _ragged_case(bc, seed=4)
+    a = gpu_forward(p, vel, src, rec, w, T)
+    b = gpu_forward(p, vel, src, rec, w, T, graph=True)
+    c = gpu_forward(p, vel, src, rec, w, T, chunks=[1, 20, 0, 33, 16])
+    d = gpu_forward(p, vel, src, rec, w, T, graph=True, chunks=[35, 35])
+    for other in (b, c, d):
+        for x, y in zip(a[:3], other[:3]):
+            assert np.array_equal(x, y)
+
+
+def test_minimal_and_degenerate_grids():
+    """Smallest grids the damping allows (n = 2 nb + 1), a one-cell-thick
+    grid with bc none, and runs with no receivers or no sources."""
+    rng = np.random.default_rng(8)
+    cases = [((11, 11, 11), mm.BC_SPONGE, 5), ((11, 13, 17), mm.BC_CPML, 5), ((1, 5, 9), mm.BC_NONE, 0),
+             ((7, 1, 6), mm.BC_NONE, 0), ((6, 5, 1), mm.BC_NONE, 0)]
+    for shape, bc, nb in cases:
+        nz, ny, nx = shape
+        vel = rng.uniform(1800, 2500, shape).astype(np.float32)
+        p = params(shape, bc=bc, nb=nb)
+        dt = mm.dt_for(p, float(vel.max()))
+        T = 25
+        src = np.array([[nx // 2, ny // 2, nz // 2]], dtype=np.int32)
+        rec = np.array([[0, 0, 0], [nx - 1, ny - 1, nz - 1], [nx // 2, ny // 2, nz // 2]], dtype=np.int32)
+        w = rng.standard_normal((T, 1))
+        tr, pc, _, _ = gpu_forward(p, vel, src, rec, w, T)
+        rtr, rpc, _ = oracle_forward(p, dt, vel, src, rec, w, T)
+        assert rel(tr, rtr) <= 1e-5 and rel(pc, rpc) <= 1e-5, (shape, rel(tr, rtr), rel(pc, rpc))
+        # no receivers: the field is the same
+        _, pc2, _, _ = gpu_forward(p, vel, src, np.zeros((0, 3), np.int32), w, T)
+        assert np.array_equal(pc, pc2)
+        # no sources: the field stays exactly zero
+        _, pc3, _, _ = gpu_forward(p, vel, np.zeros((0, 3), np.int32), rec, np.zeros((T, 0)), T)
+        assert not np.any(pc3)
+
+
+def test_zero_steps_and_determinism():
+    p, vel, src, rec, w, T, dt = _ragged_case(mm.BC_CPML, seed=5)
+    a = gpu_forward(p, vel, src, rec, w, T)
+    b = gpu_forward(p, vel, src, rec, w, T)
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+    z = gpu_forward(p, vel, src, rec, w[:0], 0)
+    assert not np.any(z[1]) and not np.any(z[2])
+
+
+def test_state_save_restore_resume_bitwise():
+    """100 steps, save, 100 more == 100 steps, restore into a fresh context,
+    100 more (CPML memory included)."""
+    p, vel, src, rec, w, T, dt = _ragged_case(mm.BC_CPML, seed=6)
+    T = 60
+    vt = torch.from_numpy(vel).to(DEV)
+    wt = torch.from_numpy(np.asarray(w[:T], dtype=np.float32)).to(DEV)
+    a = mm.Context.single(p, vt, src, rec)
+    a.forward(30, wt[:30])
+    st = a.get_state().clone()
+    a.forward(30, wt[30:])
+    b = mm.Context.single(p, vt, src, rec)
+    b.set_state(st, 30)
+    b.forward(30, wt[30:])
+    sa, sb = a.get_state(), b.get_state()
+    torch.cuda.synchronize()
+    assert torch.equal(sa, sb)
+    assert a.info()["step"] == b.info()["step"] == 60
+
+
+def test_batched_shots_equal_single_shot_runs():
+    """Three uneven sub-volumes in one context (one launch per kernel per step
+    for all shots) give bitwise the single-shot results."""
+    rng = np.random.default_rng(9)
+    shapes = [(20, 26, 33), (31, 17, 22), (18, 18, 41)]
+    p = params(shapes[0], bc=mm.BC_CPML, nb=4, f0=25.0)
+    vels = [rng.uniform(1500, 3000, s).astype(np.float32) for s in shapes]
+    vmax = float(max(v.max() for v in vels))
+    p.vmax = vmax
+    T = 40
+    srcs = [np.array([[s[2] // 2, s[1] // 2, s[0] // 2]], np.int32) for s in shapes]
+    recs = [W.plane(s[2], s[1], 3, inc=2) for s in shapes]
+    ws = [rng.standard_normal((T, 1)).astype(np.float32) for _ in shapes]
+    ctx = mm.Context(p, [(torch.from_numpy(v).to(DEV), s, r) for v, s, r in zip(vels, srcs, recs)])
+    wcat = torch.from_numpy(np.concatenate(ws, axis=1)).to(DEV)
+    tr = torch.zeros((T, ctx.nrec), dtype=torch.float32, device=DEV)
+    ctx.forward(T, wcat, tr)
+    trb = tr.cpu().numpy()
+    off = 0
+    for v, s, r, w in zip(vels, srcs, recs, ws):
+        q = mm.default_params(**{k: getattr(p, k) for k, _ in mm.Params._fields_})
+        q.nz, q.ny, q.nx = v.shape
+        t1, _, _, _ = gpu_forward(q, v, s, r, w, T)
+        assert np.array_equal(t1, trb[:, off:off + len(r)])
+        off += len(r)
+
+
+def test_errors_leave_context_usable():
+    vel = np.full((16, 16, 16), 2000.0, np.float32)
+    src = np.array([[8, 8, 8]], np.int32)
+    vt = torch.from_numpy(vel).to(DEV)
+    p = params(vel.shape, bc=mm.BC_SPONGE, nb=4)
+    p.cfl = 1.01
+    with pytest.raises(mm.MinimodError) as e:
+        mm.Context.single(p, vt, src, src)
+    assert e.value.status == mm.MM_ERR_UNSTABLE
+    p.cfl = 0.5
+    bad = vel.copy()
+    bad[3, 4, 5] = np.nan
+    with pytest.raises(mm.MinimodError) as e:
+        mm.Context.single(p, torch.from_numpy(bad).to(DEV), src, src)
+    assert e.value.status == mm.MM_ERR_NONFINITE
+    bad[3, 4, 5] = -1.0
+    with pytest.raises(mm.MinimodError) as e:
+        mm.Context.single(p, torch.from_numpy(bad).to(DEV), src, src)
+    assert e.value.status == mm.MM_ERR_NONFINITE
+    with pytest.raises(mm.MinimodError) as e:
+        mm.Context.single(p, vt, np.array([[16, 0, 0]], np.int32), src)
+    assert e.value.status == mm.MM_ERR_ARG
+    ctx = mm.Context.single(p, vt, src, src)
+    with pytest.raises(mm.MinimodError) as e:
+        ctx.forward(3, None)
+    assert e.value.status == mm.MM_ERR_ARG
+    with pytest.raises(mm.MinimodError) as e:
+        ctx.adjoint(1, torch.zeros((1, 1), device=DEV))
+    assert e.value.status == mm.MM_ERR_STATE  # made without adjoint storage
+    w = torch.ones((3, 1), device=DEV)
+    ctx.forward(3, w)
+    assert ctx.info()["step"] == 3
