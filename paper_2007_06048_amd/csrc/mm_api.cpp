@@ -35,11 +35,6 @@ struct ShotGeom {
     long long n() const { return (long long)nx * ny * nz; }
 };
 
-long long slab_points(const ShotGeom& g, int nb) {
-    const long long nb2 = 2LL * nb;
-    return nb2 * g.ny * g.nx + (g.nz - nb2) * nb2 * g.nx + (g.nz - nb2) * (g.ny - nb2) * nb2;
-}
-
 // Tiles of one variant over all shots, in shot-major, z-chunk, y, x order.
 void build_tiles(int variant, const std::vector<ShotGeom>& shots, std::vector<TileEnt>& out) {
     const TileShape& ts = tile_variant(variant);
@@ -217,7 +212,10 @@ struct mm_ctx {
     InjTab src_inj{}, rec_inj{};
     GatherTab rec_gather{}, src_gather{};
     int nsrc = 0, nrec = 0;
-    int max_slab = 0;
+    int mx = 0, my = 0, mz = 0;  // largest grid sizes over the shots
+    long long max_rows = 0;      // largest ny * nz
+    bool inline_src = false;
+    std::vector<std::vector<long long>> src_cells;  // per shot, for tile flags
     Coefs cf{};
     bool sponge = false, cpml = false;
     // time state
@@ -280,6 +278,7 @@ mm_status check_params(const mm_params* p, mm_ctx* c) {
     if (p->bc < MM_BC_NONE || p->bc > MM_BC_CPML) return fail(c, MM_ERR_ARG, "unknown boundary kind");
     if (p->bc != MM_BC_NONE && p->nb < 1) return fail(c, MM_ERR_ARG, "damping width nb must be >= 1");
     if (p->nb < 0 || p->nb > 4096) return fail(c, MM_ERR_ARG, "damping width nb out of range");
+    if (p->bc == MM_BC_CPML && p->nb > 128) return fail(c, MM_ERR_ARG, "CPML width nb must be <= 128");
     if (p->bc == MM_BC_SPONGE && !(std::isfinite(p->sponge_sigma) && p->sponge_sigma >= 0.0))
         return fail(c, MM_ERR_ARG, "sponge_sigma must be finite and >= 0");
     if (p->bc == MM_BC_CPML && !(std::isfinite(p->cpml_R) && p->cpml_R > 0.0 && p->cpml_R <= 1.0))
@@ -304,12 +303,17 @@ mm_status check_shot(const mm_params* p, const mm_shot& s, int idx, bool need_ve
             snprintf(buf, sizeof buf, "shot %d: grid size %d out of range", idx, n[a]);
             return fail(c, MM_ERR_ARG, buf);
         }
-        if (p->bc != MM_BC_NONE && n[a] < 2 * p->nb + 1) {
-            snprintf(buf, sizeof buf, "shot %d: grid size %d < 2*nb+1 = %d", idx, n[a], 2 * p->nb + 1);
+        // the two layers of an axis must not overlap; CPML also keeps them a stencil radius apart
+        const int nmin = p->bc == MM_BC_CPML ? 2 * p->nb + 4 : 2 * p->nb + 1;
+        if (p->bc != MM_BC_NONE && n[a] < nmin) {
+            snprintf(buf, sizeof buf, "shot %d: grid size %d < %s = %d", idx, n[a],
+                     p->bc == MM_BC_CPML ? "2*nb+4" : "2*nb+1", nmin);
             return fail(c, MM_ERR_ARG, buf);
         }
     }
     if ((long long)s.nx * s.ny * s.nz > (1LL << 34)) return fail(c, MM_ERR_ARG, "grid too large");
+    if (p->bc == MM_BC_CPML && (s.ny > 65535 || s.nz > 65535 || (long long)s.ny * s.nz > (1LL << 30)))
+        return fail(c, MM_ERR_ARG, "CPML grids need ny, nz <= 65535");
     if (need_vel && !s.vel) return fail(c, MM_ERR_ARG, "velocity pointer is NULL");
     if (s.nsrc < 0 || s.nrec < 0) return fail(c, MM_ERR_ARG, "negative source/receiver count");
     if ((s.nsrc > 0 && !s.src_ijk) || (s.nrec > 0 && !s.rec_ijk))
@@ -377,8 +381,25 @@ mm_status upload(mm_ctx* c, void* dst, const void* src, size_t bytes) {
     return dev(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream), "upload");
 }
 
+void tile_flags(mm_ctx* c, int v) {
+    const int TX = tile_variant(v).tx, TY = tile_rows(v);
+    for (TileEnt& t : c->tiles_h) {
+        const ShotGeom& g = c->geom[t.shot];
+        const int x1 = std::min(g.nx, t.x0 + TX), y1 = std::min(g.ny, t.y0 + TY);
+        int f = 0;
+        if (c->inline_src)
+            for (long long o : c->src_cells[t.shot]) {
+                const int z = (int)(o / ((long long)g.nx * g.ny));
+                const int y = (int)((o / g.nx) % g.ny), x = (int)(o % g.nx);
+                if (x >= t.x0 && x < x1 && y >= t.y0 && y < y1 && z >= t.z0 && z < t.z1) f |= TF_SRC;
+            }
+        t.flags = f;
+    }
+}
+
 mm_status set_variant(mm_ctx* c, int v) {
     build_tiles(v, c->geom, c->tiles_h);
+    tile_flags(c, v);
     if ((int)c->tiles_h.size() > c->L.max_tiles) return fail(c, MM_ERR_WORKSPACE, "tile table overflow");
     MM_TRY(dev(c, hipStreamSynchronize(c->stream), "sync"));
     MM_TRY(upload(c, c->d_tiles, c->tiles_h.data(), sizeof(TileEnt) * c->tiles_h.size()));
@@ -436,14 +457,17 @@ mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, co
         }
         MM_TRY(dev(c, hipEventRecord(c->prof_ev[c->prof_used], s), "event"));
     }
-    MM_TRY(dev(c, launch_step(c->variant, c->sponge, mode, c->d_tiles, c->ntiles, shots, parity, c->cf, aux, s),
+    MM_TRY(dev(c, launch_step(c->variant, c->p.bc, mode, c->d_tiles, c->ntiles, shots, parity, c->cf, aux, s),
                "stencil launch"));
     if (timed) {
         MM_TRY(dev(c, hipEventRecord(c->prof_ev[c->prof_used + 1], s), "event"));
         c->prof_used += 2;
     }
-    if (c->cpml && shots == c->d_shots)
-        MM_TRY(dev(c, launch_cpml(shots, (int)c->geom.size(), c->max_slab, parity, c->cf, s), "cpml launch"));
+    if (c->cpml) {
+        if (shots != c->d_shots) return fail(c, MM_ERR_UNSUPPORTED, "CPML has no adjoint");
+        MM_TRY(dev(c, launch_cpml(shots, (int)c->geom.size(), c->p.nb, c->max_rows, c->mx, c->my, c->mz, parity, c->cf, s),
+                   "cpml launch"));
+    }
     return MM_OK;
 }
 
@@ -498,10 +522,12 @@ mm_status enqueue_forward(mm_ctx* c, int nsteps, const float* wav, float* traces
         const int k = c->step + j;
         const int parity = k & 1;
         if (ck && k % c->p.ckpt_every == 0) MM_TRY(save_ckpt(c, k / c->p.ckpt_every, parity, s));
-        MM_TRY(enqueue_step(c, c->d_shots, parity, MODE_PLAIN, none, s));
-        if (c->nsrc > 0)
-            MM_TRY(dev(c, launch_inject(c->src_inj, c->d_shots, parity, wav + (size_t)j * c->nsrc, c->nsrc, MODE_PLAIN,
-                                        none, s),
+        StepAux aux = none;
+        aux.src_scale = c->src_inj.scale;
+        aux.wrow = c->nsrc > 0 ? wav + (size_t)j * c->nsrc : nullptr;
+        MM_TRY(enqueue_step(c, c->d_shots, parity, MODE_PLAIN, aux, s));
+        if (c->nsrc > 0 && !c->inline_src)
+            MM_TRY(dev(c, launch_inject(c->src_inj, c->d_shots, parity, aux.wrow, c->nsrc, MODE_PLAIN, none, s),
                        "inject"));
         if (traces && c->nrec > 0)
             MM_TRY(dev(c, launch_gather(c->rec_gather, c->d_shots, parity, traces + (size_t)j * c->nrec, s), "record"));
@@ -537,10 +563,11 @@ mm_status replay_segment(mm_ctx* c, int sg, hipStream_t s) {
     for (int n = n0; n < n1; ++n) {
         StepAux aux{};
         aux.d2p_out = seg + (size_t)(n - n0) * N;
+        aux.src_scale = c->src_inj.scale;
+        aux.wrow = c->nsrc > 0 ? wav + (size_t)n * c->nsrc : nullptr;
         MM_TRY(enqueue_step(c, c->d_shots, n & 1, MODE_D2P, aux, s));
-        if (c->nsrc > 0)
-            MM_TRY(dev(c, launch_inject(c->src_inj, c->d_shots, n & 1, wav + (size_t)n * c->nsrc, c->nsrc, MODE_D2P,
-                                        aux, s),
+        if (c->nsrc > 0 && !c->inline_src)
+            MM_TRY(dev(c, launch_inject(c->src_inj, c->d_shots, n & 1, aux.wrow, c->nsrc, MODE_D2P, aux, s),
                        "inject"));
     }
     c->seg_loaded = sg;
@@ -742,7 +769,6 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
 
     // shot descriptors and 1D boundary tables
     std::vector<std::vector<float>> prof(nshots);
-    c->max_slab = 0;
     for (int i = 0; i < nshots; ++i) {
         const ShotGeom& g = geom[i];
         ShotDev sd{};
@@ -760,6 +786,7 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
         sd.nb = p->nb;
         c->shots_h.push_back(sd);
         ShotDev sa = sd;
+        sa.nsrc_in = 0;
         sa.buf[0] = L.adjoint ? at<float>(c->ws, L.ebuf0[i]) : nullptr;
         sa.buf[1] = L.adjoint ? at<float>(c->ws, L.ebuf1[i]) : nullptr;
         c->shots_adj_h.push_back(sa);
@@ -772,7 +799,10 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
                 cpml_table(n[a], p->nb, h[a], c->dt, c->vmax, p->cpml_R, p->cpml_f0, q, q + n[a]);
                 q += 2 * n[a];
             }
-            c->max_slab = std::max<long long>(c->max_slab, slab_points(g, p->nb));
+            c->max_rows = std::max(c->max_rows, (long long)g.ny * g.nz);
+            c->mx = std::max(c->mx, g.nx);
+            c->my = std::max(c->my, g.ny);
+            c->mz = std::max(c->mz, g.nz);
         } else {
             pr.resize(g.nx + g.ny + g.nz);
             float* q = pr.data();
@@ -813,6 +843,22 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
     Csr cs, cr;
     build_csr(s_shot, s_off, s_g, cs);
     build_csr(r_shot, r_off, r_g, cr);
+    // sources are added inside the stencil kernel when no shot has more than MAX_INLINE_SRC
+    c->inline_src = true;
+    for (int i = 0; i < nshots; ++i) c->inline_src = c->inline_src && shots[i].nsrc <= MAX_INLINE_SRC;
+    c->src_cells.assign(nshots, {});
+    {
+        int col = 0;
+        for (int i = 0; i < nshots; ++i)
+            for (int k = 0; k < shots[i].nsrc; ++k, ++col) {
+                if (!c->inline_src) continue;
+                ShotDev& sd = c->shots_h[i];
+                sd.src_col[sd.nsrc_in] = col;
+                sd.src_off[sd.nsrc_in] = s_off[col];
+                sd.nsrc_in++;
+                c->src_cells[i].push_back(s_off[col]);
+            }
+    }
 
     // stage every host table in one buffer kept alive in the context
     size_t hb = 0;
@@ -1076,7 +1122,7 @@ mm_status mm_autotune(mm_ctx* c, int32_t steps, int32_t* tile_out) {
     MM_TRY(dev(c, hipEventCreate(&e1), "event"));
     int best = c->variant;
     float best_ms = 1e30f;
-    const StepAux none{};
+    const StepAux none{};  // trial steps inject nothing (no wavelet row)
     mm_status st = MM_OK;
     for (int v = 0; v < num_tile_variants() && !st; ++v) {
         st = set_variant(c, v);

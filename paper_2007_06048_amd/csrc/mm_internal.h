@@ -15,12 +15,20 @@ struct ShotDev {
     float* psi[3];        // CPML memory, slab layouts (see minimod.h)
     float* zeta[3];
     int nx, ny, nz, nb;
+    int nsrc_in;          // sources added inside the stencil kernel (0..4)
+    int src_col[4];       // their columns in the wavelet row
+    long long src_off[4]; // their cells
 };
+
+enum { MAX_INLINE_SRC = 4 };
 
 // One z-marching tile: an xy rectangle of one shot and a z range [z0, z1).
 struct TileEnt {
-    int shot, x0, y0, z0, z1, pad0, pad1, pad2;
+    int shot, x0, y0, z0, z1, flags, pad1, pad2;
 };
+
+// TileEnt::flags: the tile holds a source added inside the stencil kernel.
+enum { TF_SRC = 1 };
 
 // Stencil weights a_m / h^2 per axis (m = 1..4) and first-derivative weights
 // beta_m / h (CPML).
@@ -52,11 +60,14 @@ struct GatherTab {
 //  mode 1: d2p[x] = G (dt v)^2 Lap p^n  (= p^{n+1} - 2G p^n + G^2 p^{n-1}
 //          before the source term; single shot)
 //  mode 2: grad[x] += neg_inv_dt2 / G * p^{n+1}[x] * d2p[x]  (imaging)
+//  inline sources: lap += src_scale * wrow[col] at a shot's source cells
 struct StepAux {
     float* d2p_out;
     const float* d2p_in;
     float* grad;
     float neg_inv_dt2;
+    float src_scale;
+    const float* wrow;
 };
 
 enum { MODE_PLAIN = 0, MODE_D2P = 1, MODE_IMAGE = 2 };
@@ -72,11 +83,15 @@ int num_tile_variants();
 const TileShape& tile_variant(int t);
 int tile_rows(int t);  // TY of variant t
 
-hipError_t launch_step(int variant, bool sponge, int mode, const TileEnt* tiles, int ntiles,
+// bc: 0 none, 1 sponge, 2 CPML (the stencil itself; launch_cpml adds the
+// layer terms of the same step afterwards)
+hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int ntiles,
                        const ShotDev* shots, int parity, const Coefs& cf, const StepAux& aux,
                        hipStream_t s);
-hipError_t launch_cpml(const ShotDev* shots, int nshots, int max_slab_pts, int parity, const Coefs& cf,
-                       hipStream_t s);
+// CPML layers of every shot (shared nb <= 128); max_rows = largest ny*nz and
+// mx, my, mz = largest grid sizes over the shots
+hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, long long max_rows, int mx, int my, int mz,
+                       int parity, const Coefs& cf, hipStream_t s);
 hipError_t launch_inject(const InjTab& tab, const ShotDev* shots, int parity, const float* vals, int ncols,
                          int mode, const StepAux& aux, hipStream_t s);
 hipError_t launch_gather(const GatherTab& tab, const ShotDev* shots, int parity, float* out, hipStream_t s);

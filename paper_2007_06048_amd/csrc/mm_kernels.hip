@@ -43,7 +43,7 @@ int tile_rows(int t) { return (256 / kTiles[t].tx) * kTiles[t].ry; }
 
 // ------------------------------------------------------------- stencil step
 
-template <int TX, int RY, bool SPONGE, int MODE>
+template <int TX, int RY, int BC, int MODE>
 __global__ __launch_bounds__(256) void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd,
                                               const ShotDev* __restrict__ shots, int parity, Coefs cf,
                                               StepAux aux) {
@@ -51,6 +51,7 @@ __global__ __launch_bounds__(256) void k_step(const TileEnt* __restrict__ tiles,
     constexpr int TY = BY * RY;
     constexpr int LW = TX + 8;
     constexpr int YH = 8 / BY;
+    constexpr bool SPONGE = BC == 1;
     static_assert(BY <= 8 && 8 % BY == 0, "y halo split");
     __shared__ float lds[2][TY + 8][LW];
 
@@ -164,15 +165,21 @@ __global__ __launch_bounds__(256) void k_step(const TileEnt* __restrict__ tiles,
         for (int r = 0; r < RY; ++r) {
             const int yy = 4 + ty + r * BY;
             const float c = q[r][4];
-            float lap = 0.0f;
+            float lx = 0.0f, ly = 0.0f, lzv = 0.0f;
 #pragma unroll
             for (int m = 1; m <= 4; ++m) {
-                lap = fmaf(cf.cx[m - 1], (L[yy][xx + m] - c) + (L[yy][xx - m] - c), lap);
-                lap = fmaf(cf.cy[m - 1], (L[yy + m][xx] - c) + (L[yy - m][xx] - c), lap);
-                lap = fmaf(cf.cz[m - 1], (q[r][4 + m] - c) + (q[r][4 - m] - c), lap);
+                lx = fmaf(cf.cx[m - 1], (L[yy][xx + m] - c) + (L[yy][xx - m] - c), lx);
+                ly = fmaf(cf.cy[m - 1], (L[yy + m][xx] - c) + (L[yy - m][xx] - c), ly);
+                lzv = fmaf(cf.cz[m - 1], (q[r][4 + m] - c) + (q[r][4 - m] - c), lzv);
             }
+            float lap = (lx + ly) + lzv;
             if (in[r]) {
                 const long long o = zoff + (long long)row[r] * nx + x;
+                if ((te.flags & TF_SRC) && aux.wrow) {
+#pragma unroll
+                    for (int k = 0; k < MAX_INLINE_SRC; ++k)
+                        if (k < sd.nsrc_in && o == sd.src_off[k]) lap = fmaf(aux.src_scale, aux.wrow[sd.src_col[k]], lap);
+                }
                 float out, G = 1.0f;
                 if (SPONGE) {
                     G = gx * gyv[r] * gz;
@@ -192,195 +199,192 @@ __global__ __launch_bounds__(256) void k_step(const TileEnt* __restrict__ tiles,
     }
 }
 
-template <int TX, int RY>
-static hipError_t launch_step_t(bool sponge, int mode, dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd,
-                                const ShotDev* shots, int parity, const Coefs& cf, const StepAux& aux,
-                                hipStream_t s) {
+template <int TX, int RY, int BC>
+static hipError_t launch_step_bc(int mode, dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd,
+                                 const ShotDev* shots, int parity, const Coefs& cf, const StepAux& aux,
+                                 hipStream_t s) {
     dim3 block(TX, 256 / TX);
-    if (sponge) {
-        if (mode == MODE_PLAIN)
-            k_step<TX, RY, true, MODE_PLAIN><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
-        else if (mode == MODE_D2P)
-            k_step<TX, RY, true, MODE_D2P><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
-        else
-            k_step<TX, RY, true, MODE_IMAGE><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
-    } else {
-        if (mode == MODE_PLAIN)
-            k_step<TX, RY, false, MODE_PLAIN><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
-        else if (mode == MODE_D2P)
-            k_step<TX, RY, false, MODE_D2P><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
-        else
-            k_step<TX, RY, false, MODE_IMAGE><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf,
-                                                                       aux);
-    }
+    if (mode == MODE_PLAIN)
+        k_step<TX, RY, BC, MODE_PLAIN><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
+    else if (mode == MODE_D2P)
+        k_step<TX, RY, BC, MODE_D2P><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
+    else
+        k_step<TX, RY, BC, MODE_IMAGE><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
     return hipGetLastError();
 }
 
-hipError_t launch_step(int variant, bool sponge, int mode, const TileEnt* tiles, int ntiles, const ShotDev* shots,
+template <int TX, int RY>
+static hipError_t launch_step_t(int bc, int mode, dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd,
+                                const ShotDev* shots, int parity, const Coefs& cf, const StepAux& aux,
+                                hipStream_t s) {
+    if (bc == 1) return launch_step_bc<TX, RY, 1>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+    // CPML: the stencil kernel is the plain one; launch_cpml adds the layer terms afterwards
+    return launch_step_bc<TX, RY, 0>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+}
+
+hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int ntiles, const ShotDev* shots,
                        int parity, const Coefs& cf, const StepAux& aux, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     const int per_xcd = (ntiles + 7) / 8;
     dim3 grid(8 * per_xcd);
     const TileShape& ts = kTiles[variant];
     if (ts.tx == 64) {
-        if (ts.ry == 2) return launch_step_t<64, 2>(sponge, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
-        if (ts.ry == 4) return launch_step_t<64, 4>(sponge, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
-        return launch_step_t<64, 8>(sponge, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+        if (ts.ry == 2) return launch_step_t<64, 2>(bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+        if (ts.ry == 4) return launch_step_t<64, 4>(bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+        return launch_step_t<64, 8>(bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
     }
-    if (ts.ry == 1) return launch_step_t<32, 1>(sponge, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
-    if (ts.ry == 2) return launch_step_t<32, 2>(sponge, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
-    return launch_step_t<32, 4>(sponge, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+    if (ts.ry == 1) return launch_step_t<32, 1>(bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+    if (ts.ry == 2) return launch_step_t<32, 2>(bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+    return launch_step_t<32, 4>(bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
 }
 
 // -------------------------------------------------------------------- CPML
 //
-// The damping layers are the union of six slabs.  They are enumerated as
-// three disjoint regions: the two z slabs (whole planes), the two y slabs
-// of the remaining planes, the two x slabs of the remaining rows.  Each
-// point updates the memory of every axis whose layer it lies in.
+// One kernel per axis, run after the stencil kernel of the step, one thread
+// per cell of the axis' two damping layers (nb cells at each end).  Phase 1:
+//   psi <- b psi + a D1 p^n   (stored, and kept in LDS along the layer),
+// phase 2, after a barrier:
+//   zeta <- b zeta + a (D2 p^n + D1 psi);   p^{n+1} += (dt v)^2 (D1 psi + zeta),
+// with D1, D2 the order-8 first / second differences along the axis.  psi
+// is zero outside its layer and the two layers of an axis are at least 4
+// cells apart, so a block that holds a whole layer segment along the axis
+// has every psi it needs in LDS.  The axes run as three launches so a point
+// inside two or three layers is updated in a fixed order without atomics.
+// Lanes always run along x: for the x layers a block holds whole 2 nb-cell
+// rows (both ends), for the y / z layers 64 x-columns by the nb cells of
+// one end.
+//
+// Slab arrays: x [nz][ny][2nb], y [nz][2nb][nx], z [2nb][ny][nx]; slab index
+// s < nb is grid index s, s >= nb is grid index n - 2nb + s.
 
-__device__ __forceinline__ bool in_layer(int i, int n, int nb) { return i < nb || i >= n - nb; }
-
-__device__ __forceinline__ int slab_index(int i, int n, int nb) { return i < nb ? i : i - (n - 2 * nb); }
-
-__device__ __forceinline__ long long slab_count(const ShotDev& sd) {
-    const long long nb2 = 2LL * sd.nb;
-    return nb2 * sd.ny * sd.nx + (sd.nz - nb2) * nb2 * sd.nx + (sd.nz - nb2) * (sd.ny - nb2) * nb2;
-}
-
-__device__ __forceinline__ bool slab_point(const ShotDev& sd, long long i, int& x, int& y, int& z) {
+// x layers: thread e of the block -> row r = e / nb2, slab cell s = e % nb2
+__global__ __launch_bounds__(256) void k_cpml_x(const ShotDev* __restrict__ shots, int parity, Coefs cf,
+                                                int rows_per_block) {
+    extern __shared__ float lds_psi[];
+    const ShotDev& sd = shots[blockIdx.z];
     const int nx = sd.nx, ny = sd.ny, nz = sd.nz, nb = sd.nb, nb2 = 2 * nb;
-    const long long r0 = (long long)nb2 * ny * nx;
-    if (i < r0) {
-        const int s = (int)(i / ((long long)ny * nx));
-        const long long rem = i - (long long)s * ny * nx;
-        z = s < nb ? s : nz - nb2 + s;
-        y = (int)(rem / nx);
-        x = (int)(rem - (long long)y * nx);
-        return true;
-    }
-    i -= r0;
-    const long long r1 = (long long)(nz - nb2) * nb2 * nx;
-    if (i < r1) {
-        const long long per = (long long)nb2 * nx;
-        z = nb + (int)(i / per);
-        const long long rem = i - (long long)(z - nb) * per;
-        const int s = (int)(rem / nx);
-        y = s < nb ? s : ny - nb2 + s;
-        x = (int)(rem - (long long)s * nx);
-        return true;
-    }
-    i -= r1;
-    const long long r2 = (long long)(nz - nb2) * (ny - nb2) * nb2;
-    if (i < r2) {
-        const long long per = (long long)(ny - nb2) * nb2;
-        z = nb + (int)(i / per);
-        const long long rem = i - (long long)(z - nb) * per;
-        y = nb + (int)(rem / nb2);
-        const int s = (int)(rem - (long long)(y - nb) * nb2);
-        x = s < nb ? s : nx - nb2 + s;
-        return true;
-    }
-    return false;
-}
-
-// linear index of (x, y, z) in the slab array of axis ax
-__device__ __forceinline__ long long slab_lin(const ShotDev& sd, int ax, int x, int y, int z) {
-    const int nb2 = 2 * sd.nb;
-    if (ax == 0) return ((long long)z * sd.ny + y) * nb2 + slab_index(x, sd.nx, sd.nb);
-    if (ax == 1) return ((long long)z * nb2 + slab_index(y, sd.ny, sd.nb)) * sd.nx + x;
-    return ((long long)slab_index(z, sd.nz, sd.nb) * sd.ny + y) * sd.nx + x;
-}
-
-__device__ __forceinline__ const float* prof_a(const ShotDev& sd, int ax) {
-    return ax == 0 ? sd.prof : (ax == 1 ? sd.prof + 2 * sd.nx : sd.prof + 2 * sd.nx + 2 * sd.ny);
-}
-
-// psi_ax <- b psi_ax + a D1_ax p^n in the layer of each axis
-__global__ __launch_bounds__(256) void k_cpml_psi(const ShotDev* __restrict__ shots, int parity, Coefs cf) {
-    const ShotDev& sd = shots[blockIdx.y];
-    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (i >= slab_count(sd)) return;
-    int x, y, z;
-    if (!slab_point(sd, i, x, y, z)) return;
+    const int e = threadIdx.x;
+    const int r = e / nb2, sl = e - r * nb2;
+    const int row = blockIdx.x * rows_per_block + r;
+    const bool active = r < rows_per_block && row < ny * nz;
+    const int x = sl < nb ? sl : nx - nb2 + sl;
+    const long long o = (long long)row * nx + x;  // row = z * ny + y
+    const long long si = (long long)row * nb2 + sl;
     const float* __restrict__ p = sd.buf[parity];
-    const int pos[3] = {x, y, z};
-    const int n[3] = {sd.nx, sd.ny, sd.nz};
-    const long long stride[3] = {1, sd.nx, (long long)sd.nx * sd.ny};
-    const long long o = (long long)z * stride[2] + (long long)y * sd.nx + x;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        if (!in_layer(pos[ax], n[ax], sd.nb)) continue;
-        float d1 = 0.0f;
+    float c = 0.0f, d1 = 0.0f, d2 = 0.0f;
+    if (active) {
+        c = p[o];
 #pragma unroll
         for (int m = 1; m <= 4; ++m) {
-            const float bw = ax == 0 ? cf.bx[m - 1] : (ax == 1 ? cf.by[m - 1] : cf.bz[m - 1]);
-            const float fp = pos[ax] + m < n[ax] ? p[o + m * stride[ax]] : 0.0f;
-            const float fm = pos[ax] - m >= 0 ? p[o - m * stride[ax]] : 0.0f;
-            d1 = fmaf(bw, fp - fm, d1);
+            const float fp = x + m < nx ? p[o + m] : 0.0f;
+            const float fm = x - m >= 0 ? p[o - m] : 0.0f;
+            d1 = fmaf(cf.bx[m - 1], fp - fm, d1);
+            d2 = fmaf(cf.cx[m - 1], (fp - c) + (fm - c), d2);
         }
-        const float* pa = prof_a(sd, ax);
-        const float a = pa[pos[ax]], bb = pa[n[ax] + pos[ax]];
-        float* psi = sd.psi[ax];
-        const long long s = slab_lin(sd, ax, x, y, z);
-        psi[s] = fmaf(bb, psi[s], a * d1);
+        const float ps = fmaf(sd.prof[nx + x], sd.psi[0][si], sd.prof[x] * d1);
+        sd.psi[0][si] = ps;
+        lds_psi[e] = ps;
     }
-}
-
-// zeta_ax <- b zeta_ax + a (D2_ax p^n + D1_ax psi_ax); p^{n+1} += D sum (D1 psi + zeta)
-__global__ __launch_bounds__(256) void k_cpml_corr(const ShotDev* __restrict__ shots, int parity, Coefs cf) {
-    const ShotDev& sd = shots[blockIdx.y];
-    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (i >= slab_count(sd)) return;
-    int x, y, z;
-    if (!slab_point(sd, i, x, y, z)) return;
-    const float* __restrict__ p = sd.buf[parity];
+    __syncthreads();
+    if (!active) return;
+    // neighbours along x inside the same end of the row (the other end is >= 4 cells away)
+    const int lo = sl < nb ? 0 : nb, hi = lo + nb;
+    float dpsi = 0.0f;
+#pragma unroll
+    for (int m = 1; m <= 4; ++m) {
+        const float vp = sl + m < hi ? lds_psi[e + m] : 0.0f;
+        const float vm = sl - m >= lo ? lds_psi[e - m] : 0.0f;
+        dpsi = fmaf(cf.bx[m - 1], vp - vm, dpsi);
+    }
+    float* __restrict__ ze = sd.zeta[0];
+    const float zn = fmaf(sd.prof[nx + x], ze[si], sd.prof[x] * (d2 + dpsi));
+    ze[si] = zn;
     float* __restrict__ pn = sd.buf[parity ^ 1];
-    const int pos[3] = {x, y, z};
-    const int n[3] = {sd.nx, sd.ny, sd.nz};
-    const long long stride[3] = {1, sd.nx, (long long)sd.nx * sd.ny};
-    const long long o = (long long)z * stride[2] + (long long)y * sd.nx + x;
-    const float c = p[o];
-    float corr = 0.0f;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        if (!in_layer(pos[ax], n[ax], sd.nb)) continue;
-        const float* psi = sd.psi[ax];
-        float d2 = 0.0f, dpsi = 0.0f;
-#pragma unroll
-        for (int m = 1; m <= 4; ++m) {
-            const int ip = pos[ax] + m, im = pos[ax] - m;
-            const float fp = ip < n[ax] ? p[o + m * stride[ax]] : 0.0f;
-            const float fm = im >= 0 ? p[o - m * stride[ax]] : 0.0f;
-            const float cw = ax == 0 ? cf.cx[m - 1] : (ax == 1 ? cf.cy[m - 1] : cf.cz[m - 1]);
-            const float bw = ax == 0 ? cf.bx[m - 1] : (ax == 1 ? cf.by[m - 1] : cf.bz[m - 1]);
-            d2 = fmaf(cw, (fp - c) + (fm - c), d2);
-            int pp[3] = {x, y, z}, pm[3] = {x, y, z};
-            pp[ax] = ip;
-            pm[ax] = im;
-            const float sp = (ip < n[ax] && in_layer(ip, n[ax], sd.nb)) ? psi[slab_lin(sd, ax, pp[0], pp[1], pp[2])] : 0.0f;
-            const float sm = (im >= 0 && in_layer(im, n[ax], sd.nb)) ? psi[slab_lin(sd, ax, pm[0], pm[1], pm[2])] : 0.0f;
-            dpsi = fmaf(bw, sp - sm, dpsi);
-        }
-        const float* pa = prof_a(sd, ax);
-        const float a = pa[pos[ax]], bb = pa[n[ax] + pos[ax]];
-        float* zeta = sd.zeta[ax];
-        const long long s = slab_lin(sd, ax, x, y, z);
-        const float zn = fmaf(bb, zeta[s], a * (d2 + dpsi));
-        zeta[s] = zn;
-        corr += dpsi + zn;
-    }
-    pn[o] = fmaf(sd.vdt2[o], corr, pn[o]);
+    pn[o] = fmaf(sd.vdt2[o], dpsi + zn, pn[o]);
 }
 
-hipError_t launch_cpml(const ShotDev* shots, int nshots, int max_slab_pts, int parity, const Coefs& cf,
-                       hipStream_t s) {
-    if (nshots <= 0 || max_slab_pts <= 0) return hipSuccess;
-    dim3 grid((max_slab_pts + 255) / 256, nshots);
-    k_cpml_psi<<<grid, 256, 0, s>>>(shots, parity, cf);
+// y (AX = 1) or z (AX = 2) layers: block (64, 4) = 64 x-columns, threads of
+// one column share the nb cells of one end (thread row ty takes cells ty,
+// ty + 4, ...); blockIdx.y is z (AX = 1) or y (AX = 2); blockIdx.z = 2 shot + end.
+template <int AX>
+__global__ __launch_bounds__(256) void k_cpml_yz(const ShotDev* __restrict__ shots, int parity, Coefs cf) {
+    extern __shared__ float lds[];
+    const ShotDev& sd = shots[blockIdx.z >> 1];
+    const int side = blockIdx.z & 1;
+    const int nx = sd.nx, ny = sd.ny, nz = sd.nz, nb = sd.nb, nb2 = 2 * nb;
+    const int w = blockIdx.y;
+    if (w >= (AX == 2 ? ny : nz)) return;  // whole block
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int x = blockIdx.x * 64 + tx;
+    const bool active = x < nx;
+    const long long plane = (long long)nx * ny;
+    const int n = AX == 2 ? nz : ny;
+    const long long stride = AX == 2 ? plane : (long long)nx;
+    const long long base = AX == 2 ? (long long)w * nx + x : (long long)w * plane + x;
+    const long long sbase = AX == 2 ? (long long)w * nx + x : (long long)w * nb2 * nx + x;
+    const long long sstride = AX == 2 ? plane : (long long)nx;
+    const float* prof = AX == 2 ? sd.prof + 2 * nx + 2 * ny : sd.prof + 2 * nx;
+    const int s0 = side ? n - nb : 0;
+    const int soff = side ? nb : 0;  // slab index of the first cell of this end
+    float* psl = lds;                // [nb][64]
+    float* d2l = lds + nb * 64;      // [nb][64]
+    const float* __restrict__ p = sd.buf[parity];
+    float* __restrict__ psi = sd.psi[AX];
+    if (active) {
+        for (int s = ty; s < nb; s += 4) {
+            const int z = s0 + s;
+            const long long o = base + z * stride;
+            const float c = p[o];
+            float d1 = 0.0f, d2 = 0.0f;
+#pragma unroll
+            for (int m = 1; m <= 4; ++m) {
+                const float fp = z + m < n ? p[o + m * stride] : 0.0f;
+                const float fm = z - m >= 0 ? p[o - m * stride] : 0.0f;
+                d1 = fmaf(AX == 2 ? cf.bz[m - 1] : cf.by[m - 1], fp - fm, d1);
+                d2 = fmaf(AX == 2 ? cf.cz[m - 1] : cf.cy[m - 1], (fp - c) + (fm - c), d2);
+            }
+            const long long si = sbase + (long long)(soff + s) * sstride;
+            const float ps = fmaf(prof[n + z], psi[si], prof[z] * d1);
+            psi[si] = ps;
+            psl[s * 64 + tx] = ps;
+            d2l[s * 64 + tx] = d2;
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    float* __restrict__ ze = sd.zeta[AX];
+    float* __restrict__ pn = sd.buf[parity ^ 1];
+    const float* __restrict__ vd = sd.vdt2;
+    for (int s = ty; s < nb; s += 4) {
+        const int z = s0 + s;
+        float dpsi = 0.0f;
+#pragma unroll
+        for (int m = 1; m <= 4; ++m) {
+            const float vp = s + m < nb ? psl[(s + m) * 64 + tx] : 0.0f;
+            const float vm = s - m >= 0 ? psl[(s - m) * 64 + tx] : 0.0f;
+            dpsi = fmaf(AX == 2 ? cf.bz[m - 1] : cf.by[m - 1], vp - vm, dpsi);
+        }
+        const long long si = sbase + (long long)(soff + s) * sstride;
+        const float zn = fmaf(prof[n + z], ze[si], prof[z] * (d2l[s * 64 + tx] + dpsi));
+        ze[si] = zn;
+        const long long o = base + z * stride;
+        pn[o] = fmaf(vd[o], dpsi + zn, pn[o]);
+    }
+}
+
+hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, long long max_rows, int mx, int my, int mz,
+                       int parity, const Coefs& cf, hipStream_t s) {
+    if (nshots <= 0) return hipSuccess;
+    const int rpb = 256 / (2 * nb);
+    k_cpml_x<<<dim3((unsigned)((max_rows + rpb - 1) / rpb), 1, nshots), 256, sizeof(float) * 256, s>>>(shots, parity,
+                                                                                                     cf, rpb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_cpml_corr<<<grid, 256, 0, s>>>(shots, parity, cf);
+    const size_t sh = sizeof(float) * 2 * nb * 64;
+    k_cpml_yz<1><<<dim3((mx + 63) / 64, mz, 2 * nshots), dim3(64, 4), sh, s>>>(shots, parity, cf);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_cpml_yz<2><<<dim3((mx + 63) / 64, my, 2 * nshots), dim3(64, 4), sh, s>>>(shots, parity, cf);
     return hipGetLastError();
 }
 
