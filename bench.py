@@ -88,6 +88,109 @@ def cpu_baseline(wl, budget_s):
                       f"after 1 warm-up step"}
 
 
+def _timed(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def gradient_leg(dev, reps=2):
+    """FWI gradient on the 200^3 workload (sponge-20, 1000 steps, checkpoints
+    every 32): seconds per shot for the plain forward run and for the
+    gradient (forward with checkpoints + residual + adjoint with segment
+    replay and imaging) with FP32 and BF16 snapshots.  d_obs is the library's
+    own forward run on the true model (input data for timing only)."""
+    import torch
+    from paper_2007_06048_amd import minimod as mm
+    from paper_2007_06048_amd import workloads as W
+    wl = W.fwi_200()
+    s = wl.shots[0]
+    T = wl.nsteps
+    res = {"workload": wl.name, "shots_timed": 1}
+    base = dict(nx=wl.nx, ny=wl.ny, nz=wl.nz, dx=wl.h, dy=wl.h, dz=wl.h, cfl=wl.cfl, bc=wl.bc, nb=wl.nb,
+                sponge_sigma=wl.sigma, vmax=wl.vmax, tile=-1)
+    p0 = mm.default_params(**base)
+    vt = torch.from_numpy(wl.vel_true).to(dev)
+    v0 = torch.from_numpy(s.vel).to(dev)
+    ct = mm.Context.single(p0, vt, s.src, s.rec)
+    w = torch.from_numpy(mm.ricker(wl.f0, wl.t0, ct.dt, T)).to(dev).reshape(T, 1)
+    d_obs = torch.empty((T, len(s.rec)), dtype=torch.float32, device=dev)
+    ct.forward(T, w, d_obs)
+    del ct
+    cf = mm.Context.single(p0, v0, s.src, s.rec)
+    tr = torch.empty_like(d_obs)
+
+    def fwd():
+        cf.reset()
+        cf.forward(T, w, tr)
+
+    res["forward_s"] = round(_timed(fwd, reps), 4)
+    del cf
+    for name, snap in (("fp32", mm.SNAP_FP32), ("bf16", mm.SNAP_BF16)):
+        pg = mm.default_params(**base, ckpt_every=wl.ckpt_every, snap=snap, nsteps_max=T)
+        cg = mm.Context.single(pg, v0, s.src, s.rec)
+        g = torch.empty(s.vel.shape, dtype=torch.float32, device=dev)
+        res[f"gradient_{name}_s"] = round(_timed(lambda: cg.gradient(T, w, d_obs, g, tr), reps), 4)
+        res[f"workspace_{name}_GB"] = round(cg.ws_bytes / 1e9, 2)
+        del cg, g
+        torch.cuda.empty_cache()
+    res["gradient_fp32_vs_forward"] = round(res["gradient_fp32_s"] / res["forward_s"], 2)
+    res["gradient_bf16_vs_forward"] = round(res["gradient_bf16_s"] / res["forward_s"], 2)
+    return res
+
+
+def batched_leg(dev, reps=2):
+    """32 shots on uneven sub-volumes (CPML-16, 800 steps): one context over
+    all shots launched as one HIP graph, against the plain single-shot path
+    run 32 times in sequence (same kernels, bitwise-identical traces)."""
+    import torch
+    from paper_2007_06048_amd import minimod as mm
+    from paper_2007_06048_amd import workloads as W
+    wl = W.batched_shots()
+    T = wl.nsteps
+    pts = wl.points
+    base = dict(dx=wl.h, dy=wl.h, dz=wl.h, cfl=wl.cfl, bc=wl.bc, nb=wl.nb, cpml_R=wl.cpml_R, cpml_f0=wl.f0,
+                vmax=wl.vmax)
+    p = mm.default_params(**base, tile=-1)
+    vels = [torch.from_numpy(sh.vel).to(dev) for sh in wl.shots]
+    ctx = mm.Context(p, [(v, sh.src, sh.rec) for v, sh in zip(vels, wl.shots)])
+    dt = ctx.dt
+    w1 = mm.ricker(wl.f0, wl.t0, dt, T)
+    w = torch.from_numpy(w1).to(dev).reshape(T, 1).repeat(1, len(wl.shots)).contiguous()
+    tr = torch.empty((T, ctx.nrec), dtype=torch.float32, device=dev)
+
+    def batch():
+        ctx.reset()
+        ctx.forward(T, w, tr, graph=True)
+
+    t_batch = _timed(batch, reps)
+    tile = mm.tile_name(ctx.info()["tile"])
+    del ctx, tr
+    torch.cuda.empty_cache()
+    singles = []
+    for v, sh in zip(vels, wl.shots):
+        q = mm.default_params(**base, tile=-1)
+        c = mm.Context.single(q, v, sh.src, sh.rec)
+        singles.append((c, torch.empty((T, len(sh.rec)), dtype=torch.float32, device=dev)))
+    ws = torch.from_numpy(w1).to(dev).reshape(T, 1)
+
+    def seq():
+        for c, t in singles:
+            c.reset()
+            c.forward(T, ws, t)
+
+    t_seq = _timed(seq, reps)
+    return {"workload": wl.name, "shots": len(wl.shots), "points": pts, "time_steps": T, "tile": tile,
+            "batched_graph_s": round(t_batch, 4), "batched_gpts": round(pts * T / t_batch / 1e9, 2),
+            "sequential_single_s": round(t_seq, 4), "sequential_gpts": round(pts * T / t_seq / 1e9, 2),
+            "speedup": round(t_seq / t_batch, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +203,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--graph", action="store_true", help="launch the step loop as one HIP graph")
     ap.add_argument("--calib", action="store_true", help="also run a 1 GiB copy (counter calibration)")
+    ap.add_argument("--time-steps", type=int, default=0, help="override the workload's step count (profiling)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the gradient and batched-shot legs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (shots and z-slabs would shard "
@@ -113,6 +218,8 @@ def main():
     dev = torch.device("cuda:0")
     wl = load_workload(args.workload)
     s = wl.shots[0]
+    if args.time_steps > 0:
+        wl.nsteps = args.time_steps
     T = wl.nsteps
     p = mm.default_params(nx=wl.nx, ny=wl.ny, nz=wl.nz, dx=wl.h, dy=wl.h, dz=wl.h, cfl=wl.cfl, bc=wl.bc, nb=wl.nb,
                           sponge_sigma=wl.sigma, cpml_R=wl.cpml_R, cpml_f0=wl.f0, tile=args.tile)
@@ -184,6 +291,13 @@ def main():
                    "init_s": round(t_init, 3), "dt_s": dt},
         "roofline": roof,
     }
+    del ctx, traces
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        out["gradient"] = gradient_leg(dev)
+        torch.cuda.empty_cache()
+        out["batched"] = batched_leg(dev)
+        torch.cuda.empty_cache()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -26,6 +26,8 @@ class _Grid(ctypes.Structure):
         ("bc", ctypes.c_int), ("nb", ctypes.c_int),
         ("sigma", ctypes.c_double),
         ("R", ctypes.c_double), ("f0", ctypes.c_double), ("vmax", ctypes.c_double),
+        ("wx0", ctypes.c_int), ("wy0", ctypes.c_int), ("wz0", ctypes.c_int),
+        ("wnx", ctypes.c_int), ("wny", ctypes.c_int), ("wnz", ctypes.c_int),
     ]
 
 
@@ -54,9 +56,10 @@ class Grid:
     def n(self):
         return self.nx * self.ny * self.nz
 
-    def _c(self):
+    def _c(self, window=None):
+        w = (0, 0, 0, 0, 0, 0) if window is None else tuple(window[0]) + tuple(window[1])
         return _Grid(self.nx, self.ny, self.nz, self.hx, self.hy, self.hz, self.dt,
-                     self.bc, self.nb, self.sigma, self.R, self.f0, self.vmax)
+                     self.bc, self.nb, self.sigma, self.R, self.f0, self.vmax, *w)
 
 
 _lib = None
@@ -179,15 +182,22 @@ def forward(g: Grid, vel, src, wav, rec, T, p_prev=None, p_cur=None, cpml_mem=No
     return traces, p_prev, p_cur, cpml_mem
 
 
-def step_points(g: Grid, vel, p_prev, p_cur, cpml_mem, pts, src_term=None):
-    vel = _vel(g, vel)
+def step_points(g: Grid, vel, p_prev, p_cur, cpml_mem, pts, src_term=None, window=None):
+    """p^{n+1} at the points `pts` (global (i, j, k)).  With window =
+    ((i0, j0, k0), (wnx, wny, wnz)) the arrays hold only that box ([wnz][wny][wnx],
+    cpml_mem [6][wnz][wny][wnx])."""
+    if window is None:
+        vel = _vel(g, vel)
+    else:
+        vel = np.ascontiguousarray(vel, dtype=np.float64)
+        assert vel.shape == tuple(window[1][::-1]), (vel.shape, window)
     pts = _pts(pts)
     p_prev = np.ascontiguousarray(p_prev, dtype=np.float64)
     p_cur = np.ascontiguousarray(p_cur, dtype=np.float64)
     mem = None if cpml_mem is None else np.ascontiguousarray(cpml_mem, dtype=np.float64)
     st = None if src_term is None else np.ascontiguousarray(src_term, dtype=np.float64)
     out = np.zeros(len(pts))
-    gc = g._c()
+    gc = g._c(window)
     rc = lib().orc_step_points(ctypes.byref(gc), _f(vel), _d(p_prev), _d(p_cur), _d(mem), len(pts), _i(pts),
                                _d(st), _d(out))
     _check(rc, "orc_step_points")

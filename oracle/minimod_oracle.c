@@ -80,7 +80,15 @@ typedef struct {
     double R;        /* CPML nominal reflection coefficient */
     double f0;       /* CPML alpha_max = pi * f0 */
     double vmax;     /* CPML d0 uses the model maximum velocity */
+    /* Optional storage window (orc_step_points only): when wnx > 0 every
+     * array holds just the box [wx0, wx0+wnx) x [wy0, wy0+wny) x
+     * [wz0, wz0+wnz) of the grid, indexed like a full array of that box.
+     * Indices stay global: the domain edges, layers and sources are those
+     * of the nx x ny x nz grid. */
+    int wx0, wy0, wz0, wnx, wny, wnz;
 } orc_grid;
+
+static int g_window_miss;  /* set when a windowed access falls outside the window */
 
 /* Order-8 central second-derivative weights a_m and first-derivative
  * weights beta_m, m = 1..4 (index 0 unused). */
@@ -89,7 +97,22 @@ static const double B1[5] = {0.0, 4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280
 
 static size_t npts(const orc_grid* g) { return (size_t)g->nx * g->ny * g->nz; }
 
+/* points stored per array: the window if there is one, else the grid */
+static size_t nstore(const orc_grid* g) {
+    return g->wnx > 0 ? (size_t)g->wnx * g->wny * g->wnz : npts(g);
+}
+
 static size_t lin(const orc_grid* g, int i, int j, int k) {
+    if (g->wnx > 0) {
+        i -= g->wx0;
+        j -= g->wy0;
+        k -= g->wz0;
+        if (i < 0 || j < 0 || k < 0 || i >= g->wnx || j >= g->wny || k >= g->wnz) {
+            g_window_miss = 1;
+            return 0;
+        }
+        return ((size_t)k * g->wny + j) * g->wnx + i;
+    }
     return ((size_t)k * g->ny + j) * g->nx + i;
 }
 
@@ -260,6 +283,7 @@ static void cpml_update(const orc_grid* g, const double* p, double* mem, double*
 
 static int check_grid(const orc_grid* g) {
     if (!g || g->nx < 1 || g->ny < 1 || g->nz < 1) return ORC_ERR_ARG;
+    if (g->wnx < 0 || g->wny < 0 || g->wnz < 0) return ORC_ERR_ARG;
     if (g->hx <= 0 || g->hy <= 0 || g->hz <= 0 || g->dt <= 0) return ORC_ERR_ARG;
     if (g->bc < 0 || g->bc > 3) return ORC_ERR_ARG;
     if ((g->bc == BC_SPONGE || g->bc == BC_CPML) && g->nb < 1) return ORC_ERR_ARG;
@@ -310,6 +334,7 @@ static void fill_D(const orc_grid* g, const double* vel, double* D) {
  * at zero. */
 int orc_forward(const orc_grid* g, const double* vel, int nsrc, const int* src, const double* wav, int nrec,
                 const int* rec, int T, double* traces, double* p_prev, double* p_cur, double* cpml_mem) {
+    if (g && g->wnx > 0) return ORC_ERR_ARG;
     if (check_grid(g) || T < 0 || nsrc < 0 || nrec < 0) return ORC_ERR_ARG;
     if (check_pts(g, nsrc, src) || check_pts(g, nrec, rec)) return ORC_ERR_ARG;
     size_t N = npts(g);
@@ -352,14 +377,16 @@ int orc_forward(const orc_grid* g, const double* vel, int nsrc, const int* src, 
 
 /* p^{n+1} at a list of points from a given state: the same step as
  * orc_forward, evaluated point by point (for sampled checks on grids too
- * large to step whole).  cpml_mem (6*N, may be NULL when bc != CPML) holds
+ * large to step whole; with a storage window the arrays cover only a box
+ * around the points, at least 8 cells wide on every side for CPML).  cpml_mem (6*N, may be NULL when bc != CPML) holds
  * psi and zeta of step n-1 and is not modified.  src_term_at[q] is s^n at
  * point q (the caller adds w/(hx hy hz) where a source sits). */
 int orc_step_points(const orc_grid* g, const double* vel, const double* p_prev, const double* p_cur,
                     const double* cpml_mem, int npt, const int* ijk, const double* src_term_at, double* out) {
     if (check_grid(g) || check_pts(g, npt, ijk)) return ORC_ERR_ARG;
     if (g->bc == BC_CPML && !cpml_mem) return ORC_ERR_ARG;
-    size_t N = npts(g);
+    size_t N = nstore(g);
+    g_window_miss = 0;
     for (int q = 0; q < npt; ++q) {
         int i = ijk[3 * q], j = ijk[3 * q + 1], k = ijk[3 * q + 2];
         size_t id = lin(g, i, j, k);
@@ -398,7 +425,7 @@ int orc_step_points(const orc_grid* g, const double* vel, const double* p_prev, 
         double s = src_term_at ? src_term_at[q] : 0.0;
         out[q] = G * (2.0 * p_cur[id] - G * p_prev[id] + D * (L + s));
     }
-    return ORC_OK;
+    return g_window_miss ? ORC_ERR_ARG : ORC_OK;
 }
 
 /* Discrete energy between consecutive states p^n and p^{n+1}:
@@ -446,6 +473,7 @@ static void adj_step(const orc_grid* g, const double* D, const double* e2, const
  *   sum_n <R p^{n+1}, r^n> = sum_n <s^n, eta^{n+1}(src)>. */
 int orc_adjoint(const orc_grid* g, const double* vel, int nrec, const int* rec, const double* resid, int T, int nsrc,
                 const int* src, double* adj_src) {
+    if (g && g->wnx > 0) return ORC_ERR_ARG;
     if (check_grid(g) || T < 0) return ORC_ERR_ARG;
     if (!adjoint_supported(g)) return ORC_ERR_UNSUPPORTED;
     if (check_pts(g, nsrc, src) || check_pts(g, nrec, rec)) return ORC_ERR_ARG;
@@ -479,6 +507,7 @@ int orc_adjoint(const orc_grid* g, const double* vel, int nrec, const int* rec, 
  * not change the result.  traces [T][nrec] and loss may be NULL. */
 int orc_gradient(const orc_grid* g, const double* vel, int nsrc, const int* src, const double* wav, int nrec,
                  const int* rec, const double* d_obs, int T, int ckpt, double* grad, double* traces, double* loss) {
+    if (g && g->wnx > 0) return ORC_ERR_ARG;
     if (check_grid(g) || T < 1 || ckpt < 1) return ORC_ERR_ARG;
     if (!adjoint_supported(g)) return ORC_ERR_UNSUPPORTED;
     if (check_pts(g, nsrc, src) || check_pts(g, nrec, rec)) return ORC_ERR_ARG;

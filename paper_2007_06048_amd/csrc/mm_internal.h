@@ -77,6 +77,7 @@ struct TileShape {
     int tx;     // tile width in x (threads per row)
     int ry;     // rows per thread
     int target; // desired number of blocks (z-chunking)
+    int pd;     // planes of loads in flight ahead of the current plane (1 or 2)
     const char* name;
 };
 int num_tile_variants();

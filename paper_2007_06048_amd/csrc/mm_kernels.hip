@@ -28,13 +28,20 @@
 
 namespace mm {
 
+// shapes (TX, RY) x z-chunking targets x prefetch depths; entry 0 is the default
 static const TileShape kTiles[] = {
-    {64, 4, 2048, "64x16/2048"}, {64, 4, 1024, "64x16/1024"}, {64, 4, 4096, "64x16/4096"},
-    {64, 2, 2048, "64x8/2048"},  {64, 2, 1024, "64x8/1024"},  {64, 2, 4096, "64x8/4096"},
-    {64, 8, 2048, "64x32/2048"}, {64, 8, 1024, "64x32/1024"}, {64, 8, 4096, "64x32/4096"},
-    {32, 2, 2048, "32x16/2048"}, {32, 2, 1024, "32x16/1024"}, {32, 2, 4096, "32x16/4096"},
-    {32, 4, 2048, "32x32/2048"}, {32, 4, 1024, "32x32/1024"}, {32, 4, 4096, "32x32/4096"},
-    {32, 1, 2048, "32x8/2048"},  {32, 1, 1024, "32x8/1024"},  {32, 1, 4096, "32x8/4096"},
+    {64, 4, 2048, 1, "64x16/2048/p1"}, {64, 4, 1024, 1, "64x16/1024/p1"}, {64, 4, 4096, 1, "64x16/4096/p1"},
+    {64, 2, 2048, 1, "64x8/2048/p1"},  {64, 2, 1024, 1, "64x8/1024/p1"},  {64, 2, 4096, 1, "64x8/4096/p1"},
+    {64, 8, 2048, 1, "64x32/2048/p1"}, {64, 8, 1024, 1, "64x32/1024/p1"}, {64, 8, 4096, 1, "64x32/4096/p1"},
+    {32, 2, 2048, 1, "32x16/2048/p1"}, {32, 2, 1024, 1, "32x16/1024/p1"}, {32, 2, 4096, 1, "32x16/4096/p1"},
+    {32, 4, 2048, 1, "32x32/2048/p1"}, {32, 4, 1024, 1, "32x32/1024/p1"}, {32, 4, 4096, 1, "32x32/4096/p1"},
+    {32, 1, 2048, 1, "32x8/2048/p1"},  {32, 1, 1024, 1, "32x8/1024/p1"},  {32, 1, 4096, 1, "32x8/4096/p1"},
+    {64, 4, 2048, 2, "64x16/2048/p2"}, {64, 4, 1024, 2, "64x16/1024/p2"}, {64, 4, 4096, 2, "64x16/4096/p2"},
+    {64, 2, 2048, 2, "64x8/2048/p2"},  {64, 2, 1024, 2, "64x8/1024/p2"},  {64, 2, 4096, 2, "64x8/4096/p2"},
+    {64, 8, 2048, 2, "64x32/2048/p2"}, {64, 8, 1024, 2, "64x32/1024/p2"}, {64, 8, 4096, 2, "64x32/4096/p2"},
+    {32, 2, 2048, 2, "32x16/2048/p2"}, {32, 2, 1024, 2, "32x16/1024/p2"}, {32, 2, 4096, 2, "32x16/4096/p2"},
+    {32, 4, 2048, 2, "32x32/2048/p2"}, {32, 4, 1024, 2, "32x32/1024/p2"}, {32, 4, 4096, 2, "32x32/4096/p2"},
+    {32, 1, 2048, 2, "32x8/2048/p2"},  {32, 1, 1024, 2, "32x8/1024/p2"},  {32, 1, 4096, 2, "32x8/4096/p2"},
 };
 
 int num_tile_variants() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
@@ -43,7 +50,7 @@ int tile_rows(int t) { return (256 / kTiles[t].tx) * kTiles[t].ry; }
 
 // ------------------------------------------------------------- stencil step
 
-template <int TX, int RY, int BC, int MODE>
+template <int TX, int RY, int PD, int BC, int MODE>
 __global__ __launch_bounds__(256) void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd,
                                               const ShotDev* __restrict__ shots, int parity, Coefs cf,
                                               StepAux aux) {
@@ -111,39 +118,58 @@ __global__ __launch_bounds__(256) void k_step(const TileEnt* __restrict__ tiles,
 #pragma unroll
         for (int m = 0; m < 8; ++m) q[r][m] = ld(pc, in[r], row[r], x, z0 - 4 + m);
 
-    float nq[RY], npp[RY], nvd[RY], nxh[RY], nyh[YH];
+    // prefetch stages: stage k holds the loads for plane z + k (queue head p^n(z+k+4),
+    // p^{n-1}(z+k), (dt v)^2(z+k), the x / y halos of plane z+k)
+    float nq[PD][RY], npp[PD][RY], nvd[PD][RY], nxh[PD][RY], nyh[PD][YH];
 #pragma unroll
-    for (int r = 0; r < RY; ++r) {
-        nq[r] = ld(pc, in[r], row[r], x, z0 + 4);
-        npp[r] = ld(pn, in[r], row[r], x, z0);
-        nvd[r] = ld(vd, in[r], row[r], x, z0);
-        nxh[r] = ld(pc, hx_lane && row[r] < ny, row[r], hcol, z0);
+    for (int k = 0; k < PD; ++k) {
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const bool ok = z0 + k < z1;
+            nq[k][r] = ld(pc, ok && in[r], row[r], x, z0 + k + 4);
+            npp[k][r] = ld(pn, ok && in[r], row[r], x, z0 + k);
+            nvd[k][r] = ld(vd, ok && in[r], row[r], x, z0 + k);
+            nxh[k][r] = ld(pc, ok && hx_lane && row[r] < ny, row[r], hcol, z0 + k);
+        }
+#pragma unroll
+        for (int h = 0; h < YH; ++h) nyh[k][h] = ld(pc, z0 + k < z1 && hy_ok[h], hrow[h], x, z0 + k);
     }
-#pragma unroll
-    for (int h = 0; h < YH; ++h) nyh[h] = ld(pc, hy_ok[h], hrow[h], x, z0);
 
     const int xx = 4 + tx;
     for (int z = z0; z < z1; ++z) {
         float cpp[RY], cvd[RY], cxh[RY], cyh[YH];
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            q[r][8] = nq[r];
-            cpp[r] = npp[r];
-            cvd[r] = nvd[r];
-            cxh[r] = nxh[r];
+            q[r][8] = nq[0][r];
+            cpp[r] = npp[0][r];
+            cvd[r] = nvd[0][r];
+            cxh[r] = nxh[0][r];
         }
 #pragma unroll
-        for (int h = 0; h < YH; ++h) cyh[h] = nyh[h];
-        if (z + 1 < z1) {
+        for (int h = 0; h < YH; ++h) cyh[h] = nyh[0][h];
+#pragma unroll
+        for (int k = 0; k + 1 < PD; ++k) {
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
-                nq[r] = ld(pc, in[r], row[r], x, z + 5);
-                npp[r] = ld(pn, in[r], row[r], x, z + 1);
-                nvd[r] = ld(vd, in[r], row[r], x, z + 1);
-                nxh[r] = ld(pc, hx_lane && row[r] < ny, row[r], hcol, z + 1);
+                nq[k][r] = nq[k + 1][r];
+                npp[k][r] = npp[k + 1][r];
+                nvd[k][r] = nvd[k + 1][r];
+                nxh[k][r] = nxh[k + 1][r];
             }
 #pragma unroll
-            for (int h = 0; h < YH; ++h) nyh[h] = ld(pc, hy_ok[h], hrow[h], x, z + 1);
+            for (int h = 0; h < YH; ++h) nyh[k][h] = nyh[k + 1][h];
+        }
+        if (z + PD < z1) {
+            const int zn = z + PD;
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                nq[PD - 1][r] = ld(pc, in[r], row[r], x, zn + 4);
+                npp[PD - 1][r] = ld(pn, in[r], row[r], x, zn);
+                nvd[PD - 1][r] = ld(vd, in[r], row[r], x, zn);
+                nxh[PD - 1][r] = ld(pc, hx_lane && row[r] < ny, row[r], hcol, zn);
+            }
+#pragma unroll
+            for (int h = 0; h < YH; ++h) nyh[PD - 1][h] = ld(pc, hy_ok[h], hrow[h], x, zn);
         }
 
         float(*L)[LW] = lds[z & 1];
@@ -199,27 +225,31 @@ __global__ __launch_bounds__(256) void k_step(const TileEnt* __restrict__ tiles,
     }
 }
 
-template <int TX, int RY, int BC>
+template <int TX, int RY, int PD, int BC>
 static hipError_t launch_step_bc(int mode, dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd,
                                  const ShotDev* shots, int parity, const Coefs& cf, const StepAux& aux,
                                  hipStream_t s) {
     dim3 block(TX, 256 / TX);
     if (mode == MODE_PLAIN)
-        k_step<TX, RY, BC, MODE_PLAIN><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
+        k_step<TX, RY, PD, BC, MODE_PLAIN><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
     else if (mode == MODE_D2P)
-        k_step<TX, RY, BC, MODE_D2P><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
+        k_step<TX, RY, PD, BC, MODE_D2P><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
     else
-        k_step<TX, RY, BC, MODE_IMAGE><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
+        k_step<TX, RY, PD, BC, MODE_IMAGE><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
     return hipGetLastError();
 }
 
 template <int TX, int RY>
-static hipError_t launch_step_t(int bc, int mode, dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd,
+static hipError_t launch_step_t(int pd, int bc, int mode, dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd,
                                 const ShotDev* shots, int parity, const Coefs& cf, const StepAux& aux,
                                 hipStream_t s) {
-    if (bc == 1) return launch_step_bc<TX, RY, 1>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
     // CPML: the stencil kernel is the plain one; launch_cpml adds the layer terms afterwards
-    return launch_step_bc<TX, RY, 0>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+    if (pd == 1) {
+        if (bc == 1) return launch_step_bc<TX, RY, 1, 1>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+        return launch_step_bc<TX, RY, 1, 0>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+    }
+    if (bc == 1) return launch_step_bc<TX, RY, 2, 1>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+    return launch_step_bc<TX, RY, 2, 0>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
 }
 
 hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int ntiles, const ShotDev* shots,
@@ -229,13 +259,13 @@ hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int 
     dim3 grid(8 * per_xcd);
     const TileShape& ts = kTiles[variant];
     if (ts.tx == 64) {
-        if (ts.ry == 2) return launch_step_t<64, 2>(bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
-        if (ts.ry == 4) return launch_step_t<64, 4>(bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
-        return launch_step_t<64, 8>(bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+        if (ts.ry == 2) return launch_step_t<64, 2>(ts.pd, bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+        if (ts.ry == 4) return launch_step_t<64, 4>(ts.pd, bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+        return launch_step_t<64, 8>(ts.pd, bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
     }
-    if (ts.ry == 1) return launch_step_t<32, 1>(bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
-    if (ts.ry == 2) return launch_step_t<32, 2>(bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
-    return launch_step_t<32, 4>(bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+    if (ts.ry == 1) return launch_step_t<32, 1>(ts.pd, bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+    if (ts.ry == 2) return launch_step_t<32, 2>(ts.pd, bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+    return launch_step_t<32, 4>(ts.pd, bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
 }
 
 // -------------------------------------------------------------------- CPML

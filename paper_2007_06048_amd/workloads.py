@@ -68,27 +68,48 @@ def smooth_random(shape, sigma, vmin, vmax, seed):
     return x
 
 
-def _upsample_trilinear(c, shape):
-    """Trilinear interpolation of a coarse field onto `shape`, corner-aligned."""
-    from scipy.ndimage import map_coordinates
+def _lin_weights(n_out, n_in, lo=0, count=None):
+    """[count][n_in] weights of corner-aligned linear interpolation from n_in
+    to n_out samples, rows lo .. lo+count-1 of the full n_out x n_in matrix."""
+    count = n_out - lo if count is None else count
+    pos = (np.arange(lo, lo + count) * (n_in - 1) / max(n_out - 1, 1)).astype(np.float64)
+    i0 = np.minimum(np.floor(pos).astype(np.int64), n_in - 2) if n_in > 1 else np.zeros(count, np.int64)
+    f = pos - i0
+    W = np.zeros((count, n_in))
+    r = np.arange(count)
+    if n_in == 1:
+        W[:, 0] = 1.0
+        return W
+    W[r, i0] = 1.0 - f
+    W[r, i0 + 1] += f
+    return W
 
-    out = np.empty(shape, dtype=np.float32)
-    cz = np.linspace(0, c.shape[0] - 1, shape[0])
-    cy = np.linspace(0, c.shape[1] - 1, shape[1])
-    cx = np.linspace(0, c.shape[2] - 1, shape[2])
-    yy, xx = np.meshgrid(cy, cx, indexing="ij")
-    for kz, z in enumerate(cz):
-        zz = np.full_like(yy, z)
-        out[kz] = map_coordinates(c, [zz, yy, xx], order=1, mode="nearest")
-    return out
+
+def _upsample_trilinear(c, shape, origin=(0, 0, 0), full=None):
+    """Trilinear interpolation (corner-aligned) of the coarse field c onto the
+    box `shape` = (nz, ny, nx) starting at `origin` (k, j, i) of a full grid of
+    shape `full` (default: the box itself).  Separable, so it is three small
+    matrix products."""
+    full = shape if full is None else full
+    Wz = _lin_weights(full[0], c.shape[0], origin[0], shape[0])
+    Wy = _lin_weights(full[1], c.shape[1], origin[1], shape[1])
+    Wx = _lin_weights(full[2], c.shape[2], origin[2], shape[2])
+    t = np.tensordot(c, Wx.T, axes=([2], [0]))          # [cz][cy][nx]
+    t = np.tensordot(Wy, t, axes=([1], [1]))            # [ny][cz][nx]
+    t = np.tensordot(Wz, t, axes=([1], [1]))            # [nz][ny][nx]
+    return t.astype(np.float32)
 
 
-def smooth_random_coarse(shape, sigma, vmin, vmax, seed, factor=8):
+def smooth_random_coarse(shape, sigma, vmin, vmax, seed, factor=8, box=None):
     """Large-model variant: noise on a grid `factor` times coarser, filtered
-    with sigma/factor, rescaled, then trilinearly upsampled."""
+    with sigma/factor, rescaled, then trilinearly upsampled to `shape`.  With
+    box = (origin, size) only that sub-box of the upsampled field is built."""
     cshape = tuple(max(2, -(-n // factor) + 1) for n in shape)
     c = smooth_random(cshape, sigma / factor, vmin, vmax, seed)
-    return _upsample_trilinear(c, shape)
+    if box is None:
+        return _upsample_trilinear(c, shape)
+    origin, size = box
+    return _upsample_trilinear(c, size, origin, shape)
 
 
 def plane(nx, ny, z, inc=1):
@@ -143,19 +164,20 @@ def batched_shots(nshots=32, big=(400, 1024, 1024), side=(128, 256), seed=4, nst
     16-cell CPML; Ricker 15 Hz at each sub-volume's centre; receivers on the
     full plane z = 16; 800 steps."""
     rng = np.random.default_rng(seed)
-    model = smooth_random_coarse(big, 8.0, 1500.0, 4500.0, seed, factor=8)
+    cshape = tuple(max(2, -(-n // 8) + 1) for n in big)
+    coarse = smooth_random(cshape, 1.0, 1500.0, 4500.0, seed)
     shots = []
     for _ in range(nshots):
         nx, ny, nz = (int(rng.integers(side[0], side[1] + 1)) for _ in range(3))
         ox = int(rng.integers(0, big[2] - nx + 1))
         oy = int(rng.integers(0, big[1] - ny + 1))
         oz = int(rng.integers(0, big[0] - nz + 1))
-        v = np.ascontiguousarray(model[oz:oz + nz, oy:oy + ny, ox:ox + nx])
+        v = _upsample_trilinear(coarse, (nz, ny, nx), (oz, oy, ox), big)
         shots.append(Shot(v, np.array([[nx // 2, ny // 2, nz // 2]], dtype=np.int32), plane(nx, ny, 16),
                           origin=(ox, oy, oz)))
     w = Workload(f"batched_{nshots}shots_cpml16_{nsteps}steps", 0, 0, 0, 10.0, nsteps, BC_CPML, 16, 15.0, 0.1,
                  shots=shots)
-    w.vmax = float(model.max())
+    w.vmax = float(coarse.max())  # trilinear interpolation never exceeds the coarse maximum
     return w
 
 

@@ -500,6 +500,32 @@ def test_step_points_matches_whole_step():
         assert np.abs(got - want).max() <= 1e-14 * np.abs(pn).max()
 
 
+def test_step_points_on_a_storage_window_equals_full_arrays():
+    """The windowed form used for sampled checks on the big grids gives the
+    same numbers as the full arrays, and refuses a window that is too small."""
+    rng = np.random.default_rng(31)
+    nx, ny, nz = 30, 28, 26
+    h = (10.0, 11.0, 12.0)
+    vel = rng.uniform(1500, 3000, (nz, ny, nx))
+    dt = 0.5 * C.dt_stab(vel.max(), *h)
+    for bc in (C.BC_NONE, C.BC_SPONGE, C.BC_CPML):
+        g = C.Grid(nx, ny, nz, *h, dt, bc=bc, nb=6, sigma=0.05, R=1e-3, f0=20.0, vmax=vel.max())
+        _, pm, pc, mem = C.forward(g, vel, [[15, 14, 13]], rng.standard_normal((20, 1)), [], 20)
+        pts = np.array([[0, 0, 0], [15, 14, 13], [29, 27, 25], [10, 3, 20], [5, 20, 2]])
+        full = C.step_points(g, vel, pm, pc, mem, pts)
+        for q, pt in enumerate(pts):
+            lo = np.maximum(pt - 8, 0)
+            hi = np.minimum(pt + 9, [nx, ny, nz])
+            sl = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+            m = None if mem is None else np.ascontiguousarray(mem[(slice(None),) + sl])
+            w = (tuple(int(v) for v in lo), tuple(int(v) for v in hi - lo))
+            assert C.step_points(g, vel[sl], pm[sl], pc[sl], m, pt[None], window=w)[0] == full[q]
+        sl = (slice(10, 14),) * 3
+        m = None if mem is None else np.ascontiguousarray(mem[(slice(None),) + sl])
+        with pytest.raises(RuntimeError):
+            C.step_points(g, vel[sl], pm[sl], pc[sl], m, [[12, 12, 12]], window=((10, 10, 10), (4, 4, 4)))
+
+
 # ----------------------------------------------------------------- wavelet
 def test_ricker_is_normalised_second_derivative_of_gaussian():
     """w(t) = -(1/(2 pi^2 f0^2)) d^2/dt^2 exp(-pi^2 f0^2 (t-t0)^2): the Ricker
