@@ -88,6 +88,60 @@ def cpu_baseline(wl, budget_s):
                       f"after 1 warm-up step"}
 
 
+def pmc_summary(fetch_dir, write_dir, workload, out_path):
+    """HBM traffic of the stencil kernel from two rocprofv3 --pmc passes
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
+    same counter reads for kernels of known size in the same program:
+    k_vcheck reads exactly 4 N bytes (the velocity model), k_vdt2 writes
+    exactly 4 N bytes."""
+    import csv
+    import numpy as np
+    from paper_2007_06048_amd import workloads as W
+    wl = {"smooth240": W.smooth_240, "layered1024": W.layered_1024}[workload]()
+    n = wl.nx * wl.ny * wl.nz
+
+    def per_kernel(d, counter):
+        vals = {}
+        with open(os.path.join(d, "run_counter_collection.csv")) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] == counter:
+                    vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+        return vals
+
+    fetch = per_kernel(fetch_dir, "FETCH_SIZE")
+    write = per_kernel(write_dir, "WRITE_SIZE")
+
+    def pick(vals, key):
+        ks = [k for k in vals if key in k]
+        assert len(ks) == 1, (key, ks)
+        return np.mean(vals[ks[0]]), ks[0], len(vals[ks[0]])
+
+    f_cal, _, _ = pick(fetch, "k_vcheck")
+    w_cal, _, _ = pick(write, "k_vdt2")
+    f_fac, w_fac = 4.0 * n / f_cal, 4.0 * n / w_cal
+    f_step, kname, nd = pick(fetch, "k_step<")
+    w_step, _, _ = pick(write, "k_step<")
+    entry = {"kernel": kname, "dispatches": nd, "kernel_hash": kernel_hash(), "points": n,
+             "fetch_scale": round(f_fac, 4), "write_scale": round(w_fac, 4),
+             "fetch_bytes_per_launch": round(f_step * f_fac), "write_bytes_per_launch": round(w_step * w_fac),
+             "bytes_per_launch": round(f_step * f_fac + w_step * w_fac),
+             "alg_bytes_per_launch": ALG_BYTES_STENCIL * n,
+             "note": "L2-miss bytes (FETCH_SIZE/WRITE_SIZE count traffic below L2, so infinity-cache hits are "
+                     "included); calibration kernels k_vcheck (read 4N B) and k_vdt2 (write 4N B)"}
+    for k in [k for k in set(fetch) | set(write) if "cpml" in k]:
+        entry.setdefault("cpml", {})[k] = {"fetch_bytes": round(np.mean(fetch.get(k, [0])) * f_fac),
+                                           "write_bytes": round(np.mean(write.get(k, [0])) * w_fac)}
+    try:
+        with open(out_path) as f:
+            allv = json.load(f)
+    except (OSError, ValueError):
+        allv = {}
+    allv[wl.name] = entry
+    with open(out_path, "w") as f:
+        json.dump(allv, f, indent=1)
+    print(json.dumps(entry, indent=1))
+
+
 def _timed(fn, reps):
     import torch
     fn()
@@ -205,7 +259,13 @@ def main():
     ap.add_argument("--calib", action="store_true", help="also run a 1 GiB copy (counter calibration)")
     ap.add_argument("--time-steps", type=int, default=0, help="override the workload's step count (profiling)")
     ap.add_argument("--no-extras", action="store_true", help="skip the gradient and batched-shot legs")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs into profiles/stencil_traffic.json and exit")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.workload,
+                    os.path.join(ROOT, "profiles", "stencil_traffic.json"))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (shots and z-slabs would shard "
               "across GPUs; see the design notes). Run with --gpus 1.", file=sys.stderr)

@@ -61,10 +61,11 @@ struct Layout {
     size_t shots_dev = 0, shots_adj = 0, tiles = 0, scratch = 0;
     int max_tiles = 0;
     std::vector<size_t> buf0, buf1, vdt2, prof, ebuf0, ebuf1;
-    std::vector<size_t> psi[3], zeta[3];
+    std::vector<size_t> psi[3], zeta[3], corr[3];
     size_t src_shot = 0, src_off = 0, src_start = 0, src_col = 0, src_g = 0;
     size_t rin_shot = 0, rin_off = 0, rin_start = 0, rin_col = 0, rin_g = 0;
     size_t rg_shot = 0, rg_off = 0, sg_shot = 0, sg_off = 0;
+    size_t cpml_off = 0;  // CPML block table
     bool adjoint = false, grad = false;
     int nseg = 0;
     size_t seg = 0, ckpt = 0, ckpt_scale = 0, wav_store = 0, tr_store = 0, resid_store = 0;
@@ -110,6 +111,7 @@ void compute_layout(const mm_params& p, const std::vector<ShotGeom>& shots, int 
             const bool c = p.bc == MM_BC_CPML;
             L.psi[a].push_back(c ? take(L, sizeof(float) * sl[a]) : 0);
             L.zeta[a].push_back(c ? take(L, sizeof(float) * sl[a]) : 0);
+            L.corr[a].push_back(c ? take(L, sizeof(float) * sl[a]) : 0);
         }
         L.ebuf0.push_back(L.adjoint ? take(L, fb) : 0);
         L.ebuf1.push_back(L.adjoint ? take(L, fb) : 0);
@@ -128,6 +130,7 @@ void compute_layout(const mm_params& p, const std::vector<ShotGeom>& shots, int 
     L.rg_off = take(L, sizeof(long long) * nrec);
     L.sg_shot = take(L, sizeof(int) * nsrc);
     L.sg_off = take(L, sizeof(long long) * nsrc);
+    L.cpml_off = take(L, sizeof(int) * 3 * (S + 1));
     if (L.grad) {
         const long long N = shots[0].n();
         const int K = p.ckpt_every;
@@ -212,8 +215,8 @@ struct mm_ctx {
     InjTab src_inj{}, rec_inj{};
     GatherTab rec_gather{}, src_gather{};
     int nsrc = 0, nrec = 0;
-    int mx = 0, my = 0, mz = 0;  // largest grid sizes over the shots
-    long long max_rows = 0;      // largest ny * nz
+    std::vector<int> cpml_off_h;  // CPML block table (host copy)
+    const int* cpml_off_d = nullptr;
     bool inline_src = false;
     std::vector<std::vector<long long>> src_cells;  // per shot, for tile flags
     Coefs cf{};
@@ -312,6 +315,7 @@ mm_status check_shot(const mm_params* p, const mm_shot& s, int idx, bool need_ve
         }
     }
     if ((long long)s.nx * s.ny * s.nz > (1LL << 34)) return fail(c, MM_ERR_ARG, "grid too large");
+    if ((long long)s.nx * s.ny >= (1LL << 30)) return fail(c, MM_ERR_ARG, "grid plane nx*ny must be < 2^30");
     if (p->bc == MM_BC_CPML && (s.ny > 65535 || s.nz > 65535 || (long long)s.ny * s.nz > (1LL << 30)))
         return fail(c, MM_ERR_ARG, "CPML grids need ny, nz <= 65535");
     if (need_vel && !s.vel) return fail(c, MM_ERR_ARG, "velocity pointer is NULL");
@@ -382,11 +386,17 @@ mm_status upload(mm_ctx* c, void* dst, const void* src, size_t bytes) {
 }
 
 void tile_flags(mm_ctx* c, int v) {
-    const int TX = tile_variant(v).tx, TY = tile_rows(v);
+    const int TX = tile_variant(v).tx, TY = tile_rows(v), nb = c->p.nb;
+    auto meets = [nb](int a0, int a1, int n) { return a0 < nb || a1 > n - nb; };  // [a0, a1) vs the layers
     for (TileEnt& t : c->tiles_h) {
         const ShotGeom& g = c->geom[t.shot];
         const int x1 = std::min(g.nx, t.x0 + TX), y1 = std::min(g.ny, t.y0 + TY);
         int f = 0;
+        if (c->cpml) {
+            if (meets(t.x0, x1, g.nx)) f |= TF_LX;
+            if (meets(t.y0, y1, g.ny)) f |= TF_LY;
+            if (meets(t.z0, t.z1, g.nz)) f |= TF_LZ;
+        }
         if (c->inline_src)
             for (long long o : c->src_cells[t.shot]) {
                 const int z = (int)(o / ((long long)g.nx * g.ny));
@@ -449,6 +459,12 @@ mm_status zero_adjoint(mm_ctx* c, hipStream_t s) {
 // One leapfrog step of the forward (or adjoint) field set.
 mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, const StepAux& aux, hipStream_t s) {
     const bool timed = c->prof_stride > 0 && s == c->stream && (c->prof_count++ % c->prof_stride) == 0;
+    if (c->cpml) {
+        if (shots != c->d_shots) return fail(c, MM_ERR_UNSUPPORTED, "CPML has no adjoint");
+        MM_TRY(dev(c, launch_cpml(shots, (int)c->geom.size(), c->p.nb, c->cpml_off_d, c->cpml_off_h.data(), parity,
+                                  c->cf, s),
+                   "cpml launch"));
+    }
     if (timed) {
         while (c->prof_ev.size() < c->prof_used + 2) {
             hipEvent_t e;
@@ -462,11 +478,6 @@ mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, co
     if (timed) {
         MM_TRY(dev(c, hipEventRecord(c->prof_ev[c->prof_used + 1], s), "event"));
         c->prof_used += 2;
-    }
-    if (c->cpml) {
-        if (shots != c->d_shots) return fail(c, MM_ERR_UNSUPPORTED, "CPML has no adjoint");
-        MM_TRY(dev(c, launch_cpml(shots, (int)c->geom.size(), c->p.nb, c->max_rows, c->mx, c->my, c->mz, parity, c->cf, s),
-                   "cpml launch"));
     }
     return MM_OK;
 }
@@ -525,13 +536,23 @@ mm_status enqueue_forward(mm_ctx* c, int nsteps, const float* wav, float* traces
         StepAux aux = none;
         aux.src_scale = c->src_inj.scale;
         aux.wrow = c->nsrc > 0 ? wav + (size_t)j * c->nsrc : nullptr;
+        if (j > 0 && traces && c->nrec > 0) {
+            // the stencil launch also records the previous step's receivers
+            aux.g_shot = c->rec_gather.shot;
+            aux.g_off = c->rec_gather.off;
+            aux.g_n = c->nrec;
+            aux.gather_blocks = ((c->nrec + 255) / 256 + 7) / 8 * 8;
+            aux.gather_out = traces + (size_t)(j - 1) * c->nrec;
+        }
         MM_TRY(enqueue_step(c, c->d_shots, parity, MODE_PLAIN, aux, s));
         if (c->nsrc > 0 && !c->inline_src)
             MM_TRY(dev(c, launch_inject(c->src_inj, c->d_shots, parity, aux.wrow, c->nsrc, MODE_PLAIN, none, s),
                        "inject"));
-        if (traces && c->nrec > 0)
-            MM_TRY(dev(c, launch_gather(c->rec_gather, c->d_shots, parity, traces + (size_t)j * c->nrec, s), "record"));
     }
+    if (nsteps > 0 && traces && c->nrec > 0)
+        MM_TRY(dev(c, launch_gather(c->rec_gather, c->d_shots, (c->step + nsteps - 1) & 1,
+                                    traces + (size_t)(nsteps - 1) * c->nrec, s),
+                   "record"));
     return MM_OK;
 }
 
@@ -779,6 +800,7 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
         for (int a = 0; a < 3; ++a) {
             sd.psi[a] = c->cpml ? at<float>(c->ws, L.psi[a][i]) : nullptr;
             sd.zeta[a] = c->cpml ? at<float>(c->ws, L.zeta[a][i]) : nullptr;
+            sd.corr[a] = c->cpml ? at<float>(c->ws, L.corr[a][i]) : nullptr;
         }
         sd.nx = g.nx;
         sd.ny = g.ny;
@@ -799,10 +821,6 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
                 cpml_table(n[a], p->nb, h[a], c->dt, c->vmax, p->cpml_R, p->cpml_f0, q, q + n[a]);
                 q += 2 * n[a];
             }
-            c->max_rows = std::max(c->max_rows, (long long)g.ny * g.nz);
-            c->mx = std::max(c->mx, g.nx);
-            c->my = std::max(c->my, g.ny);
-            c->mz = std::max(c->mz, g.nz);
         } else {
             pr.resize(g.nx + g.ny + g.nz);
             float* q = pr.data();
@@ -894,6 +912,18 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
     up(L.rg_off, r_off.data(), sizeof(long long) * r_off.size());
     up(L.sg_shot, s_shot.data(), sizeof(int) * s_shot.size());
     up(L.sg_off, s_off.data(), sizeof(long long) * s_off.size());
+    if (c->cpml) {
+        std::vector<int> gx, gy, gz;
+        for (const auto& g : geom) {
+            gx.push_back(g.nx);
+            gy.push_back(g.ny);
+            gz.push_back(g.nz);
+        }
+        c->cpml_off_h.assign(3 * (nshots + 1), 0);
+        cpml_block_table(gx.data(), gy.data(), gz.data(), nshots, p->nb, c->cpml_off_h.data());
+        c->cpml_off_d = at<int>(c->ws, L.cpml_off);
+        up(L.cpml_off, c->cpml_off_h.data(), sizeof(int) * c->cpml_off_h.size());
+    }
     for (int i = 0; i < nshots && !st; ++i)
         st = dev(c, launch_vdt2(shots[i].vel, c->shots_h[i].vdt2, geom[i].n(), c->dt, s), "vdt2");
     if (!st) st = dev(c, hipStreamSynchronize(s), "sync");

@@ -14,6 +14,7 @@ struct ShotDev {
     const float* prof;    // sponge: g_x[nx] g_y[ny] g_z[nz]; CPML: a_x b_x [nx], a_y b_y [ny], a_z b_z [nz]
     float* psi[3];        // CPML memory, slab layouts (see minimod.h)
     float* zeta[3];
+    float* corr[3];       // CPML correction D1 psi + zeta of the current step, slab layouts
     int nx, ny, nz, nb;
     int nsrc_in;          // sources added inside the stencil kernel (0..4)
     int src_col[4];       // their columns in the wavelet row
@@ -27,8 +28,9 @@ struct TileEnt {
     int shot, x0, y0, z0, z1, flags, pad1, pad2;
 };
 
-// TileEnt::flags: the tile holds a source added inside the stencil kernel.
-enum { TF_SRC = 1 };
+// TileEnt::flags: the tile meets the x / y / z damping layer (CPML), or
+// holds a source added inside the stencil kernel.
+enum { TF_LX = 1, TF_LY = 2, TF_LZ = 4, TF_SRC = 8 };
 
 // Stencil weights a_m / h^2 per axis (m = 1..4) and first-derivative weights
 // beta_m / h (CPML).
@@ -61,6 +63,8 @@ struct GatherTab {
 //          before the source term; single shot)
 //  mode 2: grad[x] += neg_inv_dt2 / G * p^{n+1}[x] * d2p[x]  (imaging)
 //  inline sources: lap += src_scale * wrow[col] at a shot's source cells
+//  folded record: the first gather_blocks blocks copy p^n (the previous
+//  step's output) at the receivers into gather_out
 struct StepAux {
     float* d2p_out;
     const float* d2p_in;
@@ -68,6 +72,11 @@ struct StepAux {
     float neg_inv_dt2;
     float src_scale;
     const float* wrow;
+    const int* g_shot;
+    const long long* g_off;
+    int g_n;
+    int gather_blocks;  // multiple of 8 (keeps the XCD pattern of the tile blocks)
+    float* gather_out;
 };
 
 enum { MODE_PLAIN = 0, MODE_D2P = 1, MODE_IMAGE = 2 };
@@ -84,14 +93,17 @@ int num_tile_variants();
 const TileShape& tile_variant(int t);
 int tile_rows(int t);  // TY of variant t
 
-// bc: 0 none, 1 sponge, 2 CPML (the stencil itself; launch_cpml adds the
-// layer terms of the same step afterwards)
+// bc: 0 none, 1 sponge, 2 CPML (launch_cpml must have written the layer
+// corrections of the same step first)
 hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int ntiles,
                        const ShotDev* shots, int parity, const Coefs& cf, const StepAux& aux,
                        hipStream_t s);
-// CPML layers of every shot (shared nb <= 128); max_rows = largest ny*nz and
-// mx, my, mz = largest grid sizes over the shots
-hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, long long max_rows, int mx, int my, int mz,
+// CPML memory update and corrections of every shot for this step, before the
+// stencil kernel (shared nb <= 128).  The block table (3 (nshots + 1) ints,
+// made by cpml_block_table) is passed both as the device copy the kernel
+// reads and as the host copy that sizes the grid.
+void cpml_block_table(const int* nx, const int* ny, const int* nz, int nshots, int nb, int* off);
+hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, const int* block_off_dev, const int* block_off_host,
                        int parity, const Coefs& cf, hipStream_t s);
 hipError_t launch_inject(const InjTab& tab, const ShotDev* shots, int parity, const float* vals, int ncols,
                          int mode, const StepAux& aux, hipStream_t s);

@@ -28,20 +28,39 @@
 
 namespace mm {
 
-// shapes (TX, RY) x z-chunking targets x prefetch depths; entry 0 is the default
+// Global-memory views: loads through a buffer resource (scalar base, 32-bit
+// per-lane byte offset, hardware range check returning 0 past the end, so
+// ghost cells need no branch), stores through address-space-1 pointers.
+typedef __attribute__((address_space(1))) float gfloat;
+constexpr unsigned OOB = 0xFFFFFFFFu;  // byte offset that is always out of range
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float* base, int z, long long plane) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(base + (long long)z * plane), (short)0, (int)(plane * 4),
+                                             0x00020000);
+}
+
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned voff) {
+    return __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, 0, 0));
+}
+
+// shapes (TX, RY) x z-chunking targets (total blocks over all shots; chunks
+// are at least 4 planes) with one plane of prefetch, plus a few two-plane
+// prefetch variants of the large tiles; entry 0 is the default
 static const TileShape kTiles[] = {
-    {64, 4, 2048, 1, "64x16/2048/p1"}, {64, 4, 1024, 1, "64x16/1024/p1"}, {64, 4, 4096, 1, "64x16/4096/p1"},
-    {64, 2, 2048, 1, "64x8/2048/p1"},  {64, 2, 1024, 1, "64x8/1024/p1"},  {64, 2, 4096, 1, "64x8/4096/p1"},
-    {64, 8, 2048, 1, "64x32/2048/p1"}, {64, 8, 1024, 1, "64x32/1024/p1"}, {64, 8, 4096, 1, "64x32/4096/p1"},
-    {32, 2, 2048, 1, "32x16/2048/p1"}, {32, 2, 1024, 1, "32x16/1024/p1"}, {32, 2, 4096, 1, "32x16/4096/p1"},
-    {32, 4, 2048, 1, "32x32/2048/p1"}, {32, 4, 1024, 1, "32x32/1024/p1"}, {32, 4, 4096, 1, "32x32/4096/p1"},
-    {32, 1, 2048, 1, "32x8/2048/p1"},  {32, 1, 1024, 1, "32x8/1024/p1"},  {32, 1, 4096, 1, "32x8/4096/p1"},
-    {64, 4, 2048, 2, "64x16/2048/p2"}, {64, 4, 1024, 2, "64x16/1024/p2"}, {64, 4, 4096, 2, "64x16/4096/p2"},
-    {64, 2, 2048, 2, "64x8/2048/p2"},  {64, 2, 1024, 2, "64x8/1024/p2"},  {64, 2, 4096, 2, "64x8/4096/p2"},
-    {64, 8, 2048, 2, "64x32/2048/p2"}, {64, 8, 1024, 2, "64x32/1024/p2"}, {64, 8, 4096, 2, "64x32/4096/p2"},
-    {32, 2, 2048, 2, "32x16/2048/p2"}, {32, 2, 1024, 2, "32x16/1024/p2"}, {32, 2, 4096, 2, "32x16/4096/p2"},
-    {32, 4, 2048, 2, "32x32/2048/p2"}, {32, 4, 1024, 2, "32x32/1024/p2"}, {32, 4, 4096, 2, "32x32/4096/p2"},
-    {32, 1, 2048, 2, "32x8/2048/p2"},  {32, 1, 1024, 2, "32x8/1024/p2"},  {32, 1, 4096, 2, "32x8/4096/p2"},
+    {64, 4, 2048, 1, "64x16/2048/p1"},   {64, 4, 1024, 1, "64x16/1024/p1"},   {64, 4, 4096, 1, "64x16/4096/p1"},
+    {64, 4, 16384, 1, "64x16/16k/p1"},   {64, 4, 65536, 1, "64x16/64k/p1"},
+    {64, 2, 2048, 1, "64x8/2048/p1"},    {64, 2, 1024, 1, "64x8/1024/p1"},    {64, 2, 4096, 1, "64x8/4096/p1"},
+    {64, 2, 16384, 1, "64x8/16k/p1"},    {64, 2, 65536, 1, "64x8/64k/p1"},
+    {64, 8, 2048, 1, "64x32/2048/p1"},   {64, 8, 1024, 1, "64x32/1024/p1"},   {64, 8, 4096, 1, "64x32/4096/p1"},
+    {64, 8, 16384, 1, "64x32/16k/p1"},   {64, 8, 65536, 1, "64x32/64k/p1"},
+    {32, 2, 2048, 1, "32x16/2048/p1"},   {32, 2, 1024, 1, "32x16/1024/p1"},   {32, 2, 4096, 1, "32x16/4096/p1"},
+    {32, 2, 16384, 1, "32x16/16k/p1"},   {32, 2, 65536, 1, "32x16/64k/p1"},
+    {32, 4, 2048, 1, "32x32/2048/p1"},   {32, 4, 1024, 1, "32x32/1024/p1"},   {32, 4, 4096, 1, "32x32/4096/p1"},
+    {32, 4, 16384, 1, "32x32/16k/p1"},   {32, 4, 65536, 1, "32x32/64k/p1"},
+    {32, 1, 2048, 1, "32x8/2048/p1"},    {32, 1, 1024, 1, "32x8/1024/p1"},    {32, 1, 4096, 1, "32x8/4096/p1"},
+    {32, 1, 16384, 1, "32x8/16k/p1"},    {32, 1, 65536, 1, "32x8/64k/p1"},
+    {64, 4, 1024, 2, "64x16/1024/p2"},   {64, 4, 4096, 2, "64x16/4096/p2"},   {64, 8, 1024, 2, "64x32/1024/p2"},
+    {64, 8, 2048, 2, "64x32/2048/p2"},   {32, 2, 4096, 2, "32x16/4096/p2"},   {32, 1, 4096, 2, "32x8/4096/p2"},
 };
 
 int num_tile_variants() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
@@ -59,11 +78,18 @@ __global__ __launch_bounds__(256) void k_step(const TileEnt* __restrict__ tiles,
     constexpr int LW = TX + 8;
     constexpr int YH = 8 / BY;
     constexpr bool SPONGE = BC == 1;
+    constexpr bool CPML = BC == 2;
     static_assert(BY <= 8 && 8 % BY == 0, "y halo split");
     __shared__ float lds[2][TY + 8][LW];
 
+    if ((int)blockIdx.x < aux.gather_blocks) {
+        // record of the previous step: its output is this step's p^n
+        const int r = blockIdx.x * 256 + threadIdx.y * TX + threadIdx.x;
+        if (r < aux.g_n) aux.gather_out[r] = shots[aux.g_shot[r]].buf[parity][aux.g_off[r]];
+        return;
+    }
     // consecutive tiles on one XCD: block b runs on XCD b % 8
-    const int b = blockIdx.x;
+    const int b = blockIdx.x - aux.gather_blocks;
     const int t = (b & 7) * per_xcd + (b >> 3);
     if (t >= ntiles) return;
     const TileEnt te = tiles[t];
@@ -98,9 +124,33 @@ __global__ __launch_bounds__(256) void k_step(const TileEnt* __restrict__ tiles,
         hy_ok[h] = xin && hrow[h] >= 0 && hrow[h] < ny;
     }
 
-    auto ld = [&](const float* __restrict__ base, bool ok, int yy, int xx, int z) -> float {
-        return (ok && z >= 0 && z < nz) ? base[(long long)z * plane + (long long)yy * nx + xx] : 0.0f;
-    };
+    // per-lane byte offsets inside a plane (OOB where the cell is outside the grid)
+    unsigned voc[RY], vox[RY], voy[YH];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        voc[r] = in[r] ? (unsigned)(row[r] * nx + x) * 4u : OOB;
+        vox[r] = (hx_lane && row[r] < ny) ? (unsigned)(row[r] * nx + hcol) * 4u : OOB;
+    }
+#pragma unroll
+    for (int h = 0; h < YH; ++h) voy[h] = hy_ok[h] ? (unsigned)(hrow[h] * nx + x) * 4u : OOB;
+    // CPML corrections (slab arrays; OOB where the cell is not in that axis' layer)
+    const int nb = sd.nb, nb2 = 2 * nb;
+    const bool tile_layer = CPML && (te.flags & (TF_LX | TF_LY | TF_LZ));
+    unsigned vcx[CPML ? RY : 1], vcy[CPML ? RY : 1], vcz[CPML ? RY : 1];
+    if (CPML) {
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const int y = row[r];
+            const bool lxr = in[r] && (x < nb || x >= nx - nb);
+            const bool lyr = in[r] && (y < nb || y >= ny - nb);
+            // x slab of plane z: rows (z * ny + y) of 2nb cells -> offset (y * 2nb + s) inside plane z's block
+            vcx[r] = lxr ? (unsigned)(y * nb2 + (x < nb ? x : x - (nx - nb2))) * 4u : OOB;
+            // y slab of plane z: [2nb][nx] per plane
+            vcy[r] = lyr ? (unsigned)((y < nb ? y : y - (ny - nb2)) * nx + x) * 4u : OOB;
+            // z slab: [2nb][ny][nx]; the plane is chosen per z
+            vcz[r] = in[r] ? (unsigned)(y * nx + x) * 4u : OOB;
+        }
+    }
 
     float gx = 1.0f, gyv[RY];
 #pragma unroll
@@ -114,36 +164,74 @@ __global__ __launch_bounds__(256) void k_step(const TileEnt* __restrict__ tiles,
     const int z0 = te.z0, z1 = te.z1;
     float q[RY][9];
 #pragma unroll
-    for (int r = 0; r < RY; ++r)
+    for (int m = 0; m < 8; ++m) {
+        const int z = z0 - 4 + m;
+        const bool zin = z >= 0 && z < nz;  // block-uniform
+        const __amdgpu_buffer_rsrc_t rp = plane_rsrc(pc, zin ? z : 0, plane);
 #pragma unroll
-        for (int m = 0; m < 8; ++m) q[r][m] = ld(pc, in[r], row[r], x, z0 - 4 + m);
+        for (int r = 0; r < RY; ++r) q[r][m] = zin ? bload(rp, voc[r]) : 0.0f;
+    }
 
     // prefetch stages: stage k holds the loads for plane z + k (queue head p^n(z+k+4),
     // p^{n-1}(z+k), (dt v)^2(z+k), the x / y halos of plane z+k)
     float nq[PD][RY], npp[PD][RY], nvd[PD][RY], nxh[PD][RY], nyh[PD][YH];
-#pragma unroll
-    for (int k = 0; k < PD; ++k) {
+    constexpr int RC = CPML ? RY : 1;
+    float ncr[PD][RC];  // sum of the CPML corrections of the cell (0 outside the layers)
+    auto fetch = [&](int k, int zn) {
+        const bool hin = zn + 4 < nz;
+        const __amdgpu_buffer_rsrc_t rh = plane_rsrc(pc, hin ? zn + 4 : 0, plane);
+        const __amdgpu_buffer_rsrc_t rc = plane_rsrc(pc, zn, plane);
+        const __amdgpu_buffer_rsrc_t rm = plane_rsrc(pn, zn, plane);
+        const __amdgpu_buffer_rsrc_t rv = plane_rsrc(vd, zn, plane);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            const bool ok = z0 + k < z1;
-            nq[k][r] = ld(pc, ok && in[r], row[r], x, z0 + k + 4);
-            npp[k][r] = ld(pn, ok && in[r], row[r], x, z0 + k);
-            nvd[k][r] = ld(vd, ok && in[r], row[r], x, z0 + k);
-            nxh[k][r] = ld(pc, ok && hx_lane && row[r] < ny, row[r], hcol, z0 + k);
+            nq[k][r] = hin ? bload(rh, voc[r]) : 0.0f;
+            npp[k][r] = bload(rm, voc[r]);
+            nvd[k][r] = bload(rv, voc[r]);
+            nxh[k][r] = bload(rc, vox[r]);
         }
 #pragma unroll
-        for (int h = 0; h < YH; ++h) nyh[k][h] = ld(pc, z0 + k < z1 && hy_ok[h], hrow[h], x, z0 + k);
-    }
+        for (int h = 0; h < YH; ++h) nyh[k][h] = bload(rc, voy[h]);
+        if (CPML) {
+#pragma unroll
+            for (int r = 0; r < RC; ++r) ncr[k][r] = 0.0f;
+            if (tile_layer) {
+                const long long pxs = (long long)ny * nb2, pys = (long long)nb2 * nx;
+                const __amdgpu_buffer_rsrc_t cx = __builtin_amdgcn_make_buffer_rsrc(
+                    (void*)(sd.corr[0] + zn * pxs), (short)0, (int)(pxs * 4), 0x00020000);
+                const __amdgpu_buffer_rsrc_t cy = __builtin_amdgcn_make_buffer_rsrc(
+                    (void*)(sd.corr[1] + zn * pys), (short)0, (int)(pys * 4), 0x00020000);
+                const bool zl = zn < nb || zn >= nz - nb;
+                const int zs = zn < nb ? zn : zn - (nz - nb2);
+                const __amdgpu_buffer_rsrc_t cz = __builtin_amdgcn_make_buffer_rsrc(
+                    (void*)(sd.corr[2] + (long long)(zl ? zs : 0) * plane), (short)0, (int)(plane * 4), 0x00020000);
+#pragma unroll
+                for (int r = 0; r < RC; ++r) {
+                    const float a = bload(cx, vcx[r]), b = bload(cy, vcy[r]);
+                    const float c = zl ? bload(cz, vcz[r]) : 0.0f;
+                    ncr[k][r] = (a + b) + c;
+                }
+            }
+        }
+    };
+#pragma unroll
+    for (int k = 0; k < PD; ++k)
+        if (z0 + k < z1) fetch(k, z0 + k);
 
     const int xx = 4 + tx;
+    gfloat* __restrict__ pn_g = (gfloat*)pn;
     for (int z = z0; z < z1; ++z) {
-        float cpp[RY], cvd[RY], cxh[RY], cyh[YH];
+        float cpp[RY], cvd[RY], cxh[RY], cyh[YH], ccr[RC];
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             q[r][8] = nq[0][r];
             cpp[r] = npp[0][r];
             cvd[r] = nvd[0][r];
             cxh[r] = nxh[0][r];
+        }
+        if (CPML) {
+#pragma unroll
+            for (int r = 0; r < RC; ++r) ccr[r] = ncr[0][r];
         }
 #pragma unroll
         for (int h = 0; h < YH; ++h) cyh[h] = nyh[0][h];
@@ -158,19 +246,12 @@ __global__ __launch_bounds__(256) void k_step(const TileEnt* __restrict__ tiles,
             }
 #pragma unroll
             for (int h = 0; h < YH; ++h) nyh[k][h] = nyh[k + 1][h];
-        }
-        if (z + PD < z1) {
-            const int zn = z + PD;
+            if (CPML) {
 #pragma unroll
-            for (int r = 0; r < RY; ++r) {
-                nq[PD - 1][r] = ld(pc, in[r], row[r], x, zn + 4);
-                npp[PD - 1][r] = ld(pn, in[r], row[r], x, zn);
-                nvd[PD - 1][r] = ld(vd, in[r], row[r], x, zn);
-                nxh[PD - 1][r] = ld(pc, hx_lane && row[r] < ny, row[r], hcol, zn);
+                for (int r = 0; r < RC; ++r) ncr[k][r] = ncr[k + 1][r];
             }
-#pragma unroll
-            for (int h = 0; h < YH; ++h) nyh[PD - 1][h] = ld(pc, hy_ok[h], hrow[h], x, zn);
         }
+        if (z + PD < z1) fetch(PD - 1, z + PD);
 
         float(*L)[LW] = lds[z & 1];
 #pragma unroll
@@ -199,8 +280,9 @@ __global__ __launch_bounds__(256) void k_step(const TileEnt* __restrict__ tiles,
                 lzv = fmaf(cf.cz[m - 1], (q[r][4 + m] - c) + (q[r][4 - m] - c), lzv);
             }
             float lap = (lx + ly) + lzv;
+            if (CPML) lap += ccr[CPML ? r : 0];
             if (in[r]) {
-                const long long o = zoff + (long long)row[r] * nx + x;
+                const long long o = zoff + (row[r] * nx + x);
                 if ((te.flags & TF_SRC) && aux.wrow) {
 #pragma unroll
                     for (int k = 0; k < MAX_INLINE_SRC; ++k)
@@ -213,9 +295,12 @@ __global__ __launch_bounds__(256) void k_step(const TileEnt* __restrict__ tiles,
                 } else {
                     out = c + fmaf(cvd[r], lap, c - cpp[r]);
                 }
-                pn[o] = out;
-                if (MODE == MODE_D2P) aux.d2p_out[o] = G * (cvd[r] * lap);
-                if (MODE == MODE_IMAGE) aux.grad[o] = fmaf(aux.neg_inv_dt2 / G * out, aux.d2p_in[o], aux.grad[o]);
+                pn_g[o] = out;
+                if (MODE == MODE_D2P) ((gfloat*)aux.d2p_out)[o] = G * (cvd[r] * lap);
+                if (MODE == MODE_IMAGE) {
+                    gfloat* gr = (gfloat*)aux.grad;
+                    gr[o] = fmaf(aux.neg_inv_dt2 / G * out, ((const gfloat*)aux.d2p_in)[o], gr[o]);
+                }
             }
         }
 #pragma unroll
@@ -230,12 +315,18 @@ static hipError_t launch_step_bc(int mode, dim3 grid, const TileEnt* tiles, int 
                                  const ShotDev* shots, int parity, const Coefs& cf, const StepAux& aux,
                                  hipStream_t s) {
     dim3 block(TX, 256 / TX);
-    if (mode == MODE_PLAIN)
+    if constexpr (BC == 2) {
+        // the CPML memory belongs to the forward field; there is no CPML adjoint
+        if (mode != MODE_PLAIN) return hipErrorInvalidValue;
         k_step<TX, RY, PD, BC, MODE_PLAIN><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
-    else if (mode == MODE_D2P)
-        k_step<TX, RY, PD, BC, MODE_D2P><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
-    else
-        k_step<TX, RY, PD, BC, MODE_IMAGE><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
+    } else {
+        if (mode == MODE_PLAIN)
+            k_step<TX, RY, PD, BC, MODE_PLAIN><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
+        else if (mode == MODE_D2P)
+            k_step<TX, RY, PD, BC, MODE_D2P><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
+        else
+            k_step<TX, RY, PD, BC, MODE_IMAGE><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
+    }
     return hipGetLastError();
 }
 
@@ -243,12 +334,14 @@ template <int TX, int RY>
 static hipError_t launch_step_t(int pd, int bc, int mode, dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd,
                                 const ShotDev* shots, int parity, const Coefs& cf, const StepAux& aux,
                                 hipStream_t s) {
-    // CPML: the stencil kernel is the plain one; launch_cpml adds the layer terms afterwards
+    // CPML: launch_cpml has written the layer corrections of this step; only the forward mode exists
     if (pd == 1) {
         if (bc == 1) return launch_step_bc<TX, RY, 1, 1>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+        if (bc == 2) return launch_step_bc<TX, RY, 1, 2>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
         return launch_step_bc<TX, RY, 1, 0>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
     }
     if (bc == 1) return launch_step_bc<TX, RY, 2, 1>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+    if (bc == 2) return launch_step_bc<TX, RY, 2, 2>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
     return launch_step_bc<TX, RY, 2, 0>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
 }
 
@@ -256,7 +349,7 @@ hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int 
                        int parity, const Coefs& cf, const StepAux& aux, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     const int per_xcd = (ntiles + 7) / 8;
-    dim3 grid(8 * per_xcd);
+    dim3 grid(8 * per_xcd + aux.gather_blocks);
     const TileShape& ts = kTiles[variant];
     if (ts.tx == 64) {
         if (ts.ry == 2) return launch_step_t<64, 2>(ts.pd, bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
@@ -270,82 +363,100 @@ hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int 
 
 // -------------------------------------------------------------------- CPML
 //
-// One kernel per axis, run after the stencil kernel of the step, one thread
-// per cell of the axis' two damping layers (nb cells at each end).  Phase 1:
+// One launch per step, before the stencil kernel, one thread per cell of the
+// damping layers of every axis (nb cells at each end).  Phase 1:
 //   psi <- b psi + a D1 p^n   (stored, and kept in LDS along the layer),
 // phase 2, after a barrier:
-//   zeta <- b zeta + a (D2 p^n + D1 psi);   p^{n+1} += (dt v)^2 (D1 psi + zeta),
-// with D1, D2 the order-8 first / second differences along the axis.  psi
-// is zero outside its layer and the two layers of an axis are at least 4
-// cells apart, so a block that holds a whole layer segment along the axis
-// has every psi it needs in LDS.  The axes run as three launches so a point
-// inside two or three layers is updated in a fixed order without atomics.
-// Lanes always run along x: for the x layers a block holds whole 2 nb-cell
-// rows (both ends), for the y / z layers 64 x-columns by the nb cells of
-// one end.
+//   zeta <- b zeta + a (D2 p^n + D1 psi)   (stored),   corr = D1 psi + zeta,
+// with D1, D2 the order-8 first / second differences along the axis.  The
+// stencil kernel of the same step adds corr_x + corr_y + corr_z to the
+// Laplacian of the cells inside the layers.  psi is zero outside its layer
+// and the two layers of an axis are at least 4 cells apart, so a block that
+// holds a whole layer segment along the axis has every psi it needs in LDS.
+// The axes write disjoint arrays, so they share one launch: the grid is the
+// x-layer blocks (whole 2 nb-cell rows, lanes along x), then the y-layer and
+// z-layer blocks (64 x-columns by the nb cells of one end).
 //
 // Slab arrays: x [nz][ny][2nb], y [nz][2nb][nx], z [2nb][ny][nx]; slab index
 // s < nb is grid index s, s >= nb is grid index n - 2nb + s.
 
-// x layers: thread e of the block -> row r = e / nb2, slab cell s = e % nb2
-__global__ __launch_bounds__(256) void k_cpml_x(const ShotDev* __restrict__ shots, int parity, Coefs cf,
-                                                int rows_per_block) {
-    extern __shared__ float lds_psi[];
-    const ShotDev& sd = shots[blockIdx.z];
+// Compact block enumeration over the shots: part x has, per shot, one block
+// per CPML_XG * rows_per_block rows; parts y and z have 2 ends x 64-column
+// blocks x the planes (nz for y, ny for z).  off[3 * (nshots + 1)] holds the
+// exclusive prefix sums of the block counts of each part.
+constexpr int CPML_XG = 8;  // row groups per x-layer block
+
+struct CpmlGrid {
+    const int* off;  // [3][nshots + 1]
+    int nshots;
+    int rows_per_block;
+};
+
+__device__ __forceinline__ int find_shot(const int* off, int nshots, int b) {
+    int lo = 0, hi = nshots - 1;  // largest s with off[s] <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ void cpml_x_block(const ShotDev& sd, int parity, const Coefs& cf, int blk, int rpb, float* lds) {
     const int nx = sd.nx, ny = sd.ny, nz = sd.nz, nb = sd.nb, nb2 = 2 * nb;
     const int e = threadIdx.x;
     const int r = e / nb2, sl = e - r * nb2;
-    const int row = blockIdx.x * rows_per_block + r;
-    const bool active = r < rows_per_block && row < ny * nz;
     const int x = sl < nb ? sl : nx - nb2 + sl;
-    const long long o = (long long)row * nx + x;  // row = z * ny + y
-    const long long si = (long long)row * nb2 + sl;
+    const int lo = sl < nb ? 0 : nb, hi = lo + nb;  // this end of the row (the other is >= 4 cells away)
     const float* __restrict__ p = sd.buf[parity];
-    float c = 0.0f, d1 = 0.0f, d2 = 0.0f;
-    if (active) {
-        c = p[o];
-#pragma unroll
-        for (int m = 1; m <= 4; ++m) {
-            const float fp = x + m < nx ? p[o + m] : 0.0f;
-            const float fm = x - m >= 0 ? p[o - m] : 0.0f;
-            d1 = fmaf(cf.bx[m - 1], fp - fm, d1);
-            d2 = fmaf(cf.cx[m - 1], (fp - c) + (fm - c), d2);
-        }
-        const float ps = fmaf(sd.prof[nx + x], sd.psi[0][si], sd.prof[x] * d1);
-        sd.psi[0][si] = ps;
-        lds_psi[e] = ps;
-    }
-    __syncthreads();
-    if (!active) return;
-    // neighbours along x inside the same end of the row (the other end is >= 4 cells away)
-    const int lo = sl < nb ? 0 : nb, hi = lo + nb;
-    float dpsi = 0.0f;
-#pragma unroll
-    for (int m = 1; m <= 4; ++m) {
-        const float vp = sl + m < hi ? lds_psi[e + m] : 0.0f;
-        const float vm = sl - m >= lo ? lds_psi[e - m] : 0.0f;
-        dpsi = fmaf(cf.bx[m - 1], vp - vm, dpsi);
-    }
+    float* __restrict__ ps = sd.psi[0];
     float* __restrict__ ze = sd.zeta[0];
-    const float zn = fmaf(sd.prof[nx + x], ze[si], sd.prof[x] * (d2 + dpsi));
-    ze[si] = zn;
-    float* __restrict__ pn = sd.buf[parity ^ 1];
-    pn[o] = fmaf(sd.vdt2[o], dpsi + zn, pn[o]);
+    float* __restrict__ co = sd.corr[0];
+    const float a = sd.prof[x], b = sd.prof[nx + x];
+    for (int g = 0; g < CPML_XG; ++g) {
+        const int row = (blk * CPML_XG + g) * rpb + r;
+        const bool active = r < rpb && row < ny * nz;
+        const long long o = (long long)row * nx + x;  // row = z * ny + y
+        const long long si = (long long)row * nb2 + sl;
+        float c = 0.0f, d1 = 0.0f, d2 = 0.0f;
+        if (active) {
+            c = p[o];
+#pragma unroll
+            for (int m = 1; m <= 4; ++m) {
+                const float fp = x + m < nx ? p[o + m] : 0.0f;
+                const float fm = x - m >= 0 ? p[o - m] : 0.0f;
+                d1 = fmaf(cf.bx[m - 1], fp - fm, d1);
+                d2 = fmaf(cf.cx[m - 1], (fp - c) + (fm - c), d2);
+            }
+            const float pv = fmaf(b, ps[si], a * d1);
+            ps[si] = pv;
+            lds[e] = pv;
+        }
+        __syncthreads();
+        if (active) {
+            float dpsi = 0.0f;
+#pragma unroll
+            for (int m = 1; m <= 4; ++m) {
+                const float vp = sl + m < hi ? lds[e + m] : 0.0f;
+                const float vm = sl - m >= lo ? lds[e - m] : 0.0f;
+                dpsi = fmaf(cf.bx[m - 1], vp - vm, dpsi);
+            }
+            const float zn = fmaf(b, ze[si], a * (d2 + dpsi));
+            ze[si] = zn;
+            co[si] = dpsi + zn;
+        }
+        __syncthreads();  // lds is rewritten by the next row group
+    }
 }
 
-// y (AX = 1) or z (AX = 2) layers: block (64, 4) = 64 x-columns, threads of
-// one column share the nb cells of one end (thread row ty takes cells ty,
-// ty + 4, ...); blockIdx.y is z (AX = 1) or y (AX = 2); blockIdx.z = 2 shot + end.
+// y (AX = 1) or z (AX = 2) layers of one end: block = 64 x-columns, thread row
+// ty takes cells ty, ty + 4, ... of the nb cells; w is z (AX = 1) or y (AX = 2).
 template <int AX>
-__global__ __launch_bounds__(256) void k_cpml_yz(const ShotDev* __restrict__ shots, int parity, Coefs cf) {
-    extern __shared__ float lds[];
-    const ShotDev& sd = shots[blockIdx.z >> 1];
-    const int side = blockIdx.z & 1;
+__device__ void cpml_yz_block(const ShotDev& sd, int parity, const Coefs& cf, int xblk, int w, int side, float* lds) {
     const int nx = sd.nx, ny = sd.ny, nz = sd.nz, nb = sd.nb, nb2 = 2 * nb;
-    const int w = blockIdx.y;
     if (w >= (AX == 2 ? ny : nz)) return;  // whole block
-    const int tx = threadIdx.x, ty = threadIdx.y;
-    const int x = blockIdx.x * 64 + tx;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int x = xblk * 64 + tx;
     const bool active = x < nx;
     const long long plane = (long long)nx * ny;
     const int n = AX == 2 ? nz : ny;
@@ -383,8 +494,7 @@ __global__ __launch_bounds__(256) void k_cpml_yz(const ShotDev* __restrict__ sho
     __syncthreads();
     if (!active) return;
     float* __restrict__ ze = sd.zeta[AX];
-    float* __restrict__ pn = sd.buf[parity ^ 1];
-    const float* __restrict__ vd = sd.vdt2;
+    float* __restrict__ co = sd.corr[AX];
     for (int s = ty; s < nb; s += 4) {
         const int z = s0 + s;
         float dpsi = 0.0f;
@@ -397,24 +507,66 @@ __global__ __launch_bounds__(256) void k_cpml_yz(const ShotDev* __restrict__ sho
         const long long si = sbase + (long long)(soff + s) * sstride;
         const float zn = fmaf(prof[n + z], ze[si], prof[z] * (d2l[s * 64 + tx] + dpsi));
         ze[si] = zn;
-        const long long o = base + z * stride;
-        pn[o] = fmaf(vd[o], dpsi + zn, pn[o]);
+        co[si] = dpsi + zn;
     }
 }
 
-hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, long long max_rows, int mx, int my, int mz,
+__global__ __launch_bounds__(256) void k_cpml(const ShotDev* __restrict__ shots, int parity, Coefs cf, CpmlGrid g) {
+    extern __shared__ float lds[];
+    const int S = g.nshots;
+    const int* ox = g.off;
+    const int* oy = g.off + (S + 1);
+    const int* oz = g.off + 2 * (S + 1);
+    int b = blockIdx.x;
+    if (b < ox[S]) {
+        const int s = find_shot(ox, S, b);
+        cpml_x_block(shots[s], parity, cf, b - ox[s], g.rows_per_block, lds);
+        return;
+    }
+    b -= ox[S];
+    const bool ypart = b < oy[S];
+    if (!ypart) b -= oy[S];
+    const int* o = ypart ? oy : oz;
+    const int s = find_shot(o, S, b);
+    const ShotDev& sd = shots[s];
+    const int local = b - o[s];
+    const int xb = (sd.nx + 63) / 64;
+    const int W = ypart ? sd.nz : sd.ny;
+    const int xblk = local % xb, rest = local / xb;
+    const int w = rest % W, side = rest / W;
+    if (ypart) cpml_yz_block<1>(sd, parity, cf, xblk, w, side, lds);
+    else cpml_yz_block<2>(sd, parity, cf, xblk, w, side, lds);
+}
+
+int cpml_rows_per_block(int nb) { return 256 / (2 * nb); }
+
+void cpml_block_table(const int* nx, const int* ny, const int* nz, int nshots, int nb, int* off) {
+    const int rpb = cpml_rows_per_block(nb);
+    int* ox = off;
+    int* oy = off + (nshots + 1);
+    int* oz = off + 2 * (nshots + 1);
+    ox[0] = oy[0] = oz[0] = 0;
+    for (int i = 0; i < nshots; ++i) {
+        const long long rows = (long long)ny[i] * nz[i];
+        const int xb = (nx[i] + 63) / 64;
+        ox[i + 1] = ox[i] + (int)((rows + (long long)rpb * CPML_XG - 1) / ((long long)rpb * CPML_XG));
+        oy[i + 1] = oy[i] + 2 * xb * nz[i];
+        oz[i + 1] = oz[i] + 2 * xb * ny[i];
+    }
+}
+
+hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, const int* block_off_dev, const int* block_off_host,
                        int parity, const Coefs& cf, hipStream_t s) {
     if (nshots <= 0) return hipSuccess;
-    const int rpb = 256 / (2 * nb);
-    k_cpml_x<<<dim3((unsigned)((max_rows + rpb - 1) / rpb), 1, nshots), 256, sizeof(float) * 256, s>>>(shots, parity,
-                                                                                                     cf, rpb);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const size_t sh = sizeof(float) * 2 * nb * 64;
-    k_cpml_yz<1><<<dim3((mx + 63) / 64, mz, 2 * nshots), dim3(64, 4), sh, s>>>(shots, parity, cf);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_cpml_yz<2><<<dim3((mx + 63) / 64, my, 2 * nshots), dim3(64, 4), sh, s>>>(shots, parity, cf);
+    CpmlGrid g;
+    g.off = block_off_dev;
+    g.nshots = nshots;
+    g.rows_per_block = cpml_rows_per_block(nb);
+    const int S = nshots;
+    const long long blocks =
+        (long long)block_off_host[S] + block_off_host[(S + 1) + S] + block_off_host[2 * (S + 1) + S];
+    const size_t sh = sizeof(float) * (size_t)(2 * nb * 64 > 256 ? 2 * nb * 64 : 256);
+    k_cpml<<<dim3((unsigned)blocks), 256, sh, s>>>(shots, parity, cf, g);
     return hipGetLastError();
 }
 
