@@ -99,6 +99,11 @@ typedef struct {
     int32_t snap;            /* mm_snap for the checkpoints */
     int32_t nsteps_max;      /* longest gradient / adjoint run the workspace must hold */
     int32_t tile;            /* stencil tile variant; 0 => library default, -1 => autotune at init */
+    int32_t group_kb;        /* batches: consecutive shots run in groups whose working set (fields,
+                                CPML memory) is at most this many KiB, each group's time steps back to
+                                back, so a group stays resident in the 256 MB last-level cache; a shot
+                                larger than the budget is a group of its own; 0 => 262144 (256 MiB),
+                                -1 => one group: all shots advance together */
 } mm_params;
 
 /* One shot of a batched context. */
@@ -192,8 +197,9 @@ mm_status mm_state_size(const mm_ctx* ctx, size_t* bytes);
 mm_status mm_get_state(mm_ctx* ctx, void* dst_dev);
 mm_status mm_set_state(mm_ctx* ctx, const void* src_dev, int32_t step);
 
-/* Time step, step counter and launch geometry actually in use. */
-mm_status mm_get_info(const mm_ctx* ctx, double* dt, int32_t* step, int32_t* tile);
+/* Time step, step counter, tile variant and number of shot groups in use.
+ * Any output pointer may be NULL. */
+mm_status mm_get_info(const mm_ctx* ctx, double* dt, int32_t* step, int32_t* tile, int32_t* ngroups);
 
 /* Pick the stencil tile variant by timing each candidate on this context
  * (state is zeroed afterwards; synchronises).  Results are cached per

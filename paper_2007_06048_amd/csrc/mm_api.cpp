@@ -35,24 +35,64 @@ struct ShotGeom {
     long long n() const { return (long long)nx * ny * nz; }
 };
 
-// Tiles of one variant over all shots, in shot-major, z-chunk, y, x order.
-void build_tiles(int variant, const std::vector<ShotGeom>& shots, std::vector<TileEnt>& out) {
+// Shot groups of a batch: consecutive shots whose working set (three
+// fields, CPML memory and corrections) fits the budget; every shot alone if
+// it is larger.  One group holds all shots when the budget is negative.
+std::vector<std::pair<int, int>> make_groups(const mm_params& p, const std::vector<ShotGeom>& shots) {
+    std::vector<std::pair<int, int>> g;
+    const double budget = p.group_kb < 0 ? 1e300 : (p.group_kb == 0 ? 262144.0 : (double)p.group_kb) * 1024.0;
+    int s0 = 0;
+    double acc = 0.0;
+    for (int s = 0; s < (int)shots.size(); ++s) {
+        const ShotGeom& q = shots[s];
+        double b = 12.0 * q.n();
+        if (p.bc == MM_BC_CPML) {
+            const double nb2 = 2.0 * p.nb;
+            b += 12.0 * ((double)q.nz * q.ny * nb2 + (double)q.nz * nb2 * q.nx + nb2 * q.ny * q.nx);
+        }
+        if (s > s0 && acc + b > budget) {
+            g.push_back({s0, s});
+            s0 = s;
+            acc = 0.0;
+        }
+        acc += b;
+    }
+    g.push_back({s0, (int)shots.size()});
+    return g;
+}
+
+// Tiles of one variant over shots [s0, s1), in shot-major, z-chunk, y, x
+// order; the z-chunk count aims at the variant's block target over the range.
+void build_tiles_range(int variant, const std::vector<ShotGeom>& shots, int s0, int s1, std::vector<TileEnt>& out) {
     const TileShape& ts = tile_variant(variant);
     const int TX = ts.tx, TY = tile_rows(variant);
     long long xy = 0;
-    for (const auto& g : shots) xy += (long long)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
+    for (int s = s0; s < s1; ++s) xy += (long long)((shots[s].nx + TX - 1) / TX) * ((shots[s].ny + TY - 1) / TY);
     long long nch = xy > 0 ? (ts.target + xy - 1) / xy : 1;
     if (nch < 1) nch = 1;
-    out.clear();
-    for (size_t s = 0; s < shots.size(); ++s) {
+    for (int s = s0; s < s1; ++s) {
         const auto& g = shots[s];
         int zlen = (int)((g.nz + nch - 1) / nch);
         if (zlen < 4) zlen = 4;
         for (int z0 = 0; z0 < g.nz; z0 += zlen) {
             const int z1 = std::min(g.nz, z0 + zlen);
             for (int y0 = 0; y0 < g.ny; y0 += TY)
-                for (int x0 = 0; x0 < g.nx; x0 += TX) out.push_back(TileEnt{(int)s, x0, y0, z0, z1, 0, 0, 0});
+                for (int x0 = 0; x0 < g.nx; x0 += TX) out.push_back(TileEnt{s, x0, y0, z0, z1, 0, 0, 0});
         }
+    }
+}
+
+// Tiles of every group, concatenated; tile_off[g] / count[g] locate group g.
+void build_tiles(int variant, const std::vector<ShotGeom>& shots, const std::vector<std::pair<int, int>>& groups,
+                 std::vector<TileEnt>& out, std::vector<int>* tile_off = nullptr, std::vector<int>* count = nullptr) {
+    out.clear();
+    if (tile_off) tile_off->clear();
+    if (count) count->clear();
+    for (const auto& gr : groups) {
+        const size_t before = out.size();
+        build_tiles_range(variant, shots, gr.first, gr.second, out);
+        if (tile_off) tile_off->push_back((int)before);
+        if (count) count->push_back((int)(out.size() - before));
     }
 }
 
@@ -87,8 +127,9 @@ void compute_layout(const mm_params& p, const std::vector<ShotGeom>& shots, int 
     L.shots_adj = take(L, sizeof(ShotDev) * S);
     int mt = 0;
     std::vector<TileEnt> tmp;
+    const auto groups = make_groups(p, shots);
     for (int v = 0; v < num_tile_variants(); ++v) {
-        build_tiles(v, shots, tmp);
+        build_tiles(v, shots, groups, tmp);
         mt = std::max(mt, (int)tmp.size());
     }
     L.max_tiles = mt;
@@ -130,7 +171,7 @@ void compute_layout(const mm_params& p, const std::vector<ShotGeom>& shots, int 
     L.rg_off = take(L, sizeof(long long) * nrec);
     L.sg_shot = take(L, sizeof(int) * nsrc);
     L.sg_off = take(L, sizeof(long long) * nsrc);
-    L.cpml_off = take(L, sizeof(int) * 3 * (S + 1));
+    L.cpml_off = take(L, sizeof(int) * 3 * (S + (int)groups.size()));
     if (L.grad) {
         const long long N = shots[0].n();
         const int K = p.ckpt_every;
@@ -215,8 +256,15 @@ struct mm_ctx {
     InjTab src_inj{}, rec_inj{};
     GatherTab rec_gather{}, src_gather{};
     int nsrc = 0, nrec = 0;
-    std::vector<int> cpml_off_h;  // CPML block table (host copy)
-    const int* cpml_off_d = nullptr;
+    struct Group {
+        int s0, s1;            // shots [s0, s1)
+        int tile_off, ntiles;  // slice of the tile table
+        int rec0, rec1;        // receivers (columns of a trace row)
+        int cell0, cell1;      // source cells of the injection table
+        std::vector<int> cpml_h;  // CPML block table of the group (host copy)
+        const int* cpml_d = nullptr;
+    };
+    std::vector<Group> groups;
     bool inline_src = false;
     std::vector<std::vector<long long>> src_cells;  // per shot, for tile flags
     Coefs cf{};
@@ -295,6 +343,7 @@ mm_status check_params(const mm_params* p, mm_ctx* c) {
     if (p->ckpt_every > 0 && p->nsteps_max < 1) return fail(c, MM_ERR_ARG, "nsteps_max must be >= 1");
     if (p->snap != MM_SNAP_FP32 && p->snap != MM_SNAP_BF16) return fail(c, MM_ERR_ARG, "unknown snapshot kind");
     if (p->tile < -1 || p->tile >= num_tile_variants()) return fail(c, MM_ERR_ARG, "unknown tile variant");
+    if (p->group_kb < -1) return fail(c, MM_ERR_ARG, "group_kb must be >= -1");
     return MM_OK;
 }
 
@@ -408,7 +457,14 @@ void tile_flags(mm_ctx* c, int v) {
 }
 
 mm_status set_variant(mm_ctx* c, int v) {
-    build_tiles(v, c->geom, c->tiles_h);
+    std::vector<std::pair<int, int>> gr;
+    for (const auto& g : c->groups) gr.push_back({g.s0, g.s1});
+    std::vector<int> off, cnt;
+    build_tiles(v, c->geom, gr, c->tiles_h, &off, &cnt);
+    for (size_t i = 0; i < c->groups.size(); ++i) {
+        c->groups[i].tile_off = off[i];
+        c->groups[i].ntiles = cnt[i];
+    }
     tile_flags(c, v);
     if ((int)c->tiles_h.size() > c->L.max_tiles) return fail(c, MM_ERR_WORKSPACE, "tile table overflow");
     MM_TRY(dev(c, hipStreamSynchronize(c->stream), "sync"));
@@ -456,13 +512,14 @@ mm_status zero_adjoint(mm_ctx* c, hipStream_t s) {
     return MM_OK;
 }
 
-// One leapfrog step of the forward (or adjoint) field set.
-mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, const StepAux& aux, hipStream_t s) {
+// One leapfrog step of the forward (or adjoint) field set, for the shots of
+// group g (nullptr: every shot in one launch; forward CPML needs a group).
+mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, const StepAux& aux, hipStream_t s,
+                       const mm_ctx::Group* g) {
     const bool timed = c->prof_stride > 0 && s == c->stream && (c->prof_count++ % c->prof_stride) == 0;
     if (c->cpml) {
-        if (shots != c->d_shots) return fail(c, MM_ERR_UNSUPPORTED, "CPML has no adjoint");
-        MM_TRY(dev(c, launch_cpml(shots, (int)c->geom.size(), c->p.nb, c->cpml_off_d, c->cpml_off_h.data(), parity,
-                                  c->cf, s),
+        if (shots != c->d_shots || !g) return fail(c, MM_ERR_UNSUPPORTED, "CPML has no adjoint");
+        MM_TRY(dev(c, launch_cpml(shots + g->s0, g->s1 - g->s0, c->p.nb, g->cpml_d, g->cpml_h.data(), parity, c->cf, s),
                    "cpml launch"));
     }
     if (timed) {
@@ -473,13 +530,32 @@ mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, co
         }
         MM_TRY(dev(c, hipEventRecord(c->prof_ev[c->prof_used], s), "event"));
     }
-    MM_TRY(dev(c, launch_step(c->variant, c->p.bc, mode, c->d_tiles, c->ntiles, shots, parity, c->cf, aux, s),
-               "stencil launch"));
+    const TileEnt* tiles = g ? c->d_tiles + g->tile_off : c->d_tiles;
+    const int nt = g ? g->ntiles : c->ntiles;
+    MM_TRY(dev(c, launch_step(c->variant, c->p.bc, mode, tiles, nt, shots, parity, c->cf, aux, s), "stencil launch"));
     if (timed) {
         MM_TRY(dev(c, hipEventRecord(c->prof_ev[c->prof_used + 1], s), "event"));
         c->prof_used += 2;
     }
     return MM_OK;
+}
+
+InjTab group_cells(const InjTab& t, const mm_ctx::Group& g) {
+    InjTab r = t;
+    r.cell_shot += g.cell0;
+    r.cell_off += g.cell0;
+    r.start += g.cell0;
+    r.cell_g += g.cell0;
+    r.ncell = g.cell1 - g.cell0;
+    return r;
+}
+
+GatherTab group_recs(const GatherTab& t, const mm_ctx::Group& g) {
+    GatherTab r = t;
+    r.shot += g.rec0;
+    r.off += g.rec0;
+    r.n = g.rec1 - g.rec0;
+    return r;
 }
 
 float* ckpt_field(mm_ctx* c, int seg, int which) {
@@ -522,37 +598,43 @@ mm_status restore_ckpt(mm_ctx* c, int seg, int parity, hipStream_t s) {
     return MM_OK;
 }
 
+// Forward steps: each group of shots runs all nsteps steps before the next
+// group starts (shots are independent, so this is the same result as
+// advancing every shot together).
 mm_status enqueue_forward(mm_ctx* c, int nsteps, const float* wav, float* traces, hipStream_t s) {
     const StepAux none{};
-    const bool ck = c->ckpt_active;
+    const bool ck = c->ckpt_active;  // single-shot contexts only: one group
     if (ck && c->nsrc > 0)
         MM_TRY(dev(c, hipMemcpyAsync(at<float>(c->ws, c->L.wav_store) + (size_t)c->step * c->nsrc, wav,
                                      sizeof(float) * (size_t)nsteps * c->nsrc, hipMemcpyDeviceToDevice, s),
                    "wavelet copy"));
-    for (int j = 0; j < nsteps; ++j) {
-        const int k = c->step + j;
-        const int parity = k & 1;
-        if (ck && k % c->p.ckpt_every == 0) MM_TRY(save_ckpt(c, k / c->p.ckpt_every, parity, s));
-        StepAux aux = none;
-        aux.src_scale = c->src_inj.scale;
-        aux.wrow = c->nsrc > 0 ? wav + (size_t)j * c->nsrc : nullptr;
-        if (j > 0 && traces && c->nrec > 0) {
-            // the stencil launch also records the previous step's receivers
-            aux.g_shot = c->rec_gather.shot;
-            aux.g_off = c->rec_gather.off;
-            aux.g_n = c->nrec;
-            aux.gather_blocks = ((c->nrec + 255) / 256 + 7) / 8 * 8;
-            aux.gather_out = traces + (size_t)(j - 1) * c->nrec;
+    for (const auto& g : c->groups) {
+        const GatherTab rg = group_recs(c->rec_gather, g);
+        const InjTab inj = group_cells(c->src_inj, g);
+        for (int j = 0; j < nsteps; ++j) {
+            const int k = c->step + j;
+            const int parity = k & 1;
+            if (ck && k % c->p.ckpt_every == 0) MM_TRY(save_ckpt(c, k / c->p.ckpt_every, parity, s));
+            StepAux aux = none;
+            aux.src_scale = c->src_inj.scale;
+            aux.wrow = c->nsrc > 0 ? wav + (size_t)j * c->nsrc : nullptr;
+            if (j > 0 && traces && rg.n > 0) {
+                // the stencil launch also records the previous step's receivers
+                aux.g_shot = rg.shot;
+                aux.g_off = rg.off;
+                aux.g_n = rg.n;
+                aux.gather_blocks = ((rg.n + 255) / 256 + 7) / 8 * 8;
+                aux.gather_out = traces + (size_t)(j - 1) * c->nrec + g.rec0;
+            }
+            MM_TRY(enqueue_step(c, c->d_shots, parity, MODE_PLAIN, aux, s, &g));
+            if (inj.ncell > 0 && !c->inline_src)
+                MM_TRY(dev(c, launch_inject(inj, c->d_shots, parity, aux.wrow, c->nsrc, MODE_PLAIN, none, s), "inject"));
         }
-        MM_TRY(enqueue_step(c, c->d_shots, parity, MODE_PLAIN, aux, s));
-        if (c->nsrc > 0 && !c->inline_src)
-            MM_TRY(dev(c, launch_inject(c->src_inj, c->d_shots, parity, aux.wrow, c->nsrc, MODE_PLAIN, none, s),
-                       "inject"));
+        if (nsteps > 0 && traces && rg.n > 0)
+            MM_TRY(dev(c, launch_gather(rg, c->d_shots, (c->step + nsteps - 1) & 1,
+                                        traces + (size_t)(nsteps - 1) * c->nrec + g.rec0, s),
+                       "record"));
     }
-    if (nsteps > 0 && traces && c->nrec > 0)
-        MM_TRY(dev(c, launch_gather(c->rec_gather, c->d_shots, (c->step + nsteps - 1) & 1,
-                                    traces + (size_t)(nsteps - 1) * c->nrec, s),
-                   "record"));
     return MM_OK;
 }
 
@@ -586,7 +668,7 @@ mm_status replay_segment(mm_ctx* c, int sg, hipStream_t s) {
         aux.d2p_out = seg + (size_t)(n - n0) * N;
         aux.src_scale = c->src_inj.scale;
         aux.wrow = c->nsrc > 0 ? wav + (size_t)n * c->nsrc : nullptr;
-        MM_TRY(enqueue_step(c, c->d_shots, n & 1, MODE_D2P, aux, s));
+        MM_TRY(enqueue_step(c, c->d_shots, n & 1, MODE_D2P, aux, s, &c->groups[0]));
         if (c->nsrc > 0 && !c->inline_src)
             MM_TRY(dev(c, launch_inject(c->src_inj, c->d_shots, n & 1, aux.wrow, c->nsrc, MODE_D2P, aux, s),
                        "inject"));
@@ -615,7 +697,7 @@ mm_status enqueue_adjoint(mm_ctx* c, int nsteps, const float* resid, float* adj_
             aux.neg_inv_dt2 = (float)(-1.0 / (c->dt * c->dt));
             mode = MODE_IMAGE;
         }
-        MM_TRY(enqueue_step(c, c->d_shots_adj, parity, mode, aux, s));
+        MM_TRY(enqueue_step(c, c->d_shots_adj, parity, mode, aux, s, nullptr));
         const int row = m - m0;
         if (c->nrec > 0)
             MM_TRY(dev(c, launch_inject(c->rec_inj, c->d_shots_adj, parity, resid + (size_t)row * c->nrec, c->nrec,
@@ -630,6 +712,7 @@ mm_status enqueue_adjoint(mm_ctx* c, int nsteps, const float* resid, float* adj_
 
 std::string tune_key(const mm_ctx* c) {
     std::string k = std::to_string(c->p.bc) + "/" + std::to_string(c->p.nb);
+    for (const auto& g : c->groups) k += "/" + std::to_string(g.s1 - g.s0);
     for (const auto& g : c->geom) k += ":" + std::to_string(g.nx) + "x" + std::to_string(g.ny) + "x" + std::to_string(g.nz);
     return k;
 }
@@ -912,17 +995,38 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
     up(L.rg_off, r_off.data(), sizeof(long long) * r_off.size());
     up(L.sg_shot, s_shot.data(), sizeof(int) * s_shot.size());
     up(L.sg_off, s_off.data(), sizeof(long long) * s_off.size());
-    if (c->cpml) {
-        std::vector<int> gx, gy, gz;
-        for (const auto& g : geom) {
-            gx.push_back(g.nx);
-            gy.push_back(g.ny);
-            gz.push_back(g.nz);
+    {
+        // shot groups: receivers, source cells and the CPML block table of each
+        int cpml_pos = 0;
+        std::vector<int> rec_start(nshots + 1, 0);
+        for (int i = 0; i < nshots; ++i) rec_start[i + 1] = rec_start[i] + shots[i].nrec;
+        for (const auto& gr : make_groups(*p, geom)) {
+            mm_ctx::Group g;
+            g.s0 = gr.first;
+            g.s1 = gr.second;
+            g.tile_off = g.ntiles = 0;
+            g.rec0 = rec_start[g.s0];
+            g.rec1 = rec_start[g.s1];
+            g.cell0 = (int)(std::lower_bound(cs.shot.begin(), cs.shot.end(), g.s0) - cs.shot.begin());
+            g.cell1 = (int)(std::lower_bound(cs.shot.begin(), cs.shot.end(), g.s1) - cs.shot.begin());
+            if (c->cpml) {
+                std::vector<int> gx, gy, gz;
+                for (int i = g.s0; i < g.s1; ++i) {
+                    gx.push_back(geom[i].nx);
+                    gy.push_back(geom[i].ny);
+                    gz.push_back(geom[i].nz);
+                }
+                const int ng = g.s1 - g.s0;
+                g.cpml_h.assign(3 * (ng + 1), 0);
+                cpml_block_table(gx.data(), gy.data(), gz.data(), ng, p->nb, g.cpml_h.data());
+                g.cpml_d = at<int>(c->ws, L.cpml_off) + cpml_pos;
+                cpml_pos += 3 * (ng + 1);
+            }
+            c->groups.push_back(std::move(g));
         }
-        c->cpml_off_h.assign(3 * (nshots + 1), 0);
-        cpml_block_table(gx.data(), gy.data(), gz.data(), nshots, p->nb, c->cpml_off_h.data());
-        c->cpml_off_d = at<int>(c->ws, L.cpml_off);
-        up(L.cpml_off, c->cpml_off_h.data(), sizeof(int) * c->cpml_off_h.size());
+        for (const auto& g : c->groups)
+            if (c->cpml) up(L.cpml_off + sizeof(int) * (g.cpml_d - at<int>(c->ws, L.cpml_off)), g.cpml_h.data(),
+                            sizeof(int) * g.cpml_h.size());
     }
     for (int i = 0; i < nshots && !st; ++i)
         st = dev(c, launch_vdt2(shots[i].vel, c->shots_h[i].vdt2, geom[i].n(), c->dt, s), "vdt2");
@@ -1125,11 +1229,12 @@ mm_status mm_set_state(mm_ctx* c, const void* src, int32_t step) {
     return state_copy(c, const_cast<char*>(reinterpret_cast<const char*>(src)), false);
 }
 
-mm_status mm_get_info(const mm_ctx* c, double* dt, int32_t* step, int32_t* tile) {
+mm_status mm_get_info(const mm_ctx* c, double* dt, int32_t* step, int32_t* tile, int32_t* ngroups) {
     if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
     if (dt) *dt = c->dt;
     if (step) *step = c->step;
     if (tile) *tile = c->variant;
+    if (ngroups) *ngroups = (int32_t)c->groups.size();
     return MM_OK;
 }
 
@@ -1156,9 +1261,12 @@ mm_status mm_autotune(mm_ctx* c, int32_t steps, int32_t* tile_out) {
     mm_status st = MM_OK;
     for (int v = 0; v < num_tile_variants() && !st; ++v) {
         st = set_variant(c, v);
-        for (int j = 0; j < 2 && !st; ++j) st = enqueue_step(c, c->d_shots, j & 1, MODE_PLAIN, none, c->stream);
+        for (const auto& g : c->groups)
+            for (int j = 0; j < 2 && !st; ++j) st = enqueue_step(c, c->d_shots, j & 1, MODE_PLAIN, none, c->stream, &g);
         if (!st) st = dev(c, hipEventRecord(e0, c->stream), "event");
-        for (int j = 0; j < steps && !st; ++j) st = enqueue_step(c, c->d_shots, j & 1, MODE_PLAIN, none, c->stream);
+        for (const auto& g : c->groups)
+            for (int j = 0; j < steps && !st; ++j)
+                st = enqueue_step(c, c->d_shots, j & 1, MODE_PLAIN, none, c->stream, &g);
         if (!st) st = dev(c, hipEventRecord(e1, c->stream), "event");
         if (!st) st = dev(c, hipEventSynchronize(e1), "event");
         float ms = 0.0f;

@@ -35,7 +35,7 @@ class Params(ctypes.Structure):
         ("bc", ctypes.c_int32), ("nb", ctypes.c_int32),
         ("sponge_sigma", ctypes.c_double), ("cpml_R", ctypes.c_double), ("cpml_f0", ctypes.c_double),
         ("ckpt_every", ctypes.c_int32), ("snap", ctypes.c_int32), ("nsteps_max", ctypes.c_int32),
-        ("tile", ctypes.c_int32),
+        ("tile", ctypes.c_int32), ("group_kb", ctypes.c_int32),
     ]
 
 
@@ -84,7 +84,7 @@ def load():
         "mm_state_size": (st, [vp, ctypes.POINTER(ctypes.c_size_t)]),
         "mm_get_state": (st, [vp, vp]),
         "mm_set_state": (st, [vp, vp, i32]),
-        "mm_get_info": (st, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "mm_get_info": (st, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "mm_autotune": (st, [vp, i32, ctypes.POINTER(i32)]),
         "mm_set_tile": (st, [vp, i32]),
         "mm_profile": (st, [vp, i32]),
@@ -230,9 +230,10 @@ class Context:
         _check(load().mm_set_state(self.h, _ptr(state), step), self.h)
 
     def info(self):
-        dt, step, tile = ctypes.c_double(), ctypes.c_int32(), ctypes.c_int32()
-        _check(load().mm_get_info(self.h, ctypes.byref(dt), ctypes.byref(step), ctypes.byref(tile)), self.h)
-        return {"dt": dt.value, "step": step.value, "tile": tile.value}
+        dt, step, tile, ng = ctypes.c_double(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(load().mm_get_info(self.h, ctypes.byref(dt), ctypes.byref(step), ctypes.byref(tile),
+                                  ctypes.byref(ng)), self.h)
+        return {"dt": dt.value, "step": step.value, "tile": tile.value, "groups": ng.value}
 
     @property
     def dt(self):

@@ -141,28 +141,54 @@ def test_state_save_restore_resume_bitwise():
     assert a.info()["step"] == b.info()["step"] == 60
 
 
-def test_batched_shots_equal_single_shot_runs():
-    """Three uneven sub-volumes in one context (one launch per kernel per step
-    for all shots) give bitwise the single-shot results."""
+def _batch_traces(p, vels, srcs, recs, ws, T, graph):
+    ctx = mm.Context(p, [(torch.from_numpy(v).to(DEV), s, r) for v, s, r in zip(vels, srcs, recs)])
+    wcat = torch.from_numpy(np.concatenate(ws, axis=1)).to(DEV)
+    tr = torch.zeros((T, ctx.nrec), dtype=torch.float32, device=DEV)
+    if graph:
+        for j in range(0, T, 10):
+            ctx.forward(10, wcat[j:j + 10], tr[j:j + 10], graph=True)
+    else:
+        ctx.forward(T, wcat, tr)
+    out = tr.cpu().numpy()
+    ng = ctx.info()["groups"]
+    ctx.close()
+    return out, ng
+
+
+@pytest.mark.parametrize("group_kb,graph,many_src", [(-1, False, False), (1, False, False), (1, True, False),
+                                                     (0, True, False), (1, False, True), (700, True, True)])
+def test_batched_shots_equal_single_shot_runs(group_kb, graph, many_src):
+    """Three uneven sub-volumes in one context give bitwise the single-shot
+    results, whether all shots advance together (group_kb -1 or the default
+    budget), one shot at a time (1 KiB budget) or two and one (700 KiB),
+    eagerly or from captured graphs.  With a shot of six sources every source
+    goes through the injection kernel; then the reference is the same batch
+    advanced as one group."""
     rng = np.random.default_rng(9)
     shapes = [(20, 26, 33), (31, 17, 22), (18, 18, 41)]
     p = params(shapes[0], bc=mm.BC_CPML, nb=4, f0=25.0)
     vels = [rng.uniform(1500, 3000, s).astype(np.float32) for s in shapes]
-    vmax = float(max(v.max() for v in vels))
-    p.vmax = vmax
+    p.vmax = float(max(v.max() for v in vels))
     T = 40
     srcs = [np.array([[s[2] // 2, s[1] // 2, s[0] // 2]], np.int32) for s in shapes]
+    if many_src:
+        srcs[1] = W.random_points(rng, 6, shapes[1], margin=1)
     recs = [W.plane(s[2], s[1], 3, inc=2) for s in shapes]
-    ws = [rng.standard_normal((T, 1)).astype(np.float32) for _ in shapes]
-    ctx = mm.Context(p, [(torch.from_numpy(v).to(DEV), s, r) for v, s, r in zip(vels, srcs, recs)])
-    wcat = torch.from_numpy(np.concatenate(ws, axis=1)).to(DEV)
-    tr = torch.zeros((T, ctx.nrec), dtype=torch.float32, device=DEV)
-    ctx.forward(T, wcat, tr)
-    trb = tr.cpu().numpy()
+    ws = [rng.standard_normal((T, len(s))).astype(np.float32) for s in srcs]
+    p.group_kb = group_kb
+    trb, ng = _batch_traces(p, vels, srcs, recs, ws, T, graph)
+    assert ng == {-1: 1, 0: 1, 1: 3, 700: 2}[group_kb]
+    if many_src:
+        p.group_kb = -1
+        ref, _ = _batch_traces(p, vels, srcs, recs, ws, T, False)
+        assert np.array_equal(trb, ref)
+        return
     off = 0
     for v, s, r, w in zip(vels, srcs, recs, ws):
         q = mm.default_params(**{k: getattr(p, k) for k, _ in mm.Params._fields_})
         q.nz, q.ny, q.nx = v.shape
+        q.group_kb = 0
         t1, _, _, _ = gpu_forward(q, v, s, r, w, T)
         assert np.array_equal(t1, trb[:, off:off + len(r)])
         off += len(r)
