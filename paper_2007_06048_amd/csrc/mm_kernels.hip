@@ -69,10 +69,13 @@ int tile_rows(int t) { return (256 / kTiles[t].tx) * kTiles[t].ry; }
 
 // ------------------------------------------------------------- stencil step
 
+// The small-tile, one-plane-prefetch shapes are held to 72 VGPRs (7 waves per
+// SIMD instead of 6 for the CPML and imaging instantiations); they fit
+// without spilling, the larger shapes would not.
 template <int TX, int RY, int PD, int BC, int MODE>
-__global__ __launch_bounds__(256) void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd,
-                                              const ShotDev* __restrict__ shots, int parity, Coefs cf,
-                                              StepAux aux) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PD == 1 && RY <= 2) ? 7 : 1)))
+void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const ShotDev* __restrict__ shots,
+            int parity, Coefs cf, StepAux aux) {
     constexpr int BY = 256 / TX;
     constexpr int TY = BY * RY;
     constexpr int LW = TX + 8;
@@ -136,7 +139,8 @@ __global__ __launch_bounds__(256) void k_step(const TileEnt* __restrict__ tiles,
     // CPML corrections (slab arrays; OOB where the cell is not in that axis' layer)
     const int nb = sd.nb, nb2 = 2 * nb;
     const bool tile_layer = CPML && (te.flags & (TF_LX | TF_LY | TF_LZ));
-    unsigned vcx[CPML ? RY : 1], vcy[CPML ? RY : 1], vcz[CPML ? RY : 1];
+    // (the z slab [2nb][ny][nx] is indexed like a plane of the grid: offset voc)
+    unsigned vcx[CPML ? RY : 1], vcy[CPML ? RY : 1];
     if (CPML) {
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
@@ -147,8 +151,6 @@ __global__ __launch_bounds__(256) void k_step(const TileEnt* __restrict__ tiles,
             vcx[r] = lxr ? (unsigned)(y * nb2 + (x < nb ? x : x - (nx - nb2))) * 4u : OOB;
             // y slab of plane z: [2nb][nx] per plane
             vcy[r] = lyr ? (unsigned)((y < nb ? y : y - (ny - nb2)) * nx + x) * 4u : OOB;
-            // z slab: [2nb][ny][nx]; the plane is chosen per z
-            vcz[r] = in[r] ? (unsigned)(y * nx + x) * 4u : OOB;
         }
     }
 
@@ -196,21 +198,33 @@ __global__ __launch_bounds__(256) void k_step(const TileEnt* __restrict__ tiles,
 #pragma unroll
             for (int r = 0; r < RC; ++r) ncr[k][r] = 0.0f;
             if (tile_layer) {
-                const long long pxs = (long long)ny * nb2, pys = (long long)nb2 * nx;
-                const __amdgpu_buffer_rsrc_t cx = __builtin_amdgcn_make_buffer_rsrc(
-                    (void*)(sd.corr[0] + zn * pxs), (short)0, (int)(pxs * 4), 0x00020000);
-                const __amdgpu_buffer_rsrc_t cy = __builtin_amdgcn_make_buffer_rsrc(
-                    (void*)(sd.corr[1] + zn * pys), (short)0, (int)(pys * 4), 0x00020000);
-                const bool zl = zn < nb || zn >= nz - nb;
-                const int zs = zn < nb ? zn : zn - (nz - nb2);
-                const __amdgpu_buffer_rsrc_t cz = __builtin_amdgcn_make_buffer_rsrc(
-                    (void*)(sd.corr[2] + (long long)(zl ? zs : 0) * plane), (short)0, (int)(plane * 4), 0x00020000);
+                // each axis only where the tile meets its layers (block-uniform tests)
+                float a[RC], b[RC], c[RC];
 #pragma unroll
-                for (int r = 0; r < RC; ++r) {
-                    const float a = bload(cx, vcx[r]), b = bload(cy, vcy[r]);
-                    const float c = zl ? bload(cz, vcz[r]) : 0.0f;
-                    ncr[k][r] = (a + b) + c;
+                for (int r = 0; r < RC; ++r) a[r] = b[r] = c[r] = 0.0f;
+                if (te.flags & TF_LX) {
+                    const long long pxs = (long long)ny * nb2;
+                    const __amdgpu_buffer_rsrc_t cx = __builtin_amdgcn_make_buffer_rsrc(
+                        (void*)(sd.corr[0] + zn * pxs), (short)0, (int)(pxs * 4), 0x00020000);
+#pragma unroll
+                    for (int r = 0; r < RC; ++r) a[r] = bload(cx, vcx[r]);
                 }
+                if (te.flags & TF_LY) {
+                    const long long pys = (long long)nb2 * nx;
+                    const __amdgpu_buffer_rsrc_t cy = __builtin_amdgcn_make_buffer_rsrc(
+                        (void*)(sd.corr[1] + zn * pys), (short)0, (int)(pys * 4), 0x00020000);
+#pragma unroll
+                    for (int r = 0; r < RC; ++r) b[r] = bload(cy, vcy[r]);
+                }
+                if ((te.flags & TF_LZ) && (zn < nb || zn >= nz - nb)) {
+                    const int zs = zn < nb ? zn : zn - (nz - nb2);
+                    const __amdgpu_buffer_rsrc_t cz = __builtin_amdgcn_make_buffer_rsrc(
+                        (void*)(sd.corr[2] + (long long)zs * plane), (short)0, (int)(plane * 4), 0x00020000);
+#pragma unroll
+                    for (int r = 0; r < RC; ++r) c[r] = bload(cz, voc[r]);
+                }
+#pragma unroll
+                for (int r = 0; r < RC; ++r) ncr[k][r] = (a[r] + b[r]) + c[r];
             }
         }
     };
