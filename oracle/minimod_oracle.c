@@ -47,9 +47,11 @@
  *
  * Adjoint and gradient (the inverse problem the paper names as motivation
  * in "Seismic Modeling"): the exact discrete adjoint of the forward
- * recursion for bc none / sponge / periodic, written in the scaled variable
- * eta = D G mu, which obeys the forward recursion run backward in time:
- *   eta^m = G (2 eta^{m+1} - G eta^{m+2} + D (Lap eta^{m+1} + R^T r^m)),
+ * recursion, written in the scaled variable eta = D G mu, which obeys the
+ * forward recursion run backward in time:
+ *   eta^m = G (2 eta^{m+1} - G eta^{m+2} + D (Lap eta^{m+1} + C + R^T r^m)),
+ * where C = 0 except for CPML, whose memory recursions are transposed too
+ * (adj_cpml below),
  * and the gradient with respect to squared slowness m = 1/v^2:
  *   dJ/dm = -(1/(dt^2 G)) sum_n eta^{n+1} (p^{n+1} - 2 G p^n + G^2 p^{n-1}).
  *
@@ -448,21 +450,109 @@ double orc_energy(const orc_grid* g, const double* vel, const double* pn, const 
 
 /* ------------------------------------------------------------- adjoint */
 
-static int adjoint_supported(const orc_grid* g) { return g->bc != BC_CPML; }
+/* Adjoint of the CPML recursions, for one backward step.  The forward step n
+ * is, per damped axis i with layer mask M_i (all operators with zero ghosts):
+ *   psi^{n+1}  = M (b psi^n + a D1 p^n),
+ *   zeta^{n+1} = M (b zeta^n + a (D2 p^n + D1 psi^{n+1})),
+ *   p^{n+1}    = 2 p^n - p^{n-1} + D (Lap p^n + M (D1 psi^{n+1} + zeta^{n+1}) + s^n).
+ * With mu the adjoint of p, eta = D mu, and Zb, Pb the adjoints of zeta and
+ * psi, transposing each line (D1^T = -D1, D2^T = D2 on the zero-ghost grid):
+ *   Zb^{m+1} = M (eta^{m+1} + b Zb^{m+2}),
+ *   Pb^{m+1} = M (-D1 (M eta^{m+1} + a Zb^{m+1}) + b Pb^{m+2}),
+ * and the adjoint of p^m gains  C = sum_i (-D1 (a Pb^{m+1}) + D2 (a Zb^{m+1})),
+ * which reaches 4 cells past the layer.  amem holds Pb_x,y,z then Zb_x,y,z
+ * (6 full-grid arrays): on entry the values of level m+2, on return m+1.
+ * C (full grid) is overwritten. */
+static void adj_cpml(const orc_grid* g, const double* e1, double* amem, double* C, double* u, double* az,
+                     double* ap) {
+    size_t N = npts(g);
+    memset(C, 0, N * sizeof(double));
+    for (int ax = 0; ax < 3; ++ax) {
+        double* Pb = amem + (size_t)ax * N;
+        double* Zb = amem + (size_t)(3 + ax) * N;
+        /* Zb <- M (eta + b Zb);  u = M eta + a Zb;  az = a Zb */
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < g->nz; ++k)
+            for (int j = 0; j < g->ny; ++j)
+                for (int i = 0; i < g->nx; ++i) {
+                    int kk = ax == 0 ? i : (ax == 1 ? j : k);
+                    double a, b;
+                    size_t id = lin(g, i, j, k);
+                    if (cpml_ab(g, ax, kk, &a, &b)) {
+                        Zb[id] = e1[id] + b * Zb[id];
+                        u[id] = e1[id] + a * Zb[id];
+                        az[id] = a * Zb[id];
+                    } else {
+                        Zb[id] = 0.0;
+                        u[id] = 0.0;
+                        az[id] = 0.0;
+                    }
+                }
+        /* Pb <- M (-D1 u + b Pb);  ap = a Pb */
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < g->nz; ++k)
+            for (int j = 0; j < g->ny; ++j)
+                for (int i = 0; i < g->nx; ++i) {
+                    int kk = ax == 0 ? i : (ax == 1 ? j : k);
+                    double a, b;
+                    size_t id = lin(g, i, j, k);
+                    if (cpml_ab(g, ax, kk, &a, &b)) {
+                        Pb[id] = -d1_axis(g, u, i, j, k, ax) + b * Pb[id];
+                        ap[id] = a * Pb[id];
+                    } else {
+                        Pb[id] = 0.0;
+                        ap[id] = 0.0;
+                    }
+                }
+        /* C += -D1 (a Pb) + D2 (a Zb), on every cell */
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < g->nz; ++k)
+            for (int j = 0; j < g->ny; ++j)
+                for (int i = 0; i < g->nx; ++i) {
+                    size_t id = lin(g, i, j, k);
+                    C[id] += -d1_axis(g, ap, i, j, k, ax) + d2_axis(g, az, i, j, k, ax);
+                }
+    }
+}
 
-/* One backward step of the scaled adjoint: eta^m from eta^{m+1}, eta^{m+2}
- * and the receiver residual r^m.  It is the forward step with the residual
- * as a source of unit scale at the receivers. */
+/* Work arrays of the CPML adjoint: memory (6N) and C, u, az, ap (N each). */
+typedef struct {
+    double* amem;
+    double *C, *u, *az, *ap;
+} adj_work;
+
+static int adj_work_alloc(const orc_grid* g, adj_work* w) {
+    memset(w, 0, sizeof(*w));
+    if (g->bc != BC_CPML) return ORC_OK;
+    size_t N = npts(g);
+    w->amem = alloc_d(6 * N);
+    w->C = alloc_d(N);
+    w->u = alloc_d(N);
+    w->az = alloc_d(N);
+    w->ap = alloc_d(N);
+    return (w->amem && w->C && w->u && w->az && w->ap) ? ORC_OK : ORC_ERR_MEM;
+}
+
+static void adj_work_free(adj_work* w) {
+    free(w->amem); free(w->C); free(w->u); free(w->az); free(w->ap);
+}
+
+/* One backward step of the scaled adjoint: eta^m from eta^{m+1}, eta^{m+2},
+ * the receiver residual r^m and (CPML) the adjoint memory.  Without CPML it
+ * is the forward step with the residual as a source of unit scale at the
+ * receivers. */
 static void adj_step(const orc_grid* g, const double* D, const double* e2, const double* e1, const double* rt,
-                     double* Lp, double* out) {
+                     double* Lp, adj_work* w, double* out) {
     orc_laplacian(g, e1, Lp);
+    if (g->bc == BC_CPML) adj_cpml(g, e1, w->amem, w->C, w->u, w->az, w->ap);
 #pragma omp parallel for schedule(static)
     for (int k = 0; k < g->nz; ++k)
         for (int j = 0; j < g->ny; ++j)
             for (int i = 0; i < g->nx; ++i) {
                 size_t id = lin(g, i, j, k);
                 double G = orc_sponge_G(g, i, j, k);
-                out[id] = G * (2.0 * e1[id] - G * e2[id] + D[id] * (Lp[id] + rt[id]));
+                double c = g->bc == BC_CPML ? w->C[id] : 0.0;
+                out[id] = G * (2.0 * e1[id] - G * e2[id] + D[id] * (Lp[id] + c + rt[id]));
             }
 }
 
@@ -475,13 +565,15 @@ int orc_adjoint(const orc_grid* g, const double* vel, int nrec, const int* rec, 
                 const int* src, double* adj_src) {
     if (g && g->wnx > 0) return ORC_ERR_ARG;
     if (check_grid(g) || T < 0) return ORC_ERR_ARG;
-    if (!adjoint_supported(g)) return ORC_ERR_UNSUPPORTED;
     if (check_pts(g, nsrc, src) || check_pts(g, nrec, rec)) return ORC_ERR_ARG;
     size_t N = npts(g);
     double *D = alloc_d(N), *Lp = alloc_d(N), *e2 = alloc_d(N), *e1 = alloc_d(N), *en = alloc_d(N),
            *rt = alloc_d(N);
-    if (!D || !Lp || !e2 || !e1 || !en || !rt) {
+    adj_work w;
+    int rc = adj_work_alloc(g, &w);
+    if (!D || !Lp || !e2 || !e1 || !en || !rt || rc) {
         free(D); free(Lp); free(e2); free(e1); free(en); free(rt);
+        adj_work_free(&w);
         return ORC_ERR_MEM;
     }
     fill_D(g, vel, D);
@@ -489,7 +581,7 @@ int orc_adjoint(const orc_grid* g, const double* vel, int nrec, const int* rec, 
         memset(rt, 0, N * sizeof(double));
         for (int r = 0; r < nrec; ++r)
             rt[lin(g, rec[3 * r], rec[3 * r + 1], rec[3 * r + 2])] += resid[(size_t)(m - 1) * nrec + r];
-        adj_step(g, D, e2, e1, rt, Lp, en);
+        adj_step(g, D, e2, e1, rt, Lp, &w, en);
         if (adj_src)
             for (int s = 0; s < nsrc; ++s)
                 adj_src[(size_t)(m - 1) * nsrc + s] = en[lin(g, src[3 * s], src[3 * s + 1], src[3 * s + 2])];
@@ -497,21 +589,25 @@ int orc_adjoint(const orc_grid* g, const double* vel, int nrec, const int* rec, 
         memcpy(e1, en, N * sizeof(double));
     }
     free(D); free(Lp); free(e2); free(e1); free(en); free(rt);
+    adj_work_free(&w);
     return ORC_OK;
 }
 
 /* FWI gradient of J = 1/2 sum_n sum_r (d^n_r - dobs^n_r)^2 with respect to
  * m = 1/v^2, for a forward run from zero state.  The forward wavefields are
  * regenerated segment by segment from FP64 checkpoints taken every ckpt
- * steps (ckpt >= T keeps one segment); FP64 replay is exact, so ckpt does
+ * steps (ckpt >= T keeps one segment); a checkpoint holds (p^{cK-1}, p^{cK})
+ * and, for CPML, the six memory arrays.  FP64 replay is exact, so ckpt does
  * not change the result.  traces [T][nrec] and loss may be NULL. */
 int orc_gradient(const orc_grid* g, const double* vel, int nsrc, const int* src, const double* wav, int nrec,
                  const int* rec, const double* d_obs, int T, int ckpt, double* grad, double* traces, double* loss) {
     if (g && g->wnx > 0) return ORC_ERR_ARG;
     if (check_grid(g) || T < 1 || ckpt < 1) return ORC_ERR_ARG;
-    if (!adjoint_supported(g)) return ORC_ERR_UNSUPPORTED;
     if (check_pts(g, nsrc, src) || check_pts(g, nrec, rec)) return ORC_ERR_ARG;
     size_t N = npts(g);
+    const int cpml = g->bc == BC_CPML;
+    size_t M6 = cpml ? 6 * N : 0;  /* CPML memory per state */
+    size_t CK = 2 * N + M6;         /* one checkpoint */
     int nseg = (T + ckpt - 1) / ckpt;
     double* D = alloc_d(N);
     double* Lp = alloc_d(N);
@@ -519,28 +615,34 @@ int orc_gradient(const orc_grid* g, const double* vel, int nsrc, const int* src,
     double* a = alloc_d(N);
     double* b = alloc_d(N);
     double* c = alloc_d(N);
-    double* ck = alloc_d((size_t)nseg * 2 * N);
+    double* mem = alloc_d(M6);
+    double* scratch = alloc_d(N);
+    double* ck = alloc_d((size_t)nseg * CK);
     double* tr = alloc_d((size_t)T * nrec);
     double* res = alloc_d((size_t)T * nrec);
     double* seg = alloc_d((size_t)(ckpt + 2) * N);
     double *e2 = alloc_d(N), *e1 = alloc_d(N), *en = alloc_d(N), *rt = alloc_d(N);
-    int rc = ORC_OK;
-    if (!D || !Lp || !S || !a || !b || !c || !ck || !tr || !res || !seg || !e2 || !e1 || !en || !rt) {
+    adj_work w;
+    int rc = adj_work_alloc(g, &w);
+    if (!D || !Lp || !S || !a || !b || !c || !mem || !scratch || !ck || !tr || !res || !seg || !e2 || !e1 || !en ||
+        !rt || rc) {
         rc = ORC_ERR_MEM;
         goto done;
     }
     fill_D(g, vel, D);
     double inv_vol = 1.0 / (g->hx * g->hy * g->hz);
-    /* forward: a = p^{n-1}, b = p^n, checkpoint (p^{cK-1}, p^{cK}) */
+    /* forward: a = p^{n-1}, b = p^n, checkpoint (p^{cK-1}, p^{cK}, memory) */
     for (int n = 0; n < T; ++n) {
         if (n % ckpt == 0) {
-            memcpy(ck + (size_t)(n / ckpt) * 2 * N, a, N * sizeof(double));
-            memcpy(ck + (size_t)(n / ckpt) * 2 * N + N, b, N * sizeof(double));
+            double* cp = ck + (size_t)(n / ckpt) * CK;
+            memcpy(cp, a, N * sizeof(double));
+            memcpy(cp + N, b, N * sizeof(double));
+            if (cpml) memcpy(cp + 2 * N, mem, M6 * sizeof(double));
         }
         memset(S, 0, N * sizeof(double));
         for (int s = 0; s < nsrc; ++s)
             S[lin(g, src[3 * s], src[3 * s + 1], src[3 * s + 2])] += wav[(size_t)n * nsrc + s] * inv_vol;
-        step(g, D, a, b, S, NULL, Lp, NULL, c);
+        step(g, D, a, b, S, cpml ? mem : NULL, Lp, scratch, c);
         for (int r = 0; r < nrec; ++r) tr[(size_t)n * nrec + r] = c[lin(g, rec[3 * r], rec[3 * r + 1], rec[3 * r + 2])];
         double* t = a; a = b; b = c; c = t;
     }
@@ -557,19 +659,21 @@ int orc_gradient(const orc_grid* g, const double* vel, int nsrc, const int* src,
         int n0 = cseg * ckpt;
         int n1 = n0 + ckpt < T ? n0 + ckpt : T;
         /* seg[t - n0 + 1] = p^t for t = n0-1 .. n1 */
-        memcpy(seg, ck + (size_t)cseg * 2 * N, 2 * N * sizeof(double));
+        const double* cp = ck + (size_t)cseg * CK;
+        memcpy(seg, cp, 2 * N * sizeof(double));
+        if (cpml) memcpy(mem, cp + 2 * N, M6 * sizeof(double));
         for (int n = n0; n < n1; ++n) {
             memset(S, 0, N * sizeof(double));
             for (int s = 0; s < nsrc; ++s)
                 S[lin(g, src[3 * s], src[3 * s + 1], src[3 * s + 2])] += wav[(size_t)n * nsrc + s] * inv_vol;
-            step(g, D, seg + (size_t)(n - n0) * N, seg + (size_t)(n - n0 + 1) * N, S, NULL, Lp, NULL,
+            step(g, D, seg + (size_t)(n - n0) * N, seg + (size_t)(n - n0 + 1) * N, S, cpml ? mem : NULL, Lp, scratch,
                  seg + (size_t)(n - n0 + 2) * N);
         }
         for (int m = n1; m >= n0 + 1; --m) {
             memset(rt, 0, N * sizeof(double));
             for (int r = 0; r < nrec; ++r)
                 rt[lin(g, rec[3 * r], rec[3 * r + 1], rec[3 * r + 2])] += res[(size_t)(m - 1) * nrec + r];
-            adj_step(g, D, e2, e1, rt, Lp, en);
+            adj_step(g, D, e2, e1, rt, Lp, &w, en);
             const double* pm = seg + (size_t)(m - n0 + 1) * N;
             const double* pm1 = seg + (size_t)(m - n0) * N;
             const double* pm2 = seg + (size_t)(m - n0 - 1) * N;
@@ -586,8 +690,9 @@ int orc_gradient(const orc_grid* g, const double* vel, int nsrc, const int* src,
         }
     }
 done:
-    free(D); free(Lp); free(S); free(a); free(b); free(c); free(ck); free(tr); free(res); free(seg);
-    free(e2); free(e1); free(en); free(rt);
+    free(D); free(Lp); free(S); free(a); free(b); free(c); free(mem); free(scratch); free(ck); free(tr); free(res);
+    free(seg); free(e2); free(e1); free(en); free(rt);
+    adj_work_free(&w);
     return rc;
 }
 

@@ -348,16 +348,18 @@ def test_cpml_mirror_and_axis_symmetry():
 
 
 # --------------------------------------------------------------------- P9
-@pytest.mark.parametrize("bc", [C.BC_NONE, C.BC_SPONGE, C.BC_PERIODIC])
+@pytest.mark.parametrize("bc", [C.BC_NONE, C.BC_SPONGE, C.BC_PERIODIC, C.BC_CPML])
 def test_p9_dot_product(bc):
     """<F s, r> = <s, F^T r>: the adjoint recursion is the exact transpose of
-    the forward map from source wavelets to traces."""
+    the forward map from source wavelets to traces (for CPML including the
+    transposed memory recursions; sources and receivers inside the layers
+    too)."""
     rng = np.random.default_rng(9)
     nx, ny, nz = 21, 19, 17
     h = (10.0, 9.0, 11.0)
     vel = rng.uniform(1500, 3500, (nz, ny, nx))
     dt = 0.6 * C.dt_stab(vel.max(), *h)
-    g = C.Grid(nx, ny, nz, *h, dt, bc=bc, nb=5, sigma=0.05)
+    g = C.Grid(nx, ny, nz, *h, dt, bc=bc, nb=5, sigma=0.05, f0=40.0, vmax=float(vel.max()))
     T = 50
     src = rng.integers(0, [nx, ny, nz], size=(4, 3))
     rec = rng.integers(0, [nx, ny, nz], size=(7, 3))
@@ -372,10 +374,12 @@ def test_p9_dot_product(bc):
 
 
 # --------------------------------------------------------------------- P10
-def test_p10_gradient_finite_differences():
+@pytest.mark.parametrize("bc", [C.BC_SPONGE, C.BC_CPML])
+def test_p10_gradient_finite_differences(bc):
     """Central finite differences of J(m) along a smooth direction match
     <grad, dm> with O(eps^2) convergence; J and the gradient are w.r.t.
-    squared slowness m = 1/v^2."""
+    squared slowness m = 1/v^2.  For CPML the damping profile is held fixed
+    (vmax is given), so J depends on m only through the wave equation."""
     rng = np.random.default_rng(10)
     nx, ny, nz = 20, 18, 16
     h = (10.0, 10.0, 10.0)
@@ -384,7 +388,10 @@ def test_p10_gradient_finite_differences():
     vel_true[6:11, 6:12, 7:13] += 250.0
     vel0 = (2000.0 + 40.0 * k) * np.ones((nz, ny, nx))
     dt = 0.5 * C.dt_stab(vel_true.max() * 1.05, *h)
-    g = C.Grid(nx, ny, nz, *h, dt, bc=C.BC_SPONGE, nb=4, sigma=0.08)
+    if bc == C.BC_SPONGE:
+        g = C.Grid(nx, ny, nz, *h, dt, bc=C.BC_SPONGE, nb=4, sigma=0.08)
+    else:
+        g = C.Grid(nx, ny, nz, *h, dt, bc=C.BC_CPML, nb=4, R=1e-3, f0=30.0, vmax=float(vel_true.max()))
     T = 70
     w = C.ricker(30.0, 0.05, dt, T)[:, None]
     src = [[10, 9, 3]]
@@ -429,15 +436,16 @@ def test_p10_gradient_zero_residual_and_linearity():
     assert np.abs(g2 - 2 * g1).max() <= 1e-12 * np.abs(g1).max()
 
 
-def test_gradient_checkpoint_interval_invariant():
+@pytest.mark.parametrize("bc", [C.BC_SPONGE, C.BC_CPML])
+def test_gradient_checkpoint_interval_invariant(bc):
     """FP64 replay from checkpoints is exact: the gradient does not depend on
-    the checkpoint interval (bitwise)."""
+    the checkpoint interval (bitwise); CPML checkpoints carry the memory."""
     rng = np.random.default_rng(13)
     nx, ny, nz = 14, 13, 12
     h = (10.0, 10.0, 10.0)
     vel = rng.uniform(1800, 2600, (nz, ny, nx))
     dt = 0.5 * C.dt_stab(vel.max(), *h)
-    g = C.Grid(nx, ny, nz, *h, dt, bc=C.BC_SPONGE, nb=3, sigma=0.06)
+    g = C.Grid(nx, ny, nz, *h, dt, bc=bc, nb=3, sigma=0.06, f0=25.0, vmax=float(vel.max()))
     T = 45
     w = rng.standard_normal((T, 1))
     src, rec = [[7, 6, 5]], [[3, 3, 2], [9, 8, 2]]
