@@ -91,12 +91,13 @@ typedef struct {
     double cfl;              /* fraction of the stability limit, (0, 1]; used when dt == 0 */
     double vmax;             /* velocity for dt and CPML d0; 0 => max of the model(s) */
     int32_t bc;              /* mm_bc */
-    int32_t nb;              /* damping layer width in cells (sponge, CPML); each axis needs n >= 2 nb + 1 */
+    int32_t nb;              /* damping layer width in cells; each axis needs n >= 2 nb + 1 (sponge),
+                                2 nb + 4 (CPML, nb <= 128), 2 nb + 8 (CPML with ckpt_every > 0, nb <= 64) */
     double sponge_sigma;     /* sponge strength (0.015 typical) */
     double cpml_R;           /* CPML nominal reflection coefficient, (0, 1]; 1 disables damping */
     double cpml_f0;          /* CPML frequency: alpha_max = pi * cpml_f0, >= 0 */
     int32_t ckpt_every;      /* gradient checkpoint interval in steps; 0 => no gradient support */
-    int32_t snap;            /* mm_snap for the checkpoints */
+    int32_t snap;            /* mm_snap for the checkpointed wavefields (CPML memory is kept in FP32) */
     int32_t nsteps_max;      /* longest gradient / adjoint run the workspace must hold */
     int32_t tile;            /* stencil tile variant; 0 => library default, -1 => autotune at init */
     int32_t group_kb;        /* batches: consecutive shots run in groups whose working set (fields,
@@ -158,10 +159,14 @@ mm_status mm_forward_steps(mm_ctx* ctx, int32_t nsteps, const float* wavelet, fl
  * pointers are unchanged).  Bitwise identical to mm_forward_steps. */
 mm_status mm_forward_steps_graph(mm_ctx* ctx, int32_t nsteps, const float* wavelet, float* traces);
 
-/* Adjoint (reverse-time) steps, bc none or sponge only (MM_ERR_UNSUPPORTED
- * for CPML).  The scaled adjoint eta obeys the forward recursion run
- * backward with the residual injected at the receivers with unit scale:
- *   eta^m = G (2 eta^{m+1} - G eta^{m+2} + D (Lap eta^{m+1} + R^T r^m)).
+/* Adjoint (reverse-time) steps: the exact transpose of the forward steps
+ * (the inverse problem motivating the method, section "Seismic Modeling").
+ * The scaled adjoint eta obeys the forward recursion run backward with the
+ * residual injected at the receivers with unit scale:
+ *   eta^m = G (2 eta^{m+1} - G eta^{m+2} + D (Lap eta^{m+1} + C + R^T r^m)),
+ * C = 0 except for CPML, where the transposed memory recursions
+ *   Zb <- eta^{m+1} + b Zb,  Pb <- b Pb - D1 (eta^{m+1} + a Zb)  (layer cells)
+ * give C = sum over damped axes of D2 (a Zb) - D1 (a Pb).
  * The first call starts from eta = 0 at time m = T (the forward step count)
  * and each call continues downward.  resid: device [nsteps][nrec_total] in
  * forward time order (row j pairs with the trace of p^{m0+j}, where

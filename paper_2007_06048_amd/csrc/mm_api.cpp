@@ -102,14 +102,16 @@ struct Layout {
     int max_tiles = 0;
     std::vector<size_t> buf0, buf1, vdt2, prof, ebuf0, ebuf1;
     std::vector<size_t> psi[3], zeta[3], corr[3];
+    std::vector<size_t> apsi[3], azeta[3], acorr[3];  // CPML adjoint memory and corrections
     size_t src_shot = 0, src_off = 0, src_start = 0, src_col = 0, src_g = 0;
     size_t rin_shot = 0, rin_off = 0, rin_start = 0, rin_col = 0, rin_g = 0;
     size_t rg_shot = 0, rg_off = 0, sg_shot = 0, sg_off = 0;
-    size_t cpml_off = 0;  // CPML block table
+    size_t cpml_off = 0;  // CPML block tables: per group (forward), then all shots (adjoint)
     bool adjoint = false, grad = false;
     int nseg = 0;
     size_t seg = 0, ckpt = 0, ckpt_scale = 0, wav_store = 0, tr_store = 0, resid_store = 0;
     size_t ckpt_field_bytes = 0;
+    size_t ckpt_mem = 0, ckpt_mem_bytes = 0;  // CPML memory of each checkpoint (FP32)
 };
 
 const int kPartials = 2048;  // reduction partial slots
@@ -148,11 +150,16 @@ void compute_layout(const mm_params& p, const std::vector<ShotGeom>& shots, int 
         L.prof.push_back(take(L, sizeof(float) * np));
         const size_t nb2 = 2 * (size_t)std::max(p.nb, 0);
         const size_t sl[3] = {(size_t)g.nz * g.ny * nb2, (size_t)g.nz * nb2 * g.nx, nb2 * g.ny * g.nx};
+        const size_t w2 = nb2 + 8;  // adjoint corrections: nb + 4 cells per end
+        const size_t wl[3] = {(size_t)g.nz * g.ny * w2, (size_t)g.nz * w2 * g.nx, w2 * g.ny * g.nx};
+        const bool c = p.bc == MM_BC_CPML, ca = c && L.adjoint;
         for (int a = 0; a < 3; ++a) {
-            const bool c = p.bc == MM_BC_CPML;
             L.psi[a].push_back(c ? take(L, sizeof(float) * sl[a]) : 0);
             L.zeta[a].push_back(c ? take(L, sizeof(float) * sl[a]) : 0);
             L.corr[a].push_back(c ? take(L, sizeof(float) * sl[a]) : 0);
+            L.apsi[a].push_back(ca ? take(L, sizeof(float) * sl[a]) : 0);
+            L.azeta[a].push_back(ca ? take(L, sizeof(float) * sl[a]) : 0);
+            L.acorr[a].push_back(ca ? take(L, sizeof(float) * wl[a]) : 0);
         }
         L.ebuf0.push_back(L.adjoint ? take(L, fb) : 0);
         L.ebuf1.push_back(L.adjoint ? take(L, fb) : 0);
@@ -171,7 +178,7 @@ void compute_layout(const mm_params& p, const std::vector<ShotGeom>& shots, int 
     L.rg_off = take(L, sizeof(long long) * nrec);
     L.sg_shot = take(L, sizeof(int) * nsrc);
     L.sg_off = take(L, sizeof(long long) * nsrc);
-    L.cpml_off = take(L, sizeof(int) * 3 * (S + (int)groups.size()));
+    L.cpml_off = take(L, sizeof(int) * 3 * (S + (int)groups.size() + S + 1));
     if (L.grad) {
         const long long N = shots[0].n();
         const int K = p.ckpt_every;
@@ -180,6 +187,12 @@ void compute_layout(const mm_params& p, const std::vector<ShotGeom>& shots, int 
         L.ckpt_field_bytes = align256((p.snap == MM_SNAP_BF16 ? 2 : 4) * (size_t)N);
         L.ckpt = take(L, (size_t)L.nseg * 2 * L.ckpt_field_bytes);
         L.ckpt_scale = take(L, sizeof(float) * 2 * L.nseg);
+        if (p.bc == MM_BC_CPML) {
+            const auto& g = shots[0];
+            const size_t nb2 = 2 * (size_t)p.nb;
+            L.ckpt_mem_bytes = 2 * sizeof(float) * ((size_t)g.nz * g.ny * nb2 + (size_t)g.nz * nb2 * g.nx + nb2 * g.ny * g.nx);
+            L.ckpt_mem = take(L, (size_t)L.nseg * L.ckpt_mem_bytes);
+        }
         L.wav_store = take(L, sizeof(float) * (size_t)p.nsteps_max * nsrc);
         L.tr_store = take(L, sizeof(float) * (size_t)p.nsteps_max * nrec);
         L.resid_store = take(L, sizeof(float) * (size_t)p.nsteps_max * nrec);
@@ -265,6 +278,8 @@ struct mm_ctx {
         const int* cpml_d = nullptr;
     };
     std::vector<Group> groups;
+    std::vector<int> cpml_adj_h;  // CPML block table of the adjoint (all shots, width nb + 4)
+    const int* cpml_adj_d = nullptr;
     bool inline_src = false;
     std::vector<std::vector<long long>> src_cells;  // per shot, for tile flags
     Coefs cf{};
@@ -330,6 +345,8 @@ mm_status check_params(const mm_params* p, mm_ctx* c) {
     if (p->bc != MM_BC_NONE && p->nb < 1) return fail(c, MM_ERR_ARG, "damping width nb must be >= 1");
     if (p->nb < 0 || p->nb > 4096) return fail(c, MM_ERR_ARG, "damping width nb out of range");
     if (p->bc == MM_BC_CPML && p->nb > 128) return fail(c, MM_ERR_ARG, "CPML width nb must be <= 128");
+    if (p->bc == MM_BC_CPML && p->ckpt_every > 0 && p->nb > 64)
+        return fail(c, MM_ERR_ARG, "CPML width nb must be <= 64 with adjoint storage (ckpt_every > 0)");
     if (p->bc == MM_BC_SPONGE && !(std::isfinite(p->sponge_sigma) && p->sponge_sigma >= 0.0))
         return fail(c, MM_ERR_ARG, "sponge_sigma must be finite and >= 0");
     if (p->bc == MM_BC_CPML && !(std::isfinite(p->cpml_R) && p->cpml_R > 0.0 && p->cpml_R <= 1.0))
@@ -355,11 +372,14 @@ mm_status check_shot(const mm_params* p, const mm_shot& s, int idx, bool need_ve
             snprintf(buf, sizeof buf, "shot %d: grid size %d out of range", idx, n[a]);
             return fail(c, MM_ERR_ARG, buf);
         }
-        // the two layers of an axis must not overlap; CPML also keeps them a stencil radius apart
-        const int nmin = p->bc == MM_BC_CPML ? 2 * p->nb + 4 : 2 * p->nb + 1;
+        // the two layers of an axis must not overlap; CPML also keeps them a stencil radius apart,
+        // and its adjoint (whose correction reaches 4 cells past each layer) two radii
+        const bool cadj = p->bc == MM_BC_CPML && p->ckpt_every > 0;
+        const int nmin = p->bc == MM_BC_CPML ? 2 * p->nb + (cadj ? 8 : 4) : 2 * p->nb + 1;
         if (p->bc != MM_BC_NONE && n[a] < nmin) {
             snprintf(buf, sizeof buf, "shot %d: grid size %d < %s = %d", idx, n[a],
-                     p->bc == MM_BC_CPML ? "2*nb+4" : "2*nb+1", nmin);
+                     p->bc == MM_BC_CPML ? (cadj ? "2*nb+8 (CPML with adjoint storage)" : "2*nb+4") : "2*nb+1",
+                     nmin);
             return fail(c, MM_ERR_ARG, buf);
         }
     }
@@ -435,8 +455,9 @@ mm_status upload(mm_ctx* c, void* dst, const void* src, size_t bytes) {
 }
 
 void tile_flags(mm_ctx* c, int v) {
-    const int TX = tile_variant(v).tx, TY = tile_rows(v), nb = c->p.nb;
-    auto meets = [nb](int a0, int a1, int n) { return a0 < nb || a1 > n - nb; };  // [a0, a1) vs the layers
+    // correction slabs: nb cells per end, nb + 4 when the adjoint shares the table
+    const int TX = tile_variant(v).tx, TY = tile_rows(v), nb = c->p.nb + (c->L.adjoint ? 4 : 0);
+    auto meets = [nb](int a0, int a1, int n) { return a0 < nb || a1 > n - nb; };  // [a0, a1) vs the slabs
     for (TileEnt& t : c->tiles_h) {
         const ShotGeom& g = c->geom[t.shot];
         const int x1 = std::min(g.nx, t.x0 + TX), y1 = std::min(g.ny, t.y0 + TY);
@@ -508,6 +529,15 @@ mm_status zero_adjoint(mm_ctx* c, hipStream_t s) {
         const long long n = c->geom[i].n();
         MM_TRY(dev(c, launch_fill(c->shots_adj_h[i].buf[0], n, 0.0f, s), "fill"));
         MM_TRY(dev(c, launch_fill(c->shots_adj_h[i].buf[1], n, 0.0f, s), "fill"));
+        if (c->cpml) {
+            const long long nb2 = 2LL * c->p.nb;
+            const auto& g = c->geom[i];
+            const long long sl[3] = {(long long)g.nz * g.ny * nb2, (long long)g.nz * nb2 * g.nx, nb2 * g.ny * g.nx};
+            for (int a = 0; a < 3; ++a) {
+                MM_TRY(dev(c, launch_fill(c->shots_adj_h[i].psi[a], sl[a], 0.0f, s), "fill"));
+                MM_TRY(dev(c, launch_fill(c->shots_adj_h[i].zeta[a], sl[a], 0.0f, s), "fill"));
+            }
+        }
     }
     return MM_OK;
 }
@@ -518,9 +548,16 @@ mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, co
                        const mm_ctx::Group* g) {
     const bool timed = c->prof_stride > 0 && s == c->stream && (c->prof_count++ % c->prof_stride) == 0;
     if (c->cpml) {
-        if (shots != c->d_shots || !g) return fail(c, MM_ERR_UNSUPPORTED, "CPML has no adjoint");
-        MM_TRY(dev(c, launch_cpml(shots + g->s0, g->s1 - g->s0, c->p.nb, g->cpml_d, g->cpml_h.data(), parity, c->cf, s),
-                   "cpml launch"));
+        if (shots == c->d_shots) {
+            if (!g) return fail(c, MM_ERR_STATE, "forward CPML step without a shot group");
+            MM_TRY(dev(c, launch_cpml(shots + g->s0, g->s1 - g->s0, c->p.nb, false, g->cpml_d, g->cpml_h.data(), parity,
+                                      c->cf, s),
+                       "cpml launch"));
+        } else {
+            MM_TRY(dev(c, launch_cpml(shots, (int)c->geom.size(), c->p.nb, true, c->cpml_adj_d, c->cpml_adj_h.data(),
+                                      parity, c->cf, s),
+                       "adjoint cpml launch"));
+        }
     }
     if (timed) {
         while (c->prof_ev.size() < c->prof_used + 2) {
@@ -562,6 +599,25 @@ float* ckpt_field(mm_ctx* c, int seg, int which) {
     return reinterpret_cast<float*>(c->ws + c->L.ckpt + ((size_t)seg * 2 + which) * c->L.ckpt_field_bytes);
 }
 
+// CPML memory (psi_x,y,z, zeta_x,y,z) of checkpoint seg, kept in FP32
+mm_status ckpt_memory(mm_ctx* c, int seg, bool save, hipStream_t s) {
+    if (!c->cpml) return MM_OK;
+    const auto& g = c->geom[0];
+    const size_t nb2 = 2 * (size_t)c->p.nb;
+    const size_t sl[3] = {(size_t)g.nz * g.ny * nb2, (size_t)g.nz * nb2 * g.nx, nb2 * g.ny * g.nx};
+    char* base = c->ws + c->L.ckpt_mem + (size_t)seg * c->L.ckpt_mem_bytes;
+    size_t o = 0;
+    for (int k = 0; k < 6; ++k) {
+        float* f = k < 3 ? c->shots_h[0].psi[k] : c->shots_h[0].zeta[k - 3];
+        const size_t bytes = sizeof(float) * sl[k % 3];
+        float* dst = save ? reinterpret_cast<float*>(base + o) : f;
+        const float* src = save ? f : reinterpret_cast<const float*>(base + o);
+        MM_TRY(dev(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s), "checkpoint copy"));
+        o += bytes;
+    }
+    return MM_OK;
+}
+
 mm_status save_ckpt(mm_ctx* c, int seg, int parity, hipStream_t s) {
     const long long N = c->geom[0].n();
     const ShotDev& sd = c->shots_h[0];
@@ -577,7 +633,7 @@ mm_status save_ckpt(mm_ctx* c, int seg, int parity, hipStream_t s) {
                        "pack"));
         }
     }
-    return MM_OK;
+    return ckpt_memory(c, seg, true, s);
 }
 
 mm_status restore_ckpt(mm_ctx* c, int seg, int parity, hipStream_t s) {
@@ -595,7 +651,7 @@ mm_status restore_ckpt(mm_ctx* c, int seg, int parity, hipStream_t s) {
                        "unpack"));
         }
     }
-    return MM_OK;
+    return ckpt_memory(c, seg, false, s);
 }
 
 // Forward steps: each group of shots runs all nsteps steps before the next
@@ -889,11 +945,19 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
         sd.ny = g.ny;
         sd.nz = g.nz;
         sd.nb = p->nb;
+        sd.cw = p->nb;
         c->shots_h.push_back(sd);
         ShotDev sa = sd;
         sa.nsrc_in = 0;
         sa.buf[0] = L.adjoint ? at<float>(c->ws, L.ebuf0[i]) : nullptr;
         sa.buf[1] = L.adjoint ? at<float>(c->ws, L.ebuf1[i]) : nullptr;
+        for (int a = 0; a < 3; ++a) {
+            const bool ca = c->cpml && L.adjoint;
+            sa.psi[a] = ca ? at<float>(c->ws, L.apsi[a][i]) : nullptr;
+            sa.zeta[a] = ca ? at<float>(c->ws, L.azeta[a][i]) : nullptr;
+            sa.corr[a] = ca ? at<float>(c->ws, L.acorr[a][i]) : nullptr;
+        }
+        sa.cw = p->nb + 4;
         c->shots_adj_h.push_back(sa);
         const int n[3] = {g.nx, g.ny, g.nz};
         std::vector<float>& pr = prof[i];
@@ -1027,6 +1091,18 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
         for (const auto& g : c->groups)
             if (c->cpml) up(L.cpml_off + sizeof(int) * (g.cpml_d - at<int>(c->ws, L.cpml_off)), g.cpml_h.data(),
                             sizeof(int) * g.cpml_h.size());
+        if (c->cpml && L.adjoint) {
+            std::vector<int> gx, gy, gz;
+            for (const auto& q : geom) {
+                gx.push_back(q.nx);
+                gy.push_back(q.ny);
+                gz.push_back(q.nz);
+            }
+            c->cpml_adj_h.assign(3 * (nshots + 1), 0);
+            cpml_block_table(gx.data(), gy.data(), gz.data(), nshots, p->nb + 4, c->cpml_adj_h.data());
+            c->cpml_adj_d = at<int>(c->ws, L.cpml_off) + cpml_pos;
+            up(L.cpml_off + sizeof(int) * cpml_pos, c->cpml_adj_h.data(), sizeof(int) * c->cpml_adj_h.size());
+        }
     }
     for (int i = 0; i < nshots && !st; ++i)
         st = dev(c, launch_vdt2(shots[i].vel, c->shots_h[i].vdt2, geom[i].n(), c->dt, s), "vdt2");
@@ -1109,7 +1185,6 @@ mm_status mm_forward_steps_graph(mm_ctx* c, int32_t nsteps, const float* wav, fl
 
 mm_status mm_adjoint_steps(mm_ctx* c, int32_t nsteps, const float* resid, float* adj_src, float* grad) {
     if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
-    if (c->cpml) return fail(c, MM_ERR_UNSUPPORTED, "the adjoint is implemented for bc none and sponge only");
     if (!c->L.adjoint) return fail(c, MM_ERR_STATE, "context was created with ckpt_every = 0 (no adjoint storage)");
     if (nsteps < 0) return fail(c, MM_ERR_ARG, "nsteps must be >= 0");
     if (c->nrec > 0 && nsteps > 0 && !resid) return fail(c, MM_ERR_ARG, "residual is NULL");
@@ -1149,7 +1224,6 @@ mm_status mm_reset(mm_ctx* c) {
 mm_status mm_gradient(mm_ctx* c, int32_t nsteps, const float* wav, const float* d_obs, float* grad, float* traces,
                       double* loss_host) {
     if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
-    if (c->cpml) return fail(c, MM_ERR_UNSUPPORTED, "the gradient is implemented for bc none and sponge only");
     if (!c->L.grad) return fail(c, MM_ERR_STATE, "gradients need a single-shot context with ckpt_every > 0");
     if (nsteps < 1 || nsteps > c->p.nsteps_max) return fail(c, MM_ERR_ARG, "nsteps must be in [1, nsteps_max]");
     if (!grad || (c->nrec > 0 && !d_obs) || (c->nsrc > 0 && !wav)) return fail(c, MM_ERR_ARG, "NULL operand");

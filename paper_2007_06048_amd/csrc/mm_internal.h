@@ -12,10 +12,11 @@ struct ShotDev {
     float* buf[2];        // wavefields: after k steps p^k is buf[k&1], p^{k-1} is buf[(k+1)&1]
     float* vdt2;          // (dt v)^2
     const float* prof;    // sponge: g_x[nx] g_y[ny] g_z[nz]; CPML: a_x b_x [nx], a_y b_y [ny], a_z b_z [nz]
-    float* psi[3];        // CPML memory, slab layouts (see minimod.h)
+    float* psi[3];        // CPML memory, slab layouts (see minimod.h); adjoint fields: its adjoint
     float* zeta[3];
-    float* corr[3];       // CPML correction D1 psi + zeta of the current step, slab layouts
+    float* corr[3];       // CPML correction added to the Laplacian this step, slabs of cw cells per end
     int nx, ny, nz, nb;
+    int cw;               // width of the correction slabs: nb (forward), nb + 4 (adjoint)
     int nsrc_in;          // sources added inside the stencil kernel (0..4)
     int src_col[4];       // their columns in the wavelet row
     long long src_off[4]; // their cells
@@ -99,12 +100,15 @@ hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int 
                        const ShotDev* shots, int parity, const Coefs& cf, const StepAux& aux,
                        hipStream_t s);
 // CPML memory update and corrections of every shot for this step, before the
-// stencil kernel (shared nb <= 128).  The block table (3 (nshots + 1) ints,
-// made by cpml_block_table) is passed both as the device copy the kernel
-// reads and as the host copy that sizes the grid.
-void cpml_block_table(const int* nx, const int* ny, const int* nz, int nshots, int nb, int* off);
-hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, const int* block_off_dev, const int* block_off_host,
-                       int parity, const Coefs& cf, hipStream_t s);
+// stencil kernel (shared nb <= 128).  With adjoint set, the same for the
+// adjoint fields: the transposed memory recursions and a correction reaching
+// 4 cells past the layer (nb <= 64).  The block table (3 (nshots + 1) ints,
+// made by cpml_block_table with width nb, or nb + 4 for the adjoint) is
+// passed both as the device copy the kernel reads and as the host copy that
+// sizes the grid.
+void cpml_block_table(const int* nx, const int* ny, const int* nz, int nshots, int width, int* off);
+hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, bool adjoint, const int* block_off_dev,
+                       const int* block_off_host, int parity, const Coefs& cf, hipStream_t s);
 hipError_t launch_inject(const InjTab& tab, const ShotDev* shots, int parity, const float* vals, int ncols,
                          int mode, const StepAux& aux, hipStream_t s);
 hipError_t launch_gather(const GatherTab& tab, const ShotDev* shots, int parity, float* out, hipStream_t s);

@@ -24,6 +24,8 @@
 //    halo exchange between neighbouring tiles inside one XCD's L2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "mm_internal.h"
 
 namespace mm {
@@ -70,10 +72,12 @@ int tile_rows(int t) { return (256 / kTiles[t].tx) * kTiles[t].ry; }
 // ------------------------------------------------------------- stencil step
 
 // The small-tile, one-plane-prefetch shapes are held to 72 VGPRs (7 waves per
-// SIMD instead of 6 for the CPML and imaging instantiations); they fit
-// without spilling, the larger shapes would not.
+// SIMD instead of 6 for the CPML forward and the imaging instantiations);
+// they fit without spilling, the larger shapes and the CPML replay / imaging
+// modes would not.
 template <int TX, int RY, int PD, int BC, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PD == 1 && RY <= 2) ? 7 : 1)))
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu((PD == 1 && RY <= 2 && !(BC == 2 && MODE != MODE_PLAIN)) ? 7 : 1)))
 void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const ShotDev* __restrict__ shots,
             int parity, Coefs cf, StepAux aux) {
     constexpr int BY = 256 / TX;
@@ -136,21 +140,21 @@ void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const Sh
     }
 #pragma unroll
     for (int h = 0; h < YH; ++h) voy[h] = hy_ok[h] ? (unsigned)(hrow[h] * nx + x) * 4u : OOB;
-    // CPML corrections (slab arrays; OOB where the cell is not in that axis' layer)
-    const int nb = sd.nb, nb2 = 2 * nb;
+    // CPML corrections (slab arrays of cw cells per end; OOB where the cell is not in them)
+    const int cw = sd.cw, cw2 = 2 * cw;
     const bool tile_layer = CPML && (te.flags & (TF_LX | TF_LY | TF_LZ));
-    // (the z slab [2nb][ny][nx] is indexed like a plane of the grid: offset voc)
+    // (the z slab [2cw][ny][nx] is indexed like a plane of the grid: offset voc)
     unsigned vcx[CPML ? RY : 1], vcy[CPML ? RY : 1];
     if (CPML) {
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             const int y = row[r];
-            const bool lxr = in[r] && (x < nb || x >= nx - nb);
-            const bool lyr = in[r] && (y < nb || y >= ny - nb);
-            // x slab of plane z: rows (z * ny + y) of 2nb cells -> offset (y * 2nb + s) inside plane z's block
-            vcx[r] = lxr ? (unsigned)(y * nb2 + (x < nb ? x : x - (nx - nb2))) * 4u : OOB;
-            // y slab of plane z: [2nb][nx] per plane
-            vcy[r] = lyr ? (unsigned)((y < nb ? y : y - (ny - nb2)) * nx + x) * 4u : OOB;
+            const bool lxr = in[r] && (x < cw || x >= nx - cw);
+            const bool lyr = in[r] && (y < cw || y >= ny - cw);
+            // x slab of plane z: rows (z * ny + y) of 2cw cells -> offset (y * 2cw + s) inside plane z's block
+            vcx[r] = lxr ? (unsigned)(y * cw2 + (x < cw ? x : x - (nx - cw2))) * 4u : OOB;
+            // y slab of plane z: [2cw][nx] per plane
+            vcy[r] = lyr ? (unsigned)((y < cw ? y : y - (ny - cw2)) * nx + x) * 4u : OOB;
         }
     }
 
@@ -203,21 +207,21 @@ void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const Sh
 #pragma unroll
                 for (int r = 0; r < RC; ++r) a[r] = b[r] = c[r] = 0.0f;
                 if (te.flags & TF_LX) {
-                    const long long pxs = (long long)ny * nb2;
+                    const long long pxs = (long long)ny * cw2;
                     const __amdgpu_buffer_rsrc_t cx = __builtin_amdgcn_make_buffer_rsrc(
                         (void*)(sd.corr[0] + zn * pxs), (short)0, (int)(pxs * 4), 0x00020000);
 #pragma unroll
                     for (int r = 0; r < RC; ++r) a[r] = bload(cx, vcx[r]);
                 }
                 if (te.flags & TF_LY) {
-                    const long long pys = (long long)nb2 * nx;
+                    const long long pys = (long long)cw2 * nx;
                     const __amdgpu_buffer_rsrc_t cy = __builtin_amdgcn_make_buffer_rsrc(
                         (void*)(sd.corr[1] + zn * pys), (short)0, (int)(pys * 4), 0x00020000);
 #pragma unroll
                     for (int r = 0; r < RC; ++r) b[r] = bload(cy, vcy[r]);
                 }
-                if ((te.flags & TF_LZ) && (zn < nb || zn >= nz - nb)) {
-                    const int zs = zn < nb ? zn : zn - (nz - nb2);
+                if ((te.flags & TF_LZ) && (zn < cw || zn >= nz - cw)) {
+                    const int zs = zn < cw ? zn : zn - (nz - cw2);
                     const __amdgpu_buffer_rsrc_t cz = __builtin_amdgcn_make_buffer_rsrc(
                         (void*)(sd.corr[2] + (long long)zs * plane), (short)0, (int)(plane * 4), 0x00020000);
 #pragma unroll
@@ -329,18 +333,12 @@ static hipError_t launch_step_bc(int mode, dim3 grid, const TileEnt* tiles, int 
                                  const ShotDev* shots, int parity, const Coefs& cf, const StepAux& aux,
                                  hipStream_t s) {
     dim3 block(TX, 256 / TX);
-    if constexpr (BC == 2) {
-        // the CPML memory belongs to the forward field; there is no CPML adjoint
-        if (mode != MODE_PLAIN) return hipErrorInvalidValue;
+    if (mode == MODE_PLAIN)
         k_step<TX, RY, PD, BC, MODE_PLAIN><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
-    } else {
-        if (mode == MODE_PLAIN)
-            k_step<TX, RY, PD, BC, MODE_PLAIN><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
-        else if (mode == MODE_D2P)
-            k_step<TX, RY, PD, BC, MODE_D2P><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
-        else
-            k_step<TX, RY, PD, BC, MODE_IMAGE><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
-    }
+    else if (mode == MODE_D2P)
+        k_step<TX, RY, PD, BC, MODE_D2P><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
+    else
+        k_step<TX, RY, PD, BC, MODE_IMAGE><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
     return hipGetLastError();
 }
 
@@ -348,7 +346,7 @@ template <int TX, int RY>
 static hipError_t launch_step_t(int pd, int bc, int mode, dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd,
                                 const ShotDev* shots, int parity, const Coefs& cf, const StepAux& aux,
                                 hipStream_t s) {
-    // CPML: launch_cpml has written the layer corrections of this step; only the forward mode exists
+    // CPML: launch_cpml has written the layer corrections of this step
     if (pd == 1) {
         if (bc == 1) return launch_step_bc<TX, RY, 1, 1>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
         if (bc == 2) return launch_step_bc<TX, RY, 1, 2>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
@@ -525,6 +523,160 @@ __device__ void cpml_yz_block(const ShotDev& sd, int parity, const Coefs& cf, in
     }
 }
 
+// Adjoint of the CPML step, run on the adjoint fields before their stencil
+// kernel.  With eta the current adjoint field and Zb, Pb the adjoints of
+// zeta and psi (held in the adjoint fields' psi / zeta slabs), transposing
+// the forward recursions gives, per damped axis,
+//   Zb <- eta + b Zb,   Pb <- b Pb - D1 (eta + a Zb)   (layer cells),
+// and the adjoint stencil adds  C = D2 (a Zb) - D1 (a Pb),  which reaches 4
+// cells past the layer, so its slabs (corr) are cw = nb + 4 cells per end.
+// D1 is antisymmetric and D2 symmetric on the zero-ghost grid, hence the
+// signs.  Three phases, each reading the previous one's values along the
+// axis from LDS (zero outside the layer).
+__device__ void cpml_x_block_adj(const ShotDev& sd, int parity, const Coefs& cf, int blk, int rpb, float* lds) {
+    const int nx = sd.nx, ny = sd.ny, nz = sd.nz, nb = sd.nb, nb2 = 2 * nb, W = sd.cw, W2 = 2 * W;
+    const int e = threadIdx.x;
+    const int r = e / W2, sl = e - r * W2;
+    const int x = sl < W ? sl : nx - W2 + sl;
+    const int lo = sl < W ? 0 : W, hi = lo + W;  // this end of the row
+    const bool layer = x < nb || x >= nx - nb;
+    const int ms = x < nb ? x : x - (nx - nb2);  // memory slab index (layer cells)
+    const float* __restrict__ eta = sd.buf[parity];
+    float* __restrict__ Pb = sd.psi[0];
+    float* __restrict__ Zb = sd.zeta[0];
+    float* __restrict__ co = sd.corr[0];
+    float* lu = lds;
+    float* laz = lds + 256;
+    float* lap = lds + 512;
+    const float a = sd.prof[x], b = sd.prof[nx + x];
+    for (int g = 0; g < CPML_XG; ++g) {
+        const int row = (blk * CPML_XG + g) * rpb + r;
+        const bool active = r < rpb && row < ny * nz;
+        const long long o = (long long)row * nx + x;  // row = z * ny + y
+        const long long mi = (long long)row * nb2 + ms;
+        float u = 0.0f, az = 0.0f;
+        if (active && layer) {
+            const float ev = eta[o];
+            const float zb = fmaf(b, Zb[mi], ev);
+            Zb[mi] = zb;
+            u = fmaf(a, zb, ev);
+            az = a * zb;
+        }
+        lu[e] = u;
+        laz[e] = az;
+        __syncthreads();
+        float ap = 0.0f;
+        if (active && layer) {
+            float d1u = 0.0f;
+#pragma unroll
+            for (int m = 1; m <= 4; ++m) {
+                const float vp = sl + m < hi ? lu[e + m] : 0.0f;
+                const float vm = sl - m >= lo ? lu[e - m] : 0.0f;
+                d1u = fmaf(cf.bx[m - 1], vp - vm, d1u);
+            }
+            const float pb = fmaf(b, Pb[mi], -d1u);
+            Pb[mi] = pb;
+            ap = a * pb;
+        }
+        lap[e] = ap;
+        __syncthreads();
+        if (active) {
+            float d1 = 0.0f, d2 = 0.0f;
+            const float c = laz[e];
+#pragma unroll
+            for (int m = 1; m <= 4; ++m) {
+                const bool okp = sl + m < hi, okm = sl - m >= lo;
+                const float pp = okp ? lap[e + m] : 0.0f, pm = okm ? lap[e - m] : 0.0f;
+                const float zp = okp ? laz[e + m] : 0.0f, zm = okm ? laz[e - m] : 0.0f;
+                d1 = fmaf(cf.bx[m - 1], pp - pm, d1);
+                d2 = fmaf(cf.cx[m - 1], (zp - c) + (zm - c), d2);
+            }
+            co[(long long)row * W2 + sl] = d2 - d1;
+        }
+        __syncthreads();  // lds is rewritten by the next row group
+    }
+}
+
+template <int AX>
+__device__ void cpml_yz_block_adj(const ShotDev& sd, int parity, const Coefs& cf, int xblk, int w, int side,
+                                  float* lds) {
+    const int nx = sd.nx, ny = sd.ny, nz = sd.nz, nb = sd.nb, nb2 = 2 * nb, W = sd.cw, W2 = 2 * W;
+    if (w >= (AX == 2 ? ny : nz)) return;  // whole block
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int x = xblk * 64 + tx;
+    const bool active = x < nx;
+    const long long plane = (long long)nx * ny;
+    const int n = AX == 2 ? nz : ny;
+    const long long stride = AX == 2 ? plane : (long long)nx;
+    const long long base = AX == 2 ? (long long)w * nx + x : (long long)w * plane + x;
+    // memory slabs (2 nb cells) and correction slabs (2 W cells) along the axis
+    const long long mbase = AX == 2 ? (long long)w * nx + x : (long long)w * nb2 * nx + x;
+    const long long cbase = AX == 2 ? (long long)w * nx + x : (long long)w * W2 * nx + x;
+    const long long sstride = AX == 2 ? plane : (long long)nx;
+    const float* prof = AX == 2 ? sd.prof + 2 * nx + 2 * ny : sd.prof + 2 * nx;
+    const int s0 = side ? n - W : 0;  // first grid index of this end's W cells
+    const int l0 = side ? W - nb : 0;  // its layer cells are [l0, l0 + nb)
+    float* lu = lds;                   // [W][64] each
+    float* laz = lds + W * 64;
+    float* lap = lds + 2 * W * 64;
+    const float* __restrict__ eta = sd.buf[parity];
+    float* __restrict__ Pb = sd.psi[AX];
+    float* __restrict__ Zb = sd.zeta[AX];
+    float* __restrict__ co = sd.corr[AX];
+    const float bc1 = AX == 2 ? cf.bz[0] : cf.by[0], bc2 = AX == 2 ? cf.bz[1] : cf.by[1];
+    const float bc3 = AX == 2 ? cf.bz[2] : cf.by[2], bc4 = AX == 2 ? cf.bz[3] : cf.by[3];
+    const float bcoef[4] = {bc1, bc2, bc3, bc4};
+    for (int s = ty; s < W; s += 4) {
+        float u = 0.0f, az = 0.0f;
+        if (active && s >= l0 && s < l0 + nb) {
+            const int z = s0 + s;
+            const long long mi = mbase + (long long)((side ? nb : 0) + s - l0) * sstride;
+            const float ev = eta[base + z * stride];
+            const float zb = fmaf(prof[n + z], Zb[mi], ev);
+            Zb[mi] = zb;
+            u = fmaf(prof[z], zb, ev);
+            az = prof[z] * zb;
+        }
+        lu[s * 64 + tx] = u;
+        laz[s * 64 + tx] = az;
+    }
+    __syncthreads();
+    for (int s = ty; s < W; s += 4) {
+        float ap = 0.0f;
+        if (active && s >= l0 && s < l0 + nb) {
+            const int z = s0 + s;
+            const long long mi = mbase + (long long)((side ? nb : 0) + s - l0) * sstride;
+            float d1u = 0.0f;
+#pragma unroll
+            for (int m = 1; m <= 4; ++m) {
+                const float vp = s + m < W ? lu[(s + m) * 64 + tx] : 0.0f;
+                const float vm = s - m >= 0 ? lu[(s - m) * 64 + tx] : 0.0f;
+                d1u = fmaf(bcoef[m - 1], vp - vm, d1u);
+            }
+            const float pb = fmaf(prof[n + z], Pb[mi], -d1u);
+            Pb[mi] = pb;
+            ap = prof[z] * pb;
+        }
+        lap[s * 64 + tx] = ap;
+    }
+    __syncthreads();
+    if (!active) return;
+    for (int s = ty; s < W; s += 4) {
+        float d1 = 0.0f, d2 = 0.0f;
+        const float c = laz[s * 64 + tx];
+#pragma unroll
+        for (int m = 1; m <= 4; ++m) {
+            const bool okp = s + m < W, okm = s - m >= 0;
+            const float pp = okp ? lap[(s + m) * 64 + tx] : 0.0f, pm = okm ? lap[(s - m) * 64 + tx] : 0.0f;
+            const float zp = okp ? laz[(s + m) * 64 + tx] : 0.0f, zm = okm ? laz[(s - m) * 64 + tx] : 0.0f;
+            d1 = fmaf(bcoef[m - 1], pp - pm, d1);
+            d2 = fmaf(AX == 2 ? cf.cz[m - 1] : cf.cy[m - 1], (zp - c) + (zm - c), d2);
+        }
+        co[cbase + (long long)((side ? W : 0) + s) * sstride] = d2 - d1;
+    }
+}
+
+template <bool ADJ>
 __global__ __launch_bounds__(256) void k_cpml(const ShotDev* __restrict__ shots, int parity, Coefs cf, CpmlGrid g) {
     extern __shared__ float lds[];
     const int S = g.nshots;
@@ -534,7 +686,8 @@ __global__ __launch_bounds__(256) void k_cpml(const ShotDev* __restrict__ shots,
     int b = blockIdx.x;
     if (b < ox[S]) {
         const int s = find_shot(ox, S, b);
-        cpml_x_block(shots[s], parity, cf, b - ox[s], g.rows_per_block, lds);
+        if (ADJ) cpml_x_block_adj(shots[s], parity, cf, b - ox[s], g.rows_per_block, lds);
+        else cpml_x_block(shots[s], parity, cf, b - ox[s], g.rows_per_block, lds);
         return;
     }
     b -= ox[S];
@@ -548,14 +701,19 @@ __global__ __launch_bounds__(256) void k_cpml(const ShotDev* __restrict__ shots,
     const int W = ypart ? sd.nz : sd.ny;
     const int xblk = local % xb, rest = local / xb;
     const int w = rest % W, side = rest / W;
-    if (ypart) cpml_yz_block<1>(sd, parity, cf, xblk, w, side, lds);
-    else cpml_yz_block<2>(sd, parity, cf, xblk, w, side, lds);
+    if (ADJ) {
+        if (ypart) cpml_yz_block_adj<1>(sd, parity, cf, xblk, w, side, lds);
+        else cpml_yz_block_adj<2>(sd, parity, cf, xblk, w, side, lds);
+    } else {
+        if (ypart) cpml_yz_block<1>(sd, parity, cf, xblk, w, side, lds);
+        else cpml_yz_block<2>(sd, parity, cf, xblk, w, side, lds);
+    }
 }
 
-int cpml_rows_per_block(int nb) { return 256 / (2 * nb); }
+int cpml_rows_per_block(int width) { return 256 / (2 * width); }
 
-void cpml_block_table(const int* nx, const int* ny, const int* nz, int nshots, int nb, int* off) {
-    const int rpb = cpml_rows_per_block(nb);
+void cpml_block_table(const int* nx, const int* ny, const int* nz, int nshots, int width, int* off) {
+    const int rpb = cpml_rows_per_block(width);
     int* ox = off;
     int* oy = off + (nshots + 1);
     int* oz = off + 2 * (nshots + 1);
@@ -569,18 +727,24 @@ void cpml_block_table(const int* nx, const int* ny, const int* nz, int nshots, i
     }
 }
 
-hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, const int* block_off_dev, const int* block_off_host,
-                       int parity, const Coefs& cf, hipStream_t s) {
+hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, bool adjoint, const int* block_off_dev,
+                       const int* block_off_host, int parity, const Coefs& cf, hipStream_t s) {
     if (nshots <= 0) return hipSuccess;
+    if (nb < 1 || nb > (adjoint ? 64 : 128)) return hipErrorInvalidValue;
+    const int width = adjoint ? nb + 4 : nb;
     CpmlGrid g;
     g.off = block_off_dev;
     g.nshots = nshots;
-    g.rows_per_block = cpml_rows_per_block(nb);
+    g.rows_per_block = cpml_rows_per_block(width);
     const int S = nshots;
     const long long blocks =
         (long long)block_off_host[S] + block_off_host[(S + 1) + S] + block_off_host[2 * (S + 1) + S];
-    const size_t sh = sizeof(float) * (size_t)(2 * nb * 64 > 256 ? 2 * nb * 64 : 256);
-    k_cpml<<<dim3((unsigned)blocks), 256, sh, s>>>(shots, parity, cf, g);
+    // forward: psi and D2 p of one end [nb][64] (x part: 256); adjoint: three [W][64] arrays (x part: 3 x 256)
+    const size_t fl = adjoint ? 3 * (size_t)std::max(width * 64, 256) : (size_t)std::max(2 * nb * 64, 256);
+    if (adjoint)
+        k_cpml<true><<<dim3((unsigned)blocks), 256, sizeof(float) * fl, s>>>(shots, parity, cf, g);
+    else
+        k_cpml<false><<<dim3((unsigned)blocks), 256, sizeof(float) * fl, s>>>(shots, parity, cf, g);
     return hipGetLastError();
 }
 

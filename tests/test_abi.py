@@ -101,6 +101,16 @@ def test_workspace_size_and_argument_checks():
     st, _ = _ws(p3, [s])
     assert st == mm.MM_ERR_ARG
     assert "2*nb+4" in mm.load().mm_last_error(None).decode()
+    # with adjoint storage the CPML adjoint needs two stencil radii between the layers, and nb <= 64
+    p4 = mm.default_params(bc=mm.BC_CPML, nb=17, ckpt_every=8, nsteps_max=10)
+    st, _ = _ws(p4, [s])
+    assert st == mm.MM_ERR_ARG and "2*nb+8" in mm.load().mm_last_error(None).decode()
+    p4.nb = 16
+    assert _ws(p4, [s])[0] == mm.MM_OK
+    big, keep5 = _shot(200, 200, 200, [[5, 5, 5]], [[1, 2, 3]])
+    p4.nb = 65
+    st, _ = _ws(p4, [big])
+    assert st == mm.MM_ERR_ARG and "64" in mm.load().mm_last_error(None).decode()
     # receiver outside the grid
     bad, keep2 = _shot(64, 48, 40, [[5, 5, 5]], [[64, 0, 0]])
     st, _ = _ws(p, [bad])

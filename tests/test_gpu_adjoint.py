@@ -1,6 +1,6 @@
 """GPU adjoint and FWI gradient: dot-product test, parity with the FP64
-oracle's adjoint and gradient (FP32 and BF16 checkpoints), the autograd
-binding, and chunked adjoint runs."""
+oracle's adjoint and gradient (FP32 and BF16 checkpoints; sponge, CPML and
+no boundary), the autograd binding, chunked and batched adjoint runs."""
 import numpy as np
 import pytest
 import torch
@@ -25,7 +25,8 @@ def _case(bc, nsrc, seed, shape=(26, 30, 34), T=80):
     return rng, vel, src, rec, p, T
 
 
-@pytest.mark.parametrize("bc,nsrc", [(mm.BC_SPONGE, 1), (mm.BC_SPONGE, 6), (mm.BC_NONE, 3)])
+@pytest.mark.parametrize("bc,nsrc", [(mm.BC_SPONGE, 1), (mm.BC_SPONGE, 6), (mm.BC_NONE, 3), (mm.BC_CPML, 1),
+                                     (mm.BC_CPML, 6)])
 def test_dot_product_and_adjoint_parity(bc, nsrc):
     """<F s, r> = <s, F^T r> on the GPU (FP32), and the GPU adjoint seismograms
     at the sources match the FP64 oracle's adjoint."""
@@ -50,8 +51,9 @@ def test_dot_product_and_adjoint_parity(bc, nsrc):
     assert rel(adj.cpu().numpy(), ref) <= 1e-5, rel(adj.cpu().numpy(), ref)
 
 
-def test_adjoint_in_chunks_is_bitwise_one_call():
-    rng, vel, src, rec, p, T = _case(mm.BC_SPONGE, 2, seed=21)
+@pytest.mark.parametrize("bc", [mm.BC_SPONGE, mm.BC_CPML])
+def test_adjoint_in_chunks_is_bitwise_one_call(bc):
+    rng, vel, src, rec, p, T = _case(bc, 2, seed=21)
     p.ckpt_every = 16
     p.nsteps_max = T
     w = torch.from_numpy(rng.standard_normal((T, 2)).astype(np.float32)).to(DEV)
@@ -70,10 +72,12 @@ def test_adjoint_in_chunks_is_bitwise_one_call():
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
-@pytest.mark.parametrize("snap,tol", [(mm.SNAP_FP32, 1e-4), (mm.SNAP_BF16, 2e-2)])
-def test_gradient_matches_oracle(snap, tol):
+@pytest.mark.parametrize("bc,snap,tol", [(mm.BC_SPONGE, mm.SNAP_FP32, 1e-4), (mm.BC_SPONGE, mm.SNAP_BF16, 2e-2),
+                                          (mm.BC_CPML, mm.SNAP_FP32, 1e-4), (mm.BC_CPML, mm.SNAP_BF16, 2e-2)])
+def test_gradient_matches_oracle(bc, snap, tol):
     """FWI gradient w.r.t. m = 1/v^2 with checkpoints every 16 steps (a partial
-    last segment included) against the oracle's exact FP64 gradient."""
+    last segment included) against the oracle's exact FP64 gradient; CPML
+    checkpoints carry the layer memory."""
     rng = np.random.default_rng(30)
     shape = (28, 32, 36)
     nz, ny, nx = shape
@@ -81,7 +85,7 @@ def test_gradient_matches_oracle(snap, tol):
     v0 = ((2000.0 + 30.0 * k) * np.ones(shape)).astype(np.float32)
     vt = v0.copy()
     vt[6:16, 10:22, 12:26] += 400.0
-    p = params(shape, bc=mm.BC_SPONGE, nb=6, sigma=0.05)
+    p = params(shape, bc=bc, nb=6, sigma=0.05, f0=25.0)
     p.vmax = float(vt.max())
     p.ckpt_every = 16
     p.snap = snap
@@ -104,7 +108,7 @@ def test_gradient_matches_oracle(snap, tol):
     gg = grad.cpu().numpy()
     e = rel(gg, ref)
     cos = float(np.sum(gg * ref) / (np.linalg.norm(gg) * np.linalg.norm(ref)))
-    print(f"snap={snap}: gradient rel L2 {e:.2e}, cosine {cos:.8f}, J {J:.6e} vs {ref_J:.6e}")
+    print(f"bc={bc} snap={snap}: gradient rel L2 {e:.2e}, cosine {cos:.8f}, J {J:.6e} vs {ref_J:.6e}")
     assert rel(tr.cpu().numpy(), ref_tr) <= 1e-5
     assert abs(J - ref_J) <= 1e-4 * ref_J
     assert e <= tol
@@ -140,13 +144,52 @@ def test_autograd_binding_matches_library_gradient():
     assert rel(m.grad.cpu().numpy(), grad.cpu().numpy()) <= 1e-6
 
 
-def test_cpml_adjoint_is_refused():
-    vel = np.full((16, 16, 16), 2000.0, np.float32)
-    p = params(vel.shape, bc=mm.BC_CPML, nb=4)
+def test_batched_adjoint_equals_single_shot_adjoints():
+    """Adjoint seismograms of a two-shot CPML context (one adjoint CPML and
+    stencil launch per step for both shots) equal the single-shot runs."""
+    rng = np.random.default_rng(50)
+    shapes = [(24, 27, 30), (22, 26, 21)]
+    p = params(shapes[0], bc=mm.BC_CPML, nb=5, f0=25.0)
+    vels = [rng.uniform(1600.0, 2800.0, sh).astype(np.float32) for sh in shapes]
+    p.vmax = float(max(v.max() for v in vels))
+    T = 40
+    p.ckpt_every = 8
+    p.nsteps_max = T
+    srcs = [np.array([[sh[2] // 2, sh[1] // 2, sh[0] // 2]], np.int32) for sh in shapes]
+    recs = [np.array([[1, 2, 3], [sh[2] - 2, sh[1] - 3, 2], [6, 7, 8]], np.int32) for sh in shapes]
+    ws = [rng.standard_normal((T, 1)).astype(np.float32) for _ in shapes]
+    rs = [rng.standard_normal((T, 3)).astype(np.float32) for _ in shapes]
+    ctx = mm.Context(p, [(torch.from_numpy(v).to(DEV), s_, r_) for v, s_, r_ in zip(vels, srcs, recs)])
+    ctx.forward(T, torch.from_numpy(np.concatenate(ws, 1)).to(DEV))
+    adj = torch.zeros((T, 2), device=DEV)
+    ctx.adjoint(T, torch.from_numpy(np.concatenate(rs, 1)).to(DEV), adj)
+    both = adj.cpu().numpy()
+    for i, (v, s_, r_, w, r) in enumerate(zip(vels, srcs, recs, ws, rs)):
+        q = mm.default_params(**{k: getattr(p, k) for k, _ in mm.Params._fields_})
+        q.nz, q.ny, q.nx = v.shape
+        c1 = mm.Context.single(q, torch.from_numpy(v).to(DEV), s_, r_)
+        c1.forward(T, torch.from_numpy(w).to(DEV))
+        a1 = torch.zeros((T, 1), device=DEV)
+        c1.adjoint(T, torch.from_numpy(r).to(DEV), a1)
+        assert np.array_equal(a1.cpu().numpy()[:, 0], both[:, i])
+
+
+def test_cpml_adjoint_limits():
+    """With adjoint storage, CPML needs nb <= 64 and n >= 2 nb + 8 per axis
+    (its adjoint correction reaches 4 cells past each layer)."""
+    vel = np.full((24, 24, 24), 2000.0, np.float32)
+    vt = torch.from_numpy(vel).to(DEV)
+    p = params(vel.shape, bc=mm.BC_CPML, nb=9)
     p.ckpt_every = 8
     p.nsteps_max = 10
-    ctx = mm.Context.single(p, torch.from_numpy(vel).to(DEV), [[8, 8, 8]], [[4, 4, 4]])
-    ctx.forward(4, torch.ones((4, 1), device=DEV))
     with pytest.raises(mm.MinimodError) as e:
-        ctx.adjoint(4, torch.zeros((4, 1), device=DEV))
-    assert e.value.status == mm.MM_ERR_UNSUPPORTED
+        mm.Context.single(p, vt, [[8, 8, 8]], [[4, 4, 4]])
+    assert e.value.status == mm.MM_ERR_ARG and "2*nb+8" in str(e.value)
+    p.nb = 8
+    ctx = mm.Context.single(p, vt, [[8, 8, 8]], [[4, 4, 4]])
+    ctx.forward(4, torch.ones((4, 1), device=DEV))
+    ctx.adjoint(4, torch.zeros((4, 1), device=DEV))
+    ctx.close()
+    p.ckpt_every = 0
+    p.nb = 10  # forward only: 2 nb + 4 suffices
+    mm.Context.single(p, vt, [[8, 8, 8]], [[4, 4, 4]]).close()
