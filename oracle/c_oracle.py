@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY.  Every array crossing this boundary is a C-ordered
 numpy array indexed [z][y][x] (x fastest); point lists are int32 [n][3] in
 (i, j, k) = (x, y, z) order.
 
-Boundary kinds: 0 none (zero ghost cells), 1 sponge, 2 CPML, 3 periodic.
+Boundary kinds: 0 none (zero ghost cells), 1 sponge, 2 CPML, 3 periodic;
+fs = 1 puts a free surface on the top face (p = 0 at k = 0, odd mirror above).
 """
 import ctypes
 import os
@@ -28,6 +29,7 @@ class _Grid(ctypes.Structure):
         ("R", ctypes.c_double), ("f0", ctypes.c_double), ("vmax", ctypes.c_double),
         ("wx0", ctypes.c_int), ("wy0", ctypes.c_int), ("wz0", ctypes.c_int),
         ("wnx", ctypes.c_int), ("wny", ctypes.c_int), ("wnz", ctypes.c_int),
+        ("fs", ctypes.c_int),
     ]
 
 
@@ -47,6 +49,7 @@ class Grid:
     R: float = 1e-3
     f0: float = 15.0
     vmax: float = 0.0
+    fs: int = 0  # free surface at k = 0
 
     @property
     def shape(self):
@@ -59,7 +62,7 @@ class Grid:
     def _c(self, window=None):
         w = (0, 0, 0, 0, 0, 0) if window is None else tuple(window[0]) + tuple(window[1])
         return _Grid(self.nx, self.ny, self.nz, self.hx, self.hy, self.hz, self.dt,
-                     self.bc, self.nb, self.sigma, self.R, self.f0, self.vmax, *w)
+                     self.bc, self.nb, self.sigma, self.R, self.f0, self.vmax, *w, int(self.fs))
 
 
 _lib = None

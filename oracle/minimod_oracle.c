@@ -88,6 +88,11 @@ typedef struct {
      * Indices stay global: the domain edges, layers and sources are those
      * of the nx x ny x nz grid. */
     int wx0, wy0, wz0, wnx, wny, wnz;
+    /* Free surface on the top face (section "Minimod Description" names it
+     * as the option at the surface): p = 0 on the plane k = 0 at every time
+     * level, cells above it hold the odd mirror p(i,j,-k) = -p(i,j,k), and
+     * the top face has no damping layer.  Not with bc periodic. */
+    int fs;
 } orc_grid;
 
 static int g_window_miss;  /* set when a windowed access falls outside the window */
@@ -123,11 +128,13 @@ static int wrap(int i, int n) {
     return r < 0 ? r + n : r;
 }
 
-/* Value of field f at (i,j,k); zero outside the domain unless periodic. */
+/* Value of field f at (i,j,k); zero outside the domain unless periodic;
+ * with a free surface, the odd mirror image above the plane k = 0. */
 static double at(const orc_grid* g, const double* f, int i, int j, int k) {
     if (g->bc == BC_PERIODIC) {
         return f[lin(g, wrap(i, g->nx), wrap(j, g->ny), wrap(k, g->nz))];
     }
+    if (g->fs && k < 0) return -at(g, f, i, j, -k);
     if (i < 0 || j < 0 || k < 0 || i >= g->nx || j >= g->ny || k >= g->nz) return 0.0;
     return f[lin(g, i, j, k)];
 }
@@ -208,9 +215,17 @@ static int layer_depth(int k, int n, int nb) {
     return d > 0 ? d : 0;
 }
 
-/* Sponge factor of one axis at index k. */
-static double sponge_g(const orc_grid* g, int k, int n) {
-    int d = layer_depth(k, n, g->nb);
+/* Depth inside the damping layer of axis ax (0 x, 1 y, 2 z) at index k;
+ * a free surface removes the layer at the top (k < nb on the z axis). */
+static int axis_depth(const orc_grid* g, int ax, int k) {
+    int n = ax == 0 ? g->nx : (ax == 1 ? g->ny : g->nz);
+    if (g->fs && ax == 2 && k < g->nb) return 0;
+    return layer_depth(k, n, g->nb);
+}
+
+/* Sponge factor of axis ax at index k. */
+static double sponge_g(const orc_grid* g, int ax, int k) {
+    int d = axis_depth(g, ax, k);
     if (d == 0) return 1.0;
     double x = g->sigma * d;
     return exp(-x * x);
@@ -218,15 +233,14 @@ static double sponge_g(const orc_grid* g, int k, int n) {
 
 double orc_sponge_G(const orc_grid* g, int i, int j, int k) {
     if (g->bc != BC_SPONGE) return 1.0;
-    return sponge_g(g, i, g->nx) * sponge_g(g, j, g->ny) * sponge_g(g, k, g->nz);
+    return sponge_g(g, 0, i) * sponge_g(g, 1, j) * sponge_g(g, 2, k);
 }
 
 /* CPML coefficients (a, b) of axis ax at index k along that axis.  Returns 0
  * if k is outside the layer of that axis (then a = 0 and psi stays zero). */
 static int cpml_ab(const orc_grid* g, int ax, int k, double* a, double* b) {
-    int n = ax == 0 ? g->nx : (ax == 1 ? g->ny : g->nz);
     double h = ax == 0 ? g->hx : (ax == 1 ? g->hy : g->hz);
-    int d = layer_depth(k, n, g->nb);
+    int d = axis_depth(g, ax, k);
     if (d == 0) {
         *a = 0.0;
         *b = 1.0;
@@ -289,6 +303,7 @@ static int check_grid(const orc_grid* g) {
     if (g->hx <= 0 || g->hy <= 0 || g->hz <= 0 || g->dt <= 0) return ORC_ERR_ARG;
     if (g->bc < 0 || g->bc > 3) return ORC_ERR_ARG;
     if ((g->bc == BC_SPONGE || g->bc == BC_CPML) && g->nb < 1) return ORC_ERR_ARG;
+    if (g->fs && g->bc == BC_PERIODIC) return ORC_ERR_ARG;
     return ORC_OK;
 }
 
@@ -315,6 +330,7 @@ static void step(const orc_grid* g, const double* D, const double* p_prev, const
                 double G = orc_sponge_G(g, i, j, k);
                 double s = src_term ? src_term[id] : 0.0;
                 p_next[id] = G * (2.0 * p_cur[id] - G * p_prev[id] + D[id] * (Lp[id] + s));
+                if (g->fs && k == 0) p_next[id] = 0.0;
             }
 }
 
@@ -425,7 +441,7 @@ int orc_step_points(const orc_grid* g, const double* vel, const double* p_prev, 
         double v = vel[id];
         double D = g->dt * g->dt * v * v;
         double s = src_term_at ? src_term_at[q] : 0.0;
-        out[q] = G * (2.0 * p_cur[id] - G * p_prev[id] + D * (L + s));
+        out[q] = (g->fs && k == 0) ? 0.0 : G * (2.0 * p_cur[id] - G * p_prev[id] + D * (L + s));
     }
     return g_window_miss ? ORC_ERR_ARG : ORC_OK;
 }
@@ -553,6 +569,7 @@ static void adj_step(const orc_grid* g, const double* D, const double* e2, const
                 double G = orc_sponge_G(g, i, j, k);
                 double c = g->bc == BC_CPML ? w->C[id] : 0.0;
                 out[id] = G * (2.0 * e1[id] - G * e2[id] + D[id] * (Lp[id] + c + rt[id]));
+                if (g->fs && k == 0) out[id] = 0.0;
             }
 }
 

@@ -551,3 +551,116 @@ def test_ricker_is_normalised_second_derivative_of_gaussian():
     want = -d2 / (2 * np.pi ** 2 * f0 ** 2)
     assert np.abs(w - want).max() < 1e-5
     assert w[int(round(t0 / dt))] == pytest.approx(1.0, abs=1e-12)
+
+
+# ------------------------------------------------------------ free surface
+@pytest.mark.parametrize("bc", [C.BC_NONE, C.BC_SPONGE, C.BC_CPML])
+def test_free_surface_equals_method_of_images(bc):
+    """A free surface at k = 0 is the odd mirror of the problem: the run on
+    nz planes with the free surface equals the upper half of a run on the
+    2 nz - 1 planes of the mirrored model (velocity even in k) with the
+    source and a negated image source, computed with ordinary zero ghosts;
+    damping on the remaining faces is mirrored too."""
+    rng = np.random.default_rng(60 + bc)
+    nx, ny, nz = 19, 17, 15
+    h = (10.0, 9.0, 11.0)
+    vel = rng.uniform(1600, 3200, (nz, ny, nx))
+    dt = 0.5 * C.dt_stab(vel.max(), *h)
+    kw = dict(bc=bc, nb=4, sigma=0.06, f0=30.0, vmax=float(vel.max()))
+    T = 60
+    src = np.array([[9, 8, 3], [4, 11, 6]])
+    w = rng.standard_normal((T, 2))
+    rec = np.array([[2, 3, 1], [10, 9, 4], [17, 15, 13], [9, 8, 3], [5, 5, 0]])
+    gfs = C.Grid(nx, ny, nz, *h, dt, fs=1, **kw)
+    tr, pm, pc, _ = C.forward(gfs, vel, src, w, rec, T)
+    # mirrored model: plane K = nz - 1 + k holds k, K = nz - 1 - k holds its image
+    M = 2 * nz - 1
+    velm = np.concatenate([vel[:0:-1], vel], axis=0)
+    srcm = np.concatenate([src + [0, 0, nz - 1], src * [1, 1, -1] + [0, 0, nz - 1]])
+    wm = np.concatenate([w, -w], axis=1)
+    recm = rec + [0, 0, nz - 1]
+    gm = C.Grid(nx, ny, M, *h, dt, **kw)
+    trm, pmm, pcm, _ = C.forward(gm, velm, srcm, wm, recm, T)
+    scale = np.abs(pc).max()
+    assert np.abs(pcm[nz - 1:] - pc).max() <= 1e-12 * scale
+    assert np.abs(pmm[nz - 1:] - pm).max() <= 1e-12 * scale
+    assert np.abs(trm - tr).max() <= 1e-12 * np.abs(tr).max()
+    assert np.all(pc[0] == 0.0) and np.all(tr[:, 4] == 0.0)  # surface plane and a receiver on it
+
+
+def test_free_surface_conserves_energy():
+    rng = np.random.default_rng(61)
+    nx, ny, nz = 18, 16, 14
+    h = (10.0, 10.0, 10.0)
+    vel = rng.uniform(1500, 3000, (nz, ny, nx))
+    dt = 0.8 * C.dt_stab(vel.max(), *h)
+    g = C.Grid(nx, ny, nz, *h, dt, bc=C.BC_NONE, fs=1)
+    T = 30
+    w = np.zeros((T, 1))
+    w[:5, 0] = [1.0, -2.0, 3.0, -1.0, 0.5]
+    _, pm, pc, _ = C.forward(g, vel, [[9, 8, 5]], w, [[1, 1, 1]], T)
+    e0 = C.energy(g, vel, pm, pc)
+    _, pm2, pc2, _ = C.forward(g, vel, [[9, 8, 5]], np.zeros((200, 1)), [[1, 1, 1]], 200, p_prev=pm, p_cur=pc)
+    e1 = C.energy(g, vel, pm2, pc2)
+    assert e0 > 0 and abs(e1 - e0) <= 1e-10 * e0
+
+
+@pytest.mark.parametrize("bc", [C.BC_NONE, C.BC_SPONGE, C.BC_CPML])
+def test_free_surface_dot_product(bc):
+    """The adjoint with a free surface (the same odd-mirror operator, and
+    eta = 0 on the surface) is the exact transpose of the forward map,
+    sources and receivers on the surface plane included."""
+    rng = np.random.default_rng(62 + bc)
+    nx, ny, nz = 20, 18, 16
+    h = (10.0, 9.0, 11.0)
+    vel = rng.uniform(1500, 3500, (nz, ny, nx))
+    dt = 0.6 * C.dt_stab(vel.max(), *h)
+    g = C.Grid(nx, ny, nz, *h, dt, bc=bc, nb=4, sigma=0.05, f0=40.0, vmax=float(vel.max()), fs=1)
+    T = 50
+    src = rng.integers(0, [nx, ny, nz], size=(4, 3))
+    src[0, 2] = 0
+    src[1, 2] = 2
+    rec = rng.integers(0, [nx, ny, nz], size=(7, 3))
+    rec[0, 2] = 1
+    rec[3] = src[1]
+    w = rng.standard_normal((T, 4))
+    r = rng.standard_normal((T, 7))
+    tr, _, _, _ = C.forward(g, vel, src, w, rec, T)
+    adj = C.adjoint(g, vel, rec, r, T, src)
+    lhs = float(np.sum(tr * r))
+    rhs = float(np.sum(w / (h[0] * h[1] * h[2]) * adj))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    assert np.all(adj[:, 0] == 0.0)  # a source on the surface radiates nothing
+
+
+def test_free_surface_gradient_finite_differences():
+    rng = np.random.default_rng(63)
+    nx, ny, nz = 18, 16, 14
+    h = (10.0, 10.0, 10.0)
+    k = np.arange(nz)[:, None, None]
+    vel_true = (2000.0 + 40.0 * k) * np.ones((nz, ny, nx))
+    vel_true[5:10, 5:11, 6:12] += 250.0
+    vel0 = (2000.0 + 40.0 * k) * np.ones((nz, ny, nx))
+    dt = 0.5 * C.dt_stab(vel_true.max() * 1.05, *h)
+    g = C.Grid(nx, ny, nz, *h, dt, bc=C.BC_CPML, nb=4, f0=30.0, vmax=float(vel_true.max()), fs=1)
+    T = 60
+    w = C.ricker(30.0, 0.05, dt, T)[:, None]
+    src, rec = [[9, 8, 2]], [[i, j, 1] for i in range(2, 16, 3) for j in range(2, 14, 3)]
+    d_obs, _, _, _ = C.forward(g, vel_true, src, w, rec, T)
+    grad, _, _ = C.gradient(g, vel0, src, w, rec, d_obs, T)
+    m0 = 1.0 / vel0 ** 2
+    from scipy.ndimage import gaussian_filter
+    dm = gaussian_filter(rng.standard_normal(m0.shape), 2.0)
+    dm *= 1e-2 * np.abs(m0).max() / np.abs(dm).max()
+
+    def J(m):
+        tr, _, _, _ = C.forward(g, 1.0 / np.sqrt(m), src, w, rec, T)
+        return 0.5 * np.sum((tr - d_obs) ** 2)
+
+    want = float(np.sum(grad * dm))
+    errs = []
+    for eps in (4e-3, 2e-3, 1e-3):
+        fd = (J(m0 + eps * dm) - J(m0 - eps * dm)) / (2 * eps)
+        errs.append(abs(fd - want) / abs(want))
+    assert errs[-1] < 1e-6, errs
+    assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0, errs
