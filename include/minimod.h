@@ -105,6 +105,10 @@ typedef struct {
                                 back, so a group stays resident in the 256 MB last-level cache; a shot
                                 larger than the budget is a group of its own; 0 => 262144 (256 MiB),
                                 -1 => one group: all shots advance together */
+    int32_t free_surface;    /* 1: free surface on the top face (section "Minimod Description": the
+                                option at the surface): p = 0 on the plane z = 0, the cells above it
+                                mirror p with odd symmetry, and the top face has no damping layer;
+                                sources and receivers on that plane inject and record nothing */
 } mm_params;
 
 /* One shot of a batched context. */
@@ -219,8 +223,9 @@ int32_t mm_num_tiles(void);
 const char* mm_tile_name(int32_t t);
 
 /* Kernel timing on the context's stream: while stride > 0, every stride-th
- * launch of the stencil kernel (the dominant kernel of a step) is bracketed
- * by a pair of HIP events.  mm_profile_read synchronises the stream, returns
+ * launch of the stencil kernel (the dominant kernel of a step) records its
+ * own start and end into a pair of HIP events (hipExtLaunchKernel, no extra
+ * stream packets).  mm_profile_read synchronises the stream, returns
  * the summed milliseconds and the number of timed launches, and clears the
  * record.  stride 0 stops timing.  Graph launches are not timed. */
 mm_status mm_profile(mm_ctx* ctx, int32_t stride);

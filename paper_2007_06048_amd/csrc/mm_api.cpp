@@ -361,6 +361,7 @@ mm_status check_params(const mm_params* p, mm_ctx* c) {
     if (p->snap != MM_SNAP_FP32 && p->snap != MM_SNAP_BF16) return fail(c, MM_ERR_ARG, "unknown snapshot kind");
     if (p->tile < -1 || p->tile >= num_tile_variants()) return fail(c, MM_ERR_ARG, "unknown tile variant");
     if (p->group_kb < -1) return fail(c, MM_ERR_ARG, "group_kb must be >= -1");
+    if (p->free_surface != 0 && p->free_surface != 1) return fail(c, MM_ERR_ARG, "free_surface must be 0 or 1");
     return MM_OK;
 }
 
@@ -559,21 +560,22 @@ mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, co
                        "adjoint cpml launch"));
         }
     }
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (timed) {
+        // the launch itself stamps the start and end of the kernel into the pair
         while (c->prof_ev.size() < c->prof_used + 2) {
             hipEvent_t e;
             MM_TRY(dev(c, hipEventCreate(&e), "event"));
             c->prof_ev.push_back(e);
         }
-        MM_TRY(dev(c, hipEventRecord(c->prof_ev[c->prof_used], s), "event"));
+        ev0 = c->prof_ev[c->prof_used];
+        ev1 = c->prof_ev[c->prof_used + 1];
+        c->prof_used += 2;
     }
     const TileEnt* tiles = g ? c->d_tiles + g->tile_off : c->d_tiles;
     const int nt = g ? g->ntiles : c->ntiles;
-    MM_TRY(dev(c, launch_step(c->variant, c->p.bc, mode, tiles, nt, shots, parity, c->cf, aux, s), "stencil launch"));
-    if (timed) {
-        MM_TRY(dev(c, hipEventRecord(c->prof_ev[c->prof_used + 1], s), "event"));
-        c->prof_used += 2;
-    }
+    MM_TRY(dev(c, launch_step(c->variant, c->p.bc, mode, tiles, nt, shots, parity, c->cf, aux, s, ev0, ev1),
+               "stencil launch"));
     return MM_OK;
 }
 
@@ -946,6 +948,7 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
         sd.nz = g.nz;
         sd.nb = p->nb;
         sd.cw = p->nb;
+        sd.fs = p->free_surface;
         c->shots_h.push_back(sd);
         ShotDev sa = sd;
         sa.nsrc_in = 0;
@@ -961,11 +964,18 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
         c->shots_adj_h.push_back(sa);
         const int n[3] = {g.nx, g.ny, g.nz};
         std::vector<float>& pr = prof[i];
+        // a free surface removes the damping of the top face (z < nb): no sponge, and CPML
+        // coefficients a = b = 0 there, so the layer memory stays 0 and adds nothing
+        const bool fs = p->free_surface != 0;
         if (c->cpml) {
             pr.resize(2 * (g.nx + g.ny + g.nz));
             float* q = pr.data();
             for (int a = 0; a < 3; ++a) {
                 cpml_table(n[a], p->nb, h[a], c->dt, c->vmax, p->cpml_R, p->cpml_f0, q, q + n[a]);
+                if (fs && a == 2) {
+                    std::fill(q, q + p->nb, 0.0f);
+                    std::fill(q + n[a], q + n[a] + p->nb, 0.0f);
+                }
                 q += 2 * n[a];
             }
         } else {
@@ -974,6 +984,7 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
             for (int a = 0; a < 3; ++a) {
                 if (c->sponge) sponge_table(n[a], p->nb, p->sponge_sigma, q);
                 else std::fill(q, q + n[a], 1.0f);
+                if (fs && a == 2 && c->sponge) std::fill(q, q + p->nb, 1.0f);
                 q += n[a];
             }
         }
@@ -990,6 +1001,7 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
         const ShotGeom& g = geom[i];
         auto lin = [&](const int32_t* t) { return ((long long)t[2] * g.ny + t[1]) * g.nx + t[0]; };
         auto gval = [&](const int32_t* t) {
+            if (p->free_surface && t[2] == 0) return 0.0f;  // the surface plane stays 0
             if (!c->sponge) return 1.0f;
             const float* q = prof[i].data();
             return q[t[0]] * q[g.nx + t[1]] * q[g.nx + g.ny + t[2]];

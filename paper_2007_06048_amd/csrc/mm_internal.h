@@ -17,6 +17,7 @@ struct ShotDev {
     float* corr[3];       // CPML correction added to the Laplacian this step, slabs of cw cells per end
     int nx, ny, nz, nb;
     int cw;               // width of the correction slabs: nb (forward), nb + 4 (adjoint)
+    int fs;               // free surface on plane z = 0 (p = 0 there, odd mirror above)
     int nsrc_in;          // sources added inside the stencil kernel (0..4)
     int src_col[4];       // their columns in the wavelet row
     long long src_off[4]; // their cells
@@ -86,6 +87,7 @@ enum { MODE_PLAIN = 0, MODE_D2P = 1, MODE_IMAGE = 2 };
 struct TileShape {
     int tx;     // tile width in x (threads per row)
     int ry;     // rows per thread
+    int nt;     // threads per block (256, 512 or 1024): nt / tx thread rows
     int target; // desired number of blocks (z-chunking)
     int pd;     // planes of loads in flight ahead of the current plane (1 or 2)
     const char* name;
@@ -96,9 +98,11 @@ int tile_rows(int t);  // TY of variant t
 
 // bc: 0 none, 1 sponge, 2 CPML (launch_cpml must have written the layer
 // corrections of the same step first)
+// With ev0 / ev1 the launch records its own start and end time stamps into
+// them (hipExtLaunchKernel), for per-launch timing without extra packets.
 hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int ntiles,
                        const ShotDev* shots, int parity, const Coefs& cf, const StepAux& aux,
-                       hipStream_t s);
+                       hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // CPML memory update and corrections of every shot for this step, before the
 // stencil kernel (shared nb <= 128).  With adjoint set, the same for the
 // adjoint fields: the transposed memory recursions and a correction reaching

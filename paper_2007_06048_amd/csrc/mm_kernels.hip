@@ -22,6 +22,7 @@
 //  - blocks are remapped so that consecutive tiles run on the same XCD
 //    (hardware deals blocks round-robin over the 8 XCDs), which keeps the
 //    halo exchange between neighbouring tiles inside one XCD's L2.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,25 +50,36 @@ __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned voff) 
 // are at least 4 planes) with one plane of prefetch, plus a few two-plane
 // prefetch variants of the large tiles; entry 0 is the default
 static const TileShape kTiles[] = {
-    {64, 4, 2048, 1, "64x16/2048/p1"},   {64, 4, 1024, 1, "64x16/1024/p1"},   {64, 4, 4096, 1, "64x16/4096/p1"},
-    {64, 4, 16384, 1, "64x16/16k/p1"},   {64, 4, 65536, 1, "64x16/64k/p1"},
-    {64, 2, 2048, 1, "64x8/2048/p1"},    {64, 2, 1024, 1, "64x8/1024/p1"},    {64, 2, 4096, 1, "64x8/4096/p1"},
-    {64, 2, 16384, 1, "64x8/16k/p1"},    {64, 2, 65536, 1, "64x8/64k/p1"},
-    {64, 8, 2048, 1, "64x32/2048/p1"},   {64, 8, 1024, 1, "64x32/1024/p1"},   {64, 8, 4096, 1, "64x32/4096/p1"},
-    {64, 8, 16384, 1, "64x32/16k/p1"},   {64, 8, 65536, 1, "64x32/64k/p1"},
-    {32, 2, 2048, 1, "32x16/2048/p1"},   {32, 2, 1024, 1, "32x16/1024/p1"},   {32, 2, 4096, 1, "32x16/4096/p1"},
-    {32, 2, 16384, 1, "32x16/16k/p1"},   {32, 2, 65536, 1, "32x16/64k/p1"},
-    {32, 4, 2048, 1, "32x32/2048/p1"},   {32, 4, 1024, 1, "32x32/1024/p1"},   {32, 4, 4096, 1, "32x32/4096/p1"},
-    {32, 4, 16384, 1, "32x32/16k/p1"},   {32, 4, 65536, 1, "32x32/64k/p1"},
-    {32, 1, 2048, 1, "32x8/2048/p1"},    {32, 1, 1024, 1, "32x8/1024/p1"},    {32, 1, 4096, 1, "32x8/4096/p1"},
-    {32, 1, 16384, 1, "32x8/16k/p1"},    {32, 1, 65536, 1, "32x8/64k/p1"},
-    {64, 4, 1024, 2, "64x16/1024/p2"},   {64, 4, 4096, 2, "64x16/4096/p2"},   {64, 8, 1024, 2, "64x32/1024/p2"},
-    {64, 8, 2048, 2, "64x32/2048/p2"},   {32, 2, 4096, 2, "32x16/4096/p2"},   {32, 1, 4096, 2, "32x8/4096/p2"},
+    {64, 4, 256, 2048, 1, "64x16/2048/p1"},   {64, 4, 256, 1024, 1, "64x16/1024/p1"},
+    {64, 4, 256, 4096, 1, "64x16/4096/p1"},   {64, 4, 256, 16384, 1, "64x16/16k/p1"},
+    {64, 4, 256, 65536, 1, "64x16/64k/p1"},   {64, 2, 256, 2048, 1, "64x8/2048/p1"},
+    {64, 2, 256, 1024, 1, "64x8/1024/p1"},    {64, 2, 256, 4096, 1, "64x8/4096/p1"},
+    {64, 2, 256, 16384, 1, "64x8/16k/p1"},    {64, 2, 256, 65536, 1, "64x8/64k/p1"},
+    {64, 8, 256, 2048, 1, "64x32/2048/p1"},   {64, 8, 256, 1024, 1, "64x32/1024/p1"},
+    {64, 8, 256, 4096, 1, "64x32/4096/p1"},   {64, 8, 256, 16384, 1, "64x32/16k/p1"},
+    {64, 8, 256, 65536, 1, "64x32/64k/p1"},   {32, 2, 256, 2048, 1, "32x16/2048/p1"},
+    {32, 2, 256, 1024, 1, "32x16/1024/p1"},   {32, 2, 256, 4096, 1, "32x16/4096/p1"},
+    {32, 2, 256, 16384, 1, "32x16/16k/p1"},   {32, 2, 256, 65536, 1, "32x16/64k/p1"},
+    {32, 4, 256, 2048, 1, "32x32/2048/p1"},   {32, 4, 256, 1024, 1, "32x32/1024/p1"},
+    {32, 4, 256, 4096, 1, "32x32/4096/p1"},   {32, 4, 256, 16384, 1, "32x32/16k/p1"},
+    {32, 4, 256, 65536, 1, "32x32/64k/p1"},   {32, 1, 256, 2048, 1, "32x8/2048/p1"},
+    {32, 1, 256, 1024, 1, "32x8/1024/p1"},    {32, 1, 256, 4096, 1, "32x8/4096/p1"},
+    {32, 1, 256, 16384, 1, "32x8/16k/p1"},    {32, 1, 256, 65536, 1, "32x8/64k/p1"},
+    {64, 4, 256, 1024, 2, "64x16/1024/p2"},   {64, 4, 256, 4096, 2, "64x16/4096/p2"},
+    {64, 8, 256, 1024, 2, "64x32/1024/p2"},   {64, 8, 256, 2048, 2, "64x32/2048/p2"},
+    {32, 2, 256, 4096, 2, "32x16/4096/p2"},   {32, 1, 256, 4096, 2, "32x8/4096/p2"},
+    // larger blocks: taller tiles (fewer halo rows per point) at one or two rows per thread
+    {64, 1, 1024, 1024, 1, "64x16t1024/1024"}, {64, 1, 1024, 4096, 1, "64x16t1024/4096"},
+    {64, 2, 1024, 512, 1, "64x32t1024/512"},   {64, 2, 1024, 2048, 1, "64x32t1024/2048"},
+    {32, 1, 1024, 1024, 1, "32x32t1024/1024"}, {32, 1, 1024, 4096, 1, "32x32t1024/4096"},
+    {64, 2, 512, 1024, 1, "64x16t512/1024"},   {64, 2, 512, 4096, 1, "64x16t512/4096"},
+    {32, 2, 512, 1024, 1, "32x32t512/1024"},   {32, 2, 512, 4096, 1, "32x32t512/4096"},
+    {64, 4, 512, 1024, 1, "64x32t512/1024"},   {64, 4, 512, 4096, 1, "64x32t512/4096"},
 };
 
 int num_tile_variants() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
 const TileShape& tile_variant(int t) { return kTiles[t]; }
-int tile_rows(int t) { return (256 / kTiles[t].tx) * kTiles[t].ry; }
+int tile_rows(int t) { return (kTiles[t].nt / kTiles[t].tx) * kTiles[t].ry; }
 
 // ------------------------------------------------------------- stencil step
 
@@ -75,24 +87,28 @@ int tile_rows(int t) { return (256 / kTiles[t].tx) * kTiles[t].ry; }
 // SIMD instead of 6 for the CPML forward and the imaging instantiations);
 // they fit without spilling, the larger shapes and the CPML replay / imaging
 // modes would not.
-template <int TX, int RY, int PD, int BC, int MODE>
-__global__ __launch_bounds__(256)
+template <int TX, int RY, int PD, int BC, int MODE, int NT>
+__global__ __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu((PD == 1 && RY <= 2 && !(BC == 2 && MODE != MODE_PLAIN)) ? 7 : 1)))
 void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const ShotDev* __restrict__ shots,
             int parity, Coefs cf, StepAux aux) {
-    constexpr int BY = 256 / TX;
+    constexpr int BY = NT / TX;  // thread rows
     constexpr int TY = BY * RY;
     constexpr int LW = TX + 8;
-    constexpr int YH = 8 / BY;
+    // y halo: with BY <= 8 every thread row loads 8 / BY of the 8 halo rows,
+    // with more thread rows the first 8 load one each
+    constexpr bool YSPLIT = BY <= 8;
+    constexpr int YH = YSPLIT ? 8 / BY : 1;
     constexpr bool SPONGE = BC == 1;
     constexpr bool CPML = BC == 2;
-    static_assert(BY <= 8 && 8 % BY == 0, "y halo split");
+    static_assert(!YSPLIT || 8 % BY == 0, "y halo split");
     __shared__ float lds[2][TY + 8][LW];
 
     if ((int)blockIdx.x < aux.gather_blocks) {
-        // record of the previous step: its output is this step's p^n
-        const int r = blockIdx.x * 256 + threadIdx.y * TX + threadIdx.x;
-        if (r < aux.g_n) aux.gather_out[r] = shots[aux.g_shot[r]].buf[parity][aux.g_off[r]];
+        // record of the previous step: its output is this step's p^n (256 receivers per block)
+        const int tid = threadIdx.y * TX + threadIdx.x;
+        const int r = blockIdx.x * 256 + tid;
+        if (tid < 256 && r < aux.g_n) aux.gather_out[r] = shots[aux.g_shot[r]].buf[parity][aux.g_off[r]];
         return;
     }
     // consecutive tiles on one XCD: block b runs on XCD b % 8
@@ -122,13 +138,14 @@ void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const Sh
     const int hcol = tx < 4 ? te.x0 - 4 + tx : te.x0 + TX + (tx - 4);
     const bool hx_lane = tx < 8 && hcol >= 0 && hcol < nx;
     // y halo: thread row ty loads halo rows ty, ty + BY, ... of the 8
+    const bool hy_row = YSPLIT || ty < 8;  // wave-uniform (a wave spans 1 or 2 thread rows)
     int hrow[YH];
     bool hy_ok[YH];
 #pragma unroll
     for (int h = 0; h < YH; ++h) {
         const int hr = ty + h * BY;
         hrow[h] = hr < 4 ? te.y0 - 4 + hr : te.y0 + TY + (hr - 4);
-        hy_ok[h] = xin && hrow[h] >= 0 && hrow[h] < ny;
+        hy_ok[h] = hy_row && xin && hrow[h] >= 0 && hrow[h] < ny;
     }
 
     // per-lane byte offsets inside a plane (OOB where the cell is outside the grid)
@@ -168,14 +185,19 @@ void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const Sh
     }
 
     const int z0 = te.z0, z1 = te.z1;
+    // z queue: planes z0-4 .. z0+3; above a free surface (plane 0) the odd mirror -p(-z)
     float q[RY][9];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
         const int z = z0 - 4 + m;
-        const bool zin = z >= 0 && z < nz;  // block-uniform
-        const __amdgpu_buffer_rsrc_t rp = plane_rsrc(pc, zin ? z : 0, plane);
+        const bool zin = z >= 0 && z < nz;               // block-uniform
+        const bool zmir = sd.fs && z < 0 && -z < nz;
+        const __amdgpu_buffer_rsrc_t rp = plane_rsrc(pc, zin ? z : (zmir ? -z : 0), plane);
 #pragma unroll
-        for (int r = 0; r < RY; ++r) q[r][m] = zin ? bload(rp, voc[r]) : 0.0f;
+        for (int r = 0; r < RY; ++r) {
+            const float v = (zin || zmir) ? bload(rp, voc[r]) : 0.0f;
+            q[r][m] = zmir ? -v : v;
+        }
     }
 
     // prefetch stages: stage k holds the loads for plane z + k (queue head p^n(z+k+4),
@@ -196,8 +218,13 @@ void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const Sh
             nvd[k][r] = bload(rv, voc[r]);
             nxh[k][r] = bload(rc, vox[r]);
         }
+        if (hy_row) {
 #pragma unroll
-        for (int h = 0; h < YH; ++h) nyh[k][h] = bload(rc, voy[h]);
+            for (int h = 0; h < YH; ++h) nyh[k][h] = bload(rc, voy[h]);
+        } else {
+#pragma unroll
+            for (int h = 0; h < YH; ++h) nyh[k][h] = 0.0f;
+        }
         if (CPML) {
 #pragma unroll
             for (int r = 0; r < RC; ++r) ncr[k][r] = 0.0f;
@@ -277,14 +304,17 @@ void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const Sh
             L[4 + ty + r * BY][xx] = q[r][4];
             if (tx < 8) L[4 + ty + r * BY][tx < 4 ? tx : TX + tx] = cxh[r];
         }
+        if (hy_row) {
 #pragma unroll
-        for (int h = 0; h < YH; ++h) {
-            const int hr = ty + h * BY;
-            L[hr < 4 ? hr : TY + hr][xx] = cyh[h];
+            for (int h = 0; h < YH; ++h) {
+                const int hr = ty + h * BY;
+                L[hr < 4 ? hr : TY + hr][xx] = cyh[h];
+            }
         }
         __syncthreads();
 
         const float gz = SPONGE ? sd.prof[nx + ny + z] : 1.0f;
+        const bool surf = sd.fs && z == 0;  // free-surface plane: p stays 0
         const long long zoff = (long long)z * plane;
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
@@ -313,8 +343,9 @@ void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const Sh
                 } else {
                     out = c + fmaf(cvd[r], lap, c - cpp[r]);
                 }
+                if (surf) out = 0.0f;
                 pn_g[o] = out;
-                if (MODE == MODE_D2P) ((gfloat*)aux.d2p_out)[o] = G * (cvd[r] * lap);
+                if (MODE == MODE_D2P) ((gfloat*)aux.d2p_out)[o] = surf ? 0.0f : G * (cvd[r] * lap);
                 if (MODE == MODE_IMAGE) {
                     gfloat* gr = (gfloat*)aux.grad;
                     gr[o] = fmaf(aux.neg_inv_dt2 / G * out, ((const gfloat*)aux.d2p_in)[o], gr[o]);
@@ -328,49 +359,89 @@ void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const Sh
     }
 }
 
-template <int TX, int RY, int PD, int BC>
+template <int TX, int RY, int PD, int BC, int MODE, int NT>
+static void launch_step_k(dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd, const ShotDev* shots, int parity,
+                          const Coefs& cf, const StepAux& aux, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    const dim3 block(TX, NT / TX);
+    if (ev0)
+        hipExtLaunchKernelGGL(k_step<TX, RY, PD, BC, MODE, NT>, grid, block, 0, s, ev0, ev1, 0, tiles, ntiles,
+                              per_xcd, shots, parity, cf, aux);
+    else
+        k_step<TX, RY, PD, BC, MODE, NT><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
+}
+
+template <int TX, int RY, int PD, int BC, int NT>
 static hipError_t launch_step_bc(int mode, dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd,
                                  const ShotDev* shots, int parity, const Coefs& cf, const StepAux& aux,
-                                 hipStream_t s) {
-    dim3 block(TX, 256 / TX);
+                                 hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (mode == MODE_PLAIN)
-        k_step<TX, RY, PD, BC, MODE_PLAIN><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
+        launch_step_k<TX, RY, PD, BC, MODE_PLAIN, NT>(grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0,
+                                                      ev1);
     else if (mode == MODE_D2P)
-        k_step<TX, RY, PD, BC, MODE_D2P><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
+        launch_step_k<TX, RY, PD, BC, MODE_D2P, NT>(grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0, ev1);
     else
-        k_step<TX, RY, PD, BC, MODE_IMAGE><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
+        launch_step_k<TX, RY, PD, BC, MODE_IMAGE, NT>(grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0,
+                                                      ev1);
     return hipGetLastError();
 }
 
-template <int TX, int RY>
+template <int TX, int RY, int NT>
 static hipError_t launch_step_t(int pd, int bc, int mode, dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd,
                                 const ShotDev* shots, int parity, const Coefs& cf, const StepAux& aux,
-                                hipStream_t s) {
+                                hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     // CPML: launch_cpml has written the layer corrections of this step
-    if (pd == 1) {
-        if (bc == 1) return launch_step_bc<TX, RY, 1, 1>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
-        if (bc == 2) return launch_step_bc<TX, RY, 1, 2>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
-        return launch_step_bc<TX, RY, 1, 0>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+#define MM_BC(PD_, BC_) \
+    return launch_step_bc<TX, RY, PD_, BC_, NT>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0, ev1)
+    if constexpr (NT == 256) {
+        if (pd == 2) {
+            if (bc == 1) MM_BC(2, 1);
+            if (bc == 2) MM_BC(2, 2);
+            MM_BC(2, 0);
+        }
     }
-    if (bc == 1) return launch_step_bc<TX, RY, 2, 1>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
-    if (bc == 2) return launch_step_bc<TX, RY, 2, 2>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
-    return launch_step_bc<TX, RY, 2, 0>(mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+    if (pd != 1) return hipErrorInvalidValue;
+    if (bc == 1) MM_BC(1, 1);
+    if (bc == 2) MM_BC(1, 2);
+    MM_BC(1, 0);
+#undef MM_BC
 }
 
 hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int ntiles, const ShotDev* shots,
-                       int parity, const Coefs& cf, const StepAux& aux, hipStream_t s) {
+                       int parity, const Coefs& cf, const StepAux& aux, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (ntiles <= 0) return hipSuccess;
     const int per_xcd = (ntiles + 7) / 8;
     dim3 grid(8 * per_xcd + aux.gather_blocks);
     const TileShape& ts = kTiles[variant];
-    if (ts.tx == 64) {
-        if (ts.ry == 2) return launch_step_t<64, 2>(ts.pd, bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
-        if (ts.ry == 4) return launch_step_t<64, 4>(ts.pd, bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
-        return launch_step_t<64, 8>(ts.pd, bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+#define MM_T(TX_, RY_, NT_) \
+    return launch_step_t<TX_, RY_, NT_>(ts.pd, bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0, \
+                                        ev1)
+    if (ts.nt == 1024) {
+        if (ts.tx == 64) {
+            if (ts.ry == 1) MM_T(64, 1, 1024);
+            if (ts.ry == 2) MM_T(64, 2, 1024);
+        } else if (ts.ry == 1) {
+            MM_T(32, 1, 1024);
+        }
+        return hipErrorInvalidValue;
     }
-    if (ts.ry == 1) return launch_step_t<32, 1>(ts.pd, bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
-    if (ts.ry == 2) return launch_step_t<32, 2>(ts.pd, bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
-    return launch_step_t<32, 4>(ts.pd, bc, mode, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s);
+    if (ts.nt == 512) {
+        if (ts.tx == 64) {
+            if (ts.ry == 2) MM_T(64, 2, 512);
+            if (ts.ry == 4) MM_T(64, 4, 512);
+        } else if (ts.ry == 2) {
+            MM_T(32, 2, 512);
+        }
+        return hipErrorInvalidValue;
+    }
+    if (ts.tx == 64) {
+        if (ts.ry == 2) MM_T(64, 2, 256);
+        if (ts.ry == 4) MM_T(64, 4, 256);
+        MM_T(64, 8, 256);
+    }
+    if (ts.ry == 1) MM_T(32, 1, 256);
+    if (ts.ry == 2) MM_T(32, 2, 256);
+    MM_T(32, 4, 256);
+#undef MM_T
 }
 
 // -------------------------------------------------------------------- CPML
@@ -755,11 +826,12 @@ __global__ __launch_bounds__(256) void k_inject(InjTab tab, const ShotDev* __res
                                                 const float* __restrict__ vals, StepAux aux) {
     const int u = blockIdx.x * 256 + threadIdx.x;
     if (u >= tab.ncell) return;
+    const float g = tab.cell_g[u];
+    if (g == 0.0f) return;  // a cell on a free surface: nothing enters
     float acc = 0.0f;
     for (int q = tab.start[u]; q < tab.start[u + 1]; ++q) acc += vals[tab.col[q]];
     const ShotDev& sd = shots[tab.cell_shot[u]];
     const long long o = tab.cell_off[u];
-    const float g = tab.cell_g[u];
     const float term = g * (sd.vdt2[o] * (tab.scale * acc));
     float* pn = sd.buf[parity ^ 1];
     pn[o] += term;

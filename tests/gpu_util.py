@@ -24,7 +24,7 @@ def params(shape, h=(10.0, 10.0, 10.0), bc=mm.BC_SPONGE, nb=8, cfl=0.5, f0=15.0,
 
 def grid_for(p, dt, vmax):
     return C.Grid(p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, dt, bc=p.bc, nb=p.nb, sigma=p.sponge_sigma, R=p.cpml_R,
-                  f0=p.cpml_f0, vmax=vmax)
+                  f0=p.cpml_f0, vmax=vmax, fs=p.free_surface)
 
 
 def gpu_forward(p, vel, src, rec, wav, T, tile=None, graph=False, chunks=None):

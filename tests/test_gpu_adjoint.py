@@ -25,12 +25,18 @@ def _case(bc, nsrc, seed, shape=(26, 30, 34), T=80):
     return rng, vel, src, rec, p, T
 
 
-@pytest.mark.parametrize("bc,nsrc", [(mm.BC_SPONGE, 1), (mm.BC_SPONGE, 6), (mm.BC_NONE, 3), (mm.BC_CPML, 1),
-                                     (mm.BC_CPML, 6)])
-def test_dot_product_and_adjoint_parity(bc, nsrc):
+@pytest.mark.parametrize("bc,nsrc,fs", [(mm.BC_SPONGE, 1, 0), (mm.BC_SPONGE, 6, 0), (mm.BC_NONE, 3, 0),
+                                        (mm.BC_CPML, 1, 0), (mm.BC_CPML, 6, 0), (mm.BC_SPONGE, 1, 1),
+                                        (mm.BC_CPML, 6, 1)])
+def test_dot_product_and_adjoint_parity(bc, nsrc, fs):
     """<F s, r> = <s, F^T r> on the GPU (FP32), and the GPU adjoint seismograms
-    at the sources match the FP64 oracle's adjoint."""
+    at the sources match the FP64 oracle's adjoint (with a free surface: a
+    receiver on the surface plane and one just below it)."""
     rng, vel, src, rec, p, T = _case(bc, nsrc, seed=10 + nsrc)
+    p.free_surface = fs
+    if fs:
+        rec[0, 2] = 0
+        rec[1, 2] = 1
     p.ckpt_every = 16
     p.nsteps_max = T
     w = rng.standard_normal((T, nsrc)).astype(np.float32)
@@ -72,12 +78,14 @@ def test_adjoint_in_chunks_is_bitwise_one_call(bc):
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
-@pytest.mark.parametrize("bc,snap,tol", [(mm.BC_SPONGE, mm.SNAP_FP32, 1e-4), (mm.BC_SPONGE, mm.SNAP_BF16, 2e-2),
-                                          (mm.BC_CPML, mm.SNAP_FP32, 1e-4), (mm.BC_CPML, mm.SNAP_BF16, 2e-2)])
-def test_gradient_matches_oracle(bc, snap, tol):
+@pytest.mark.parametrize("bc,snap,tol,fs", [(mm.BC_SPONGE, mm.SNAP_FP32, 1e-4, 0), (mm.BC_SPONGE, mm.SNAP_BF16, 2e-2, 0),
+                                             (mm.BC_CPML, mm.SNAP_FP32, 1e-4, 0), (mm.BC_CPML, mm.SNAP_BF16, 2e-2, 0),
+                                             (mm.BC_CPML, mm.SNAP_FP32, 1e-4, 1)])
+def test_gradient_matches_oracle(bc, snap, tol, fs):
     """FWI gradient w.r.t. m = 1/v^2 with checkpoints every 16 steps (a partial
     last segment included) against the oracle's exact FP64 gradient; CPML
-    checkpoints carry the layer memory."""
+    checkpoints carry the layer memory; with a free surface the receivers sit
+    just below it."""
     rng = np.random.default_rng(30)
     shape = (28, 32, 36)
     nz, ny, nx = shape
@@ -89,11 +97,12 @@ def test_gradient_matches_oracle(bc, snap, tol):
     p.vmax = float(vt.max())
     p.ckpt_every = 16
     p.snap = snap
+    p.free_surface = fs
     T = 140
     p.nsteps_max = T
     dt = mm.dt_for(p, p.vmax)
     src = np.array([[18, 16, 4]], np.int32)
-    rec = np.array([[i, j, 3] for i in range(2, nx - 2, 3) for j in range(2, ny - 2, 3)], np.int32)
+    rec = np.array([[i, j, 1 if fs else 3] for i in range(2, nx - 2, 3) for j in range(2, ny - 2, 3)], np.int32)
     w = mm.ricker(25.0, 0.06, dt, T).reshape(T, 1)
     g = grid_for(p, dt, p.vmax)
     d_obs, _, _, _ = C.forward(g, vt.astype(np.float64), src, w.astype(np.float64), rec, T)

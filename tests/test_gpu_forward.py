@@ -55,12 +55,15 @@ def _ragged_case(bc, seed=3):
     return p, vel, src, rec, w, T, dt
 
 
-@pytest.mark.parametrize("bc", [mm.BC_NONE, mm.BC_SPONGE, mm.BC_CPML])
-def test_ragged_every_tile_variant(bc):
+@pytest.mark.parametrize("bc,fs", [(mm.BC_NONE, 0), (mm.BC_SPONGE, 0), (mm.BC_CPML, 0), (mm.BC_NONE, 1),
+                                   (mm.BC_SPONGE, 1), (mm.BC_CPML, 1)])
+def test_ragged_every_tile_variant(bc, fs):
     """A ragged grid (partial tiles in x, y and z), duplicate sources,
     receivers on sources and on corners: every tile variant matches the oracle
-    and all variants agree bitwise (tiling does not change the arithmetic)."""
+    and all variants agree bitwise (tiling does not change the arithmetic).
+    With a free surface a source and a receiver sit on the surface plane."""
     p, vel, src, rec, w, T, dt = _ragged_case(bc)
+    p.free_surface = fs
     rtr, rpc, _ = oracle_forward(p, dt, vel, src, rec, w, T)
     first = None
     for t in range(mm.num_tiles()):
@@ -73,9 +76,10 @@ def test_ragged_every_tile_variant(bc):
             assert np.array_equal(first[0], tr) and np.array_equal(first[1], pc) and np.array_equal(first[2], pm), t
 
 
-@pytest.mark.parametrize("bc", [mm.BC_NONE, mm.BC_SPONGE, mm.BC_CPML])
-def test_graph_and_chunked_runs_are_bitwise_equal(bc):
+@pytest.mark.parametrize("bc,fs", [(mm.BC_NONE, 0), (mm.BC_SPONGE, 0), (mm.BC_CPML, 0), (mm.BC_CPML, 1)])
+def test_graph_and_chunked_runs_are_bitwise_equal(bc, fs):
     p, vel, src, rec, w, T, dt = _ragged_case(bc, seed=4)
+    p.free_surface = fs
     a = gpu_forward(p, vel, src, rec, w, T)
     b = gpu_forward(p, vel, src, rec, w, T, graph=True)
     c = gpu_forward(p, vel, src, rec, w, T, chunks=[1, 20, 0, 33, 16])
