@@ -202,7 +202,8 @@ mm_status mm_state_size(const mm_ctx* ctx, size_t* bytes);
  * CPML psi_x, psi_y, psi_z, zeta_x, zeta_y, zeta_z in slab layout:
  * x-slabs [nz][ny][2nb], y-slabs [nz][2nb][nx], z-slabs [2nb][ny][nx],
  * where slab index s < nb is grid index s and s >= nb is grid index
- * n - 2nb + s.  mm_set_state also sets the step counter. */
+ * n - 2nb + s.  mm_set_state also sets the step counter; with a free surface
+ * it leaves p = 0 on the surface plane. */
 mm_status mm_get_state(mm_ctx* ctx, void* dst_dev);
 mm_status mm_set_state(mm_ctx* ctx, const void* src_dev, int32_t step);
 

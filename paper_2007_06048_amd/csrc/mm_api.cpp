@@ -1116,8 +1116,12 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
             up(L.cpml_off + sizeof(int) * cpml_pos, c->cpml_adj_h.data(), sizeof(int) * c->cpml_adj_h.size());
         }
     }
-    for (int i = 0; i < nshots && !st; ++i)
+    for (int i = 0; i < nshots && !st; ++i) {
         st = dev(c, launch_vdt2(shots[i].vel, c->shots_h[i].vdt2, geom[i].n(), c->dt, s), "vdt2");
+        // free surface: (dt v)^2 = 0 on plane z = 0 keeps p = 0 there (the state starts at 0)
+        if (!st && p->free_surface)
+            st = dev(c, launch_fill(c->shots_h[i].vdt2, (long long)geom[i].nx * geom[i].ny, 0.0f, s), "fill");
+    }
     if (!st) st = dev(c, hipStreamSynchronize(s), "sync");
     if (st) return bail(st);
 
@@ -1312,7 +1316,16 @@ mm_status mm_set_state(mm_ctx* c, const void* src, int32_t step) {
     c->fwd_valid = true;
     c->ckpt_active = false;
     c->adj_started = false;
-    return state_copy(c, const_cast<char*>(reinterpret_cast<const char*>(src)), false);
+    MM_TRY(state_copy(c, const_cast<char*>(reinterpret_cast<const char*>(src)), false));
+    if (c->p.free_surface) {
+        // the surface plane holds p = 0 at every time level
+        for (size_t i = 0; i < c->geom.size(); ++i)
+            for (int w = 0; w < 2; ++w)
+                MM_TRY(dev(c, launch_fill(c->shots_h[i].buf[w], (long long)c->geom[i].nx * c->geom[i].ny, 0.0f,
+                                          c->stream),
+                           "fill"));
+    }
+    return MM_OK;
 }
 
 mm_status mm_get_info(const mm_ctx* c, double* dt, int32_t* step, int32_t* tile, int32_t* ngroups) {

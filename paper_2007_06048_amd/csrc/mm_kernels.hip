@@ -22,6 +22,10 @@
 //  - blocks are remapped so that consecutive tiles run on the same XCD
 //    (hardware deals blocks round-robin over the 8 XCDs), which keeps the
 //    halo exchange between neighbouring tiles inside one XCD's L2.
+// A free surface on plane z = 0 costs nothing in the loop: the host sets
+// (dt v)^2 = 0 on that plane and keeps the state there at 0, so the update
+// leaves p = 0 exactly, and the z queue of the first chunk starts with the
+// odd mirror -p(1..4) of the planes below.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -185,18 +189,25 @@ void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const Sh
     }
 
     const int z0 = te.z0, z1 = te.z1;
-    // z queue: planes z0-4 .. z0+3; above a free surface (plane 0) the odd mirror -p(-z)
+    // z queue: planes z0-4 .. z0+3
     float q[RY][9];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
         const int z = z0 - 4 + m;
-        const bool zin = z >= 0 && z < nz;               // block-uniform
-        const bool zmir = sd.fs && z < 0 && -z < nz;
-        const __amdgpu_buffer_rsrc_t rp = plane_rsrc(pc, zin ? z : (zmir ? -z : 0), plane);
+        const bool zin = z >= 0 && z < nz;  // block-uniform
+        const __amdgpu_buffer_rsrc_t rp = plane_rsrc(pc, zin ? z : 0, plane);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) q[r][m] = zin ? bload(rp, voc[r]) : 0.0f;
+    }
+    if (z0 == 0 && sd.fs) {
+        // above a free surface on plane 0: the odd mirror, planes -1..-4 = -p(1..4)
+        const __amdgpu_buffer_rsrc_t r4 = plane_rsrc(pc, 4 < nz ? 4 : 0, plane);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            const float v = (zin || zmir) ? bload(rp, voc[r]) : 0.0f;
-            q[r][m] = zmir ? -v : v;
+            q[r][3] = -q[r][5];
+            q[r][2] = -q[r][6];
+            q[r][1] = -q[r][7];
+            q[r][0] = 4 < nz ? -bload(r4, voc[r]) : 0.0f;
         }
     }
 
@@ -314,7 +325,6 @@ void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const Sh
         __syncthreads();
 
         const float gz = SPONGE ? sd.prof[nx + ny + z] : 1.0f;
-        const bool surf = sd.fs && z == 0;  // free-surface plane: p stays 0
         const long long zoff = (long long)z * plane;
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
@@ -343,9 +353,8 @@ void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const Sh
                 } else {
                     out = c + fmaf(cvd[r], lap, c - cpp[r]);
                 }
-                if (surf) out = 0.0f;
                 pn_g[o] = out;
-                if (MODE == MODE_D2P) ((gfloat*)aux.d2p_out)[o] = surf ? 0.0f : G * (cvd[r] * lap);
+                if (MODE == MODE_D2P) ((gfloat*)aux.d2p_out)[o] = G * (cvd[r] * lap);
                 if (MODE == MODE_IMAGE) {
                     gfloat* gr = (gfloat*)aux.grad;
                     gr[o] = fmaf(aux.neg_inv_dt2 / G * out, ((const gfloat*)aux.d2p_in)[o], gr[o]);
