@@ -48,7 +48,7 @@ def load_workload(name):
 def traffic_for(workload_name):
     """HBM bytes per stencil launch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "stencil_traffic.json")
+    path = os.path.join(ROOT, "profiles", "k_step_traffic.json")
     try:
         with open(path) as f:
             d = json.load(f)
@@ -262,11 +262,11 @@ def main():
     ap.add_argument("--time-steps", type=int, default=0, help="override the workload's step count (profiling)")
     ap.add_argument("--no-extras", action="store_true", help="skip the gradient and batched-shot legs")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="summarise two rocprofv3 --pmc runs into profiles/stencil_traffic.json and exit")
+                    help="summarise two rocprofv3 --pmc runs into profiles/k_step_traffic.json and exit")
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.workload,
-                    os.path.join(ROOT, "profiles", "stencil_traffic.json"))
+                    os.path.join(ROOT, "profiles", "k_step_traffic.json"))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (shots and z-slabs would shard "
