@@ -195,7 +195,48 @@ def gradient_leg(dev, reps=2):
         torch.cuda.empty_cache()
     res["gradient_fp32_vs_forward"] = round(res["gradient_fp32_s"] / res["forward_s"], 2)
     res["gradient_bf16_vs_forward"] = round(res["gradient_bf16_s"] / res["forward_s"], 2)
+    # the same shot with a 20-cell CPML (adjoint through the transposed memory recursions)
+    cbase = dict(base, bc=2, cpml_f0=wl.f0)
+    cc = mm.Context.single(mm.default_params(**cbase), v0, s.src, s.rec)
+
+    def fwd_cpml():
+        cc.reset()
+        cc.forward(T, w, tr)
+
+    res["forward_cpml_s"] = round(_timed(fwd_cpml, reps), 4)
+    del cc
+    cg = mm.Context.single(mm.default_params(**cbase, ckpt_every=wl.ckpt_every, nsteps_max=T), v0, s.src, s.rec)
+    g = torch.empty(s.vel.shape, dtype=torch.float32, device=dev)
+    res["gradient_cpml_fp32_s"] = round(_timed(lambda: cg.gradient(T, w, d_obs, g, tr), reps), 4)
+    res["workspace_cpml_fp32_GB"] = round(cg.ws_bytes / 1e9, 2)
+    res["gradient_cpml_vs_forward"] = round(res["gradient_cpml_fp32_s"] / res["forward_cpml_s"], 2)
+    del cg, g
+    torch.cuda.empty_cache()
     return res
+
+
+def free_surface_leg(dev, reps=2):
+    """The bench workload (240^3, CPML-20, 1000 steps) with a free surface on
+    the top face instead of the top CPML layer."""
+    import torch
+    from paper_2007_06048_amd import minimod as mm
+    from paper_2007_06048_amd import workloads as W
+    wl = W.smooth_240()
+    s = wl.shots[0]
+    T = wl.nsteps
+    p = mm.default_params(nx=wl.nx, ny=wl.ny, nz=wl.nz, dx=wl.h, dy=wl.h, dz=wl.h, cfl=wl.cfl, bc=wl.bc, nb=wl.nb,
+                          cpml_R=wl.cpml_R, cpml_f0=wl.f0, tile=-1, free_surface=1)
+    ctx = mm.Context.single(p, torch.from_numpy(s.vel).to(dev), s.src, s.rec)
+    w = torch.from_numpy(mm.ricker(wl.f0, wl.t0, ctx.dt, T)).to(dev).reshape(T, 1)
+    tr = torch.empty((T, len(s.rec)), dtype=torch.float32, device=dev)
+
+    def run():
+        ctx.reset()
+        ctx.forward(T, w, tr)
+
+    t = _timed(run, reps)
+    return {"workload": wl.name + "_free_surface", "run_s": round(t, 4),
+            "gpts": round(wl.nx * wl.ny * wl.nz * T / t / 1e9, 2)}
 
 
 def batched_leg(dev, reps=2):
@@ -373,6 +414,8 @@ def main():
         out["gradient"] = gradient_leg(dev)
         torch.cuda.empty_cache()
         out["batched"] = batched_leg(dev)
+        torch.cuda.empty_cache()
+        out["free_surface"] = free_surface_leg(dev)
         torch.cuda.empty_cache()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)

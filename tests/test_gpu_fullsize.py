@@ -83,7 +83,7 @@ def _check_last_step(ctx, shot_index, shapes, vel_np, p, vmax, src, w_last, befo
     shape = shapes[shot_index]
     nz, ny, nx = shape
     g = C.Grid(nx, ny, nz, p.dx, p.dy, p.dz, ctx.dt, bc=p.bc, nb=p.nb, sigma=p.sponge_sigma, R=p.cpml_R,
-               f0=p.cpml_f0, vmax=vmax)
+               f0=p.cpml_f0, vmax=vmax, fs=p.free_surface)
     pts = _samples(rng, shape, p.nb if bc != mm.BC_NONE else 0, src, np.zeros((0, 3)))
     errs = []
     scale_all = float(before["pc"].abs().max())
@@ -112,10 +112,11 @@ def _check_last_step(ctx, shot_index, shapes, vel_np, p, vmax, src, w_last, befo
     assert errs.max() <= 2e-6, errs.max()
 
 
-def _run_single(wl, steps_before, graph=False):
+def _run_single(wl, steps_before, graph=False, free_surface=0):
     s = wl.shots[0]
     p = mm.default_params(nx=wl.nx, ny=wl.ny, nz=wl.nz, dx=wl.h, dy=wl.h, dz=wl.h, cfl=wl.cfl, bc=wl.bc, nb=wl.nb,
-                          sponge_sigma=wl.sigma, cpml_R=wl.cpml_R, cpml_f0=wl.f0, tile=-1)
+                          sponge_sigma=wl.sigma, cpml_R=wl.cpml_R, cpml_f0=wl.f0, tile=-1,
+                          free_surface=free_surface)
     vel = torch.from_numpy(s.vel).to(DEV)
     ctx = mm.Context.single(p, vel, s.src, s.rec)
     T = steps_before + 1
@@ -139,6 +140,58 @@ def test_fullsize_smooth_240_cpml_1000_steps():
     s = wl.shots[0]
     _check_last_step(ctx, 0, [s.vel.shape], s.vel.astype(np.float64), p, float(s.vel.max()), s.src, wlast, before,
                      after, np.random.default_rng(240), mm.BC_CPML)
+
+
+def test_fullsize_smooth_240_cpml_free_surface_1000_steps():
+    """The bench workload with a free surface on the top face: the sampled
+    last step (cells on and just below the surface included) against the
+    oracle, and the surface plane exactly zero."""
+    wl = W.smooth_240()
+    ctx, p, before, after, wlast = _run_single(wl, wl.nsteps - 1, free_surface=1)
+    s = wl.shots[0]
+    assert float(after["pc"][0].abs().max()) == 0.0 and float(before["pc"][1].abs().max()) > 0.0
+    _check_last_step(ctx, 0, [s.vel.shape], s.vel.astype(np.float64), p, float(s.vel.max()), s.src, wlast, before,
+                     after, np.random.default_rng(241), mm.BC_CPML)
+
+
+def test_fullsize_smooth_240_cpml_adjoint_and_gradient():
+    """CPML adjoint at the bench size (240^3, CPML-20, 300 steps): the
+    dot-product test in FP32, and the gradient from checkpoints every 32
+    steps (with the layer memory) equal bitwise to the one-segment replay."""
+    wl = W.smooth_240()
+    s = wl.shots[0]
+    T = 300
+    rng = np.random.default_rng(2400)
+    base = dict(nx=wl.nx, ny=wl.ny, nz=wl.nz, dx=wl.h, dy=wl.h, dz=wl.h, cfl=wl.cfl, bc=wl.bc, nb=wl.nb,
+                cpml_R=wl.cpml_R, cpml_f0=wl.f0, tile=-1, nsteps_max=T)
+    v = torch.from_numpy(s.vel).to(DEV)
+    ctx = mm.Context.single(mm.default_params(**base, ckpt_every=32), v, s.src, s.rec)
+    w = torch.from_numpy(rng.standard_normal((T, 1)).astype(np.float32)).to(DEV)
+    r = torch.from_numpy(rng.standard_normal((T, len(s.rec))).astype(np.float32)).to(DEV)
+    tr = torch.empty((T, len(s.rec)), dtype=torch.float32, device=DEV)
+    ctx.forward(T, w, tr)
+    adj = torch.empty((T, 1), dtype=torch.float32, device=DEV)
+    ctx.adjoint(T, r, adj)
+    torch.cuda.synchronize()
+    lhs = float((tr.double() * r.double()).sum())
+    rhs = float((w.double() / wl.h ** 3 * adj.double()).sum())
+    print(f"CPML full-size dot product {lhs:.6e} vs {rhs:.6e}: rel {abs(lhs - rhs) / abs(lhs):.2e}")
+    assert abs(lhs - rhs) <= 1e-4 * abs(lhs)
+    del ctx
+    torch.cuda.empty_cache()
+    wr = torch.from_numpy(mm.ricker(wl.f0, wl.t0, 5.0317e-4, T)).to(DEV).reshape(T, 1)
+    d_obs = (tr * 1e-3).contiguous()
+    grads = []
+    for k in (32, T):
+        c = mm.Context.single(mm.default_params(**base, ckpt_every=k), v, s.src, s.rec)
+        g = torch.empty(s.vel.shape, dtype=torch.float32, device=DEV)
+        J = c.gradient(T, wr, d_obs, g)
+        grads.append((g, J))
+        del c
+        torch.cuda.empty_cache()
+    assert grads[0][1] == grads[1][1]
+    assert torch.equal(grads[0][0], grads[1][0])
+    assert torch.isfinite(grads[0][0]).all() and float(grads[0][0].abs().max()) > 0
 
 
 def test_fullsize_layered_1024x1024x512_cpml_500_steps():
