@@ -101,6 +101,14 @@ def lib():
                                    ctypes.c_int, dp, dp, dp]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_num_threads.argtypes = []
+        L.orc_iso_dt_stab.restype = ctypes.c_double
+        L.orc_iso_dt_stab.argtypes = [ctypes.c_double] * 4
+        L.orc_iso_dplus.restype = None
+        L.orc_iso_dplus.argtypes = [gp, dp, ctypes.c_int, dp]
+        L.orc_iso_forward.restype = ctypes.c_int
+        L.orc_iso_forward.argtypes = [gp, fp, dp, ctypes.c_int, ip, dp, ctypes.c_int, ip, ctypes.c_int, dp, dp]
+        L.orc_iso_energy.restype = ctypes.c_double
+        L.orc_iso_energy.argtypes = [gp, fp, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -245,3 +253,45 @@ def gradient(g: Grid, vel, src, wav, rec, d_obs, T, ckpt=None):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+# ------------------------------------------------------------ acoustic_iso
+def iso_dt_stab(vmax, hx, hy, hz):
+    """Largest stable dt of the staggered order-8 leapfrog (acoustic_iso)."""
+    return lib().orc_iso_dt_stab(vmax, hx, hy, hz)
+
+
+def iso_dplus(g: Grid, f, ax):
+    """Staggered first difference D+ of a cell field along axis ax (0 x, 1 y,
+    2 z); element (k, j, i) is the value at the face (i, j, k) + 1/2 e_ax."""
+    f = _vel(g, f)
+    out = np.zeros(g.shape)
+    lib().orc_iso_dplus(ctypes.byref(g._c()), _d(f), ax, _d(out))
+    return out
+
+
+def iso_forward(g: Grid, vel, rho, src, wav, rec, T, state=None):
+    """acoustic_iso run of T steps.  state = [4][nz][ny][nx] (p^n, u_x, u_y,
+    u_z at n-1/2; u_x[k][j][i] is the face i+1/2), zero if None.  Returns
+    (traces [T][nrec], end state)."""
+    vel = _vel(g, vel)
+    rho = _vel(g, rho)
+    src = _pts(src)
+    rec = _pts(rec)
+    nsrc, nrec = len(src), len(rec)
+    wav = np.ascontiguousarray(np.asarray(wav, dtype=np.float64).reshape(T, nsrc)) if nsrc else np.zeros((T, 0))
+    st = np.zeros((4,) + g.shape) if state is None else np.array(state, dtype=np.float64, order="C")
+    traces = np.zeros((T, nrec))
+    rc = lib().orc_iso_forward(ctypes.byref(g._c()), _f(vel), _d(rho), nsrc, _i(src), _d(wav), nrec, _i(rec), T,
+                               _d(traces), _d(st))
+    _check(rc, "orc_iso_forward")
+    return traces, st
+
+
+def iso_energy(g: Grid, vel, rho, p_n, p_n1, u_half):
+    vel = _vel(g, vel)
+    rho = _vel(g, rho)
+    p_n = _vel(g, p_n)
+    p_n1 = _vel(g, p_n1)
+    u_half = np.ascontiguousarray(u_half, dtype=np.float64)
+    return lib().orc_iso_energy(ctypes.byref(g._c()), _f(vel), _d(rho), _d(p_n), _d(p_n1), _d(u_half))

@@ -721,3 +721,161 @@ int orc_num_threads(void) {
     return 1;
 #endif
 }
+
+/* ========================================================= acoustic_iso */
+/*
+ * The paper's second propagator, Eq. (acoustic_iso_vd): the first-order
+ * variable-density system
+ *   (1/(rho v^2)) dp/dt - div u = f,   rho du/dt - grad p = 0,
+ * on a staggered (Yee) grid, section "Finite Differences": p at the cell
+ * centres, u_x at the faces (i+1/2, j, k), u_y at (i, j+1/2, k), u_z at
+ * (i, j, k+1/2); array index (i,j,k) of u_x holds the face i+1/2.  Readings:
+ *  - staggered order-8 first differences, weights c = (1225/1024,
+ *    -245/3072, 49/5120, -5/7168):
+ *      D+ p (face i+1/2) = sum_m c_m (p(i+m) - p(i+1-m)) / h,
+ *      D- u (cell i)     = sum_m c_m (u(i+m-1) - u(i-m)) / h,
+ *    zero outside the grid (or periodic), so D- = -(D+)^T;
+ *  - leapfrog staggered in time, u at half steps:
+ *      u^{n+1/2} = G (u^{n-1/2} + dt b D+ p^n),
+ *      p^{n+1}   = G (p^n + dt K (D- . u^{n+1/2} + s^n)),
+ *    K = rho v^2, b = the face buoyancy: the mean of 1/rho of the two cells
+ *    beside the face (1/rho of the inner cell on the last face of an axis);
+ *    s^n = w(t_n)/(hx hy hz) at the source cell; G = the sponge factor of
+ *    the cell (for u, the cell whose right face it is);
+ *  - dt = cfl / (C vmax sqrt(hx^-2 + hy^-2 + hz^-2)), C = c1 - c2 + c3 - c4,
+ *    the largest symbol of the staggered derivative (checkerboard mode);
+ *  - traces[n][r] = p^{n+1} at the receivers; initial state zero.
+ * CPML and the free surface are not defined for this propagator here.
+ */
+static const double C8[5] = {0.0, 1225.0 / 1024.0, -245.0 / 3072.0, 49.0 / 5120.0, -5.0 / 7168.0};
+
+double orc_iso_dt_stab(double vmax, double hx, double hy, double hz) {
+    double C = C8[1] - C8[2] + C8[3] - C8[4];
+    double sum = 1.0 / (hx * hx) + 1.0 / (hy * hy) + 1.0 / (hz * hz);
+    return 1.0 / (C * vmax * sqrt(sum));
+}
+
+static double axis_h(const orc_grid* g, int ax) { return ax == 0 ? g->hx : (ax == 1 ? g->hy : g->hz); }
+
+/* D+ of cell field p along axis ax, at the face (i,j,k) + 1/2 e_ax. */
+static double dplus(const orc_grid* g, const double* p, int i, int j, int k, int ax) {
+    int di = ax == 0, dj = ax == 1, dk = ax == 2;
+    double h = axis_h(g, ax), s = 0.0;
+    for (int m = 1; m <= 4; ++m)
+        s += (C8[m] / h) * (at(g, p, i + m * di, j + m * dj, k + m * dk) -
+                            at(g, p, i - (m - 1) * di, j - (m - 1) * dj, k - (m - 1) * dk));
+    return s;
+}
+
+/* D- of face field u (index i holds face i+1/2) along axis ax, at cell (i,j,k). */
+static double dminus(const orc_grid* g, const double* u, int i, int j, int k, int ax) {
+    int di = ax == 0, dj = ax == 1, dk = ax == 2;
+    double h = axis_h(g, ax), s = 0.0;
+    for (int m = 1; m <= 4; ++m)
+        s += (C8[m] / h) * (at(g, u, i + (m - 1) * di, j + (m - 1) * dj, k + (m - 1) * dk) -
+                            at(g, u, i - m * di, j - m * dj, k - m * dk));
+    return s;
+}
+
+/* Buoyancy at the face (i,j,k) + 1/2 e_ax. */
+static double face_b(const orc_grid* g, const double* rho, int i, int j, int k, int ax) {
+    int n = ax == 0 ? g->nx : (ax == 1 ? g->ny : g->nz);
+    int pos = ax == 0 ? i : (ax == 1 ? j : k);
+    double b0 = 1.0 / rho[lin(g, i, j, k)];
+    int q = pos + 1;
+    if (q >= n) {
+        if (g->bc != BC_PERIODIC) return b0;
+        q = 0;
+    }
+    int i1 = ax == 0 ? q : i, j1 = ax == 1 ? q : j, k1 = ax == 2 ? q : k;
+    return 0.5 * (b0 + 1.0 / rho[lin(g, i1, j1, k1)]);
+}
+
+/* D+ along axis ax of a whole cell field (test access to the operator). */
+void orc_iso_dplus(const orc_grid* g, const double* p, int ax, double* out) {
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) out[lin(g, i, j, k)] = dplus(g, p, i, j, k, ax);
+}
+
+static int iso_check(const orc_grid* g) {
+    if (check_grid(g) || g->wnx > 0) return ORC_ERR_ARG;
+    if (g->bc == BC_CPML || g->fs) return ORC_ERR_UNSUPPORTED;
+    return ORC_OK;
+}
+
+/* acoustic_iso forward run for T steps.  state (4N: p^n, u_x, u_y, u_z at
+ * n-1/2) is the start state and receives the end state; NULL starts from
+ * zero.  wav [T][nsrc], traces [T][nrec] (may be NULL). */
+int orc_iso_forward(const orc_grid* g, const double* vel, const double* rho, int nsrc, const int* src,
+                    const double* wav, int nrec, const int* rec, int T, double* traces, double* state) {
+    int rc = iso_check(g);
+    if (rc) return rc;
+    if (T < 0 || nsrc < 0 || nrec < 0 || check_pts(g, nsrc, src) || check_pts(g, nrec, rec)) return ORC_ERR_ARG;
+    size_t N = npts(g);
+    double* st = state ? state : alloc_d(4 * N);
+    double* pn = alloc_d(N);
+    double* S = alloc_d(N);
+    if (!st || !pn || !S) {
+        if (!state) free(st);
+        free(pn); free(S);
+        return ORC_ERR_MEM;
+    }
+    double* p = st;
+    double* u[3] = {st + N, st + 2 * N, st + 3 * N};
+    double inv_vol = 1.0 / (g->hx * g->hy * g->hz);
+    for (int n = 0; n < T; ++n) {
+        /* u^{n+1/2} from p^n */
+        for (int ax = 0; ax < 3; ++ax) {
+#pragma omp parallel for schedule(static)
+            for (int k = 0; k < g->nz; ++k)
+                for (int j = 0; j < g->ny; ++j)
+                    for (int i = 0; i < g->nx; ++i) {
+                        size_t id = lin(g, i, j, k);
+                        double G = orc_sponge_G(g, i, j, k);
+                        u[ax][id] = G * (u[ax][id] + g->dt * face_b(g, rho, i, j, k, ax) * dplus(g, p, i, j, k, ax));
+                    }
+        }
+        /* p^{n+1} from p^n, u^{n+1/2} and s^n */
+        memset(S, 0, N * sizeof(double));
+        for (int s = 0; s < nsrc; ++s)
+            S[lin(g, src[3 * s], src[3 * s + 1], src[3 * s + 2])] += wav[(size_t)n * nsrc + s] * inv_vol;
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < g->nz; ++k)
+            for (int j = 0; j < g->ny; ++j)
+                for (int i = 0; i < g->nx; ++i) {
+                    size_t id = lin(g, i, j, k);
+                    double G = orc_sponge_G(g, i, j, k);
+                    double K = rho[id] * vel[id] * vel[id];
+                    double div = dminus(g, u[0], i, j, k, 0) + dminus(g, u[1], i, j, k, 1) + dminus(g, u[2], i, j, k, 2);
+                    pn[id] = G * (p[id] + g->dt * K * (div + S[id]));
+                }
+        memcpy(p, pn, N * sizeof(double));
+        if (traces)
+            for (int r = 0; r < nrec; ++r)
+                traces[(size_t)n * nrec + r] = p[lin(g, rec[3 * r], rec[3 * r + 1], rec[3 * r + 2])];
+    }
+    if (!state) free(st);
+    free(pn); free(S);
+    return ORC_OK;
+}
+
+/* Discrete energy between p^n (p_n) and p^{n+1} (p_n1) with u^{n+1/2}
+ * (u_half, 3N): E = sum over faces |u|^2 / b + sum over cells p^n p^{n+1} / K,
+ * which the scheme keeps constant without sponge and source. */
+double orc_iso_energy(const orc_grid* g, const double* vel, const double* rho, const double* p_n, const double* p_n1,
+                      const double* u_half) {
+    size_t N = npts(g);
+    double e = 0.0;
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                size_t id = lin(g, i, j, k);
+                for (int ax = 0; ax < 3; ++ax) {
+                    double w = u_half[(size_t)ax * N + id];
+                    e += w * w / face_b(g, rho, i, j, k, ax);
+                }
+                e += p_n[id] * p_n1[id] / (rho[id] * vel[id] * vel[id]);
+            }
+    return e;
+}

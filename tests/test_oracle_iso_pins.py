@@ -1,0 +1,226 @@
+"""Pins of the oracle's acoustic_iso propagator (first-order variable-density
+system on a staggered grid) against what mathematics fixes: the staggered
+derivative's exactness and textbook truncation constant, the stability limit,
+exact discrete energy conservation, the exact evolution of a Fourier mode, and
+the equivalence with a second-order scheme for constant density (an
+independent numpy restatement)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import c_oracle as C
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "closed_forms.json")
+CS = np.array([1225.0 / 1024.0, -245.0 / 3072.0, 49.0 / 5120.0, -5.0 / 7168.0])
+
+
+def _gold():
+    with open(GOLD) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("ax", [0, 1, 2])
+def test_iso_staggered_derivative_exactness_and_error_constant(ax):
+    """D+ is exact on polynomials up to degree 8 at the faces and, for x^9
+    centred on a face, returns the textbook constant -35/294912 * 9! h^8."""
+    n = (21, 19, 23)
+    h = (10.0, 7.5, 12.5)
+    g = C.Grid(n[0], n[1], n[2], h[0], h[1], h[2], 1e-4)
+    k, j, i = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    pos = (i, j, k)[ax] * h[ax]
+    c0 = (n[ax] // 2 + 0.5) * h[ax]  # a face in the middle
+    interior = (((i, j, k)[ax] >= 4) & ((i, j, k)[ax] <= n[ax] - 5))
+    for d in range(0, 9):
+        f = ((pos - c0) / h[ax]) ** d
+        got = C.iso_dplus(g, f, ax)
+        xf = (pos + 0.5 * h[ax] - c0) / h[ax]
+        want = d * xf ** max(d - 1, 0) / h[ax] if d > 0 else 0.0 * xf
+        err = np.abs(got - want)[interior].max()
+        assert err <= 1e-9 * max(1.0, np.abs(want[interior]).max()), (d, err)
+    num, den = _gold()["staggered_order8_d1_error"]
+    f = (pos - c0) ** 9
+    got = C.iso_dplus(g, f, ax)
+    face = ((i, j, k)[ax] == n[ax] // 2)  # the face at c0 (cell n//2 holds face n//2 + 1/2)
+    want = num / den * 362880.0 * h[ax] ** 8
+    assert np.allclose(got[face], want, rtol=1e-9, atol=0)
+
+
+def test_iso_stability_limit():
+    g = _gold()
+    C8 = CS[0] - CS[1] + CS[2] - CS[3]
+    assert C8 == pytest.approx(1.2863095, rel=1e-7)
+    assert 1500.0 * C.iso_dt_stab(1500.0, 10.0, 10.0, 10.0) / 10.0 == pytest.approx(
+        g["staggered_order8_courant_limit_equal_spacing"], rel=1e-5)
+
+
+def _model(rng, shape):
+    from scipy.ndimage import gaussian_filter
+    v = 1800.0 + 1200.0 * rng.random(shape)
+    rho = 1000.0 + 1500.0 * gaussian_filter(rng.random(shape), 1.0)
+    return v, rho
+
+
+def test_iso_energy_is_conserved():
+    """Without sponge and source, E = sum |u^{n+1/2}|^2 / b + sum p^n p^{n+1} / K
+    is constant (D- = -(D+)^T with zero ghosts), for variable v and rho."""
+    rng = np.random.default_rng(70)
+    shape = (14, 16, 18)
+    v, rho = _model(rng, shape)
+    h = (10.0, 9.0, 11.0)
+    dt = 0.9 * C.iso_dt_stab(v.max(), *h)
+    g = C.Grid(shape[2], shape[1], shape[0], *h, dt)
+    w = rng.standard_normal((6, 2))
+    src = [[9, 8, 7], [3, 12, 4]]
+    _, st = C.iso_forward(g, v, rho, src, w, [[1, 1, 1]], 6)
+
+    def energy_after(state, steps):
+        _, a = C.iso_forward(g, v, rho, src, np.zeros((steps, 2)), [[1, 1, 1]], steps, state=state)
+        _, b = C.iso_forward(g, v, rho, src, np.zeros((1, 2)), [[1, 1, 1]], 1, state=a)
+        return C.iso_energy(g, v, rho, a[0], b[0], b[1:]), a
+
+    e0, _ = energy_after(st, 0)
+    e1, _ = energy_after(st, 300)
+    assert e0 > 0 and abs(e1 - e0) <= 1e-10 * e0
+
+
+@pytest.mark.parametrize("ax,kmode", [(0, 3), (2, 5)])
+def test_iso_fourier_mode_evolves_exactly(ax, kmode):
+    """Periodic box, constant v and rho: with p^0 = cos(k x) and u^{-1/2} =
+    (dt b S / 2) sin(k (x + h/2)), S = (2/h) sum c_m sin((m - 1/2) k h), the
+    scheme gives p^n = cos(n theta) cos(k x) with cos theta = 1 - dt^2 v^2 S^2 / 2."""
+    n = (24, 20, 30)
+    h = (10.0, 8.0, 12.0)
+    v0, rho0 = 2500.0, 1800.0
+    dt = 0.7 * C.iso_dt_stab(v0, *h)
+    g = C.Grid(n[0], n[1], n[2], *h, dt, bc=C.BC_PERIODIC)
+    shape = (n[2], n[1], n[0])
+    k3, j3, i3 = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    idx = (i3, j3, k3)[ax]
+    kk = 2 * np.pi * kmode / (n[ax] * h[ax])
+    x = idx * h[ax]
+    S = 2.0 / h[ax] * np.sum(CS * np.sin((np.arange(1, 5) - 0.5) * kk * h[ax]))
+    b = 1.0 / rho0
+    st = np.zeros((4,) + shape)
+    st[0] = np.cos(kk * x)
+    st[1 + ax] = dt * b * S / 2 * np.sin(kk * (x + h[ax] / 2))
+    T = 60
+    _, out = C.iso_forward(g, np.full(shape, v0), np.full(shape, rho0), np.zeros((0, 3)), np.zeros((T, 0)),
+                           [[0, 0, 0]], T, state=st)
+    theta = np.arccos(1 - dt * dt * v0 * v0 * S * S / 2)
+    assert np.abs(out[0] - np.cos(T * theta) * np.cos(kk * x)).max() <= 1e-11
+
+
+def _dplus_np(p, ax, h):
+    """Numpy restatement of the staggered forward difference with zero ghosts."""
+    a = 2 - ax
+    n = p.shape[a]
+    pad = [(0, 0)] * 3
+    pad[a] = (4, 4)
+    q = np.pad(p, pad)
+    out = np.zeros_like(p)
+    for m in range(1, 5):
+        out += CS[m - 1] / h * (np.take(q, np.arange(n) + 4 + m, axis=a) - np.take(q, np.arange(n) + 4 - (m - 1), axis=a))
+    return out
+
+
+def _dminus_np(u, ax, h):
+    a = 2 - ax
+    n = u.shape[a]
+    pad = [(0, 0)] * 3
+    pad[a] = (4, 4)
+    q = np.pad(u, pad)
+    out = np.zeros_like(u)
+    for m in range(1, 5):
+        out += CS[m - 1] / h * (np.take(q, np.arange(n) + 4 + m - 1, axis=a) - np.take(q, np.arange(n) + 4 - m, axis=a))
+    return out
+
+
+def test_iso_constant_density_equals_second_order_form():
+    """For constant rho the first-order scheme is, exactly, the second-order
+    leapfrog p^{n+1} - 2 p^n + p^{n-1} = dt^2 v^2 D-.(D+ p^n) + dt K (s^n - s^{n-1})
+    (restated here in numpy with zero ghosts)."""
+    rng = np.random.default_rng(71)
+    shape = (12, 13, 15)
+    h = (10.0, 11.0, 9.0)
+    v = 1800.0 + 1000.0 * rng.random(shape)
+    rho = np.full(shape, 1700.0)
+    dt = 0.8 * C.iso_dt_stab(v.max(), *h)
+    g = C.Grid(shape[2], shape[1], shape[0], *h, dt)
+    T = 40
+    src = np.array([[7, 6, 5]])
+    w = rng.standard_normal((T, 1))
+    tr, _ = C.iso_forward(g, v, rho, src, w, [[7, 6, 5]], T)
+    K = rho * v * v
+    b = 1.0 / rho
+    pm = np.zeros(shape)
+    pc = np.zeros(shape)
+    s_prev = np.zeros(shape)
+    out = []
+    for n in range(T):
+        s = np.zeros(shape)
+        s[5, 6, 7] = w[n, 0] / (h[0] * h[1] * h[2])
+        lap = sum(_dminus_np(_dplus_np(pc, ax, h[ax]), ax, h[ax]) for ax in range(3))
+        pn = 2 * pc - pm + dt * dt * K * b * lap + dt * K * (s - s_prev)
+        pm, pc, s_prev = pc, pn, s
+        out.append(pc[5, 6, 7])
+    assert np.abs(np.array(out) - tr[:, 0]).max() <= 1e-12 * np.abs(tr).max()
+
+
+def test_iso_sponge_with_zero_strength_is_bc_none_and_sponge_absorbs():
+    rng = np.random.default_rng(72)
+    shape = (16, 17, 18)
+    v, rho = _model(rng, shape)
+    h = (10.0, 10.0, 10.0)
+    dt = 0.6 * C.iso_dt_stab(v.max(), *h)
+    T = 120
+    w = C.ricker(40.0, 0.03, dt, T)[:, None]
+    src, rec = [[9, 8, 8]], [[2, 2, 2], [15, 14, 13]]
+    g0 = C.Grid(shape[2], shape[1], shape[0], *h, dt)
+    gs0 = C.Grid(shape[2], shape[1], shape[0], *h, dt, bc=C.BC_SPONGE, nb=4, sigma=0.0)
+    a, sa = C.iso_forward(g0, v, rho, src, w, rec, T)
+    b, sb = C.iso_forward(gs0, v, rho, src, w, rec, T)
+    assert np.array_equal(a, b) and np.array_equal(sa, sb)
+    gs = C.Grid(shape[2], shape[1], shape[0], *h, dt, bc=C.BC_SPONGE, nb=4, sigma=0.1)
+    wl = np.concatenate([w, np.zeros((300, 1))])
+    _, sc = C.iso_forward(gs, v, rho, src, wl, rec, T + 300)
+    _, sd = C.iso_forward(g0, v, rho, src, wl, rec, T + 300)
+    assert np.abs(sc[0]).max() < 0.2 * np.abs(sd[0]).max()
+
+
+def test_iso_rejects_cpml_and_free_surface():
+    g = C.Grid(10, 10, 10, 10.0, 10.0, 10.0, 1e-4, bc=C.BC_CPML, nb=2)
+    with pytest.raises(RuntimeError):
+        C.iso_forward(g, np.full((10, 10, 10), 2000.0), np.full((10, 10, 10), 1000.0), [[5, 5, 5]],
+                      np.zeros((2, 1)), [[5, 5, 5]], 2)
+
+
+def test_iso_density_contrast_reflects_with_the_impedance_ratio():
+    """A plane wave at normal incidence on a density step (same velocity)
+    reflects with R = (Z2 - Z1) / (Z2 + Z1), Z = rho v: here rho triples, R = 1/2.
+    Periodic 4 x 4 x 700 column, plane source at k = 150, step at k = 300,
+    receiver at k = 200; the direct and reflected peaks are compared before
+    any wrapped arrival."""
+    nx, ny, nz = 4, 4, 700
+    h = 10.0
+    v0 = 2000.0
+    shape = (nz, ny, nx)
+    v = np.full(shape, v0)
+    rho = np.full(shape, 1000.0)
+    rho[300:] = 3000.0
+    dt = 0.5 * C.iso_dt_stab(v0, h, h, h)
+    g = C.Grid(nx, ny, nz, h, h, h, dt, bc=C.BC_PERIODIC)
+    t_end = 2.0
+    T = int(t_end / dt)
+    f0 = 8.0
+    w = C.ricker(f0, 1.5 / f0, dt, T)
+    src = np.array([[i, j, 150] for i in range(nx) for j in range(ny)])
+    tr, _ = C.iso_forward(g, v, rho, src, np.repeat(w[:, None], len(src), axis=1), [[1, 1, 200]], T)
+    t = (np.arange(T) + 1) * dt
+    t_direct = 1.5 / f0 + 50 * h / v0
+    t_refl = 1.5 / f0 + 250 * h / v0
+    win = 0.08
+    a_dir = np.abs(tr[np.abs(t - t_direct) < win, 0]).max()
+    a_ref = np.abs(tr[np.abs(t - t_refl) < win, 0]).max()
+    assert a_ref / a_dir == pytest.approx(0.5, rel=0.03), a_ref / a_dir
