@@ -78,6 +78,23 @@ typedef enum {
 
 typedef enum { MM_BC_NONE = 0, MM_BC_SPONGE = 1, MM_BC_CPML = 2 } mm_bc;
 
+/* Propagators of section "Minimod Description".
+ *  - MM_MODEL_ISO_CD: acoustic_iso_cd, Eq. (acoustic_iso_cd), the second-order
+ *    constant-density equation described above (every feature of this ABI);
+ *  - MM_MODEL_ISO: acoustic_iso, Eq. (acoustic_iso_vd), the first-order
+ *    variable-density system (1/(rho v^2)) dp/dt - div u = f, rho du/dt -
+ *    grad p = 0 on the staggered (Yee) grid: p at cell centres, u_x at the
+ *    faces (i+1/2, j, k) (array index i), u_y at (i, j+1/2, k), u_z at
+ *    (i, j, k+1/2); order-8 staggered differences c = (1225/1024, -245/3072,
+ *    49/5120, -5/7168); staggered leapfrog
+ *      u^{n+1/2} = G (u^{n-1/2} + dt b D+ p^n),
+ *      p^{n+1}   = G (p^n + dt rho v^2 (D- . u^{n+1/2} + s^n)),
+ *    b the face buoyancy (mean of 1/rho of the two cells beside the face,
+ *    1/rho of the inner cell on the last face), G the cell's sponge factor;
+ *    dt = cfl / (C vmax sqrt(dx^-2 + dy^-2 + dz^-2)), C = 2161/1680.
+ *    Forward modelling only, bc none or sponge, no free surface. */
+typedef enum { MM_MODEL_ISO_CD = 0, MM_MODEL_ISO = 1 } mm_model;
+
 /* Snapshot storage of the gradient's checkpoints. */
 typedef enum {
     MM_SNAP_FP32 = 0, /* lossless */
@@ -109,6 +126,7 @@ typedef struct {
                                 option at the surface): p = 0 on the plane z = 0, the cells above it
                                 mirror p with odd symmetry, and the top face has no damping layer;
                                 sources and receivers on that plane inject and record nothing */
+    int32_t model;           /* mm_model; 0 => acoustic_iso_cd */
 } mm_params;
 
 /* One shot of a batched context. */
@@ -119,6 +137,8 @@ typedef struct {
     int32_t nsrc;
     const int32_t* rec_ijk;        /* host [nrec][3] */
     int32_t nrec;
+    const float* rho;              /* device [nz][ny][nx] density, kg/m^3 (acoustic_iso only, read only
+                                      during init; ignored by acoustic_iso_cd) */
 } mm_shot;
 
 /* Fill *p with defaults (sponge 0.015, CPML R = 1e-3, cfl 0.5, ...). */
@@ -198,7 +218,8 @@ mm_status mm_reset(mm_ctx* ctx);
 mm_status mm_state_size(const mm_ctx* ctx, size_t* bytes);
 
 /* Copy the state to / from a caller device buffer.  Layout per shot, in
- * shot order: p^{k-1} [nz][ny][nx], p^k [nz][ny][nx] (float32), then for
+ * shot order (acoustic_iso: p^k, u_x, u_y, u_z at k - 1/2, each
+ * [nz][ny][nx]); acoustic_iso_cd: p^{k-1} [nz][ny][nx], p^k [nz][ny][nx] (float32), then for
  * CPML psi_x, psi_y, psi_z, zeta_x, zeta_y, zeta_z in slab layout:
  * x-slabs [nz][ny][2nb], y-slabs [nz][2nb][nx], z-slabs [2nb][ny][nx],
  * where slab index s < nb is grid index s and s >= nb is grid index

@@ -24,6 +24,8 @@ namespace {
 // Order-8 central weights: second derivative a_m, first derivative beta_m.
 const double kA2[4] = {8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
 const double kB1[4] = {4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
+// staggered order-8 first difference (acoustic_iso)
+const double kS1[4] = {1225.0 / 1024.0, -245.0 / 3072.0, 49.0 / 5120.0, -5.0 / 7168.0};
 const double kPi = 3.14159265358979323846;
 
 thread_local std::string g_err;  // last error without a context
@@ -103,6 +105,7 @@ struct Layout {
     std::vector<size_t> buf0, buf1, vdt2, prof, ebuf0, ebuf1;
     std::vector<size_t> psi[3], zeta[3], corr[3];
     std::vector<size_t> apsi[3], azeta[3], acorr[3];  // CPML adjoint memory and corrections
+    std::vector<size_t> iso_u[3], iso_fb[3];           // acoustic_iso face velocities and coefficients
     size_t src_shot = 0, src_off = 0, src_start = 0, src_col = 0, src_g = 0;
     size_t rin_shot = 0, rin_off = 0, rin_start = 0, rin_col = 0, rin_g = 0;
     size_t rg_shot = 0, rg_off = 0, sg_shot = 0, sg_off = 0;
@@ -163,6 +166,11 @@ void compute_layout(const mm_params& p, const std::vector<ShotGeom>& shots, int 
         }
         L.ebuf0.push_back(L.adjoint ? take(L, fb) : 0);
         L.ebuf1.push_back(L.adjoint ? take(L, fb) : 0);
+        for (int a = 0; a < 3; ++a) {
+            const bool iso = p.model == MM_MODEL_ISO;
+            L.iso_u[a].push_back(iso ? take(L, fb) : 0);
+            L.iso_fb[a].push_back(iso ? take(L, fb) : 0);
+        }
     }
     L.src_shot = take(L, sizeof(int) * nsrc);
     L.src_off = take(L, sizeof(long long) * nsrc);
@@ -233,8 +241,13 @@ void cpml_table(int n, int nb, double h, double dt, double vmax, double R, doubl
 }
 
 double dt_stab(const mm_params& p, double vmax) {
-    const double S = 4.0 * (kA2[0] + kA2[2]);
     const double sum = 1.0 / (p.dx * p.dx) + 1.0 / (p.dy * p.dy) + 1.0 / (p.dz * p.dz);
+    if (p.model == MM_MODEL_ISO) {
+        // staggered leapfrog: the checkerboard symbol of D+ is 2 C / h, C = c1 - c2 + c3 - c4
+        const double C = kS1[0] - kS1[1] + kS1[2] - kS1[3];
+        return 1.0 / (C * vmax * std::sqrt(sum));
+    }
+    const double S = 4.0 * (kA2[0] + kA2[2]);
     return 2.0 / (vmax * std::sqrt(S * sum));
 }
 
@@ -284,6 +297,7 @@ struct mm_ctx {
     std::vector<std::vector<long long>> src_cells;  // per shot, for tile flags
     Coefs cf{};
     bool sponge = false, cpml = false;
+    bool iso = false;  // acoustic_iso (staggered first-order system)
     // time state
     int step = 0;
     bool fwd_valid = true;
@@ -362,6 +376,14 @@ mm_status check_params(const mm_params* p, mm_ctx* c) {
     if (p->tile < -1 || p->tile >= num_tile_variants()) return fail(c, MM_ERR_ARG, "unknown tile variant");
     if (p->group_kb < -1) return fail(c, MM_ERR_ARG, "group_kb must be >= -1");
     if (p->free_surface != 0 && p->free_surface != 1) return fail(c, MM_ERR_ARG, "free_surface must be 0 or 1");
+    if (p->model != MM_MODEL_ISO_CD && p->model != MM_MODEL_ISO) return fail(c, MM_ERR_ARG, "unknown model");
+    if (p->model == MM_MODEL_ISO) {
+        if (p->bc == MM_BC_CPML) return fail(c, MM_ERR_UNSUPPORTED, "acoustic_iso supports bc none and sponge");
+        if (p->free_surface) return fail(c, MM_ERR_UNSUPPORTED, "acoustic_iso has no free surface");
+        if (p->ckpt_every > 0) return fail(c, MM_ERR_UNSUPPORTED, "acoustic_iso has no adjoint (ckpt_every must be 0)");
+        if (p->tile > 0 && !iso_variant_ok(p->tile))
+            return fail(c, MM_ERR_ARG, "acoustic_iso runs the 256-thread tile variants only");
+    }
     return MM_OK;
 }
 
@@ -389,6 +411,7 @@ mm_status check_shot(const mm_params* p, const mm_shot& s, int idx, bool need_ve
     if (p->bc == MM_BC_CPML && (s.ny > 65535 || s.nz > 65535 || (long long)s.ny * s.nz > (1LL << 30)))
         return fail(c, MM_ERR_ARG, "CPML grids need ny, nz <= 65535");
     if (need_vel && !s.vel) return fail(c, MM_ERR_ARG, "velocity pointer is NULL");
+    if (need_vel && p->model == MM_MODEL_ISO && !s.rho) return fail(c, MM_ERR_ARG, "acoustic_iso needs a density model");
     if (s.nsrc < 0 || s.nrec < 0) return fail(c, MM_ERR_ARG, "negative source/receiver count");
     if ((s.nsrc > 0 && !s.src_ijk) || (s.nrec > 0 && !s.rec_ijk))
         return fail(c, MM_ERR_ARG, "source/receiver list is NULL");
@@ -509,6 +532,8 @@ mm_status zero_state(mm_ctx* c, hipStream_t s) {
     for (size_t i = 0; i < c->geom.size(); ++i) {
         const long long n = c->geom[i].n();
         const ShotDev& sd = c->shots_h[i];
+        if (c->iso)
+            for (int a = 0; a < 3; ++a) MM_TRY(dev(c, launch_fill(sd.u[a], n, 0.0f, s), "fill"));
         MM_TRY(dev(c, launch_fill(sd.buf[0], n, 0.0f, s), "fill"));
         MM_TRY(dev(c, launch_fill(sd.buf[1], n, 0.0f, s), "fill"));
         if (c->cpml) {
@@ -574,6 +599,11 @@ mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, co
     }
     const TileEnt* tiles = g ? c->d_tiles + g->tile_off : c->d_tiles;
     const int nt = g ? g->ntiles : c->ntiles;
+    if (c->iso) {
+        MM_TRY(dev(c, launch_iso_step(c->variant, c->p.bc, tiles, nt, shots, parity, c->cf, s, ev0, ev1),
+                   "acoustic_iso launch"));
+        return MM_OK;
+    }
     MM_TRY(dev(c, launch_step(c->variant, c->p.bc, mode, tiles, nt, shots, parity, c->cf, aux, s, ev0, ev1),
                "stencil launch"));
     return MM_OK;
@@ -676,7 +706,7 @@ mm_status enqueue_forward(mm_ctx* c, int nsteps, const float* wav, float* traces
             StepAux aux = none;
             aux.src_scale = c->src_inj.scale;
             aux.wrow = c->nsrc > 0 ? wav + (size_t)j * c->nsrc : nullptr;
-            if (j > 0 && traces && rg.n > 0) {
+            if (j > 0 && traces && rg.n > 0 && !c->iso) {
                 // the stencil launch also records the previous step's receivers
                 aux.g_shot = rg.shot;
                 aux.g_off = rg.off;
@@ -687,6 +717,9 @@ mm_status enqueue_forward(mm_ctx* c, int nsteps, const float* wav, float* traces
             MM_TRY(enqueue_step(c, c->d_shots, parity, MODE_PLAIN, aux, s, &g));
             if (inj.ncell > 0 && !c->inline_src)
                 MM_TRY(dev(c, launch_inject(inj, c->d_shots, parity, aux.wrow, c->nsrc, MODE_PLAIN, none, s), "inject"));
+            if (c->iso && traces && rg.n > 0 && j + 1 < nsteps)
+                MM_TRY(dev(c, launch_gather(rg, c->d_shots, parity, traces + (size_t)j * c->nrec + g.rec0, s),
+                           "record"));
         }
         if (nsteps > 0 && traces && rg.n > 0)
             MM_TRY(dev(c, launch_gather(rg, c->d_shots, (c->step + nsteps - 1) & 1,
@@ -769,7 +802,7 @@ mm_status enqueue_adjoint(mm_ctx* c, int nsteps, const float* resid, float* adj_
 }
 
 std::string tune_key(const mm_ctx* c) {
-    std::string k = std::to_string(c->p.bc) + "/" + std::to_string(c->p.nb);
+    std::string k = std::to_string(c->p.model) + "/" + std::to_string(c->p.bc) + "/" + std::to_string(c->p.nb);
     for (const auto& g : c->groups) k += "/" + std::to_string(g.s1 - g.s0);
     for (const auto& g : c->geom) k += ":" + std::to_string(g.nx) + "x" + std::to_string(g.ny) + "x" + std::to_string(g.nz);
     return k;
@@ -880,6 +913,7 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
     c->nrec = nrec;
     c->sponge = p->bc == MM_BC_SPONGE;
     c->cpml = p->bc == MM_BC_CPML;
+    c->iso = p->model == MM_MODEL_ISO;
     hipStream_t s = c->stream;
     auto bail = [&](mm_status st) {
         g_err = c->err;
@@ -900,6 +934,18 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
     for (int i = 0; i < nshots; ++i) {
         st = dev(c, launch_vcheck(shots[i].vel, geom[i].n(), c->vcheck, s), "velocity check");
         if (st) return bail(st);
+    }
+    if (c->iso) {
+        // the density must be finite and positive too (its maximum goes to a second slot)
+        unsigned* dchk = c->vcheck + 2;
+        st = dev(c, launch_fill(reinterpret_cast<float*>(dchk), 2, 0.0f, s), "fill");
+        for (int i = 0; i < nshots && !st; ++i)
+            st = dev(c, launch_vcheck(shots[i].rho, geom[i].n(), dchk, s), "density check");
+        unsigned dres[2] = {0, 0};
+        if (!st) st = dev(c, hipMemcpyAsync(dres, dchk, sizeof dres, hipMemcpyDeviceToHost, s), "readback");
+        if (!st) st = dev(c, hipStreamSynchronize(s), "sync");
+        if (st) return bail(st);
+        if (dres[1]) return bail(fail(c, MM_ERR_NONFINITE, "density has NaN, Inf or non-positive values"));
     }
     unsigned vres[2] = {0, 0};
     st = dev(c, hipMemcpyAsync(vres, c->vcheck, sizeof vres, hipMemcpyDeviceToHost, s), "readback");
@@ -927,6 +973,9 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
         c->cf.bx[m] = (float)(kB1[m] / h[0]);
         c->cf.by[m] = (float)(kB1[m] / h[1]);
         c->cf.bz[m] = (float)(kB1[m] / h[2]);
+        c->cf.sx[m] = (float)(kS1[m] / h[0]);
+        c->cf.sy[m] = (float)(kS1[m] / h[1]);
+        c->cf.sz[m] = (float)(kS1[m] / h[2]);
     }
 
     // shot descriptors and 1D boundary tables
@@ -949,6 +998,10 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
         sd.nb = p->nb;
         sd.cw = p->nb;
         sd.fs = p->free_surface;
+        for (int a = 0; a < 3; ++a) {
+            sd.u[a] = c->iso ? at<float>(c->ws, L.iso_u[a][i]) : nullptr;
+            sd.fb[a] = c->iso ? at<float>(c->ws, L.iso_fb[a][i]) : nullptr;
+        }
         c->shots_h.push_back(sd);
         ShotDev sa = sd;
         sa.nsrc_in = 0;
@@ -1021,7 +1074,7 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
     build_csr(s_shot, s_off, s_g, cs);
     build_csr(r_shot, r_off, r_g, cr);
     // sources are added inside the stencil kernel when no shot has more than MAX_INLINE_SRC
-    c->inline_src = true;
+    c->inline_src = !c->iso;  // acoustic_iso adds every source with the injection kernel
     for (int i = 0; i < nshots; ++i) c->inline_src = c->inline_src && shots[i].nsrc <= MAX_INLINE_SRC;
     c->src_cells.assign(nshots, {});
     {
@@ -1117,6 +1170,13 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
         }
     }
     for (int i = 0; i < nshots && !st; ++i) {
+        if (c->iso) {
+            const ShotDev& q = c->shots_h[i];
+            st = dev(c, launch_iso_setup(shots[i].vel, shots[i].rho, geom[i].nx, geom[i].ny, geom[i].nz, c->dt, q.vdt2,
+                                         q.fb[0], q.fb[1], q.fb[2], s),
+                     "coefficients");
+            continue;
+        }
         st = dev(c, launch_vdt2(shots[i].vel, c->shots_h[i].vdt2, geom[i].n(), c->dt, s), "vdt2");
         // free surface: (dt v)^2 = 0 on plane z = 0 keeps p = 0 there (the state starts at 0)
         if (!st && p->free_surface)
@@ -1269,7 +1329,7 @@ mm_status mm_state_size(const mm_ctx* c, size_t* bytes) {
     if (!c || !bytes) return fail(nullptr, MM_ERR_ARG, "NULL argument");
     size_t b = 0;
     for (const auto& g : c->geom) {
-        b += 2 * sizeof(float) * (size_t)g.n();
+        b += (c->iso ? 4 : 2) * sizeof(float) * (size_t)g.n();
         if (c->cpml) {
             const size_t nb2 = 2 * (size_t)c->p.nb;
             b += 2 * sizeof(float) * ((size_t)g.nz * g.ny * nb2 + (size_t)g.nz * nb2 * g.nx + nb2 * g.ny * g.nx);
@@ -1291,6 +1351,12 @@ static mm_status state_copy(mm_ctx* c, char* ext, bool to_ext) {
     for (size_t i = 0; i < c->geom.size(); ++i) {
         const auto& g = c->geom[i];
         const size_t fb = sizeof(float) * (size_t)g.n();
+        if (c->iso) {
+            // acoustic_iso: p^k, then u_x, u_y, u_z at k - 1/2
+            MM_TRY(cp(c->shots_h[i].buf[par], fb));
+            for (int a = 0; a < 3; ++a) MM_TRY(cp(c->shots_h[i].u[a], fb));
+            continue;
+        }
         MM_TRY(cp(c->shots_h[i].buf[par ^ 1], fb));
         MM_TRY(cp(c->shots_h[i].buf[par], fb));
         if (c->cpml) {
@@ -1344,6 +1410,7 @@ const char* mm_tile_name(int32_t t) { return (t >= 0 && t < num_tile_variants())
 mm_status mm_set_tile(mm_ctx* c, int32_t t) {
     if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
     if (t < 0 || t >= num_tile_variants()) return fail(c, MM_ERR_ARG, "unknown tile variant");
+    if (c->iso && !iso_variant_ok(t)) return fail(c, MM_ERR_ARG, "acoustic_iso runs the 256-thread tile variants only");
     drop_graph(c);
     return set_variant(c, t);
 }
@@ -1359,6 +1426,7 @@ mm_status mm_autotune(mm_ctx* c, int32_t steps, int32_t* tile_out) {
     const StepAux none{};  // trial steps inject nothing (no wavelet row)
     mm_status st = MM_OK;
     for (int v = 0; v < num_tile_variants() && !st; ++v) {
+        if (c->iso && !iso_variant_ok(v)) continue;
         st = set_variant(c, v);
         for (const auto& g : c->groups)
             for (int j = 0; j < 2 && !st; ++j) st = enqueue_step(c, c->d_shots, j & 1, MODE_PLAIN, none, c->stream, &g);

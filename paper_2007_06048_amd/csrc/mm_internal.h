@@ -21,6 +21,11 @@ struct ShotDev {
     int nsrc_in;          // sources added inside the stencil kernel (0..4)
     int src_col[4];       // their columns in the wavelet row
     long long src_off[4]; // their cells
+    // acoustic_iso (staggered grid): vdt2 holds dt rho v^2; u[a] the particle
+    // velocity on the faces (index i of u_x is the face i+1/2), fb[a] dt times
+    // the face buoyancy
+    float* u[3];
+    float* fb[3];
 };
 
 enum { MAX_INLINE_SRC = 4 };
@@ -39,6 +44,7 @@ enum { TF_LX = 1, TF_LY = 2, TF_LZ = 4, TF_SRC = 8 };
 struct Coefs {
     float cx[4], cy[4], cz[4];
     float bx[4], by[4], bz[4];
+    float sx[4], sy[4], sz[4];  // staggered first-difference weights c_m / h (acoustic_iso)
 };
 
 // Point injection table in CSR form: unique cells, each with the list of
@@ -113,6 +119,17 @@ hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int 
 void cpml_block_table(const int* nx, const int* ny, const int* nz, int nshots, int width, int* off);
 hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, bool adjoint, const int* block_off_dev,
                        const int* block_off_host, int parity, const Coefs& cf, hipStream_t s);
+// acoustic_iso: one step is launch_iso_u (u^{n+1/2} from p^n = buf[parity])
+// then launch_iso_p (p^{n+1} into buf[parity ^ 1]), over the same tile
+// table as the stencil kernel; bc 0 none, 1 sponge.  Sources are added by
+// launch_inject (vdt2 = dt rho v^2).  ev0 / ev1 (may be null) receive the
+// start of the first and the end of the second kernel.
+hipError_t launch_iso_step(int variant, int bc, const TileEnt* tiles, int ntiles, const ShotDev* shots, int parity,
+                           const Coefs& cf, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+bool iso_variant_ok(int variant);
+// dt rho v^2 and the three face coefficients dt b of one shot
+hipError_t launch_iso_setup(const float* vel, const float* rho, int nx, int ny, int nz, double dt, float* kdt,
+                            float* fbx, float* fby, float* fbz, hipStream_t s);
 hipError_t launch_inject(const InjTab& tab, const ShotDev* shots, int parity, const float* vals, int ncols,
                          int mode, const StepAux& aux, hipStream_t s);
 hipError_t launch_gather(const GatherTab& tab, const ShotDev* shots, int parity, float* out, hipStream_t s);

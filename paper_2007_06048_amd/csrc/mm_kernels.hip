@@ -453,6 +453,355 @@ hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int 
 #undef MM_T
 }
 
+// ------------------------------------------------------------ acoustic_iso
+//
+// The first-order variable-density system (paper, Eq. (acoustic_iso_vd)) on
+// the staggered grid, two z-marching kernels per step over the stencil
+// kernel's tile table:
+//   k_iso_u:  u_a^{n+1/2} = G (u_a^{n-1/2} + (dt b_a) D+_a p^n),  a = x, y, z,
+//   k_iso_p:  p^{n+1} = G (p^n + (dt rho v^2) (D-_x u_x + D-_y u_y + D-_z u_z)),
+// with the order-8 staggered differences D+ p (face i+1/2) = sum_m c_m
+// (p(i+m) - p(i+1-m)) / h and D- u (cell i) = sum_m c_m (u(i+m-1) - u(i-m)) / h
+// (index i of u_x is the face i+1/2), zero outside the grid.  p^n lives in
+// LDS (x / y neighbours) and a register queue (z); in k_iso_p, u_x and u_y
+// are staged in LDS with their x / y halos and u_z in a register queue.
+// Sources are added to p^{n+1} by k_inject (dt rho v^2 s).
+
+template <int TX, int RY>
+struct IsoTile {
+    static constexpr int BY = 256 / TX, TY = BY * RY, YH = 8 / BY;
+};
+
+template <int TX, int RY, int BC>
+__global__ __launch_bounds__(256) void k_iso_u(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd,
+                                               const ShotDev* __restrict__ shots, int parity, Coefs cf) {
+    constexpr int BY = IsoTile<TX, RY>::BY, TY = IsoTile<TX, RY>::TY, YH = IsoTile<TX, RY>::YH;
+    constexpr int LW = TX + 8;
+    constexpr bool SPONGE = BC == 1;
+    __shared__ float lds[2][TY + 8][LW];
+    const int b = blockIdx.x;
+    const int t = (b & 7) * per_xcd + (b >> 3);
+    if (t >= ntiles) return;
+    const TileEnt te = tiles[t];
+    const ShotDev& sd = shots[te.shot];
+    const int nx = sd.nx, ny = sd.ny, nz = sd.nz;
+    const long long plane = (long long)nx * ny;
+    const float* __restrict__ pc = sd.buf[parity];
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int x = te.x0 + tx;
+    const bool xin = x < nx;
+    int row[RY];
+    bool in[RY];
+    unsigned voc[RY], vox[RY], voy[YH];
+    const int hcol = tx < 4 ? te.x0 - 4 + tx : te.x0 + TX + (tx - 4);
+    const bool hx_lane = tx < 8 && hcol >= 0 && hcol < nx;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        row[r] = te.y0 + ty + r * BY;
+        in[r] = xin && row[r] < ny;
+        voc[r] = in[r] ? (unsigned)(row[r] * nx + x) * 4u : OOB;
+        vox[r] = (hx_lane && row[r] < ny) ? (unsigned)(row[r] * nx + hcol) * 4u : OOB;
+    }
+#pragma unroll
+    for (int h = 0; h < YH; ++h) {
+        const int hr = ty + h * BY;
+        const int y = hr < 4 ? te.y0 - 4 + hr : te.y0 + TY + (hr - 4);
+        voy[h] = (xin && y >= 0 && y < ny) ? (unsigned)(y * nx + x) * 4u : OOB;
+    }
+    float gx = 1.0f, gyv[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) gyv[r] = 1.0f;
+    if (SPONGE) {
+        gx = xin ? sd.prof[x] : 1.0f;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) gyv[r] = in[r] ? sd.prof[nx + row[r]] : 1.0f;
+    }
+    const int z0 = te.z0, z1 = te.z1;
+    // p queue: planes z-4 .. z+4 (D+ at the face z+1/2 uses z-3 .. z+4)
+    float q[RY][9];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const int z = z0 - 4 + m;
+        const bool zin = z >= 0 && z < nz;
+        const __amdgpu_buffer_rsrc_t rp = plane_rsrc(pc, zin ? z : 0, plane);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) q[r][m] = zin ? bload(rp, voc[r]) : 0.0f;
+    }
+    float nq[RY], nxh[RY], nyh[YH], nu[3][RY], nf[3][RY];
+    auto fetch = [&](int zn) {
+        const bool hin = zn + 4 < nz;
+        const __amdgpu_buffer_rsrc_t rh = plane_rsrc(pc, hin ? zn + 4 : 0, plane);
+        const __amdgpu_buffer_rsrc_t rc = plane_rsrc(pc, zn, plane);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            nq[r] = hin ? bload(rh, voc[r]) : 0.0f;
+            nxh[r] = bload(rc, vox[r]);
+        }
+#pragma unroll
+        for (int h = 0; h < YH; ++h) nyh[h] = bload(rc, voy[h]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const __amdgpu_buffer_rsrc_t ru = plane_rsrc(sd.u[a], zn, plane);
+            const __amdgpu_buffer_rsrc_t rf = plane_rsrc(sd.fb[a], zn, plane);
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                nu[a][r] = bload(ru, voc[r]);
+                nf[a][r] = bload(rf, voc[r]);
+            }
+        }
+    };
+    if (z0 < z1) fetch(z0);
+    const int xx = 4 + tx;
+    for (int z = z0; z < z1; ++z) {
+        float cu[3][RY], cfb[3][RY], cxh[RY], cyh[YH];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            q[r][8] = nq[r];
+            cxh[r] = nxh[r];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                cu[a][r] = nu[a][r];
+                cfb[a][r] = nf[a][r];
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < YH; ++h) cyh[h] = nyh[h];
+        if (z + 1 < z1) fetch(z + 1);
+        float(*L)[LW] = lds[z & 1];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            L[4 + ty + r * BY][xx] = q[r][4];
+            if (tx < 8) L[4 + ty + r * BY][tx < 4 ? tx : TX + tx] = cxh[r];
+        }
+#pragma unroll
+        for (int h = 0; h < YH; ++h) {
+            const int hr = ty + h * BY;
+            L[hr < 4 ? hr : TY + hr][xx] = cyh[h];
+        }
+        __syncthreads();
+        const float gz = SPONGE ? sd.prof[nx + ny + z] : 1.0f;
+        const long long zoff = (long long)z * plane;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const int yy = 4 + ty + r * BY;
+            float dx = 0.0f, dy = 0.0f, dz = 0.0f;
+#pragma unroll
+            for (int m = 1; m <= 4; ++m) {
+                dx = fmaf(cf.sx[m - 1], L[yy][xx + m] - L[yy][xx + 1 - m], dx);
+                dy = fmaf(cf.sy[m - 1], L[yy + m][xx] - L[yy + 1 - m][xx], dy);
+                dz = fmaf(cf.sz[m - 1], q[r][4 + m] - q[r][5 - m], dz);
+            }
+            if (in[r]) {
+                const long long o = zoff + (row[r] * nx + x);
+                const float G = SPONGE ? gx * gyv[r] * gz : 1.0f;
+                ((gfloat*)sd.u[0])[o] = G * fmaf(cfb[0][r], dx, cu[0][r]);
+                ((gfloat*)sd.u[1])[o] = G * fmaf(cfb[1][r], dy, cu[1][r]);
+                ((gfloat*)sd.u[2])[o] = G * fmaf(cfb[2][r], dz, cu[2][r]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RY; ++r)
+#pragma unroll
+            for (int m = 0; m < 8; ++m) q[r][m] = q[r][m + 1];
+    }
+}
+
+template <int TX, int RY, int BC>
+__global__ __launch_bounds__(256) void k_iso_p(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd,
+                                               const ShotDev* __restrict__ shots, int parity, Coefs cf) {
+    constexpr int BY = IsoTile<TX, RY>::BY, TY = IsoTile<TX, RY>::TY, YH = IsoTile<TX, RY>::YH;
+    constexpr int LW = TX + 8;
+    constexpr bool SPONGE = BC == 1;
+    __shared__ float lx[2][TY][LW];      // u_x of the plane with its x halo
+    __shared__ float ly[2][TY + 8][TX];  // u_y of the plane with its y halo
+    const int b = blockIdx.x;
+    const int t = (b & 7) * per_xcd + (b >> 3);
+    if (t >= ntiles) return;
+    const TileEnt te = tiles[t];
+    const ShotDev& sd = shots[te.shot];
+    const int nx = sd.nx, ny = sd.ny, nz = sd.nz;
+    const long long plane = (long long)nx * ny;
+    const float* __restrict__ pc = sd.buf[parity];
+    gfloat* __restrict__ pn = (gfloat*)sd.buf[parity ^ 1];
+    const float* __restrict__ kd = sd.vdt2;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int x = te.x0 + tx;
+    const bool xin = x < nx;
+    int row[RY];
+    bool in[RY];
+    unsigned voc[RY], vox[RY], voy[YH];
+    const int hcol = tx < 4 ? te.x0 - 4 + tx : te.x0 + TX + (tx - 4);
+    const bool hx_lane = tx < 8 && hcol >= 0 && hcol < nx;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        row[r] = te.y0 + ty + r * BY;
+        in[r] = xin && row[r] < ny;
+        voc[r] = in[r] ? (unsigned)(row[r] * nx + x) * 4u : OOB;
+        vox[r] = (hx_lane && row[r] < ny) ? (unsigned)(row[r] * nx + hcol) * 4u : OOB;
+    }
+#pragma unroll
+    for (int h = 0; h < YH; ++h) {
+        const int hr = ty + h * BY;
+        const int y = hr < 4 ? te.y0 - 4 + hr : te.y0 + TY + (hr - 4);
+        voy[h] = (xin && y >= 0 && y < ny) ? (unsigned)(y * nx + x) * 4u : OOB;
+    }
+    float gx = 1.0f, gyv[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) gyv[r] = 1.0f;
+    if (SPONGE) {
+        gx = xin ? sd.prof[x] : 1.0f;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) gyv[r] = in[r] ? sd.prof[nx + row[r]] : 1.0f;
+    }
+    const int z0 = te.z0, z1 = te.z1;
+    // u_z queue: planes z-4 .. z+3 (D- at cell z uses them all)
+    float w[RY][8];
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+        const int z = z0 - 4 + m;
+        const bool zin = z >= 0 && z < nz;
+        const __amdgpu_buffer_rsrc_t rp = plane_rsrc(sd.u[2], zin ? z : 0, plane);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) w[r][m] = zin ? bload(rp, voc[r]) : 0.0f;
+    }
+    float nw[RY], nux[RY], nuxh[RY], nuy[RY], nuyh[YH], np_[RY], nk[RY];
+    auto fetch = [&](int zn) {
+        const bool hin = zn + 3 < nz;
+        const __amdgpu_buffer_rsrc_t rw = plane_rsrc(sd.u[2], hin ? zn + 3 : 0, plane);
+        const __amdgpu_buffer_rsrc_t rx = plane_rsrc(sd.u[0], zn, plane);
+        const __amdgpu_buffer_rsrc_t ry = plane_rsrc(sd.u[1], zn, plane);
+        const __amdgpu_buffer_rsrc_t rpc = plane_rsrc(pc, zn, plane);
+        const __amdgpu_buffer_rsrc_t rk = plane_rsrc(kd, zn, plane);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            nw[r] = hin ? bload(rw, voc[r]) : 0.0f;
+            nux[r] = bload(rx, voc[r]);
+            nuxh[r] = bload(rx, vox[r]);
+            nuy[r] = bload(ry, voc[r]);
+            np_[r] = bload(rpc, voc[r]);
+            nk[r] = bload(rk, voc[r]);
+        }
+#pragma unroll
+        for (int h = 0; h < YH; ++h) nuyh[h] = bload(ry, voy[h]);
+    };
+    if (z0 < z1) fetch(z0);
+    const int xx = 4 + tx;
+    for (int z = z0; z < z1; ++z) {
+        float cux[RY], cuxh[RY], cuy[RY], cuyh[YH], cp[RY], ck[RY];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            w[r][7] = nw[r];
+            cux[r] = nux[r];
+            cuxh[r] = nuxh[r];
+            cuy[r] = nuy[r];
+            cp[r] = np_[r];
+            ck[r] = nk[r];
+        }
+#pragma unroll
+        for (int h = 0; h < YH; ++h) cuyh[h] = nuyh[h];
+        if (z + 1 < z1) fetch(z + 1);
+        float(*X)[LW] = lx[z & 1];
+        float(*Y)[TX] = ly[z & 1];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            X[ty + r * BY][xx] = cux[r];
+            if (tx < 8) X[ty + r * BY][tx < 4 ? tx : TX + tx] = cuxh[r];
+            Y[4 + ty + r * BY][tx] = cuy[r];
+        }
+#pragma unroll
+        for (int h = 0; h < YH; ++h) {
+            const int hr = ty + h * BY;
+            Y[hr < 4 ? hr : TY + hr][tx] = cuyh[h];
+        }
+        __syncthreads();
+        const float gz = SPONGE ? sd.prof[nx + ny + z] : 1.0f;
+        const long long zoff = (long long)z * plane;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const int yr = ty + r * BY;
+            float dx = 0.0f, dy = 0.0f, dz = 0.0f;
+#pragma unroll
+            for (int m = 1; m <= 4; ++m) {
+                dx = fmaf(cf.sx[m - 1], X[yr][xx + m - 1] - X[yr][xx - m], dx);
+                dy = fmaf(cf.sy[m - 1], Y[4 + yr + m - 1][tx] - Y[4 + yr - m][tx], dy);
+                dz = fmaf(cf.sz[m - 1], w[r][3 + m] - w[r][4 - m], dz);
+            }
+            if (in[r]) {
+                const long long o = zoff + (row[r] * nx + x);
+                const float G = SPONGE ? gx * gyv[r] * gz : 1.0f;
+                pn[o] = G * fmaf(ck[r], (dx + dy) + dz, cp[r]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RY; ++r)
+#pragma unroll
+            for (int m = 0; m < 7; ++m) w[r][m] = w[r][m + 1];
+    }
+}
+
+template <int TX, int RY>
+static hipError_t launch_iso_t(int bc, dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd, const ShotDev* shots,
+                               int parity, const Coefs& cf, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    const dim3 block(TX, 256 / TX);
+    if (bc == 1) {
+        hipExtLaunchKernelGGL(k_iso_u<TX, RY, 1>, grid, block, 0, s, ev0, nullptr, 0, tiles, ntiles, per_xcd, shots,
+                              parity, cf);
+        hipExtLaunchKernelGGL(k_iso_p<TX, RY, 1>, grid, block, 0, s, nullptr, ev1, 0, tiles, ntiles, per_xcd, shots,
+                              parity, cf);
+    } else {
+        hipExtLaunchKernelGGL(k_iso_u<TX, RY, 0>, grid, block, 0, s, ev0, nullptr, 0, tiles, ntiles, per_xcd, shots,
+                              parity, cf);
+        hipExtLaunchKernelGGL(k_iso_p<TX, RY, 0>, grid, block, 0, s, nullptr, ev1, 0, tiles, ntiles, per_xcd, shots,
+                              parity, cf);
+    }
+    return hipGetLastError();
+}
+
+bool iso_variant_ok(int variant) { return variant >= 0 && variant < num_tile_variants() && kTiles[variant].nt == 256; }
+
+hipError_t launch_iso_step(int variant, int bc, const TileEnt* tiles, int ntiles, const ShotDev* shots, int parity,
+                           const Coefs& cf, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (ntiles <= 0) return hipSuccess;
+    if (!iso_variant_ok(variant) || (bc != 0 && bc != 1)) return hipErrorInvalidValue;
+    const int per_xcd = (ntiles + 7) / 8;
+    const dim3 grid(8 * per_xcd);
+    const TileShape& ts = kTiles[variant];
+    if (ts.tx == 64) {
+        if (ts.ry == 2) return launch_iso_t<64, 2>(bc, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
+        if (ts.ry == 4) return launch_iso_t<64, 4>(bc, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
+        return launch_iso_t<64, 8>(bc, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
+    }
+    if (ts.ry == 1) return launch_iso_t<32, 1>(bc, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
+    if (ts.ry == 2) return launch_iso_t<32, 2>(bc, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
+    return launch_iso_t<32, 4>(bc, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
+}
+
+__global__ __launch_bounds__(256) void k_iso_setup(const float* __restrict__ vel, const float* __restrict__ rho,
+                                                   int nx, int ny, int nz, double dt, float* __restrict__ kdt,
+                                                   float* __restrict__ fbx, float* __restrict__ fby,
+                                                   float* __restrict__ fbz) {
+    const long long plane = (long long)nx * ny, n = plane * nz;
+    for (long long o = blockIdx.x * 256LL + threadIdx.x; o < n; o += (long long)gridDim.x * 256) {
+        const int x = (int)(o % nx), y = (int)((o / nx) % ny), z = (int)(o / plane);
+        const double r0 = rho[o], v = vel[o];
+        const double b0 = 1.0 / r0;
+        kdt[o] = (float)(dt * r0 * v * v);
+        // the face buoyancy: mean of 1/rho of the two cells beside the face
+        fbx[o] = (float)(dt * (x + 1 < nx ? 0.5 * (b0 + 1.0 / (double)rho[o + 1]) : b0));
+        fby[o] = (float)(dt * (y + 1 < ny ? 0.5 * (b0 + 1.0 / (double)rho[o + nx]) : b0));
+        fbz[o] = (float)(dt * (z + 1 < nz ? 0.5 * (b0 + 1.0 / (double)rho[o + plane]) : b0));
+    }
+}
+
+hipError_t launch_iso_setup(const float* vel, const float* rho, int nx, int ny, int nz, double dt, float* kdt,
+                            float* fbx, float* fby, float* fbz, hipStream_t s) {
+    const long long n = (long long)nx * ny * nz;
+    if (n <= 0) return hipSuccess;
+    const long long blocks = std::min<long long>((n + 255) / 256, 65536);
+    k_iso_setup<<<dim3((unsigned)blocks), 256, 0, s>>>(vel, rho, nx, ny, nz, dt, kdt, fbx, fby, fbz);
+    return hipGetLastError();
+}
+
 // -------------------------------------------------------------------- CPML
 //
 // One launch per step, before the stencil kernel, one thread per cell of the

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libminimod.so")
 MM_OK, MM_ERR_ARG, MM_ERR_UNSTABLE, MM_ERR_WORKSPACE, MM_ERR_DEVICE, MM_ERR_STATE, MM_ERR_NONFINITE, \
     MM_ERR_UNSUPPORTED = range(8)
 BC_NONE, BC_SPONGE, BC_CPML = 0, 1, 2
+MODEL_ISO_CD, MODEL_ISO = 0, 1
 SNAP_FP32, SNAP_BF16 = 0, 1
 
 # every symbol declared in include/minimod.h
@@ -36,7 +37,7 @@ class Params(ctypes.Structure):
         ("sponge_sigma", ctypes.c_double), ("cpml_R", ctypes.c_double), ("cpml_f0", ctypes.c_double),
         ("ckpt_every", ctypes.c_int32), ("snap", ctypes.c_int32), ("nsteps_max", ctypes.c_int32),
         ("tile", ctypes.c_int32), ("group_kb", ctypes.c_int32),
-        ("free_surface", ctypes.c_int32),
+        ("free_surface", ctypes.c_int32), ("model", ctypes.c_int32),
     ]
 
 
@@ -46,6 +47,7 @@ class Shot(ctypes.Structure):
         ("vel", ctypes.c_void_p),
         ("src_ijk", ctypes.POINTER(ctypes.c_int32)), ("nsrc", ctypes.c_int32),
         ("rec_ijk", ctypes.POINTER(ctypes.c_int32)), ("nrec", ctypes.c_int32),
+        ("rho", ctypes.c_void_p),
     ]
 
 
@@ -152,7 +154,8 @@ def _ptr(t):
 
 class Context:
     """A propagator over one or more shots (sub-volumes) sharing spacing, dt,
-    boundary and width.  `shots` is a list of (vel, src, rec) where vel is a
+    boundary and width.  `shots` is a list of (vel, src, rec) or (vel, src,
+    rec, rho) where vel (and rho, the density of an acoustic_iso model) is a
     float32 CUDA tensor [nz][ny][nx] and src/rec are (n, 3) int arrays of
     (i, j, k) cells."""
 
@@ -164,17 +167,23 @@ class Context:
         arr = (Shot * len(shots))()
         self.nsrc = self.nrec = 0
         self.shapes = []
-        for i, (vel, src, rec) in enumerate(shots):
+        for i, shot in enumerate(shots):
+            vel, src, rec = shot[:3]
+            rho = shot[3] if len(shot) > 3 else None
             assert vel.is_cuda and vel.dtype == torch.float32 and vel.is_contiguous() and vel.dim() == 3
+            if rho is not None:
+                assert rho.is_cuda and rho.dtype == torch.float32 and rho.is_contiguous() and rho.shape == vel.shape
             nz, ny, nx = vel.shape
             s, r = _pts(src), _pts(rec)
-            self._keep += [vel, s, r]
+            self._keep += [vel, s, r, rho]
             arr[i] = Shot(nx, ny, nz, vel.data_ptr(), s.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(s),
-                          r.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(r))
+                          r.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(r),
+                          rho.data_ptr() if rho is not None else None)
             self.nsrc += len(s)
             self.nrec += len(r)
             self.shapes.append((nz, ny, nx))
         self.device = shots[0][0].device
+        self.iso = params.model == MODEL_ISO
         nbytes = ctypes.c_size_t()
         _check(lib.mm_workspace_size(ctypes.byref(params), len(shots), arr, ctypes.byref(nbytes)))
         self.ws_bytes = nbytes.value
@@ -187,8 +196,8 @@ class Context:
         self.h = h
 
     @classmethod
-    def single(cls, params, vel, src, rec, stream=None):
-        return cls(params, [(vel, src, rec)], stream)
+    def single(cls, params, vel, src, rec, stream=None, rho=None):
+        return cls(params, [(vel, src, rec) if rho is None else (vel, src, rec, rho)], stream)
 
     def __del__(self):
         h = getattr(self, "h", None)

@@ -28,6 +28,7 @@ class Shot:
     src: np.ndarray                 # int32 [nsrc][3]
     rec: np.ndarray                 # int32 [nrec][3]
     origin: tuple = (0, 0, 0)       # (i, j, k) of the sub-volume in the big model
+    rho: Optional[np.ndarray] = None  # float32 [nz][ny][nx] density (acoustic_iso)
 
 
 @dataclass
@@ -216,3 +217,17 @@ def random_points(rng, n, shape, margin=0):
     nz, ny, nx = shape
     return np.stack([rng.integers(margin, nx - margin, n), rng.integers(margin, ny - margin, n),
                      rng.integers(margin, nz - margin, n)], axis=1).astype(np.int32)
+
+
+def smooth_iso(n=240, nsteps=1000):
+    """acoustic_iso workload: the smooth 1500-4500 m/s model of smooth_240
+    (seed 2, sigma 8 cells, at size n) with Gardner's density rho = 310 v^0.25
+    (kg/m^3, v in m/s; the paper's models are internal, so this standard
+    velocity-density relation stands in); 20-cell sponge; Ricker 20 Hz at
+    (n/2, n/2, n/12); receivers on the full plane z = n/24; nsteps steps."""
+    v = smooth_random((n, n, n), 8.0 * n / 240, 1500.0, 4500.0, seed=2)
+    rho = 310.0 * v ** 0.25
+    src = np.array([[n // 2, n // 2, n // 12]], dtype=np.int32)
+    w = Workload(f"smooth_iso_{n}^3_sponge20_{nsteps}steps", n, n, n, 10.0, nsteps, BC_SPONGE, 20, 20.0, 0.075,
+                 shots=[Shot(v.astype(np.float32), src, plane(n, n, n // 24), rho=rho.astype(np.float32))])
+    return w
