@@ -215,6 +215,45 @@ def gradient_leg(dev, reps=2):
     return res
 
 
+def iso_leg(dev, reps=2):
+    """acoustic_iso (first-order variable-density system, staggered grid) on
+    the 240^3 smooth model with Gardner density, 20-cell sponge, 1000 steps.
+    Algorithmic bytes per point and step: 40 (read and write p and the three
+    face velocities, read rho v^2 and the buoyancy); the two kernels move 64
+    (u and p are read twice, three face buoyancy arrays)."""
+    import torch
+    from paper_2007_06048_amd import minimod as mm
+    from paper_2007_06048_amd import workloads as W
+    wl = W.smooth_iso(240, 1000)
+    s = wl.shots[0]
+    T = wl.nsteps
+    p = mm.default_params(nx=wl.nx, ny=wl.ny, nz=wl.nz, dx=wl.h, dy=wl.h, dz=wl.h, cfl=wl.cfl, bc=wl.bc, nb=wl.nb,
+                          sponge_sigma=wl.sigma, model=mm.MODEL_ISO, tile=-1)
+    ctx = mm.Context.single(p, torch.from_numpy(s.vel).to(dev), s.src, s.rec, rho=torch.from_numpy(s.rho).to(dev))
+    w = torch.from_numpy(mm.ricker(wl.f0, wl.t0, ctx.dt, T)).to(dev).reshape(T, 1)
+    tr = torch.empty((T, len(s.rec)), dtype=torch.float32, device=dev)
+
+    def run():
+        ctx.reset()
+        ctx.forward(T, w, tr)
+
+    t = _timed(run, reps)
+    ctx.profile(10)
+    ctx.profile_read()
+    run()
+    k_ms, k_n = ctx.profile_read()
+    ctx.profile(0)
+    pts = wl.nx * wl.ny * wl.nz
+    step_s = t / T
+    ach = 40.0 * pts / step_s / 1e9
+    return {"workload": wl.name, "run_s": round(t, 4), "gpts": round(pts * T / t / 1e9, 2),
+            "us_per_step": round(step_s * 1e6, 2), "tile": mm.tile_name(ctx.info()["tile"]),
+            "kernels_us_per_step": round(k_ms / max(k_n, 1) * 1e3, 2),
+            "roofline": {"bound": "hbm", "alg_bytes_per_point": 40, "achieved": round(ach, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                         "kernel_bytes_per_point": 64}}
+
+
 def free_surface_leg(dev, reps=2):
     """The bench workload (240^3, CPML-20, 1000 steps) with a free surface on
     the top face instead of the top CPML layer."""
@@ -416,6 +455,8 @@ def main():
         out["batched"] = batched_leg(dev)
         torch.cuda.empty_cache()
         out["free_surface"] = free_surface_leg(dev)
+        torch.cuda.empty_cache()
+        out["acoustic_iso"] = iso_leg(dev)
         torch.cuda.empty_cache()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
