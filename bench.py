@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 ALG_BYTES_STENCIL = 16  # read p^n, p^{n-1}, (dt v)^2; write p^{n+1}  (bytes per grid point)
+ALG_BYTES_ISO = 40      # acoustic_iso: read and write p and the three face velocities, read rho v^2 and buoyancy
 
 
 def kernel_hash():
@@ -42,6 +43,8 @@ def load_workload(name):
         return W.layered_1024()
     if name == "twolayer64":
         return W.two_layer_64()
+    if name == "smoothiso":
+        return W.smooth_iso()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -363,11 +366,13 @@ def main():
     if args.time_steps > 0:
         wl.nsteps = args.time_steps
     T = wl.nsteps
+    iso = s.rho is not None  # the acoustic_iso workload carries a density model
     p = mm.default_params(nx=wl.nx, ny=wl.ny, nz=wl.nz, dx=wl.h, dy=wl.h, dz=wl.h, cfl=wl.cfl, bc=wl.bc, nb=wl.nb,
-                          sponge_sigma=wl.sigma, cpml_R=wl.cpml_R, cpml_f0=wl.f0, tile=args.tile)
+                          sponge_sigma=wl.sigma, cpml_R=wl.cpml_R, cpml_f0=wl.f0, tile=args.tile,
+                          model=mm.MODEL_ISO if iso else mm.MODEL_ISO_CD)
     vel = torch.from_numpy(s.vel).to(dev)
     t_init0 = time.perf_counter()
-    ctx = mm.Context.single(p, vel, s.src, s.rec)
+    ctx = mm.Context.single(p, vel, s.src, s.rec, rho=torch.from_numpy(s.rho).to(dev) if iso else None)
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t_init0
     dt = ctx.dt
@@ -405,13 +410,16 @@ def main():
         torch.cuda.synchronize()
 
     roof = None
+    alg_pt = ALG_BYTES_ISO if iso else ALG_BYTES_STENCIL
     if k_n > 0:
         avg_ms = k_ms / k_n
-        bytes_launch = ALG_BYTES_STENCIL * pts
+        bytes_launch = alg_pt * pts
         ach = bytes_launch / (avg_ms / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_for(wl.name),
-                "kernel": "k_step (stencil + sponge/leapfrog update)", "avg_launch_us": round(avg_ms * 1e3, 2),
+                "kernel": ("k_iso_u + k_iso_p (face velocities, then pressure)" if iso else
+                           "k_step (stencil + sponge/leapfrog update)"),
+                "avg_launch_us": round(avg_ms * 1e3, 2),
                 "alg_bytes_per_launch": bytes_launch, "timed_launches": k_n,
                 "timed_every": args.prof_stride}
 
@@ -421,7 +429,7 @@ def main():
     if wl.bc == 2:
         for n, m in ((wl.nx, wl.ny * wl.nz), (wl.ny, wl.nx * wl.nz), (wl.nz, wl.nx * wl.ny)):
             damped_axis_pts += 2 * wl.nb * m
-    step_bytes = ALG_BYTES_STENCIL * pts + 16 * damped_axis_pts
+    step_bytes = alg_pt * pts + 16 * damped_axis_pts
     step_ach = step_bytes / (ms_step / 1e3 / T) / 1e9
     step_roof = {"bound": "hbm", "achieved": round(step_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                  "frac": round(step_ach / HBM_PEAK_GBS, 4), "alg_bytes_per_step": step_bytes,

@@ -105,7 +105,7 @@ struct Layout {
     std::vector<size_t> buf0, buf1, vdt2, prof, ebuf0, ebuf1;
     std::vector<size_t> psi[3], zeta[3], corr[3];
     std::vector<size_t> apsi[3], azeta[3], acorr[3];  // CPML adjoint memory and corrections
-    std::vector<size_t> iso_u[3], iso_fb[3];           // acoustic_iso face velocities and coefficients
+    std::vector<size_t> iso_u[3], iso_b;              // acoustic_iso face velocities, dt / rho
     size_t src_shot = 0, src_off = 0, src_start = 0, src_col = 0, src_g = 0;
     size_t rin_shot = 0, rin_off = 0, rin_start = 0, rin_col = 0, rin_g = 0;
     size_t rg_shot = 0, rg_off = 0, sg_shot = 0, sg_off = 0;
@@ -166,11 +166,9 @@ void compute_layout(const mm_params& p, const std::vector<ShotGeom>& shots, int 
         }
         L.ebuf0.push_back(L.adjoint ? take(L, fb) : 0);
         L.ebuf1.push_back(L.adjoint ? take(L, fb) : 0);
-        for (int a = 0; a < 3; ++a) {
-            const bool iso = p.model == MM_MODEL_ISO;
-            L.iso_u[a].push_back(iso ? take(L, fb) : 0);
-            L.iso_fb[a].push_back(iso ? take(L, fb) : 0);
-        }
+        const bool iso = p.model == MM_MODEL_ISO;
+        for (int a = 0; a < 3; ++a) L.iso_u[a].push_back(iso ? take(L, fb) : 0);
+        L.iso_b.push_back(iso ? take(L, fb) : 0);
     }
     L.src_shot = take(L, sizeof(int) * nsrc);
     L.src_off = take(L, sizeof(long long) * nsrc);
@@ -998,10 +996,8 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
         sd.nb = p->nb;
         sd.cw = p->nb;
         sd.fs = p->free_surface;
-        for (int a = 0; a < 3; ++a) {
-            sd.u[a] = c->iso ? at<float>(c->ws, L.iso_u[a][i]) : nullptr;
-            sd.fb[a] = c->iso ? at<float>(c->ws, L.iso_fb[a][i]) : nullptr;
-        }
+        for (int a = 0; a < 3; ++a) sd.u[a] = c->iso ? at<float>(c->ws, L.iso_u[a][i]) : nullptr;
+        sd.bdt = c->iso ? at<float>(c->ws, L.iso_b[i]) : nullptr;
         c->shots_h.push_back(sd);
         ShotDev sa = sd;
         sa.nsrc_in = 0;
@@ -1172,8 +1168,7 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
     for (int i = 0; i < nshots && !st; ++i) {
         if (c->iso) {
             const ShotDev& q = c->shots_h[i];
-            st = dev(c, launch_iso_setup(shots[i].vel, shots[i].rho, geom[i].nx, geom[i].ny, geom[i].nz, c->dt, q.vdt2,
-                                         q.fb[0], q.fb[1], q.fb[2], s),
+            st = dev(c, launch_iso_setup(shots[i].vel, shots[i].rho, geom[i].n(), c->dt, q.vdt2, q.bdt, s),
                      "coefficients");
             continue;
         }

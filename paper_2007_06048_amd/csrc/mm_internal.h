@@ -21,11 +21,10 @@ struct ShotDev {
     int nsrc_in;          // sources added inside the stencil kernel (0..4)
     int src_col[4];       // their columns in the wavelet row
     long long src_off[4]; // their cells
-    // acoustic_iso (staggered grid): vdt2 holds dt rho v^2; u[a] the particle
-    // velocity on the faces (index i of u_x is the face i+1/2), fb[a] dt times
-    // the face buoyancy
+    // acoustic_iso (staggered grid): vdt2 holds dt rho v^2, bdt dt / rho; u[a]
+    // the particle velocity on the faces (index i of u_x is the face i+1/2)
     float* u[3];
-    float* fb[3];
+    float* bdt;
 };
 
 enum { MAX_INLINE_SRC = 4 };
@@ -127,9 +126,9 @@ hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, bool adjoint, c
 hipError_t launch_iso_step(int variant, int bc, const TileEnt* tiles, int ntiles, const ShotDev* shots, int parity,
                            const Coefs& cf, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 bool iso_variant_ok(int variant);
-// dt rho v^2 and the three face coefficients dt b of one shot
-hipError_t launch_iso_setup(const float* vel, const float* rho, int nx, int ny, int nz, double dt, float* kdt,
-                            float* fbx, float* fby, float* fbz, hipStream_t s);
+// dt rho v^2 and dt / rho of one shot (n cells)
+hipError_t launch_iso_setup(const float* vel, const float* rho, long long n, double dt, float* kdt, float* bdt,
+                            hipStream_t s);
 hipError_t launch_inject(const InjTab& tab, const ShotDev* shots, int parity, const float* vals, int ncols,
                          int mode, const StepAux& aux, hipStream_t s);
 hipError_t launch_gather(const GatherTab& tab, const ShotDev* shots, int parity, float* out, hipStream_t s);

@@ -465,7 +465,9 @@ hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int 
 // (index i of u_x is the face i+1/2), zero outside the grid.  p^n lives in
 // LDS (x / y neighbours) and a register queue (z); in k_iso_p, u_x and u_y
 // are staged in LDS with their x / y halos and u_z in a register queue.
-// Sources are added to p^{n+1} by k_inject (dt rho v^2 s).
+// Sources are added to p^{n+1} by k_inject (dt rho v^2 s).  The face
+// buoyancy is formed on the fly from dt / rho of the two cells beside the
+// face (their mean; the inner cell's value on the last face of an axis).
 
 template <int TX, int RY>
 struct IsoTile {
@@ -478,7 +480,8 @@ __global__ __launch_bounds__(256) void k_iso_u(const TileEnt* __restrict__ tiles
     constexpr int BY = IsoTile<TX, RY>::BY, TY = IsoTile<TX, RY>::TY, YH = IsoTile<TX, RY>::YH;
     constexpr int LW = TX + 8;
     constexpr bool SPONGE = BC == 1;
-    __shared__ float lds[2][TY + 8][LW];
+    __shared__ float lds[2][TY + 8][LW];  // p^n of the plane with halos
+    __shared__ float ldb[2][TY + 8][LW];  // dt / rho of the plane with halos (face buoyancy)
     const int b = blockIdx.x;
     const int t = (b & 7) * per_xcd + (b >> 3);
     if (t >= ntiles) return;
@@ -487,9 +490,11 @@ __global__ __launch_bounds__(256) void k_iso_u(const TileEnt* __restrict__ tiles
     const int nx = sd.nx, ny = sd.ny, nz = sd.nz;
     const long long plane = (long long)nx * ny;
     const float* __restrict__ pc = sd.buf[parity];
+    const float* __restrict__ bd = sd.bdt;
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int x = te.x0 + tx;
     const bool xin = x < nx;
+    const bool xlast = x + 1 >= nx;  // the last x face takes the inner cell's buoyancy
     int row[RY];
     bool in[RY];
     unsigned voc[RY], vox[RY], voy[YH];
@@ -517,8 +522,8 @@ __global__ __launch_bounds__(256) void k_iso_u(const TileEnt* __restrict__ tiles
         for (int r = 0; r < RY; ++r) gyv[r] = in[r] ? sd.prof[nx + row[r]] : 1.0f;
     }
     const int z0 = te.z0, z1 = te.z1;
-    // p queue: planes z-4 .. z+4 (D+ at the face z+1/2 uses z-3 .. z+4)
-    float q[RY][9];
+    // p queue: planes z-4 .. z+4 (D+ at the face z+1/2 uses z-3 .. z+4); buoyancy of planes z, z+1
+    float q[RY][9], b0[RY], b1[RY];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
         const int z = z0 - 4 + m;
@@ -527,59 +532,78 @@ __global__ __launch_bounds__(256) void k_iso_u(const TileEnt* __restrict__ tiles
 #pragma unroll
         for (int r = 0; r < RY; ++r) q[r][m] = zin ? bload(rp, voc[r]) : 0.0f;
     }
-    float nq[RY], nxh[RY], nyh[YH], nu[3][RY], nf[3][RY];
+    {
+        const __amdgpu_buffer_rsrc_t rb = plane_rsrc(bd, z0 < nz ? z0 : 0, plane);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) b1[r] = bload(rb, voc[r]);
+    }
+    // stage for plane zn: p^n(zn+4), halos of p and dt/rho at zn, dt/rho(zn+1), u at zn
+    float nq[RY], nxh[RY], nyh[YH], nbh[RY], nbx[RY], nby[YH], nu[3][RY];
     auto fetch = [&](int zn) {
-        const bool hin = zn + 4 < nz;
+        const bool hin = zn + 4 < nz, bin = zn + 1 < nz;
         const __amdgpu_buffer_rsrc_t rh = plane_rsrc(pc, hin ? zn + 4 : 0, plane);
         const __amdgpu_buffer_rsrc_t rc = plane_rsrc(pc, zn, plane);
+        const __amdgpu_buffer_rsrc_t rbc = plane_rsrc(bd, zn, plane);
+        const __amdgpu_buffer_rsrc_t rbn = plane_rsrc(bd, bin ? zn + 1 : 0, plane);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             nq[r] = hin ? bload(rh, voc[r]) : 0.0f;
             nxh[r] = bload(rc, vox[r]);
+            nbx[r] = bload(rbc, vox[r]);
+            nbh[r] = bin ? bload(rbn, voc[r]) : 0.0f;
         }
 #pragma unroll
-        for (int h = 0; h < YH; ++h) nyh[h] = bload(rc, voy[h]);
+        for (int h = 0; h < YH; ++h) {
+            nyh[h] = bload(rc, voy[h]);
+            nby[h] = bload(rbc, voy[h]);
+        }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const __amdgpu_buffer_rsrc_t ru = plane_rsrc(sd.u[a], zn, plane);
-            const __amdgpu_buffer_rsrc_t rf = plane_rsrc(sd.fb[a], zn, plane);
 #pragma unroll
-            for (int r = 0; r < RY; ++r) {
-                nu[a][r] = bload(ru, voc[r]);
-                nf[a][r] = bload(rf, voc[r]);
-            }
+            for (int r = 0; r < RY; ++r) nu[a][r] = bload(ru, voc[r]);
         }
     };
     if (z0 < z1) fetch(z0);
     const int xx = 4 + tx;
     for (int z = z0; z < z1; ++z) {
-        float cu[3][RY], cfb[3][RY], cxh[RY], cyh[YH];
+        float cu[3][RY], cxh[RY], cyh[YH], cbx[RY], cby[YH];
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             q[r][8] = nq[r];
             cxh[r] = nxh[r];
+            cbx[r] = nbx[r];
+            b0[r] = b1[r];
+            b1[r] = nbh[r];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                cu[a][r] = nu[a][r];
-                cfb[a][r] = nf[a][r];
-            }
+            for (int a = 0; a < 3; ++a) cu[a][r] = nu[a][r];
         }
 #pragma unroll
-        for (int h = 0; h < YH; ++h) cyh[h] = nyh[h];
+        for (int h = 0; h < YH; ++h) {
+            cyh[h] = nyh[h];
+            cby[h] = nby[h];
+        }
         if (z + 1 < z1) fetch(z + 1);
         float(*L)[LW] = lds[z & 1];
+        float(*B)[LW] = ldb[z & 1];
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             L[4 + ty + r * BY][xx] = q[r][4];
-            if (tx < 8) L[4 + ty + r * BY][tx < 4 ? tx : TX + tx] = cxh[r];
+            B[4 + ty + r * BY][xx] = b0[r];
+            if (tx < 8) {
+                L[4 + ty + r * BY][tx < 4 ? tx : TX + tx] = cxh[r];
+                B[4 + ty + r * BY][tx < 4 ? tx : TX + tx] = cbx[r];
+            }
         }
 #pragma unroll
         for (int h = 0; h < YH; ++h) {
             const int hr = ty + h * BY;
             L[hr < 4 ? hr : TY + hr][xx] = cyh[h];
+            B[hr < 4 ? hr : TY + hr][xx] = cby[h];
         }
         __syncthreads();
         const float gz = SPONGE ? sd.prof[nx + ny + z] : 1.0f;
+        const bool zlast = z + 1 >= nz;
         const long long zoff = (long long)z * plane;
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
@@ -594,9 +618,13 @@ __global__ __launch_bounds__(256) void k_iso_u(const TileEnt* __restrict__ tiles
             if (in[r]) {
                 const long long o = zoff + (row[r] * nx + x);
                 const float G = SPONGE ? gx * gyv[r] * gz : 1.0f;
-                ((gfloat*)sd.u[0])[o] = G * fmaf(cfb[0][r], dx, cu[0][r]);
-                ((gfloat*)sd.u[1])[o] = G * fmaf(cfb[1][r], dy, cu[1][r]);
-                ((gfloat*)sd.u[2])[o] = G * fmaf(cfb[2][r], dz, cu[2][r]);
+                const float bc = b0[r];
+                const float fx = xlast ? bc : 0.5f * (bc + B[yy][xx + 1]);
+                const float fy = row[r] + 1 >= ny ? bc : 0.5f * (bc + B[yy + 1][xx]);
+                const float fz = zlast ? bc : 0.5f * (bc + b1[r]);
+                ((gfloat*)sd.u[0])[o] = G * fmaf(fx, dx, cu[0][r]);
+                ((gfloat*)sd.u[1])[o] = G * fmaf(fy, dy, cu[1][r]);
+                ((gfloat*)sd.u[2])[o] = G * fmaf(fz, dz, cu[2][r]);
             }
         }
 #pragma unroll
@@ -777,28 +805,20 @@ hipError_t launch_iso_step(int variant, int bc, const TileEnt* tiles, int ntiles
 }
 
 __global__ __launch_bounds__(256) void k_iso_setup(const float* __restrict__ vel, const float* __restrict__ rho,
-                                                   int nx, int ny, int nz, double dt, float* __restrict__ kdt,
-                                                   float* __restrict__ fbx, float* __restrict__ fby,
-                                                   float* __restrict__ fbz) {
-    const long long plane = (long long)nx * ny, n = plane * nz;
+                                                   long long n, double dt, float* __restrict__ kdt,
+                                                   float* __restrict__ bdt) {
     for (long long o = blockIdx.x * 256LL + threadIdx.x; o < n; o += (long long)gridDim.x * 256) {
-        const int x = (int)(o % nx), y = (int)((o / nx) % ny), z = (int)(o / plane);
         const double r0 = rho[o], v = vel[o];
-        const double b0 = 1.0 / r0;
         kdt[o] = (float)(dt * r0 * v * v);
-        // the face buoyancy: mean of 1/rho of the two cells beside the face
-        fbx[o] = (float)(dt * (x + 1 < nx ? 0.5 * (b0 + 1.0 / (double)rho[o + 1]) : b0));
-        fby[o] = (float)(dt * (y + 1 < ny ? 0.5 * (b0 + 1.0 / (double)rho[o + nx]) : b0));
-        fbz[o] = (float)(dt * (z + 1 < nz ? 0.5 * (b0 + 1.0 / (double)rho[o + plane]) : b0));
+        bdt[o] = (float)(dt / r0);
     }
 }
 
-hipError_t launch_iso_setup(const float* vel, const float* rho, int nx, int ny, int nz, double dt, float* kdt,
-                            float* fbx, float* fby, float* fbz, hipStream_t s) {
-    const long long n = (long long)nx * ny * nz;
+hipError_t launch_iso_setup(const float* vel, const float* rho, long long n, double dt, float* kdt, float* bdt,
+                            hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const long long blocks = std::min<long long>((n + 255) / 256, 65536);
-    k_iso_setup<<<dim3((unsigned)blocks), 256, 0, s>>>(vel, rho, nx, ny, nz, dt, kdt, fbx, fby, fbz);
+    k_iso_setup<<<dim3((unsigned)blocks), 256, 0, s>>>(vel, rho, n, dt, kdt, bdt);
     return hipGetLastError();
 }
 
