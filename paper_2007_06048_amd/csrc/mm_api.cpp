@@ -1211,7 +1211,7 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
 mm_status mm_init(mm_ctx** out, const mm_params* p, const float* vel_dev, const int32_t* src, int32_t nsrc,
                   const int32_t* rec, int32_t nrec, void* workspace, size_t ws_bytes, void* hip_stream) {
     if (!p) return fail(nullptr, MM_ERR_ARG, "params is NULL");
-    mm_shot s{p->nx, p->ny, p->nz, vel_dev, src, nsrc, rec, nrec};
+    mm_shot s{p->nx, p->ny, p->nz, vel_dev, src, nsrc, rec, nrec, nullptr};
     return mm_init_batch(out, p, 1, &s, workspace, ws_bytes, hip_stream);
 }
 

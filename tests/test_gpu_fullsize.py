@@ -15,7 +15,7 @@ from oracle import c_oracle as C
 from paper_2007_06048_amd import minimod as mm
 from paper_2007_06048_amd import workloads as W
 
-from .gpu_util import DEV
+from .gpu_util import DEV, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -192,6 +192,36 @@ def test_fullsize_smooth_240_cpml_adjoint_and_gradient():
     assert grads[0][1] == grads[1][1]
     assert torch.equal(grads[0][0], grads[1][0])
     assert torch.isfinite(grads[0][0]).all() and float(grads[0][0].abs().max()) > 0
+
+
+def test_fullsize_smooth_iso_240_sponge_1000_steps():
+    """acoustic_iso at its bench size (240^3, Gardner density, 20-cell sponge,
+    autotuned tile): the GPU runs 999 steps, the FP64 oracle takes the last
+    step from that state over the whole grid, and the GPU's last step (p, the
+    three face velocities and the traces) must agree."""
+    wl = W.smooth_iso(240, 1000)
+    s = wl.shots[0]
+    p = mm.default_params(nx=wl.nx, ny=wl.ny, nz=wl.nz, dx=wl.h, dy=wl.h, dz=wl.h, cfl=wl.cfl, bc=wl.bc, nb=wl.nb,
+                          sponge_sigma=wl.sigma, model=mm.MODEL_ISO, tile=-1)
+    ctx = mm.Context.single(p, torch.from_numpy(s.vel).to(DEV), s.src, s.rec, rho=torch.from_numpy(s.rho).to(DEV))
+    T = wl.nsteps
+    w = mm.ricker(wl.f0, wl.t0, ctx.dt, T).reshape(T, 1)
+    wt = torch.from_numpy(w).to(DEV)
+    tr = torch.empty((T, len(s.rec)), dtype=torch.float32, device=DEV)
+    ctx.forward(T - 1, wt[:T - 1], tr[:T - 1])
+    before = ctx.get_state().cpu().numpy().astype(np.float64).reshape((4,) + s.vel.shape)
+    ctx.forward(1, wt[T - 1:], tr[T - 1:])
+    after = ctx.get_state().cpu().numpy().reshape((4,) + s.vel.shape)
+    torch.cuda.synchronize()
+    assert np.isfinite(after).all() and torch.isfinite(tr).all()
+    assert np.abs(after[0]).max() > 0
+    g = C.Grid(p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, ctx.dt, bc=p.bc, nb=p.nb, sigma=p.sponge_sigma)
+    rtr, rst = C.iso_forward(g, s.vel.astype(np.float64), s.rho.astype(np.float64), s.src,
+                             w[T - 1:].astype(np.float64), s.rec, 1, state=before)
+    errs = [rel(after[a], rst[a]) for a in range(4)]
+    et = rel(tr[T - 1].cpu().numpy(), rtr[0])
+    print("p, u_x, u_y, u_z", errs, "traces", et)
+    assert max(errs) <= 1e-5 and et <= 1e-5
 
 
 def test_fullsize_layered_1024x1024x512_cpml_500_steps():
