@@ -233,8 +233,12 @@ mm_status mm_set_state(mm_ctx* ctx, const void* src_dev, int32_t step);
 mm_status mm_get_info(const mm_ctx* ctx, double* dt, int32_t* step, int32_t* tile, int32_t* ngroups);
 
 /* Pick the stencil tile variant by timing each candidate on this context
- * (state is zeroed afterwards; synchronises).  Results are cached per
- * (grid, boundary) for the life of the process.  *tile_out may be NULL. */
+ * (state is zeroed afterwards; synchronises).  steps_per_trial (>= 1) is a
+ * minimum: it is raised so that one trial lasts about 2 ms (at most 200
+ * steps); every variant is timed once and the four fastest twice more,
+ * interleaved, keeping each one's best time.  Results are cached per (grid,
+ * boundary, model, grouping) for the life of the process.  *tile_out may be
+ * NULL. */
 mm_status mm_autotune(mm_ctx* ctx, int32_t steps_per_trial, int32_t* tile_out);
 
 /* Force a tile variant (0 = default).  Returns MM_ERR_ARG if unknown. */
