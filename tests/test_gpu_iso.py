@@ -62,6 +62,48 @@ def test_iso_matches_oracle(bc):
         assert rel(st[a], rst[a]) <= 1e-5, a
 
 
+@pytest.mark.parametrize("shape", [(9, 11, 1), (9, 1, 13), (1, 11, 13), (1, 1, 40), (3, 70, 5)])
+def test_iso_degenerate_grids_match_oracle(shape):
+    """One-cell-thick grids, a single column, and a grid narrower than the
+    stencil radius along x: every tile variant against the oracle (bc none,
+    sources and receivers at the grid corners)."""
+    rng = np.random.default_rng(84)
+    nz, ny, nx = shape
+    v = rng.uniform(1600.0, 3200.0, shape).astype(np.float32)
+    rho = rng.uniform(1000.0, 2500.0, shape).astype(np.float32)
+    src = np.array([[nx // 2, ny // 2, nz // 2], [0, 0, 0]], np.int32)
+    rec = np.array([[nx - 1, ny - 1, nz - 1], [nx // 2, ny // 2, nz // 2], [0, ny - 1, 0]], np.int32)
+    p = mm.default_params(nx=nx, ny=ny, nz=nz, dx=10.0, dy=12.0, dz=9.0, bc=mm.BC_NONE, model=mm.MODEL_ISO, tile=0)
+    T = 30
+    w = rng.standard_normal((T, len(src))).astype(np.float32)
+    first = None
+    for t in range(mm.num_tiles()):
+        name = mm.tile_name(t)
+        if "t512" in name or "t1024" in name:
+            continue
+        tr, st, dt = _gpu(p, v, rho, src, rec, w, T, tile=t)
+        if first is None:
+            first = (tr, st)
+            rtr, rst = _oracle(p, dt, v, rho, src, rec, w, T)
+            assert rel(tr, rtr) <= 1e-5 and all(rel(st[a], rst[a]) <= 1e-5 for a in range(4))
+        else:
+            assert np.array_equal(first[0], tr) and np.array_equal(first[1], st), name
+
+
+def test_iso_zero_steps_no_sources_no_receivers():
+    p, v, rho, src, rec, w, T = _case(mm.BC_SPONGE, seed=85, T=10)
+    vt, rt = torch.from_numpy(v).to(DEV), torch.from_numpy(rho).to(DEV)
+    ctx = mm.Context.single(p, vt, src, rec, rho=rt)
+    ctx.forward(0, torch.zeros((0, len(src)), device=DEV), torch.zeros((0, len(rec)), device=DEV))
+    assert ctx.info()["step"] == 0 and not ctx.get_state().any()
+    none = np.zeros((0, 3), np.int32)
+    tr, st, _ = _gpu(p, v, rho, none, rec, np.zeros((T, 0), np.float32), T)
+    assert not st.any() and not tr.any()  # nothing excites the field
+    tr, st, dt = _gpu(p, v, rho, src, none, w, T)
+    rtr, rst = _oracle(p, dt, v, rho, src, none, w, T)
+    assert tr.shape == (T, 0) and rel(st[0], rst[0]) <= 1e-5
+
+
 def test_iso_every_tile_variant_bitwise():
     p, v, rho, src, rec, w, T = _case(mm.BC_SPONGE, seed=81, T=60)
     first = None
