@@ -11,6 +11,7 @@ Prints ONE JSON line:
   roofline  = algorithmic bytes of the stencil kernel per launch / its average
               launch time (HIP events on the library's stream), vs 8 TB/s
   cpu_baseline = the FP64 oracle timed on the host cores on a bounded sample
+  paper_context = the paper's own serial CPU rate for a 240^3 run (context only)
 """
 import argparse
 import hashlib
@@ -468,6 +469,12 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+    # the paper's only timing of this propagator, as context (a different grid, spacing, step count
+    # and boundary width, one CPU thread on unstated hardware): section "Compilation and usage"
+    # reports 30.47 s of kernel time for 240^3 points x 300 steps
+    out["paper_context"] = {"value": round(240 ** 3 * 300 / 30.47 / 1e9, 3), "unit": "Gpt/s",
+                            "what": "paper's serial CPU run: 240^3, h 20 m, 300 steps, ndamping 27, "
+                                    "1 thread, hardware unstated; kernel time 30.47 s"}
     print(json.dumps(out), flush=True)
 
 
