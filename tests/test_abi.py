@@ -127,6 +127,28 @@ def test_workspace_size_and_argument_checks():
     assert st == mm.MM_OK and nb2 > n
 
 
+def test_acoustic_iso_dt_workspace_and_argument_checks():
+    """acoustic_iso on the host side: its dt uses the staggered scheme's
+    limit (the oracle's, not the constant-density one), its workspace holds
+    the ping-pong pressure, three face velocities, dt rho v^2 and dt / rho,
+    and CPML, free surface and adjoint storage are refused."""
+    p = mm.default_params(dx=10.0, dy=12.0, dz=8.0, cfl=0.5, model=mm.MODEL_ISO, bc=mm.BC_SPONGE, nb=4)
+    assert mm.dt_for(p, 3000.0) == pytest.approx(0.5 * C.iso_dt_stab(3000.0, 10.0, 12.0, 8.0), rel=1e-15)
+    assert mm.dt_for(p, 3000.0) < mm.dt_for(mm.default_params(dx=10.0, dy=12.0, dz=8.0, cfl=0.5), 3000.0)
+    s, keep = _shot(40, 36, 32, [[5, 5, 5]], [[1, 2, 3]])
+    st, n_iso = _ws(p, [s])
+    assert st == mm.MM_OK and n_iso >= 7 * 4 * 40 * 36 * 32
+    st, n_cd = _ws(mm.default_params(dx=10.0, dy=12.0, dz=8.0, cfl=0.5, bc=mm.BC_SPONGE, nb=4), [s])
+    assert st == mm.MM_OK and n_iso - n_cd >= 4 * 4 * 40 * 36 * 32
+    for field, val in (("bc", mm.BC_CPML), ("free_surface", 1), ("ckpt_every", 8)):
+        q = mm.default_params(model=mm.MODEL_ISO, bc=mm.BC_SPONGE, nb=4, nsteps_max=10)
+        setattr(q, field, val)
+        st, _ = _ws(q, [s])
+        assert st == mm.MM_ERR_UNSUPPORTED, field
+    q = mm.default_params(model=2)
+    assert _ws(q, [s])[0] == mm.MM_ERR_ARG
+
+
 def test_init_rejects_bad_workspace_before_touching_the_device():
     p = mm.default_params(nx=32, ny=32, nz=32, bc=mm.BC_SPONGE, nb=8)
     s, keep = _shot(32, 32, 32, [[5, 5, 5]], [[1, 2, 3]])
