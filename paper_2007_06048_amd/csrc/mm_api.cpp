@@ -37,6 +37,20 @@ struct ShotGeom {
     long long n() const { return (long long)nx * ny * nz; }
 };
 
+// Bytes one forward step of a shot touches: three fields, and for CPML the
+// memory (psi, zeta) and correction slabs.
+double shot_set_bytes(const mm_params& p, const ShotGeom& q) {
+    double b = 12.0 * q.n();
+    if (p.bc == MM_BC_CPML) {
+        const double nb2 = 2.0 * p.nb;
+        b += 12.0 * ((double)q.nz * q.ny * nb2 + (double)q.nz * nb2 * q.nx + nb2 * q.ny * q.nx);
+    }
+    return b;
+}
+
+// Infinity Cache (memory-side last-level cache) of one MI355X
+constexpr double kInfinityCacheBytes = 256.0 * 1024.0 * 1024.0;
+
 // Shot groups of a batch: consecutive shots whose working set (three
 // fields, CPML memory and corrections) fits the budget; every shot alone if
 // it is larger.  One group holds all shots when the budget is negative.
@@ -46,12 +60,7 @@ std::vector<std::pair<int, int>> make_groups(const mm_params& p, const std::vect
     int s0 = 0;
     double acc = 0.0;
     for (int s = 0; s < (int)shots.size(); ++s) {
-        const ShotGeom& q = shots[s];
-        double b = 12.0 * q.n();
-        if (p.bc == MM_BC_CPML) {
-            const double nb2 = 2.0 * p.nb;
-            b += 12.0 * ((double)q.nz * q.ny * nb2 + (double)q.nz * nb2 * q.nx + nb2 * q.ny * q.nx);
-        }
+        const double b = shot_set_bytes(p, shots[s]);
         if (s > s0 && acc + b > budget) {
             g.push_back({s0, s});
             s0 = s;
@@ -287,8 +296,10 @@ struct mm_ctx {
         int cell0, cell1;      // source cells of the injection table
         std::vector<int> cpml_h;  // CPML block table of the group (host copy)
         const int* cpml_d = nullptr;
+        bool stream = false;      // working set beyond the Infinity Cache (StepAux::stream_loads)
     };
     std::vector<Group> groups;
+    bool stream_all = false;      // the same for all shots together (adjoint steps)
     std::vector<int> cpml_adj_h;  // CPML block table of the adjoint (all shots, width nb + 4)
     const int* cpml_adj_d = nullptr;
     bool inline_src = false;
@@ -602,7 +613,9 @@ mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, co
                    "acoustic_iso launch"));
         return MM_OK;
     }
-    MM_TRY(dev(c, launch_step(c->variant, c->p.bc, mode, tiles, nt, shots, parity, c->cf, aux, s, ev0, ev1),
+    StepAux a = aux;
+    a.stream_loads = (g ? g->stream : c->stream_all) ? 1 : 0;
+    MM_TRY(dev(c, launch_step(c->variant, c->p.bc, mode, tiles, nt, shots, parity, c->cf, a, s, ev0, ev1),
                "stencil launch"));
     return MM_OK;
 }
@@ -1125,10 +1138,16 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
         int cpml_pos = 0;
         std::vector<int> rec_start(nshots + 1, 0);
         for (int i = 0; i < nshots; ++i) rec_start[i + 1] = rec_start[i] + shots[i].nrec;
+        double all_bytes = 0.0;
+        for (const auto& q : geom) all_bytes += shot_set_bytes(*p, q);
+        c->stream_all = all_bytes > kInfinityCacheBytes;
         for (const auto& gr : make_groups(*p, geom)) {
             mm_ctx::Group g;
             g.s0 = gr.first;
             g.s1 = gr.second;
+            double bytes = 0.0;
+            for (int i = g.s0; i < g.s1; ++i) bytes += shot_set_bytes(*p, geom[i]);
+            g.stream = bytes > kInfinityCacheBytes;
             g.tile_off = g.ntiles = 0;
             g.rec0 = rec_start[g.s0];
             g.rec1 = rec_start[g.s1];

@@ -84,6 +84,10 @@ struct StepAux {
     int g_n;
     int gather_blocks;  // multiple of 8 (keeps the XCD pattern of the tile blocks)
     float* gather_out;
+    // 1: in forward steps p^{n-1} and (dt v)^2, read once per step, are
+    // loaded with the non-temporal hint (set when the step's working set
+    // exceeds the Infinity Cache, so they do not evict the reused p^n)
+    int stream_loads;
 };
 
 enum { MODE_PLAIN = 0, MODE_D2P = 1, MODE_IMAGE = 2 };

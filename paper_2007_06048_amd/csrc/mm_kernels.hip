@@ -49,6 +49,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float* base, 
 __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned voff) {
     return __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, 0, 0));
 }
+// the same with the non-temporal hint (aux bit 1): for data read once per step
+__device__ __forceinline__ float bload_nt(__amdgpu_buffer_rsrc_t r, unsigned voff) {
+    return __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, 0, 2));
+}
 
 // shapes (TX, RY) x z-chunking targets (total blocks over all shots; chunks
 // are at least 4 planes) with one plane of prefetch, plus a few two-plane
@@ -91,7 +95,7 @@ int tile_rows(int t) { return (kTiles[t].nt / kTiles[t].tx) * kTiles[t].ry; }
 // SIMD instead of 6 for the CPML forward and the imaging instantiations);
 // they fit without spilling, the larger shapes and the CPML replay / imaging
 // modes would not.
-template <int TX, int RY, int PD, int BC, int MODE, int NT>
+template <int TX, int RY, int PD, int BC, int MODE, int NT, bool STREAM>
 __global__ __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu((PD == 1 && RY <= 2 && !(BC == 2 && MODE != MODE_PLAIN)) ? 7 : 1)))
 void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const ShotDev* __restrict__ shots,
@@ -214,6 +218,7 @@ void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const Sh
     // prefetch stages: stage k holds the loads for plane z + k (queue head p^n(z+k+4),
     // p^{n-1}(z+k), (dt v)^2(z+k), the x / y halos of plane z+k)
     float nq[PD][RY], npp[PD][RY], nvd[PD][RY], nxh[PD][RY], nyh[PD][YH];
+    constexpr bool stream = STREAM;  // working set beyond the Infinity Cache: p^{n-1}, (dt v)^2 non-temporal
     constexpr int RC = CPML ? RY : 1;
     float ncr[PD][RC];  // sum of the CPML corrections of the cell (0 outside the layers)
     auto fetch = [&](int k, int zn) {
@@ -225,8 +230,8 @@ void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const Sh
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             nq[k][r] = hin ? bload(rh, voc[r]) : 0.0f;
-            npp[k][r] = bload(rm, voc[r]);
-            nvd[k][r] = bload(rv, voc[r]);
+            npp[k][r] = stream ? bload_nt(rm, voc[r]) : bload(rm, voc[r]);
+            nvd[k][r] = stream ? bload_nt(rv, voc[r]) : bload(rv, voc[r]);
             nxh[k][r] = bload(rc, vox[r]);
         }
         if (hy_row) {
@@ -368,22 +373,26 @@ void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const Sh
     }
 }
 
-template <int TX, int RY, int PD, int BC, int MODE, int NT>
+template <int TX, int RY, int PD, int BC, int MODE, int NT, bool STREAM = false>
 static void launch_step_k(dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd, const ShotDev* shots, int parity,
                           const Coefs& cf, const StepAux& aux, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const dim3 block(TX, NT / TX);
     if (ev0)
-        hipExtLaunchKernelGGL(k_step<TX, RY, PD, BC, MODE, NT>, grid, block, 0, s, ev0, ev1, 0, tiles, ntiles,
-                              per_xcd, shots, parity, cf, aux);
+        hipExtLaunchKernelGGL(k_step<TX, RY, PD, BC, MODE, NT, STREAM>, grid, block, 0, s, ev0, ev1, 0, tiles,
+                              ntiles, per_xcd, shots, parity, cf, aux);
     else
-        k_step<TX, RY, PD, BC, MODE, NT><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf, aux);
+        k_step<TX, RY, PD, BC, MODE, NT, STREAM><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf,
+                                                                      aux);
 }
 
 template <int TX, int RY, int PD, int BC, int NT>
 static hipError_t launch_step_bc(int mode, dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd,
                                  const ShotDev* shots, int parity, const Coefs& cf, const StepAux& aux,
                                  hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    if (mode == MODE_PLAIN)
+    if (mode == MODE_PLAIN && aux.stream_loads)
+        launch_step_k<TX, RY, PD, BC, MODE_PLAIN, NT, true>(grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s,
+                                                            ev0, ev1);
+    else if (mode == MODE_PLAIN)
         launch_step_k<TX, RY, PD, BC, MODE_PLAIN, NT>(grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0,
                                                       ev1);
     else if (mode == MODE_D2P)
