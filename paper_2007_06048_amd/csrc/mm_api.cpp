@@ -38,8 +38,10 @@ struct ShotGeom {
 };
 
 // Bytes one forward step of a shot touches: three fields, and for CPML the
-// memory (psi, zeta) and correction slabs.
+// memory (psi, zeta) and correction slabs; acoustic_iso: two pressure fields,
+// three face velocities, dt rho v^2 and dt / rho.
 double shot_set_bytes(const mm_params& p, const ShotGeom& q) {
+    if (p.model == MM_MODEL_ISO) return 28.0 * q.n();
     double b = 12.0 * q.n();
     if (p.bc == MM_BC_CPML) {
         const double nb2 = 2.0 * p.nb;
@@ -609,7 +611,8 @@ mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, co
     const TileEnt* tiles = g ? c->d_tiles + g->tile_off : c->d_tiles;
     const int nt = g ? g->ntiles : c->ntiles;
     if (c->iso) {
-        MM_TRY(dev(c, launch_iso_step(c->variant, c->p.bc, tiles, nt, shots, parity, c->cf, s, ev0, ev1),
+        MM_TRY(dev(c, launch_iso_step(c->variant, c->p.bc, g ? g->stream : c->stream_all, tiles, nt, shots, parity,
+                                      c->cf, s, ev0, ev1),
                    "acoustic_iso launch"));
         return MM_OK;
     }

@@ -125,10 +125,13 @@ hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, bool adjoint, c
 // acoustic_iso: one step is launch_iso_u (u^{n+1/2} from p^n = buf[parity])
 // then launch_iso_p (p^{n+1} into buf[parity ^ 1]), over the same tile
 // table as the stencil kernel; bc 0 none, 1 sponge.  Sources are added by
-// launch_inject (vdt2 = dt rho v^2).  ev0 / ev1 (may be null) receive the
-// start of the first and the end of the second kernel.
-hipError_t launch_iso_step(int variant, int bc, const TileEnt* tiles, int ntiles, const ShotDev* shots, int parity,
-                           const Coefs& cf, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// launch_inject (vdt2 = dt rho v^2).  stream: the working set exceeds the
+// Infinity Cache (non-temporal loads of data read for the last time).  ev0 /
+// ev1 (may be null) receive the start of the first and the end of the second
+// kernel.
+hipError_t launch_iso_step(int variant, int bc, bool stream, const TileEnt* tiles, int ntiles, const ShotDev* shots,
+                           int parity, const Coefs& cf, hipStream_t s, hipEvent_t ev0 = nullptr,
+                           hipEvent_t ev1 = nullptr);
 bool iso_variant_ok(int variant);
 // dt rho v^2 and dt / rho of one shot (n cells)
 hipError_t launch_iso_setup(const float* vel, const float* rho, long long n, double dt, float* kdt, float* bdt,

@@ -643,7 +643,9 @@ __global__ __launch_bounds__(256) void k_iso_u(const TileEnt* __restrict__ tiles
     }
 }
 
-template <int TX, int RY, int BC>
+// STREAM: the working set exceeds the Infinity Cache, so p^n (its last read
+// of the step) and dt rho v^2 (read once) are loaded with the non-temporal hint
+template <int TX, int RY, int BC, bool STREAM>
 __global__ __launch_bounds__(256) void k_iso_p(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd,
                                                const ShotDev* __restrict__ shots, int parity, Coefs cf) {
     constexpr int BY = IsoTile<TX, RY>::BY, TY = IsoTile<TX, RY>::TY, YH = IsoTile<TX, RY>::YH;
@@ -715,8 +717,8 @@ __global__ __launch_bounds__(256) void k_iso_p(const TileEnt* __restrict__ tiles
             nux[r] = bload(rx, voc[r]);
             nuxh[r] = bload(rx, vox[r]);
             nuy[r] = bload(ry, voc[r]);
-            np_[r] = bload(rpc, voc[r]);
-            nk[r] = bload(rk, voc[r]);
+            np_[r] = STREAM ? bload_nt(rpc, voc[r]) : bload(rpc, voc[r]);
+            nk[r] = STREAM ? bload_nt(rk, voc[r]) : bload(rk, voc[r]);
         }
 #pragma unroll
         for (int h = 0; h < YH; ++h) nuyh[h] = bload(ry, voy[h]);
@@ -776,41 +778,48 @@ __global__ __launch_bounds__(256) void k_iso_p(const TileEnt* __restrict__ tiles
     }
 }
 
-template <int TX, int RY>
-static hipError_t launch_iso_t(int bc, dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd, const ShotDev* shots,
-                               int parity, const Coefs& cf, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+template <int TX, int RY, int BC>
+static void launch_iso_bc(bool stream, dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd, const ShotDev* shots,
+                          int parity, const Coefs& cf, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const dim3 block(TX, 256 / TX);
-    if (bc == 1) {
-        hipExtLaunchKernelGGL(k_iso_u<TX, RY, 1>, grid, block, 0, s, ev0, nullptr, 0, tiles, ntiles, per_xcd, shots,
-                              parity, cf);
-        hipExtLaunchKernelGGL(k_iso_p<TX, RY, 1>, grid, block, 0, s, nullptr, ev1, 0, tiles, ntiles, per_xcd, shots,
-                              parity, cf);
-    } else {
-        hipExtLaunchKernelGGL(k_iso_u<TX, RY, 0>, grid, block, 0, s, ev0, nullptr, 0, tiles, ntiles, per_xcd, shots,
-                              parity, cf);
-        hipExtLaunchKernelGGL(k_iso_p<TX, RY, 0>, grid, block, 0, s, nullptr, ev1, 0, tiles, ntiles, per_xcd, shots,
-                              parity, cf);
-    }
+    hipExtLaunchKernelGGL(k_iso_u<TX, RY, BC>, grid, block, 0, s, ev0, nullptr, 0, tiles, ntiles, per_xcd, shots,
+                          parity, cf);
+    if (stream)
+        hipExtLaunchKernelGGL(k_iso_p<TX, RY, BC, true>, grid, block, 0, s, nullptr, ev1, 0, tiles, ntiles, per_xcd,
+                              shots, parity, cf);
+    else
+        hipExtLaunchKernelGGL(k_iso_p<TX, RY, BC, false>, grid, block, 0, s, nullptr, ev1, 0, tiles, ntiles, per_xcd,
+                              shots, parity, cf);
+}
+
+template <int TX, int RY>
+static hipError_t launch_iso_t(int bc, bool stream, dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd,
+                               const ShotDev* shots, int parity, const Coefs& cf, hipStream_t s, hipEvent_t ev0,
+                               hipEvent_t ev1) {
+    if (bc == 1)
+        launch_iso_bc<TX, RY, 1>(stream, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
+    else
+        launch_iso_bc<TX, RY, 0>(stream, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
     return hipGetLastError();
 }
 
 bool iso_variant_ok(int variant) { return variant >= 0 && variant < num_tile_variants() && kTiles[variant].nt == 256; }
 
-hipError_t launch_iso_step(int variant, int bc, const TileEnt* tiles, int ntiles, const ShotDev* shots, int parity,
-                           const Coefs& cf, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+hipError_t launch_iso_step(int variant, int bc, bool stream, const TileEnt* tiles, int ntiles, const ShotDev* shots,
+                           int parity, const Coefs& cf, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (ntiles <= 0) return hipSuccess;
     if (!iso_variant_ok(variant) || (bc != 0 && bc != 1)) return hipErrorInvalidValue;
     const int per_xcd = (ntiles + 7) / 8;
     const dim3 grid(8 * per_xcd);
     const TileShape& ts = kTiles[variant];
     if (ts.tx == 64) {
-        if (ts.ry == 2) return launch_iso_t<64, 2>(bc, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
-        if (ts.ry == 4) return launch_iso_t<64, 4>(bc, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
-        return launch_iso_t<64, 8>(bc, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
+        if (ts.ry == 2) return launch_iso_t<64, 2>(bc, stream, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
+        if (ts.ry == 4) return launch_iso_t<64, 4>(bc, stream, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
+        return launch_iso_t<64, 8>(bc, stream, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
     }
-    if (ts.ry == 1) return launch_iso_t<32, 1>(bc, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
-    if (ts.ry == 2) return launch_iso_t<32, 2>(bc, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
-    return launch_iso_t<32, 4>(bc, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
+    if (ts.ry == 1) return launch_iso_t<32, 1>(bc, stream, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
+    if (ts.ry == 2) return launch_iso_t<32, 2>(bc, stream, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
+    return launch_iso_t<32, 4>(bc, stream, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
 }
 
 __global__ __launch_bounds__(256) void k_iso_setup(const float* __restrict__ vel, const float* __restrict__ rho,
