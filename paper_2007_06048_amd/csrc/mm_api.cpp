@@ -587,12 +587,12 @@ mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, co
     if (c->cpml) {
         if (shots == c->d_shots) {
             if (!g) return fail(c, MM_ERR_STATE, "forward CPML step without a shot group");
-            MM_TRY(dev(c, launch_cpml(shots + g->s0, g->s1 - g->s0, c->p.nb, false, g->cpml_d, g->cpml_h.data(), parity,
-                                      c->cf, s),
+            MM_TRY(dev(c, launch_cpml(shots + g->s0, g->s1 - g->s0, c->p.nb, false, g->stream, g->cpml_d,
+                                      g->cpml_h.data(), parity, c->cf, s),
                        "cpml launch"));
         } else {
-            MM_TRY(dev(c, launch_cpml(shots, (int)c->geom.size(), c->p.nb, true, c->cpml_adj_d, c->cpml_adj_h.data(),
-                                      parity, c->cf, s),
+            MM_TRY(dev(c, launch_cpml(shots, (int)c->geom.size(), c->p.nb, true, false, c->cpml_adj_d,
+                                      c->cpml_adj_h.data(), parity, c->cf, s),
                        "adjoint cpml launch"));
         }
     }

@@ -118,9 +118,10 @@ hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int 
 // 4 cells past the layer (nb <= 64).  The block table (3 (nshots + 1) ints,
 // made by cpml_block_table with width nb, or nb + 4 for the adjoint) is
 // passed both as the device copy the kernel reads and as the host copy that
-// sizes the grid.
+// sizes the grid.  stream (forward only): psi and zeta are loaded with the
+// non-temporal hint (the step's working set exceeds the Infinity Cache).
 void cpml_block_table(const int* nx, const int* ny, const int* nz, int nshots, int width, int* off);
-hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, bool adjoint, const int* block_off_dev,
+hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, bool adjoint, bool stream, const int* block_off_dev,
                        const int* block_off_host, int parity, const Coefs& cf, hipStream_t s);
 // acoustic_iso: one step is launch_iso_u (u^{n+1/2} from p^n = buf[parity])
 // then launch_iso_p (p^{n+1} into buf[parity ^ 1]), over the same tile

@@ -254,21 +254,21 @@ void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const Sh
                     const __amdgpu_buffer_rsrc_t cx = __builtin_amdgcn_make_buffer_rsrc(
                         (void*)(sd.corr[0] + zn * pxs), (short)0, (int)(pxs * 4), 0x00020000);
 #pragma unroll
-                    for (int r = 0; r < RC; ++r) a[r] = bload(cx, vcx[r]);
+                    for (int r = 0; r < RC; ++r) a[r] = stream ? bload_nt(cx, vcx[r]) : bload(cx, vcx[r]);
                 }
                 if (te.flags & TF_LY) {
                     const long long pys = (long long)cw2 * nx;
                     const __amdgpu_buffer_rsrc_t cy = __builtin_amdgcn_make_buffer_rsrc(
                         (void*)(sd.corr[1] + zn * pys), (short)0, (int)(pys * 4), 0x00020000);
 #pragma unroll
-                    for (int r = 0; r < RC; ++r) b[r] = bload(cy, vcy[r]);
+                    for (int r = 0; r < RC; ++r) b[r] = stream ? bload_nt(cy, vcy[r]) : bload(cy, vcy[r]);
                 }
                 if ((te.flags & TF_LZ) && (zn < cw || zn >= nz - cw)) {
                     const int zs = zn < cw ? zn : zn - (nz - cw2);
                     const __amdgpu_buffer_rsrc_t cz = __builtin_amdgcn_make_buffer_rsrc(
                         (void*)(sd.corr[2] + (long long)zs * plane), (short)0, (int)(plane * 4), 0x00020000);
 #pragma unroll
-                    for (int r = 0; r < RC; ++r) c[r] = bload(cz, voc[r]);
+                    for (int r = 0; r < RC; ++r) c[r] = stream ? bload_nt(cz, voc[r]) : bload(cz, voc[r]);
                 }
 #pragma unroll
                 for (int r = 0; r < RC; ++r) ncr[k][r] = (a[r] + b[r]) + c[r];
@@ -881,6 +881,14 @@ __device__ __forceinline__ int find_shot(const int* off, int nshots, int b) {
     return lo;
 }
 
+// NT: psi and zeta (read once per step) are loaded with the non-temporal hint
+template <bool NT>
+__device__ __forceinline__ float once(const float* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <bool NT>
 __device__ void cpml_x_block(const ShotDev& sd, int parity, const Coefs& cf, int blk, int rpb, float* lds) {
     const int nx = sd.nx, ny = sd.ny, nz = sd.nz, nb = sd.nb, nb2 = 2 * nb;
     const int e = threadIdx.x;
@@ -907,7 +915,7 @@ __device__ void cpml_x_block(const ShotDev& sd, int parity, const Coefs& cf, int
                 d1 = fmaf(cf.bx[m - 1], fp - fm, d1);
                 d2 = fmaf(cf.cx[m - 1], (fp - c) + (fm - c), d2);
             }
-            const float pv = fmaf(b, ps[si], a * d1);
+            const float pv = fmaf(b, once<NT>(ps + si), a * d1);
             ps[si] = pv;
             lds[e] = pv;
         }
@@ -920,7 +928,7 @@ __device__ void cpml_x_block(const ShotDev& sd, int parity, const Coefs& cf, int
                 const float vm = sl - m >= lo ? lds[e - m] : 0.0f;
                 dpsi = fmaf(cf.bx[m - 1], vp - vm, dpsi);
             }
-            const float zn = fmaf(b, ze[si], a * (d2 + dpsi));
+            const float zn = fmaf(b, once<NT>(ze + si), a * (d2 + dpsi));
             ze[si] = zn;
             co[si] = dpsi + zn;
         }
@@ -930,7 +938,7 @@ __device__ void cpml_x_block(const ShotDev& sd, int parity, const Coefs& cf, int
 
 // y (AX = 1) or z (AX = 2) layers of one end: block = 64 x-columns, thread row
 // ty takes cells ty, ty + 4, ... of the nb cells; w is z (AX = 1) or y (AX = 2).
-template <int AX>
+template <int AX, bool NT>
 __device__ void cpml_yz_block(const ShotDev& sd, int parity, const Coefs& cf, int xblk, int w, int side, float* lds) {
     const int nx = sd.nx, ny = sd.ny, nz = sd.nz, nb = sd.nb, nb2 = 2 * nb;
     if (w >= (AX == 2 ? ny : nz)) return;  // whole block
@@ -964,7 +972,7 @@ __device__ void cpml_yz_block(const ShotDev& sd, int parity, const Coefs& cf, in
                 d2 = fmaf(AX == 2 ? cf.cz[m - 1] : cf.cy[m - 1], (fp - c) + (fm - c), d2);
             }
             const long long si = sbase + (long long)(soff + s) * sstride;
-            const float ps = fmaf(prof[n + z], psi[si], prof[z] * d1);
+            const float ps = fmaf(prof[n + z], once<NT>(psi + si), prof[z] * d1);
             psi[si] = ps;
             psl[s * 64 + tx] = ps;
             d2l[s * 64 + tx] = d2;
@@ -984,7 +992,7 @@ __device__ void cpml_yz_block(const ShotDev& sd, int parity, const Coefs& cf, in
             dpsi = fmaf(AX == 2 ? cf.bz[m - 1] : cf.by[m - 1], vp - vm, dpsi);
         }
         const long long si = sbase + (long long)(soff + s) * sstride;
-        const float zn = fmaf(prof[n + z], ze[si], prof[z] * (d2l[s * 64 + tx] + dpsi));
+        const float zn = fmaf(prof[n + z], once<NT>(ze + si), prof[z] * (d2l[s * 64 + tx] + dpsi));
         ze[si] = zn;
         co[si] = dpsi + zn;
     }
@@ -1143,7 +1151,7 @@ __device__ void cpml_yz_block_adj(const ShotDev& sd, int parity, const Coefs& cf
     }
 }
 
-template <bool ADJ>
+template <bool ADJ, bool NT>
 __global__ __launch_bounds__(256) void k_cpml(const ShotDev* __restrict__ shots, int parity, Coefs cf, CpmlGrid g) {
     extern __shared__ float lds[];
     const int S = g.nshots;
@@ -1154,7 +1162,7 @@ __global__ __launch_bounds__(256) void k_cpml(const ShotDev* __restrict__ shots,
     if (b < ox[S]) {
         const int s = find_shot(ox, S, b);
         if (ADJ) cpml_x_block_adj(shots[s], parity, cf, b - ox[s], g.rows_per_block, lds);
-        else cpml_x_block(shots[s], parity, cf, b - ox[s], g.rows_per_block, lds);
+        else cpml_x_block<NT>(shots[s], parity, cf, b - ox[s], g.rows_per_block, lds);
         return;
     }
     b -= ox[S];
@@ -1172,8 +1180,8 @@ __global__ __launch_bounds__(256) void k_cpml(const ShotDev* __restrict__ shots,
         if (ypart) cpml_yz_block_adj<1>(sd, parity, cf, xblk, w, side, lds);
         else cpml_yz_block_adj<2>(sd, parity, cf, xblk, w, side, lds);
     } else {
-        if (ypart) cpml_yz_block<1>(sd, parity, cf, xblk, w, side, lds);
-        else cpml_yz_block<2>(sd, parity, cf, xblk, w, side, lds);
+        if (ypart) cpml_yz_block<1, NT>(sd, parity, cf, xblk, w, side, lds);
+        else cpml_yz_block<2, NT>(sd, parity, cf, xblk, w, side, lds);
     }
 }
 
@@ -1194,7 +1202,7 @@ void cpml_block_table(const int* nx, const int* ny, const int* nz, int nshots, i
     }
 }
 
-hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, bool adjoint, const int* block_off_dev,
+hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, bool adjoint, bool stream, const int* block_off_dev,
                        const int* block_off_host, int parity, const Coefs& cf, hipStream_t s) {
     if (nshots <= 0) return hipSuccess;
     if (nb < 1 || nb > (adjoint ? 64 : 128)) return hipErrorInvalidValue;
@@ -1209,9 +1217,11 @@ hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, bool adjoint, c
     // forward: psi and D2 p of one end [nb][64] (x part: 256); adjoint: three [W][64] arrays (x part: 3 x 256)
     const size_t fl = adjoint ? 3 * (size_t)std::max(width * 64, 256) : (size_t)std::max(2 * nb * 64, 256);
     if (adjoint)
-        k_cpml<true><<<dim3((unsigned)blocks), 256, sizeof(float) * fl, s>>>(shots, parity, cf, g);
+        k_cpml<true, false><<<dim3((unsigned)blocks), 256, sizeof(float) * fl, s>>>(shots, parity, cf, g);
+    else if (stream)
+        k_cpml<false, true><<<dim3((unsigned)blocks), 256, sizeof(float) * fl, s>>>(shots, parity, cf, g);
     else
-        k_cpml<false><<<dim3((unsigned)blocks), 256, sizeof(float) * fl, s>>>(shots, parity, cf, g);
+        k_cpml<false, false><<<dim3((unsigned)blocks), 256, sizeof(float) * fl, s>>>(shots, parity, cf, g);
     return hipGetLastError();
 }
 
