@@ -359,10 +359,13 @@ void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const Sh
                     out = c + fmaf(cvd[r], lap, c - cpp[r]);
                 }
                 pn_g[o] = out;
-                if (MODE == MODE_D2P) ((gfloat*)aux.d2p_out)[o] = G * (cvd[r] * lap);
+                // the segment of d2p fields is written once in the replay and read once in the
+                // imaging: non-temporal, so it does not push the wavefields out of the caches
+                if (MODE == MODE_D2P) __builtin_nontemporal_store(G * (cvd[r] * lap), &((gfloat*)aux.d2p_out)[o]);
                 if (MODE == MODE_IMAGE) {
                     gfloat* gr = (gfloat*)aux.grad;
-                    gr[o] = fmaf(aux.neg_inv_dt2 / G * out, ((const gfloat*)aux.d2p_in)[o], gr[o]);
+                    gr[o] = fmaf(aux.neg_inv_dt2 / G * out, __builtin_nontemporal_load(&((const gfloat*)aux.d2p_in)[o]),
+                                 gr[o]);
                 }
             }
         }
