@@ -55,6 +55,12 @@
  * and the gradient with respect to squared slowness m = 1/v^2:
  *   dJ/dm = -(1/(dt^2 G)) sum_n eta^{n+1} (p^{n+1} - 2 G p^n + G^2 p^{n-1}).
  *
+ * Parity unpinned: the CPML profile values (d0, alpha, a, b above) and the
+ * sponge profile values are readings with no independent value to check them
+ * against; the tests pin only their structure (d = alpha = 0 and sigma = 0
+ * reduce to bc none bitwise, the layers absorb, mirror and axis-exchange
+ * symmetry) and, for CPML, the exact transpose (dot-product test).
+ *
  * Layout of every 3D array: index (k*ny + j)*nx + i, x fastest.
  */
 #include <math.h>
