@@ -388,6 +388,7 @@ mm_status check_params(const mm_params* p, mm_ctx* c) {
     if (p->group_kb < -1) return fail(c, MM_ERR_ARG, "group_kb must be >= -1");
     if (p->free_surface != 0 && p->free_surface != 1) return fail(c, MM_ERR_ARG, "free_surface must be 0 or 1");
     if (p->model != MM_MODEL_ISO_CD && p->model != MM_MODEL_ISO) return fail(c, MM_ERR_ARG, "unknown model");
+    if (p->cache_hints < 0 || p->cache_hints > 2) return fail(c, MM_ERR_ARG, "cache_hints must be 0, 1 or 2");
     if (p->model == MM_MODEL_ISO) {
         if (p->bc == MM_BC_CPML) return fail(c, MM_ERR_UNSUPPORTED, "acoustic_iso supports bc none and sponge");
         if (p->free_surface) return fail(c, MM_ERR_UNSUPPORTED, "acoustic_iso has no free surface");
@@ -816,7 +817,8 @@ mm_status enqueue_adjoint(mm_ctx* c, int nsteps, const float* resid, float* adj_
 }
 
 std::string tune_key(const mm_ctx* c) {
-    std::string k = std::to_string(c->p.model) + "/" + std::to_string(c->p.bc) + "/" + std::to_string(c->p.nb);
+    std::string k = std::to_string(c->p.model) + "/" + std::to_string(c->p.bc) + "/" + std::to_string(c->p.nb) + "/" +
+                    std::to_string(c->p.cache_hints);
     for (const auto& g : c->groups) k += "/" + std::to_string(g.s1 - g.s0);
     for (const auto& g : c->geom) k += ":" + std::to_string(g.nx) + "x" + std::to_string(g.ny) + "x" + std::to_string(g.nz);
     return k;
@@ -1143,14 +1145,17 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
         for (int i = 0; i < nshots; ++i) rec_start[i + 1] = rec_start[i] + shots[i].nrec;
         double all_bytes = 0.0;
         for (const auto& q : geom) all_bytes += shot_set_bytes(*p, q);
-        c->stream_all = all_bytes > kInfinityCacheBytes;
+        auto hinted = [&](double bytes) {
+            return p->cache_hints == 2 || (p->cache_hints == 0 && bytes > kInfinityCacheBytes);
+        };
+        c->stream_all = hinted(all_bytes);
         for (const auto& gr : make_groups(*p, geom)) {
             mm_ctx::Group g;
             g.s0 = gr.first;
             g.s1 = gr.second;
             double bytes = 0.0;
             for (int i = g.s0; i < g.s1; ++i) bytes += shot_set_bytes(*p, geom[i]);
-            g.stream = bytes > kInfinityCacheBytes;
+            g.stream = hinted(bytes);
             g.tile_off = g.ntiles = 0;
             g.rec0 = rec_start[g.s0];
             g.rec1 = rec_start[g.s1];

@@ -37,7 +37,7 @@ class Params(ctypes.Structure):
         ("sponge_sigma", ctypes.c_double), ("cpml_R", ctypes.c_double), ("cpml_f0", ctypes.c_double),
         ("ckpt_every", ctypes.c_int32), ("snap", ctypes.c_int32), ("nsteps_max", ctypes.c_int32),
         ("tile", ctypes.c_int32), ("group_kb", ctypes.c_int32),
-        ("free_surface", ctypes.c_int32), ("model", ctypes.c_int32),
+        ("free_surface", ctypes.c_int32), ("model", ctypes.c_int32), ("cache_hints", ctypes.c_int32),
     ]
 
 

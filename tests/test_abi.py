@@ -147,6 +147,10 @@ def test_acoustic_iso_dt_workspace_and_argument_checks():
         assert st == mm.MM_ERR_UNSUPPORTED, field
     q = mm.default_params(model=2)
     assert _ws(q, [s])[0] == mm.MM_ERR_ARG
+    for bad in (-1, 3):
+        q = mm.default_params(cache_hints=bad)
+        assert _ws(q, [s])[0] == mm.MM_ERR_ARG
+        assert "cache_hints" in mm.load().mm_last_error(None).decode()
 
 
 def test_init_rejects_bad_workspace_before_touching_the_device():

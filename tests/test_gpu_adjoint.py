@@ -125,6 +125,38 @@ def test_gradient_matches_oracle(bc, snap, tol, fs):
         assert cos >= 0.9995
 
 
+def test_gradient_is_independent_of_cache_hints():
+    """The CPML gradient (forward with checkpoints, replay, adjoint and
+    imaging) with non-temporal loads forced on equals the one with them off,
+    bitwise."""
+    rng = np.random.default_rng(31)
+    shape = (24, 28, 30)
+    nz, ny, nx = shape
+    v0 = rng.uniform(1800.0, 2600.0, shape).astype(np.float32)
+    p = params(shape, bc=mm.BC_CPML, nb=5, f0=25.0)
+    p.vmax = float(v0.max())
+    p.ckpt_every = 8
+    T = 60
+    p.nsteps_max = T
+    dt = mm.dt_for(p, p.vmax)
+    src = np.array([[15, 14, 12]], np.int32)
+    rec = np.array([[i, j, 3] for i in range(2, nx - 2, 4) for j in range(2, ny - 2, 4)], np.int32)
+    w = torch.from_numpy(mm.ricker(25.0, 0.06, dt, T).reshape(T, 1)).to(DEV)
+    d_obs = torch.from_numpy(rng.standard_normal((T, len(rec))).astype(np.float32) * 1e-3).to(DEV)
+    res = []
+    for h in (1, 2):
+        p.cache_hints = h
+        ctx = mm.Context.single(p, torch.from_numpy(v0).to(DEV), src, rec)
+        grad = torch.empty(shape, device=DEV)
+        tr = torch.empty((T, len(rec)), device=DEV)
+        J = ctx.gradient(T, w, d_obs, grad, tr)
+        res.append((J, grad.cpu().numpy(), tr.cpu().numpy()))
+        ctx.close()
+    assert res[0][0] == res[1][0]
+    assert np.array_equal(res[0][1], res[1][1]) and np.array_equal(res[0][2], res[1][2])
+    assert np.abs(res[0][1]).max() > 0
+
+
 def test_autograd_binding_matches_library_gradient():
     """traces_from_slowness(m).backward(r) gives the library's gradient for
     J = 1/2 |traces - d_obs|^2 when r = traces - d_obs."""

@@ -89,6 +89,21 @@ def test_graph_and_chunked_runs_are_bitwise_equal(bc, fs):
             assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("bc,fs", [(mm.BC_NONE, 0), (mm.BC_SPONGE, 0), (mm.BC_CPML, 0), (mm.BC_CPML, 1)])
+def test_cache_hints_do_not_change_results(bc, fs):
+    """Non-temporal loads (forced on, forced off) change only where data is
+    cached: traces and fields are bitwise the same, and the same as auto."""
+    p, vel, src, rec, w, T, dt = _ragged_case(bc, seed=5)
+    p.free_surface = fs
+    out = []
+    for h in (0, 1, 2):
+        p.cache_hints = h
+        out.append(gpu_forward(p, vel, src, rec, w, T))
+    for other in out[1:]:
+        for x, y in zip(out[0][:3], other[:3]):
+            assert np.array_equal(x, y)
+
+
 def test_minimal_and_degenerate_grids():
     """Smallest grids the damping allows (n = 2 nb + 1, CPML 2 nb + 4), a one-cell-thick
     grid with bc none, and runs with no receivers or no sources."""

@@ -104,6 +104,15 @@ def test_iso_zero_steps_no_sources_no_receivers():
     assert tr.shape == (T, 0) and rel(st[0], rst[0]) <= 1e-5
 
 
+def test_iso_cache_hints_do_not_change_results():
+    p, v, rho, src, rec, w, T = _case(mm.BC_SPONGE, seed=86, T=40)
+    out = []
+    for h in (1, 2):
+        p.cache_hints = h
+        out.append(_gpu(p, v, rho, src, rec, w, T))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
 def test_iso_every_tile_variant_bitwise():
     p, v, rho, src, rec, w, T = _case(mm.BC_SPONGE, seed=81, T=60)
     first = None
