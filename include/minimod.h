@@ -129,9 +129,10 @@ typedef struct {
     int32_t model;           /* mm_model; 0 => acoustic_iso_cd */
     int32_t cache_hints;     /* loads of data a step reads once (p^{n-1}, (dt v)^2, CPML memory and
                                 corrections; acoustic_iso: p^n and dt rho v^2 in the pressure kernel)
-                                with the non-temporal hint: 0 auto (when a step's working set exceeds
-                                the 256 MiB Infinity Cache), 1 never, 2 always.  Results are bitwise
-                                the same either way; only the speed differs. */
+                                with the non-temporal hint: 0 auto (when the working set of every
+                                shot of a launch exceeds the 256 MiB Infinity Cache), 1 never,
+                                2 always.  Results are bitwise the same either way; only the speed
+                                differs. */
 } mm_params;
 
 /* One shot of a batched context. */

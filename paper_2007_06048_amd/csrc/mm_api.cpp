@@ -1143,19 +1143,20 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
         int cpml_pos = 0;
         std::vector<int> rec_start(nshots + 1, 0);
         for (int i = 0; i < nshots; ++i) rec_start[i + 1] = rec_start[i] + shots[i].nrec;
-        double all_bytes = 0.0;
-        for (const auto& q : geom) all_bytes += shot_set_bytes(*p, q);
-        auto hinted = [&](double bytes) {
-            return p->cache_hints == 2 || (p->cache_hints == 0 && bytes > kInfinityCacheBytes);
+        // auto: non-temporal hints only when every shot of a launch alone overflows the cache (a
+        // large shot re-reads its own p^n planes; many small shots that together exceed it do not
+        // gain, measured 1.72 vs 2.05 ms per step for 32 shots in one group)
+        auto hinted = [&](int s0, int s1) {
+            double smallest = 1e300;
+            for (int i = s0; i < s1; ++i) smallest = std::min(smallest, shot_set_bytes(*p, geom[i]));
+            return p->cache_hints == 2 || (p->cache_hints == 0 && smallest > kInfinityCacheBytes);
         };
-        c->stream_all = hinted(all_bytes);
+        c->stream_all = hinted(0, nshots);
         for (const auto& gr : make_groups(*p, geom)) {
             mm_ctx::Group g;
             g.s0 = gr.first;
             g.s1 = gr.second;
-            double bytes = 0.0;
-            for (int i = g.s0; i < g.s1; ++i) bytes += shot_set_bytes(*p, geom[i]);
-            g.stream = hinted(bytes);
+            g.stream = hinted(g.s0, g.s1);
             g.tile_off = g.ntiles = 0;
             g.rec0 = rec_start[g.s0];
             g.rec1 = rec_start[g.s1];
