@@ -55,11 +55,12 @@
  * and the gradient with respect to squared slowness m = 1/v^2:
  *   dJ/dm = -(1/(dt^2 G)) sum_n eta^{n+1} (p^{n+1} - 2 G p^n + G^2 p^{n-1}).
  *
- * Parity unpinned: the CPML profile values (d0, alpha, a, b above) and the
- * sponge profile values are readings with no independent value to check them
- * against; the tests pin only their structure (d = alpha = 0 and sigma = 0
- * reduce to bc none bitwise, the layers absorb, mirror and axis-exchange
- * symmetry) and, for CPML, the exact transpose (dot-product test).
+ * The CPML damping profile is pinned by PML reflection theory (the layer sum
+ * of d h reproduces ln R up to its quadrature error) and alpha by the
+ * standard CFS profile.  Parity unpinned: the sponge profile values are a
+ * reading with no independent value to check them against; the tests pin
+ * only their structure (sigma = 0 reduces to bc none bitwise, the layer
+ * absorbs, mirror and axis-exchange symmetry).
  *
  * Layout of every 3D array: index (k*ny + j)*nx + i, x fastest.
  */

@@ -325,6 +325,46 @@ def test_p8_cpml_absorbs():
     assert r_cpml10 < r_cpml5, (r_cpml10, r_cpml5)
 
 
+@pytest.mark.parametrize("nb,h,vmax,R", [(20, 10.0, 4500.0, 1e-3), (32, 12.5, 5000.0, 1e-4), (300, 5.0, 2000.0, 1e-2)])
+def test_cpml_profile_matches_pml_reflection_theory(nb, h, vmax, R):
+    """Recover the damping d and the frequency shift alpha from the oracle's
+    recursive-convolution coefficients (b = exp(-(d + alpha) dt) fixes
+    d + alpha, a / (b - 1) = d / (d + alpha) fixes the split), then check them
+    against PML theory rather than against their own formula: a layer with
+    damping d(x) reflects a normally incident wave with
+    R = exp(-(2 / c) * integral of d over the layer), so the layer sum of
+    d h must give ln R up to its O(1/nb) quadrature error (a quadratic profile
+    sampled at the cells: the exponent is (1 + 3/(2 nb) + 1/(2 nb^2)) times
+    the continuous one).  alpha follows the standard CFS profile: pi f0 at
+    the interface, falling linearly to 0 at the outer edge.  Both ends of each
+    axis carry the same values at the same depth, each with its own spacing."""
+    f0 = 17.0
+    n = 2 * nb + 11
+    dt = 1e-4
+    hs = (h, 0.8 * h, 1.3 * h)
+    g = C.Grid(n, n + 1, n + 2, hs[0], hs[1], hs[2], dt, bc=C.BC_CPML, nb=nb, R=R, f0=f0, vmax=vmax)
+    for ax in range(3):
+        na = (n, n + 1, n + 2)[ax]
+        d_sum = 0.0
+        for j in range(1, nb + 1):  # depth j: cell nb - j from the low end, its mirror at the high end
+            lo = C.cpml_coeffs(g, ax, nb - j)
+            hi = C.cpml_coeffs(g, ax, na - 1 - (nb - j))
+            assert lo == hi
+            a, b = lo
+            s = -math.log(b) / dt
+            d = a / (b - 1.0) * s
+            alpha = s - d
+            q = j / nb
+            assert alpha == pytest.approx(math.pi * f0 * (1.0 - q), rel=1e-9, abs=1e-9)
+            d_sum += d * hs[ax]
+        ratio = (-2.0 / vmax * d_sum) / math.log(R)
+        want = (nb + 1) * (2 * nb + 1) / (2.0 * nb * nb)
+        assert ratio == pytest.approx(want, rel=1e-9), (ax, ratio, want)
+        assert 1.0 < ratio < 1.0 + 2.0 / nb
+        # outside the layers the memory is switched off
+        assert C.cpml_coeffs(g, ax, nb) == (0.0, 1.0)
+
+
 def test_cpml_mirror_and_axis_symmetry():
     """Constant v, centred source, cubic grid with equal spacing: the CPML
     wavefield is symmetric under each mirror and under every exchange of
