@@ -315,8 +315,8 @@ def _reflection(bc, nb):
 def test_p8_cpml_absorbs():
     """CPML (the boundary the paper says every propagator uses) leaves a
     reflection far below that of the rigid zero-ghost boundary; a wider layer
-    absorbs better.  Exact CPML values are otherwise fixed only by the
-    reading of the recursive-convolution scheme (parity unpinned)."""
+    absorbs better.  The coefficient values themselves are pinned by
+    test_cpml_profile_matches_pml_reflection_theory."""
     r_none = _reflection(C.BC_NONE, 10)
     r_cpml10 = _reflection(C.BC_CPML, 10)
     r_cpml5 = _reflection(C.BC_CPML, 5)
