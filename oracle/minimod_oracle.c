@@ -751,8 +751,12 @@ int orc_num_threads(void) {
  *    the cell (for u, the cell whose right face it is);
  *  - dt = cfl / (C vmax sqrt(hx^-2 + hy^-2 + hz^-2)), C = c1 - c2 + c3 - c4,
  *    the largest symbol of the staggered derivative (checkerboard mode);
- *  - traces[n][r] = p^{n+1} at the receivers; initial state zero.
- * CPML and the free surface are not defined for this propagator here.
+ *  - traces[n][r] = p^{n+1} at the receivers; initial state zero;
+ *  - free surface (as for acoustic_iso_cd): p = 0 on the plane k = 0, p odd
+ *    about it above (so the p-derivative faces see -p(-k)), u_z even about
+ *    it, no damping layer on the top face; sources and receivers on the
+ *    plane inject and record nothing.
+ * CPML is not defined for this propagator here.
  */
 static const double C8[5] = {0.0, 1225.0 / 1024.0, -245.0 / 3072.0, 49.0 / 5120.0, -5.0 / 7168.0};
 
@@ -774,13 +778,21 @@ static double dplus(const orc_grid* g, const double* p, int i, int j, int k, int
     return s;
 }
 
+/* u_z above a free surface: p is odd about the surface plane k = 0, so its
+ * z derivative, and u_z, are even about it: the face -1/2 - m holds u_z of
+ * the face m + 1/2 (index -1 - m mirrors index m). */
+static double at_uz(const orc_grid* g, const double* u, int i, int j, int k) {
+    if (g->fs && k < 0) return at(g, u, i, j, -1 - k);
+    return at(g, u, i, j, k);
+}
+
 /* D- of face field u (index i holds face i+1/2) along axis ax, at cell (i,j,k). */
 static double dminus(const orc_grid* g, const double* u, int i, int j, int k, int ax) {
     int di = ax == 0, dj = ax == 1, dk = ax == 2;
     double h = axis_h(g, ax), s = 0.0;
     for (int m = 1; m <= 4; ++m)
-        s += (C8[m] / h) * (at(g, u, i + (m - 1) * di, j + (m - 1) * dj, k + (m - 1) * dk) -
-                            at(g, u, i - m * di, j - m * dj, k - m * dk));
+        s += (C8[m] / h) * (at_uz(g, u, i + (m - 1) * di, j + (m - 1) * dj, k + (m - 1) * dk) -
+                            at_uz(g, u, i - m * di, j - m * dj, k - m * dk));
     return s;
 }
 
@@ -807,7 +819,7 @@ void orc_iso_dplus(const orc_grid* g, const double* p, int ax, double* out) {
 
 static int iso_check(const orc_grid* g) {
     if (check_grid(g) || g->wnx > 0) return ORC_ERR_ARG;
-    if (g->bc == BC_CPML || g->fs) return ORC_ERR_UNSUPPORTED;
+    if (g->bc == BC_CPML || (g->fs && g->bc == BC_PERIODIC)) return ORC_ERR_UNSUPPORTED;
     return ORC_OK;
 }
 
@@ -856,6 +868,7 @@ int orc_iso_forward(const orc_grid* g, const double* vel, const double* rho, int
                     double K = rho[id] * vel[id] * vel[id];
                     double div = dminus(g, u[0], i, j, k, 0) + dminus(g, u[1], i, j, k, 1) + dminus(g, u[2], i, j, k, 2);
                     pn[id] = G * (p[id] + g->dt * K * (div + S[id]));
+                    if (g->fs && k == 0) pn[id] = 0.0; /* pressure release: p = 0 on the surface plane */
                 }
         memcpy(p, pn, N * sizeof(double));
         if (traces)

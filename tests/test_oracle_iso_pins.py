@@ -189,11 +189,80 @@ def test_iso_sponge_with_zero_strength_is_bc_none_and_sponge_absorbs():
     assert np.abs(sc[0]).max() < 0.2 * np.abs(sd[0]).max()
 
 
-def test_iso_rejects_cpml_and_free_surface():
+def test_iso_rejects_cpml():
     g = C.Grid(10, 10, 10, 10.0, 10.0, 10.0, 1e-4, bc=C.BC_CPML, nb=2)
     with pytest.raises(RuntimeError):
         C.iso_forward(g, np.full((10, 10, 10), 2000.0), np.full((10, 10, 10), 1000.0), [[5, 5, 5]],
                       np.zeros((2, 1)), [[5, 5, 5]], 2)
+
+
+def _mirror_z(a, nz):
+    """[nz] planes k = 0.. -> [2 nz - 1] planes, k mirrored about the first."""
+    return np.concatenate([a[:0:-1], a], axis=0)
+
+
+def test_iso_free_surface_equals_the_mirrored_problem():
+    """A free surface at k = 0 is the symmetry plane of a grid twice as deep
+    with the model mirrored and an image source of opposite sign (ordinary
+    zero ghosts there): the run with the surface must equal the lower half of
+    that run, pressure, all three velocities and the traces, and p = 0 on
+    the surface plane.  Sources sit below and on the surface (the latter
+    injects nothing), receivers too.  The staggered grid is not symmetric at
+    its far z ends (the last face is stored, the one before the first is
+    not), so the grid is deep enough that no wave reaches them in T steps."""
+    rng = np.random.default_rng(72)
+    shape = (40, 12, 13)
+    nz, ny, nx = shape
+    v, rho = _model(rng, shape)
+    h = (10.0, 9.0, 11.0)
+    dt = 0.8 * C.iso_dt_stab(v.max(), *h)
+    T = 45
+    src = [[6, 5, 3], [2, 9, 0], [9, 3, 6]]
+    rec = [[4, 4, 0], [6, 5, 1], [1, 10, 5], [12, 0, 10]]
+    w = rng.standard_normal((T, len(src)))
+    g = C.Grid(nx, ny, nz, *h, dt, fs=1)
+    tr, st = C.iso_forward(g, v, rho, src, w, rec, T)
+    K0 = nz - 1
+    gm = C.Grid(nx, ny, 2 * nz - 1, *h, dt)
+    src_m = [[i, j, K0 + k] for i, j, k in src] + [[i, j, K0 - k] for i, j, k in src]
+    w_m = np.concatenate([w, -w], axis=1)
+    rec_m = [[i, j, K0 + k] for i, j, k in rec]
+    trm, stm = C.iso_forward(gm, _mirror_z(v, nz), _mirror_z(rho, nz), src_m, w_m, rec_m, T)
+    scale = np.abs(stm).max()
+    assert scale > 0
+    assert np.abs(st[0][0]).max() == 0.0
+    for a in range(4):
+        assert np.abs(st[a] - stm[a][K0:]).max() <= 1e-12 * scale, a
+    assert np.abs(tr - trm).max() <= 1e-12 * np.abs(trm).max()
+    # the velocities of the mirrored run are symmetric in the way the surface assumes:
+    # u_z even about the plane (face -1/2 - m mirrors face m + 1/2), p odd
+    assert np.abs(stm[0][K0 - 3:K0] + stm[0][K0 + 3:K0:-1]).max() <= 1e-12 * scale
+    assert np.abs(stm[3][K0 - 3:K0] - stm[3][K0 + 2:K0 - 1:-1]).max() <= 1e-12 * scale
+
+
+def test_iso_free_surface_conserves_energy_and_works_with_the_sponge():
+    rng = np.random.default_rng(73)
+    shape = (13, 14, 12)
+    v, rho = _model(rng, shape)
+    h = (10.0, 11.0, 9.0)
+    dt = 0.9 * C.iso_dt_stab(v.max(), *h)
+    g = C.Grid(shape[2], shape[1], shape[0], *h, dt, fs=1)
+    src = [[6, 7, 4]]
+    _, st = C.iso_forward(g, v, rho, src, rng.standard_normal((5, 1)), [[1, 1, 1]], 5)
+
+    def energy(state):
+        _, b = C.iso_forward(g, v, rho, src, np.zeros((1, 1)), [[1, 1, 1]], 1, state=state)
+        return C.iso_energy(g, v, rho, state[0], b[0], b[1:])
+
+    _, later = C.iso_forward(g, v, rho, src, np.zeros((250, 1)), [[1, 1, 1]], 250, state=st)
+    e0, e1 = energy(st), energy(later)
+    assert e0 > 0 and abs(e1 - e0) <= 1e-10 * e0
+    # with a sponge on the other five faces the field decays and the surface stays at zero
+    gs = C.Grid(shape[2], shape[1], shape[0], *h, dt, bc=C.BC_SPONGE, nb=3, sigma=0.2, fs=1)
+    _, s1 = C.iso_forward(gs, v, rho, src, rng.standard_normal((5, 1)), [[1, 1, 1]], 5)
+    _, s2 = C.iso_forward(gs, v, rho, src, np.zeros((400, 1)), [[1, 1, 1]], 400, state=s1)
+    assert np.abs(s2[0][0]).max() == 0.0
+    assert np.abs(s2[0]).max() < 0.2 * np.abs(s1[0]).max()
 
 
 def test_iso_density_contrast_reflects_with_the_impedance_ratio():
