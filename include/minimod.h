@@ -92,7 +92,8 @@ typedef enum { MM_BC_NONE = 0, MM_BC_SPONGE = 1, MM_BC_CPML = 2 } mm_bc;
  *    b the face buoyancy (mean of 1/rho of the two cells beside the face,
  *    1/rho of the inner cell on the last face), G the cell's sponge factor;
  *    dt = cfl / (C vmax sqrt(dx^-2 + dy^-2 + dz^-2)), C = 2161/1680.
- *    Forward modelling only, bc none or sponge, no free surface. */
+ *    Forward modelling only, bc none or sponge, with or without the free
+ *    surface (p = 0 on the top plane and odd above it, u_z even about it). */
 typedef enum { MM_MODEL_ISO_CD = 0, MM_MODEL_ISO = 1 } mm_model;
 
 /* Snapshot storage of the gradient's checkpoints. */

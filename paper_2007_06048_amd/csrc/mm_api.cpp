@@ -391,7 +391,6 @@ mm_status check_params(const mm_params* p, mm_ctx* c) {
     if (p->cache_hints < 0 || p->cache_hints > 2) return fail(c, MM_ERR_ARG, "cache_hints must be 0, 1 or 2");
     if (p->model == MM_MODEL_ISO) {
         if (p->bc == MM_BC_CPML) return fail(c, MM_ERR_UNSUPPORTED, "acoustic_iso supports bc none and sponge");
-        if (p->free_surface) return fail(c, MM_ERR_UNSUPPORTED, "acoustic_iso has no free surface");
         if (p->ckpt_every > 0) return fail(c, MM_ERR_UNSUPPORTED, "acoustic_iso has no adjoint (ckpt_every must be 0)");
         if (p->tile > 0 && !iso_variant_ok(p->tile))
             return fail(c, MM_ERR_ARG, "acoustic_iso runs the 256-thread tile variants only");
@@ -1198,10 +1197,11 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
             const ShotDev& q = c->shots_h[i];
             st = dev(c, launch_iso_setup(shots[i].vel, shots[i].rho, geom[i].n(), c->dt, q.vdt2, q.bdt, s),
                      "coefficients");
-            continue;
+        } else {
+            st = dev(c, launch_vdt2(shots[i].vel, c->shots_h[i].vdt2, geom[i].n(), c->dt, s), "vdt2");
         }
-        st = dev(c, launch_vdt2(shots[i].vel, c->shots_h[i].vdt2, geom[i].n(), c->dt, s), "vdt2");
-        // free surface: (dt v)^2 = 0 on plane z = 0 keeps p = 0 there (the state starts at 0)
+        // free surface: (dt v)^2 (acoustic_iso: dt rho v^2) = 0 on plane z = 0 keeps p = 0 there
+        // (the state starts at 0)
         if (!st && p->free_surface)
             st = dev(c, launch_fill(c->shots_h[i].vdt2, (long long)geom[i].nx * geom[i].ny, 0.0f, s), "fill");
     }

@@ -549,6 +549,18 @@ __global__ __launch_bounds__(256) void k_iso_u(const TileEnt* __restrict__ tiles
 #pragma unroll
         for (int r = 0; r < RY; ++r) b1[r] = bload(rb, voc[r]);
     }
+    if (z0 == 0 && sd.fs) {
+        // free surface: p is odd about the plane z = 0 (p(0) = 0), so planes -4 .. -1 hold
+        // -p(4) .. -p(1) (block-uniform branch)
+        const __amdgpu_buffer_rsrc_t r4 = plane_rsrc(pc, 4 < nz ? 4 : 0, plane);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            q[r][3] = -q[r][5];
+            q[r][2] = -q[r][6];
+            q[r][1] = -q[r][7];
+            q[r][0] = 4 < nz ? -bload(r4, voc[r]) : 0.0f;
+        }
+    }
     // stage for plane zn: p^n(zn+4), halos of p and dt/rho at zn, dt/rho(zn+1), u at zn
     float nq[RY], nxh[RY], nyh[YH], nbh[RY], nbx[RY], nby[YH], nu[3][RY];
     auto fetch = [&](int zn) {
@@ -705,6 +717,18 @@ __global__ __launch_bounds__(256) void k_iso_p(const TileEnt* __restrict__ tiles
         const __amdgpu_buffer_rsrc_t rp = plane_rsrc(sd.u[2], zin ? z : 0, plane);
 #pragma unroll
         for (int r = 0; r < RY; ++r) w[r][m] = zin ? bload(rp, voc[r]) : 0.0f;
+    }
+    if (z0 == 0 && sd.fs) {
+        // free surface: u_z is even about the plane z = 0, the face -1/2 - m holding u_z of
+        // the face m + 1/2 (index -1 - m mirrors index m; block-uniform branch)
+        const __amdgpu_buffer_rsrc_t r3 = plane_rsrc(sd.u[2], 3 < nz ? 3 : 0, plane);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            w[r][3] = w[r][4];
+            w[r][2] = w[r][5];
+            w[r][1] = w[r][6];
+            w[r][0] = 3 < nz ? bload(r3, voc[r]) : 0.0f;
+        }
     }
     float nw[RY], nux[RY], nuxh[RY], nuy[RY], nuyh[YH], np_[RY], nk[RY];
     auto fetch = [&](int zn) {

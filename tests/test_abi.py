@@ -131,7 +131,7 @@ def test_acoustic_iso_dt_workspace_and_argument_checks():
     """acoustic_iso on the host side: its dt uses the staggered scheme's
     limit (the oracle's, not the constant-density one), its workspace holds
     the ping-pong pressure, three face velocities, dt rho v^2 and dt / rho,
-    and CPML, free surface and adjoint storage are refused."""
+    and CPML and adjoint storage are refused."""
     p = mm.default_params(dx=10.0, dy=12.0, dz=8.0, cfl=0.5, model=mm.MODEL_ISO, bc=mm.BC_SPONGE, nb=4)
     assert mm.dt_for(p, 3000.0) == pytest.approx(0.5 * C.iso_dt_stab(3000.0, 10.0, 12.0, 8.0), rel=1e-15)
     assert mm.dt_for(p, 3000.0) < mm.dt_for(mm.default_params(dx=10.0, dy=12.0, dz=8.0, cfl=0.5), 3000.0)
@@ -140,7 +140,7 @@ def test_acoustic_iso_dt_workspace_and_argument_checks():
     assert st == mm.MM_OK and n_iso >= 7 * 4 * 40 * 36 * 32
     st, n_cd = _ws(mm.default_params(dx=10.0, dy=12.0, dz=8.0, cfl=0.5, bc=mm.BC_SPONGE, nb=4), [s])
     assert st == mm.MM_OK and n_iso - n_cd >= 4 * 4 * 40 * 36 * 32
-    for field, val in (("bc", mm.BC_CPML), ("free_surface", 1), ("ckpt_every", 8)):
+    for field, val in (("bc", mm.BC_CPML), ("ckpt_every", 8)):
         q = mm.default_params(model=mm.MODEL_ISO, bc=mm.BC_SPONGE, nb=4, nsteps_max=10)
         setattr(q, field, val)
         st, _ = _ws(q, [s])

@@ -46,14 +46,24 @@ def _gpu(p, v, rho, src, rec, w, T, tile=None, graph=False, chunks=None):
 
 
 def _oracle(p, dt, v, rho, src, rec, w, T):
-    g = C.Grid(p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, dt, bc=p.bc, nb=p.nb, sigma=p.sponge_sigma)
+    g = C.Grid(p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, dt, bc=p.bc, nb=p.nb, sigma=p.sponge_sigma, fs=p.free_surface)
     return C.iso_forward(g, v.astype(np.float64), rho.astype(np.float64), src, w.astype(np.float64), rec, T)
 
 
-@pytest.mark.parametrize("bc", [mm.BC_NONE, mm.BC_SPONGE])
-def test_iso_matches_oracle(bc):
+@pytest.mark.parametrize("bc,fs", [(mm.BC_NONE, 0), (mm.BC_SPONGE, 0), (mm.BC_NONE, 1), (mm.BC_SPONGE, 1)])
+def test_iso_matches_oracle(bc, fs):
+    """Ragged grid, duplicate sources, receivers on sources and corners; with a
+    free surface a source and a receiver sit on the surface plane (which
+    injects and records nothing)."""
     p, v, rho, src, rec, w, T = _case(bc)
+    p.free_surface = fs
+    if fs:
+        src = np.concatenate([src, [[4, 5, 0]]]).astype(np.int32)
+        rec = np.concatenate([rec, [[4, 5, 0], [7, 3, 1]]]).astype(np.int32)
+        w = np.concatenate([w, np.ones((T, 1), np.float32)], axis=1)
     tr, st, dt = _gpu(p, v, rho, src, rec, w, T)
+    if fs:
+        assert not st[0][0].any() and not tr[:, -2].any()
     assert dt == pytest.approx(0.5 * C.iso_dt_stab(float(v.max()), p.dx, p.dy, p.dz), rel=1e-15)
     rtr, rst = _oracle(p, dt, v, rho, src, rec, w, T)
     print("traces", rel(tr, rtr), "p", rel(st[0], rst[0]), "u", [rel(st[a], rst[a]) for a in (1, 2, 3)])
@@ -113,8 +123,10 @@ def test_iso_cache_hints_do_not_change_results():
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
-def test_iso_every_tile_variant_bitwise():
+@pytest.mark.parametrize("fs", [0, 1])
+def test_iso_every_tile_variant_bitwise(fs):
     p, v, rho, src, rec, w, T = _case(mm.BC_SPONGE, seed=81, T=60)
+    p.free_surface = fs
     first = None
     n = 0
     for t in range(mm.num_tiles()):
@@ -139,8 +151,10 @@ def test_iso_graph_and_chunked_runs_are_bitwise_equal():
         assert np.array_equal(a[0], other[0]) and np.array_equal(a[1], other[1])
 
 
-def test_iso_state_round_trip_and_resume():
+@pytest.mark.parametrize("fs", [0, 1])
+def test_iso_state_round_trip_and_resume(fs):
     p, v, rho, src, rec, w, T = _case(mm.BC_NONE, seed=83, T=40)
+    p.free_surface = fs
     whole = _gpu(p, v, rho, src, rec, w, T)
     ctx = mm.Context.single(p, torch.from_numpy(v).to(DEV), src, rec, rho=torch.from_numpy(rho).to(DEV))
     wt = torch.from_numpy(w).to(DEV)
@@ -157,8 +171,8 @@ def test_iso_state_round_trip_and_resume():
 def test_iso_argument_errors():
     p, v, rho, src, rec, w, T = _case(mm.BC_SPONGE, shape=(16, 16, 16), T=4)
     vt, rt = torch.from_numpy(v).to(DEV), torch.from_numpy(rho).to(DEV)
-    for field, val, status in (("bc", mm.BC_CPML, mm.MM_ERR_UNSUPPORTED), ("free_surface", 1, mm.MM_ERR_UNSUPPORTED),
-                               ("ckpt_every", 8, mm.MM_ERR_UNSUPPORTED), ("model", 7, mm.MM_ERR_ARG)):
+    for field, val, status in (("bc", mm.BC_CPML, mm.MM_ERR_UNSUPPORTED), ("ckpt_every", 8, mm.MM_ERR_UNSUPPORTED),
+                               ("model", 7, mm.MM_ERR_ARG)):
         q = mm.default_params(**{k: getattr(p, k) for k, _ in mm.Params._fields_})
         setattr(q, field, val)
         q.nsteps_max = 10
