@@ -11,6 +11,7 @@ Prints ONE JSON line:
   roofline  = algorithmic bytes of the stencil kernel per launch / its average
               launch time (HIP events on the library's stream), vs 8 TB/s
   cpu_baseline = the FP64 oracle timed on the host cores on a bounded sample
+                 (cpu_baseline_1thread: the same on one thread)
   paper_context = the paper's own serial CPU rate for a 240^3 run (context only)
 """
 import argparse
@@ -64,12 +65,23 @@ def traffic_for(workload_name):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(wl, budget_s):
+def cpu_baseline(wl, budget_s, threads=0):
     """Time the FP64 oracle on a bounded sample: the same grid, model,
-    boundary and source, for as many steps as fit in about budget_s."""
+    boundary and source, for as many steps as fit in about budget_s, on
+    `threads` OpenMP threads (0: the runtime's default, all host cores)."""
     import numpy as np
     from oracle import c_oracle as C
     from paper_2007_06048_amd import minimod as mm
+    default_threads = C.num_threads()
+    if threads > 0:
+        C.set_num_threads(threads)
+    try:
+        return _cpu_baseline(wl, budget_s, C, mm, np)
+    finally:
+        C.set_num_threads(default_threads)
+
+
+def _cpu_baseline(wl, budget_s, C, mm, np):
     s = wl.shots[0]
     p = mm.default_params(nx=wl.nx, ny=wl.ny, nz=wl.nz, dx=wl.h, dy=wl.h, dz=wl.h, cfl=wl.cfl, bc=wl.bc, nb=wl.nb)
     vmax = float(s.vel.max())
@@ -469,6 +481,7 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+        out["cpu_baseline_1thread"] = cpu_baseline(wl, args.cpu_budget * 2.0 / 3.0, threads=1)
     # the paper's only timing of this propagator, as context (a different grid, spacing, step count
     # and boundary width, one CPU thread on unstated hardware): section "Compilation and usage"
     # reports 30.47 s of kernel time for 240^3 points x 300 steps

@@ -101,6 +101,8 @@ def lib():
                                    ctypes.c_int, dp, dp, dp]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_num_threads.argtypes = []
+        L.orc_set_num_threads.restype = None
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         L.orc_iso_dt_stab.restype = ctypes.c_double
         L.orc_iso_dt_stab.argtypes = [ctypes.c_double] * 4
         L.orc_iso_dplus.restype = None
@@ -253,6 +255,10 @@ def gradient(g: Grid, vel, src, wav, rec, d_obs, T, ckpt=None):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    lib().orc_set_num_threads(int(n))
 
 
 # ------------------------------------------------------------ acoustic_iso

@@ -729,6 +729,15 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Threads for the following parallel loops (timing at a chosen core count). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ========================================================= acoustic_iso */
 /*
  * The paper's second propagator, Eq. (acoustic_iso_vd): the first-order
