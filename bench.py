@@ -435,6 +435,9 @@ def main():
                 "avg_launch_us": round(avg_ms * 1e3, 2),
                 "alg_bytes_per_launch": bytes_launch, "timed_launches": k_n,
                 "timed_every": args.prof_stride}
+        if roof["traffic"]:
+            # the bytes the kernel actually moves below L2, at the measured launch time
+            roof["traffic_GBs"] = round(roof["traffic"] / (avg_ms / 1e3) / 1e9, 1)
 
     # whole-step roofline over every kernel of the step: 16 B per point plus, for CPML,
     # 16 B (psi and zeta, read and write) per point and damped axis
