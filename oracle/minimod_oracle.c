@@ -754,8 +754,11 @@ void orc_set_num_threads(int n) {
  *  - leapfrog staggered in time, u at half steps:
  *      u^{n+1/2} = G (u^{n-1/2} + dt b D+ p^n),
  *      p^{n+1}   = G (p^n + dt K (D- . u^{n+1/2} + s^n)),
- *    K = rho v^2, b = the face buoyancy: the mean of 1/rho of the two cells
- *    beside the face (1/rho of the inner cell on the last face of an axis);
+ *    K = rho v^2, b = the face buoyancy: 1 over the mean density of the two
+ *    cells beside the face, 2 / (rho_0 + rho_1) (1/rho of the inner cell on
+ *    the last face of an axis).  Averaging rho, not 1/rho, is what makes a
+ *    long wave crossing layers one cell thick travel at the homogenised
+ *    speed 1/sqrt(<rho> <1/K>) of the continuous system;
  *    s^n = w(t_n)/(hx hy hz) at the source cell; G = the sponge factor of
  *    the cell (for u, the cell whose right face it is);
  *  - dt = cfl / (C vmax sqrt(hx^-2 + hy^-2 + hz^-2)), C = c1 - c2 + c3 - c4,
@@ -805,7 +808,8 @@ static double dminus(const orc_grid* g, const double* u, int i, int j, int k, in
     return s;
 }
 
-/* Buoyancy at the face (i,j,k) + 1/2 e_ax. */
+/* Buoyancy at the face (i,j,k) + 1/2 e_ax: 1 / (arithmetic mean of rho of
+ * the two cells beside it). */
 static double face_b(const orc_grid* g, const double* rho, int i, int j, int k, int ax) {
     int n = ax == 0 ? g->nx : (ax == 1 ? g->ny : g->nz);
     int pos = ax == 0 ? i : (ax == 1 ? j : k);
@@ -816,7 +820,7 @@ static double face_b(const orc_grid* g, const double* rho, int i, int j, int k, 
         q = 0;
     }
     int i1 = ax == 0 ? q : i, j1 = ax == 1 ? q : j, k1 = ax == 2 ? q : k;
-    return 0.5 * (b0 + 1.0 / rho[lin(g, i1, j1, k1)]);
+    return 2.0 / (rho[lin(g, i, j, k)] + rho[lin(g, i1, j1, k1)]);
 }
 
 /* D+ along axis ax of a whole cell field (test access to the operator). */

@@ -293,3 +293,53 @@ def test_iso_density_contrast_reflects_with_the_impedance_ratio():
     a_dir = np.abs(tr[np.abs(t - t_direct) < win, 0]).max()
     a_ref = np.abs(tr[np.abs(t - t_refl) < win, 0]).max()
     assert a_ref / a_dir == pytest.approx(0.5, rel=0.03), a_ref / a_dir
+
+
+def _peak_time(tr, dt):
+    """Time of the largest sample of a trace, refined by the parabola through
+    it and its two neighbours (traces[n] holds time (n + 1) dt)."""
+    n = int(np.argmax(tr))
+    y0, y1, y2 = tr[n - 1], tr[n], tr[n + 1]
+    off = 0.5 * (y0 - y2) / (y0 - 2.0 * y1 + y2)
+    return (n + 1 + off) * dt
+
+
+@pytest.mark.parametrize("ax", [0, 1, 2])
+@pytest.mark.parametrize("rho_pair", [(1000.0, 3000.0), (1500.0, 2500.0)])
+def test_iso_long_wave_speed_across_thin_layers_is_the_homogenised_speed(ax, rho_pair):
+    """Layers one cell thick normal to the propagation axis: constant bulk
+    modulus K, density alternating cell by cell.  A wave much longer than the
+    layering travels at the speed of the homogenised medium,
+    c = 1 / sqrt(<rho> <1/K>) (effective density = arithmetic mean of rho
+    along the path, effective compliance = mean of 1/K), here
+    sqrt(K / <rho>) = 2000 m/s for both density pairs; a face buoyancy that
+    averages 1/rho instead gives sqrt(K <1/rho>) = 2309 m/s for 1000/3000.
+    Periodic 4 x 4 x 400 column, plane source, 4 Hz Ricker (wavelength 50
+    cells), speed from the peak times at 20 and 100 cells from the source."""
+    n_long, h, K, f0 = 400, 10.0, 8.0e9, 4.0
+    shape_xyz = [4, 4, 4]
+    shape_xyz[ax] = n_long
+    nx, ny, nz = shape_xyz
+    pos = np.arange(n_long)
+    rho_line = np.where(pos % 2 == 0, rho_pair[0], rho_pair[1])
+    sh = [1, 1, 1]
+    sh[2 - ax] = n_long
+    rho = np.broadcast_to(rho_line.reshape(sh), (nz, ny, nx)).copy()
+    v = np.sqrt(K / rho)
+    dt = 0.5 * C.iso_dt_stab(v.max(), h, h, h)
+    g = C.Grid(nx, ny, nz, h, h, h, dt, bc=C.BC_PERIODIC)
+    T = int(1.1 / dt)  # the far peak arrives at 1.5 / f0 + 1000 m / c = 0.875 s
+    w = C.ricker(f0, 1.5 / f0, dt, T)
+
+    def pt(a, b, c_long):
+        q = [a, b]
+        q.insert(ax, c_long)
+        return q
+
+    src = np.array([pt(a, b, 100) for a in range(4) for b in range(4)])
+    rec = np.array([pt(1, 2, 120), pt(1, 2, 200)])
+    tr, _ = C.iso_forward(g, v.astype(np.float32).astype(np.float64), rho, src,
+                          np.repeat(w[:, None], len(src), axis=1), rec, T)
+    c = 80 * h / (_peak_time(tr[:, 1], dt) - _peak_time(tr[:, 0], dt))
+    c_hom = 1.0 / np.sqrt(rho_line.mean() * np.mean(1.0 / np.full(n_long, K)))
+    assert c == pytest.approx(c_hom, rel=5e-3), (c, c_hom)
