@@ -57,10 +57,11 @@
  *
  * The CPML damping profile is pinned by PML reflection theory (the layer sum
  * of d h reproduces ln R up to its quadrature error) and alpha by the
- * standard CFS profile.  Parity unpinned: the sponge profile values are a
- * reading with no independent value to check them against; the tests pin
- * only their structure (sigma = 0 reduces to bc none bitwise, the layer
- * absorbs, mirror and axis-exchange symmetry).
+ * standard CFS profile.  The sponge profile is read back from the forward
+ * step itself (one step from a unit impulse with and without the sponge;
+ * their ratio is G) and checked for the Cerjan form: exactly nb damped
+ * cells per end, depth 1 at the innermost, G(d) = G(1)^(d^2) and
+ * -ln G(1) = sigma^2.
  *
  * Layout of every 3D array: index (k*ny + j)*nx + i, x fastest.
  */

@@ -704,3 +704,42 @@ def test_free_surface_gradient_finite_differences():
         errs.append(abs(fd - want) / abs(want))
     assert errs[-1] < 1e-6, errs
     assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0, errs
+
+
+@pytest.mark.parametrize("ax", [0, 1, 2])
+def test_sponge_profile_read_from_one_step(ax):
+    """The sponge factor seen by the update itself: from p^{-1} = 0 and
+    p^0 = a unit impulse at cell c, one step gives G(c) (2 + D(c) c0) with
+    the sponge and 2 + D(c) c0 without it, so their ratio is G(c).  Along a
+    line through the centre (G of the other two axes is 1 there) this reads
+    the 1D profile off the forward step and checks the Cerjan reading
+    independently of the table code: exactly nb damped cells at each end
+    (depth 1 at the innermost, nb at the outermost cell), 1 everywhere else,
+    G(depth d) = G(depth 1)^(d^2) (a Gaussian in the depth), and
+    -ln G(depth 1) = sigma^2.  A depth off by one cell, a layer one cell
+    too wide or too narrow, or a non-Gaussian profile fails it."""
+    nb, sigma, h = 6, 0.21, 10.0
+    n = [15, 15, 15]
+    n[ax] = 22
+    nx, ny, nz = n
+    vel = np.full((nz, ny, nx), 2000.0, dtype=np.float32)
+    dt = 0.5 * C.dt_stab(2000.0, h, h, h)
+    gs = C.Grid(nx, ny, nz, h, h, h, dt, bc=C.BC_SPONGE, nb=nb, sigma=sigma)
+    g0 = C.Grid(nx, ny, nz, h, h, h, dt, bc=C.BC_NONE)
+    prof = np.zeros(n[ax])
+    for c in range(n[ax]):
+        cell = [7, 7, 7]
+        cell[ax] = c
+        i, j, k = cell
+        p0 = np.zeros((nz, ny, nx))
+        p0[k, j, i] = 1.0
+        _, _, s1, _ = C.forward(gs, vel, [], np.zeros((1, 0)), [], 1, p_prev=np.zeros_like(p0), p_cur=p0)
+        _, _, n1, _ = C.forward(g0, vel, [], np.zeros((1, 0)), [], 1, p_prev=np.zeros_like(p0), p_cur=p0)
+        prof[c] = s1[k, j, i] / n1[k, j, i]
+    depth = np.maximum(np.maximum(nb - np.arange(n[ax]), nb - (n[ax] - 1 - np.arange(n[ax]))), 0)
+    assert np.all(prof[depth == 0] == 1.0)
+    assert np.all(prof[depth > 0] < 1.0)
+    g1 = prof[nb - 1]
+    assert -np.log(g1) == pytest.approx(sigma ** 2, rel=1e-12)
+    want = g1 ** (depth.astype(np.float64) ** 2)
+    assert np.allclose(prof, want, rtol=1e-12, atol=0)
