@@ -4,14 +4,23 @@
 One bench step = one full forward modelling run of the workload: reset the
 state, then T leapfrog steps with CPML, source injection and recording of
 the receiver plane (all in the HIP library).  Inputs (model, wavelet, trace
-buffer) are resident in HBM before timing starts.
+buffer) are resident in HBM before timing starts.  The default workload is
+the 1024 x 1024 x 512 layered model with a 32-cell CPML and 500 steps, whose
+working set (about 7.5 GB) is far beyond the 256 MiB Infinity Cache.
 
 Prints ONE JSON line:
   value     = grid points x T / wall time of one run (Gpoint-updates/s)
-  roofline  = algorithmic bytes of the stencil kernel per launch / its average
-              launch time (HIP events on the library's stream), vs 8 TB/s
+  roofline  = algorithmic bytes of one time step (16 B per point plus 16 B
+              per point and damped CPML axis) / the average duration of a
+              step (start of its first kernel to end of its last, stamped by
+              the launches into HIP events on the library's stream), vs
+              8 TB/s; traffic = the bytes the step's kernels actually move
+              (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by calibration
+              kernels), from the committed counter summary of the same
+              kernel source
   cpu_baseline = the FP64 oracle timed on the host cores on a bounded sample
-                 (cpu_baseline_1thread: the same on one thread)
+                 of the same workload (cpu_baseline_1thread: one thread, on
+                 a sample of the 240^3 workload)
   paper_context = the paper's own serial CPU rate for a 240^3 run (context only)
 """
 import argparse
@@ -51,9 +60,9 @@ def load_workload(name):
 
 
 def traffic_for(workload_name):
-    """HBM bytes per stencil launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "k_step_traffic.json")
+    """HBM bytes per time step (all kernels of the step) from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "step_traffic.json")
     try:
         with open(path) as f:
             d = json.load(f)
@@ -62,7 +71,17 @@ def traffic_for(workload_name):
     e = d.get(workload_name)
     if not e or e.get("kernel_hash") != kernel_hash():
         return None
-    return e.get("bytes_per_launch")
+    return e.get("bytes_per_step")
+
+
+def step_alg_bytes(wl, alg_pt):
+    """Algorithmic bytes of one time step: alg_pt per grid point plus, for
+    CPML, 16 B (psi and zeta, read and write) per point and damped axis."""
+    damped_axis_pts = 0
+    if wl.bc == 2:
+        for m in (wl.ny * wl.nz, wl.nx * wl.nz, wl.nx * wl.ny):
+            damped_axis_pts += 2 * wl.nb * m
+    return alg_pt * wl.nx * wl.ny * wl.nz + 16 * damped_axis_pts
 
 
 def cpu_baseline(wl, budget_s, threads=0):
@@ -104,12 +123,16 @@ def _cpu_baseline(wl, budget_s, C, mm, np):
                       f"after 1 warm-up step"}
 
 
+# kernels that advance the forward wavefields by one time level (one launch each per step)
+STEP_KERNELS = ("k_step<", "k_cpml<")
+
+
 def pmc_summary(fetch_dir, write_dir, workload, out_path):
-    """HBM traffic of the stencil kernel from two rocprofv3 --pmc passes
-    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
-    same counter reads for kernels of known size in the same program:
-    k_vcheck reads exactly 4 N bytes (the velocity model), k_vdt2 writes
-    exactly 4 N bytes."""
+    """HBM traffic of one time step from two rocprofv3 --pmc passes
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch): the mean per dispatch of
+    every kernel of the step, summed, each counter scaled by what it reads
+    for kernels of known size in the same program: k_vcheck reads exactly
+    4 N bytes (the velocity model), k_vdt2 writes exactly 4 N bytes."""
     import csv
     import numpy as np
     from paper_2007_06048_amd import workloads as W
@@ -127,26 +150,29 @@ def pmc_summary(fetch_dir, write_dir, workload, out_path):
     fetch = per_kernel(fetch_dir, "FETCH_SIZE")
     write = per_kernel(write_dir, "WRITE_SIZE")
 
-    def pick(vals, key):
+    def one(vals, key):
         ks = [k for k in vals if key in k]
         assert len(ks) == 1, (key, ks)
-        return np.mean(vals[ks[0]]), ks[0], len(vals[ks[0]])
+        return float(np.mean(vals[ks[0]]))
 
-    f_cal, _, _ = pick(fetch, "k_vcheck")
-    w_cal, _, _ = pick(write, "k_vdt2")
-    f_fac, w_fac = 4.0 * n / f_cal, 4.0 * n / w_cal
-    f_step, kname, nd = pick(fetch, "k_step<")
-    w_step, _, _ = pick(write, "k_step<")
-    entry = {"kernel": kname, "dispatches": nd, "kernel_hash": kernel_hash(), "points": n,
+    f_fac = 4.0 * n / one(fetch, "k_vcheck")
+    w_fac = 4.0 * n / one(write, "k_vdt2")
+    kernels = {}
+    for name in sorted(set(fetch) | set(write)):
+        if not any(k in name for k in STEP_KERNELS):
+            continue
+        kernels[name] = {"dispatches": len(fetch.get(name, [])),
+                         "fetch_bytes": round(float(np.mean(fetch.get(name, [0.0]))) * f_fac),
+                         "write_bytes": round(float(np.mean(write.get(name, [0.0]))) * w_fac)}
+    fb = sum(k["fetch_bytes"] for k in kernels.values())
+    wb = sum(k["write_bytes"] for k in kernels.values())
+    entry = {"kernels": kernels, "kernel_hash": kernel_hash(), "points": n,
              "fetch_scale": round(f_fac, 4), "write_scale": round(w_fac, 4),
-             "fetch_bytes_per_launch": round(f_step * f_fac), "write_bytes_per_launch": round(w_step * w_fac),
-             "bytes_per_launch": round(f_step * f_fac + w_step * w_fac),
-             "alg_bytes_per_launch": ALG_BYTES_STENCIL * n,
-             "note": "L2-miss bytes (FETCH_SIZE/WRITE_SIZE count traffic below L2, so infinity-cache hits are "
-                     "included); calibration kernels k_vcheck (read 4N B) and k_vdt2 (write 4N B)"}
-    for k in [k for k in set(fetch) | set(write) if "cpml" in k]:
-        entry.setdefault("cpml", {})[k] = {"fetch_bytes": round(np.mean(fetch.get(k, [0])) * f_fac),
-                                           "write_bytes": round(np.mean(write.get(k, [0])) * w_fac)}
+             "fetch_bytes_per_step": fb, "write_bytes_per_step": wb, "bytes_per_step": fb + wb,
+             "alg_bytes_per_step": step_alg_bytes(wl, ALG_BYTES_STENCIL),
+             "note": "bytes below L2 (FETCH_SIZE/WRITE_SIZE; Infinity Cache hits are included), per time step "
+                     "(every kernel of the step once); calibration kernels k_vcheck (read 4N B) and k_vdt2 "
+                     "(write 4N B)"}
     try:
         with open(out_path) as f:
             allv = json.load(f)
@@ -341,47 +367,16 @@ def batched_leg(dev, reps=2):
             "speedup": round(t_seq / t_batch, 3)}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="smooth240")
-    ap.add_argument("--tile", type=int, default=-1, help="tile variant, -1 = autotune")
-    ap.add_argument("--prof-stride", type=int, default=10,
-                    help="time every k-th stencil launch with HIP events (0: none); each timed launch adds "
-                         "two event records to the stream, so sampling keeps the whole-run figure unperturbed")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--graph", action="store_true", help="launch the step loop as one HIP graph")
-    ap.add_argument("--calib", action="store_true", help="also run a 1 GiB copy (counter calibration)")
-    ap.add_argument("--time-steps", type=int, default=0, help="override the workload's step count (profiling)")
-    ap.add_argument("--no-extras", action="store_true", help="skip the gradient and batched-shot legs")
-    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="summarise two rocprofv3 --pmc runs into profiles/k_step_traffic.json and exit")
-    args = ap.parse_args()
-    if args.pmc_summary:
-        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.workload,
-                    os.path.join(ROOT, "profiles", "k_step_traffic.json"))
-        return
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (shots and z-slabs would shard "
-              "across GPUs; see the design notes). Run with --gpus 1.", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
+def run_forward_workload(dev, wl, tile=-1, graph=False, steps=1, warmup=1, prof_stride=10):
+    """Times full modelling runs of a single-shot workload: returns the
+    context's description, the seconds per run and the step timing."""
     import torch
     from paper_2007_06048_amd import minimod as mm
-
-    dev = torch.device("cuda:0")
-    wl = load_workload(args.workload)
     s = wl.shots[0]
-    if args.time_steps > 0:
-        wl.nsteps = args.time_steps
     T = wl.nsteps
     iso = s.rho is not None  # the acoustic_iso workload carries a density model
     p = mm.default_params(nx=wl.nx, ny=wl.ny, nz=wl.nz, dx=wl.h, dy=wl.h, dz=wl.h, cfl=wl.cfl, bc=wl.bc, nb=wl.nb,
-                          sponge_sigma=wl.sigma, cpml_R=wl.cpml_R, cpml_f0=wl.f0, tile=args.tile,
+                          sponge_sigma=wl.sigma, cpml_R=wl.cpml_R, cpml_f0=wl.f0, tile=tile,
                           model=mm.MODEL_ISO if iso else mm.MODEL_ISO_CD)
     vel = torch.from_numpy(s.vel).to(dev)
     t_init0 = time.perf_counter()
@@ -394,25 +389,113 @@ def main():
 
     def run():
         ctx.reset()
-        ctx.forward(T, w, traces, graph=args.graph)
+        ctx.forward(T, w, traces, graph=graph)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         run()
     torch.cuda.synchronize()
-    if args.prof_stride > 0 and not args.graph:
-        ctx.profile(args.prof_stride)
+    if prof_stride > 0 and not graph:
+        ctx.profile(prof_stride)
         ctx.profile_read()  # clear
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         run()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    k_ms, k_n = (ctx.profile_read() if args.prof_stride > 0 and not args.graph else (0.0, 0))
+    k_ms, k_n = (ctx.profile_read() if prof_stride > 0 and not graph else (0.0, 0))
     ctx.profile(0)
+    info = {"tile": mm.tile_name(ctx.info()["tile"]), "init_s": round(t_init, 3), "dt_s": dt}
+    del ctx, traces, vel
+    torch.cuda.empty_cache()
+    return info, (t1 - t0) / steps, k_ms, k_n
+
+
+def step_roofline(wl, alg_pt, step_ms, n_timed, stride, kernels):
+    """Roofline of one time step: its algorithmic bytes over the average
+    duration of the timed steps."""
+    bytes_step = step_alg_bytes(wl, alg_pt)
+    ach = bytes_step / (step_ms / 1e3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_for(wl.name),
+            "kernel": kernels, "avg_launch_us": round(step_ms * 1e3, 2),
+            "alg_bytes_per_launch": bytes_step,
+            "alg_bytes_per_point": round(bytes_step / (wl.nx * wl.ny * wl.nz), 3),
+            "timed_launches": n_timed, "timed_every": stride}
+    if roof["traffic"]:
+        # the bytes the step's kernels actually move below L2, at the measured step time
+        roof["traffic_GBs"] = round(roof["traffic"] / (step_ms / 1e3) / 1e9, 1)
+        roof["traffic_per_alg"] = round(roof["traffic"] / bytes_step, 3)
+    return roof
+
+
+def step_kernels_name(wl, iso):
+    if iso:
+        return "time step: k_iso_u + k_iso_p (face velocities, then pressure)"
+    if wl.bc == 2:
+        return "time step: k_cpml (layer memory) + k_step (stencil, leapfrog, source, record)"
+    return "time step: k_step (stencil, damping, leapfrog, source, record)"
+
+
+def cache_resident_leg(dev, reps=2):
+    """The 240^3 CPML-20 workload (1000 steps): a working set of about
+    250 MB, which the 256 MiB Infinity Cache can hold, so its rate is not an
+    HBM figure; reported beside the headline for comparison with the paper's
+    240^3 example."""
+    from paper_2007_06048_amd import workloads as W
+    wl = W.smooth_240()
+    info, t, k_ms, k_n = run_forward_workload(dev, wl, steps=reps, warmup=1)
+    out = {"workload": wl.name, "run_s": round(t, 4),
+           "gpts": round(wl.nx * wl.ny * wl.nz * wl.nsteps / t / 1e9, 2), "tile": info["tile"],
+           "note": "working set about 250 MB: Infinity-Cache resident, not an HBM figure"}
+    if k_n > 0:
+        out["roofline"] = step_roofline(wl, ALG_BYTES_STENCIL, k_ms / k_n, k_n, 10, step_kernels_name(wl, False))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="layered1024")
+    ap.add_argument("--tile", type=int, default=-1, help="tile variant, -1 = autotune")
+    ap.add_argument("--prof-stride", type=int, default=10,
+                    help="time every k-th time step with HIP events stamped by its first and last launch (0: "
+                         "none); sampling keeps the whole-run figure unperturbed")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="launch the step loop as one HIP graph")
+    ap.add_argument("--calib", action="store_true", help="also run a 1 GiB copy (counter calibration)")
+    ap.add_argument("--time-steps", type=int, default=0, help="override the workload's step count (profiling)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 240^3, gradient, batched, free-surface and acoustic_iso legs")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs into profiles/step_traffic.json and exit")
+    args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.workload,
+                    os.path.join(ROOT, "profiles", "step_traffic.json"))
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (shots and z-slabs would shard "
+              "across GPUs; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    dev = torch.device("cuda:0")
+    wl = load_workload(args.workload)
+    s = wl.shots[0]
+    if args.time_steps > 0:
+        wl.nsteps = args.time_steps
+    T = wl.nsteps
+    iso = s.rho is not None
+    info, t_run, k_ms, k_n = run_forward_workload(dev, wl, tile=args.tile, graph=args.graph, steps=args.steps,
+                                                  warmup=args.warmup, prof_stride=args.prof_stride)
+    ms_step = t_run * 1e3
     pts = wl.nx * wl.ny * wl.nz
-    value = pts * T / (ms_step / 1e3) / 1e9
+    value = pts * T / t_run / 1e9
 
     if args.calib:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -421,35 +504,17 @@ def main():
         torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
+        del a, b
 
-    roof = None
     alg_pt = ALG_BYTES_ISO if iso else ALG_BYTES_STENCIL
+    roof = None
     if k_n > 0:
-        avg_ms = k_ms / k_n
-        bytes_launch = alg_pt * pts
-        ach = bytes_launch / (avg_ms / 1e3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_for(wl.name),
-                "kernel": ("k_iso_u + k_iso_p (face velocities, then pressure)" if iso else
-                           "k_step (stencil + sponge/leapfrog update)"),
-                "avg_launch_us": round(avg_ms * 1e3, 2),
-                "alg_bytes_per_launch": bytes_launch, "timed_launches": k_n,
-                "timed_every": args.prof_stride}
-        if roof["traffic"]:
-            # the bytes the kernel actually moves below L2, at the measured launch time
-            roof["traffic_GBs"] = round(roof["traffic"] / (avg_ms / 1e3) / 1e9, 1)
-
-    # whole-step roofline over every kernel of the step: 16 B per point plus, for CPML,
-    # 16 B (psi and zeta, read and write) per point and damped axis
-    damped_axis_pts = 0
-    if wl.bc == 2:
-        for n, m in ((wl.nx, wl.ny * wl.nz), (wl.ny, wl.nx * wl.nz), (wl.nz, wl.nx * wl.ny)):
-            damped_axis_pts += 2 * wl.nb * m
-    step_bytes = alg_pt * pts + 16 * damped_axis_pts
-    step_ach = step_bytes / (ms_step / 1e3 / T) / 1e9
-    step_roof = {"bound": "hbm", "achieved": round(step_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "frac": round(step_ach / HBM_PEAK_GBS, 4), "alg_bytes_per_step": step_bytes,
-                 "alg_bytes_per_point": round(step_bytes / pts, 2), "us_per_step": round(ms_step * 1e3 / T, 2)}
+        roof = step_roofline(wl, alg_pt, k_ms / k_n, k_n, args.prof_stride, step_kernels_name(wl, iso))
+    # the same over the whole run (wall clock of a run / T): launch gaps, the trace record and reset included
+    bytes_step = step_alg_bytes(wl, alg_pt)
+    run_ach = bytes_step / (t_run / T) / 1e9
+    run_roof = {"achieved": round(run_ach, 1), "frac": round(run_ach / HBM_PEAK_GBS, 4),
+                "us_per_step": round(t_run / T * 1e6, 2)}
 
     out = {
         "metric": "Gpoint-updates/s and % HBM roofline (fwd)",
@@ -466,14 +531,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "grid": [wl.nx, wl.ny, wl.nz], "time_steps_per_run": T, "h_m": wl.h,
                    "bc": {0: "none", 1: "sponge", 2: "cpml"}[wl.bc], "nb": wl.nb, "receivers": len(s.rec),
-                   "tile": mm.tile_name(ctx.info()["tile"]), "graph": bool(args.graph),
-                   "init_s": round(t_init, 3), "dt_s": dt},
+                   "tile": info["tile"], "graph": bool(args.graph), "init_s": info["init_s"], "dt_s": info["dt_s"]},
         "roofline": roof,
-        "step_roofline": step_roof,
+        "run_roofline": run_roof,
     }
-    del ctx, traces
-    torch.cuda.empty_cache()
     if not args.no_extras:
+        out["cache_resident_240"] = cache_resident_leg(dev)
+        torch.cuda.empty_cache()
         out["gradient"] = gradient_leg(dev)
         torch.cuda.empty_cache()
         out["batched"] = batched_leg(dev)
@@ -484,7 +548,8 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
-        out["cpu_baseline_1thread"] = cpu_baseline(wl, args.cpu_budget * 2.0 / 3.0, threads=1)
+        from paper_2007_06048_amd import workloads as W
+        out["cpu_baseline_1thread"] = cpu_baseline(W.smooth_240(), args.cpu_budget * 2.0 / 3.0, threads=1)
     # the paper's only timing of this propagator, as context (a different grid, spacing, step count
     # and boundary width, one CPU thread on unstated hardware): section "Compilation and usage"
     # reports 30.47 s of kernel time for 240^3 points x 300 steps

@@ -44,9 +44,12 @@
  *    mm_forward_steps(n) produces p^{k+1} .. p^{k+n}; wavelet row j is
  *    w(t_{k+j}) and enters p^{k+j+1}; traces row j is p^{k+j+1} at the
  *    receivers.
- *  - Errors: every function returns an mm_status; on error the context is
- *    unchanged (no work enqueued) and mm_last_error() describes the
- *    problem.  A context is not thread-safe; use one per stream.
+ *  - Errors: every function returns an mm_status and mm_last_error()
+ *    describes a failure.  Argument, state, stability and workspace errors
+ *    are found before anything is enqueued, so the context is unchanged.
+ *    MM_ERR_DEVICE (a HIP call failed) can come after part of a run was
+ *    enqueued: the context then refuses further steps with MM_ERR_STATE
+ *    until mm_reset.  A context is not thread-safe; use one per stream.
  *  - Batches: a context holds one or more shots, each on its own grid
  *    (sub-volume) with its own sources and receivers; all shots share
  *    spacing, dt, boundary kind and width.  Wavelet and trace rows
@@ -89,8 +92,9 @@ typedef enum { MM_BC_NONE = 0, MM_BC_SPONGE = 1, MM_BC_CPML = 2 } mm_bc;
  *    49/5120, -5/7168); staggered leapfrog
  *      u^{n+1/2} = G (u^{n-1/2} + dt b D+ p^n),
  *      p^{n+1}   = G (p^n + dt rho v^2 (D- . u^{n+1/2} + s^n)),
- *    b the face buoyancy (mean of 1/rho of the two cells beside the face,
- *    1/rho of the inner cell on the last face), G the cell's sponge factor;
+ *    b the face buoyancy 2 / (rho_0 + rho_1), one over the mean density of
+ *    the two cells beside the face (1/rho of the inner cell on the last
+ *    face), G the cell's sponge factor;
  *    dt = cfl / (C vmax sqrt(dx^-2 + dy^-2 + dz^-2)), C = 2161/1680.
  *    Forward modelling only, bc none or sponge, with or without the free
  *    surface (p = 0 on the top plane and odd above it, u_z even about it). */
@@ -255,12 +259,16 @@ mm_status mm_set_tile(mm_ctx* ctx, int32_t tile);
 int32_t mm_num_tiles(void);
 const char* mm_tile_name(int32_t t);
 
-/* Kernel timing on the context's stream: while stride > 0, every stride-th
- * launch of the stencil kernel (the dominant kernel of a step) records its
- * own start and end into a pair of HIP events (hipExtLaunchKernel, no extra
- * stream packets).  mm_profile_read synchronises the stream, returns
- * the summed milliseconds and the number of timed launches, and clears the
- * record.  stride 0 stops timing.  Graph launches are not timed. */
+/* Step timing on the context's stream: while stride > 0, every stride-th
+ * time step (of one shot group) records the start of its first kernel and
+ * the end of its last kernel into a pair of HIP events, stamped by the
+ * launches themselves (hipExtLaunchKernel, no extra stream packets).  A
+ * step is the kernels that advance the wavefields by one time level (with
+ * CPML the layer kernel and the stencil kernel); point injection by a
+ * separate kernel (more than 4 sources per shot) is not included.
+ * mm_profile_read synchronises the stream, returns the summed
+ * milliseconds and the number of timed steps, and clears the record.
+ * stride 0 stops timing.  Graph launches are not timed. */
 mm_status mm_profile(mm_ctx* ctx, int32_t stride);
 mm_status mm_profile_read(mm_ctx* ctx, double* ms, int32_t* launches);
 

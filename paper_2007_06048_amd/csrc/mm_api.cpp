@@ -39,7 +39,7 @@ struct ShotGeom {
 
 // Bytes one forward step of a shot touches: three fields, and for CPML the
 // memory (psi, zeta) and correction slabs; acoustic_iso: two pressure fields,
-// three face velocities, dt rho v^2 and dt / rho.
+// three face velocities, dt rho v^2 and rho / dt.
 double shot_set_bytes(const mm_params& p, const ShotGeom& q) {
     if (p.model == MM_MODEL_ISO) return 28.0 * q.n();
     double b = 12.0 * q.n();
@@ -116,7 +116,7 @@ struct Layout {
     std::vector<size_t> buf0, buf1, vdt2, prof, ebuf0, ebuf1;
     std::vector<size_t> psi[3], zeta[3], corr[3];
     std::vector<size_t> apsi[3], azeta[3], acorr[3];  // CPML adjoint memory and corrections
-    std::vector<size_t> iso_u[3], iso_b;              // acoustic_iso face velocities, dt / rho
+    std::vector<size_t> iso_u[3], iso_b;              // acoustic_iso face velocities, rho / dt
     size_t src_shot = 0, src_off = 0, src_start = 0, src_col = 0, src_g = 0;
     size_t rin_shot = 0, rin_off = 0, rin_start = 0, rin_col = 0, rin_g = 0;
     size_t rg_shot = 0, rg_off = 0, sg_shot = 0, sg_off = 0;
@@ -270,8 +270,10 @@ struct GraphKey {
     float* tr = nullptr;
     int step = -1;
     int variant = -1;
+    bool ckpt = false;  // the captured steps store checkpoints (and the wavelet for the replay)
     bool operator==(const GraphKey& o) const {
-        return nsteps == o.nsteps && wav == o.wav && tr == o.tr && step == o.step && variant == o.variant;
+        return nsteps == o.nsteps && wav == o.wav && tr == o.tr && step == o.step && variant == o.variant &&
+               ckpt == o.ckpt;
     }
 };
 
@@ -584,21 +586,9 @@ mm_status zero_adjoint(mm_ctx* c, hipStream_t s) {
 mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, const StepAux& aux, hipStream_t s,
                        const mm_ctx::Group* g) {
     const bool timed = c->prof_stride > 0 && s == c->stream && (c->prof_count++ % c->prof_stride) == 0;
-    if (c->cpml) {
-        if (shots == c->d_shots) {
-            if (!g) return fail(c, MM_ERR_STATE, "forward CPML step without a shot group");
-            MM_TRY(dev(c, launch_cpml(shots + g->s0, g->s1 - g->s0, c->p.nb, false, g->stream, g->cpml_d,
-                                      g->cpml_h.data(), parity, c->cf, s),
-                       "cpml launch"));
-        } else {
-            MM_TRY(dev(c, launch_cpml(shots, (int)c->geom.size(), c->p.nb, true, false, c->cpml_adj_d,
-                                      c->cpml_adj_h.data(), parity, c->cf, s),
-                       "adjoint cpml launch"));
-        }
-    }
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (timed) {
-        // the launch itself stamps the start and end of the kernel into the pair
+        // the step's first kernel stamps its start into ev0, the last its end into ev1
         while (c->prof_ev.size() < c->prof_used + 2) {
             hipEvent_t e;
             MM_TRY(dev(c, hipEventCreate(&e), "event"));
@@ -607,6 +597,19 @@ mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, co
         ev0 = c->prof_ev[c->prof_used];
         ev1 = c->prof_ev[c->prof_used + 1];
         c->prof_used += 2;
+    }
+    if (c->cpml) {
+        if (shots == c->d_shots) {
+            if (!g) return fail(c, MM_ERR_STATE, "forward CPML step without a shot group");
+            MM_TRY(dev(c, launch_cpml(shots + g->s0, g->s1 - g->s0, c->p.nb, false, g->stream, g->cpml_d,
+                                      g->cpml_h.data(), parity, c->cf, s, ev0),
+                       "cpml launch"));
+        } else {
+            MM_TRY(dev(c, launch_cpml(shots, (int)c->geom.size(), c->p.nb, true, false, c->cpml_adj_d,
+                                      c->cpml_adj_h.data(), parity, c->cf, s, ev0),
+                       "adjoint cpml launch"));
+        }
+        ev0 = nullptr;  // stamped by the CPML kernel
     }
     const TileEnt* tiles = g ? c->d_tiles + g->tile_off : c->d_tiles;
     const int nt = g ? g->ntiles : c->ntiles;
@@ -747,7 +750,8 @@ mm_status check_forward(mm_ctx* c, int nsteps, const float* wav) {
     if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
     if (nsteps < 0) return fail(c, MM_ERR_ARG, "nsteps must be >= 0");
     if (c->nsrc > 0 && nsteps > 0 && !wav) return fail(c, MM_ERR_ARG, "wavelet is NULL");
-    if (!c->fwd_valid) return fail(c, MM_ERR_STATE, "forward state was consumed by a gradient replay; call mm_reset");
+    if (!c->fwd_valid)
+        return fail(c, MM_ERR_STATE, "forward state was consumed by a gradient replay or a failed launch; call mm_reset");
     if ((long long)c->step + nsteps > (1LL << 30)) return fail(c, MM_ERR_ARG, "step counter overflow");
     return MM_OK;
 }
@@ -1014,7 +1018,7 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
         sd.cw = p->nb;
         sd.fs = p->free_surface;
         for (int a = 0; a < 3; ++a) sd.u[a] = c->iso ? at<float>(c->ws, L.iso_u[a][i]) : nullptr;
-        sd.bdt = c->iso ? at<float>(c->ws, L.iso_b[i]) : nullptr;
+        sd.rdt = c->iso ? at<float>(c->ws, L.iso_b[i]) : nullptr;
         c->shots_h.push_back(sd);
         ShotDev sa = sd;
         sa.nsrc_in = 0;
@@ -1195,7 +1199,7 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
     for (int i = 0; i < nshots && !st; ++i) {
         if (c->iso) {
             const ShotDev& q = c->shots_h[i];
-            st = dev(c, launch_iso_setup(shots[i].vel, shots[i].rho, geom[i].n(), c->dt, q.vdt2, q.bdt, s),
+            st = dev(c, launch_iso_setup(shots[i].vel, shots[i].rho, geom[i].n(), c->dt, q.vdt2, q.rdt, s),
                      "coefficients");
         } else {
             st = dev(c, launch_vdt2(shots[i].vel, c->shots_h[i].vdt2, geom[i].n(), c->dt, s), "vdt2");
@@ -1246,7 +1250,13 @@ mm_status mm_init(mm_ctx** out, const mm_params* p, const float* vel_dev, const 
 mm_status mm_forward_steps(mm_ctx* c, int32_t nsteps, const float* wav, float* traces) {
     MM_TRY(check_forward(c, nsteps, wav));
     begin_forward(c, nsteps);
-    MM_TRY(enqueue_forward(c, nsteps, wav, traces, c->stream));
+    const mm_status st = enqueue_forward(c, nsteps, wav, traces, c->stream);
+    if (st) {
+        // a launch failed after earlier steps were enqueued: the state is no
+        // longer that of a whole number of steps
+        c->fwd_valid = false;
+        return st;
+    }
     c->step += nsteps;
     return MM_OK;
 }
@@ -1261,6 +1271,7 @@ mm_status mm_forward_steps_graph(mm_ctx* c, int32_t nsteps, const float* wav, fl
     key.tr = traces;
     key.step = c->ckpt_active ? c->step : (c->step & 1);
     key.variant = c->variant;
+    key.ckpt = c->ckpt_active;
     if (!(c->gexec && c->gkey == key)) {
         drop_graph(c);
         if (!c->cap_stream) MM_TRY(dev(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "stream"));

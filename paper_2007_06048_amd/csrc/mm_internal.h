@@ -21,10 +21,10 @@ struct ShotDev {
     int nsrc_in;          // sources added inside the stencil kernel (0..4)
     int src_col[4];       // their columns in the wavelet row
     long long src_off[4]; // their cells
-    // acoustic_iso (staggered grid): vdt2 holds dt rho v^2, bdt dt / rho; u[a]
+    // acoustic_iso (staggered grid): vdt2 holds dt rho v^2, rdt rho / dt; u[a]
     // the particle velocity on the faces (index i of u_x is the face i+1/2)
     float* u[3];
-    float* bdt;
+    float* rdt;
 };
 
 enum { MAX_INLINE_SRC = 4 };
@@ -121,8 +121,10 @@ hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int 
 // sizes the grid.  stream (forward only): psi and zeta are loaded with the
 // non-temporal hint (the step's working set exceeds the Infinity Cache).
 void cpml_block_table(const int* nx, const int* ny, const int* nz, int nshots, int width, int* off);
+// ev0 (may be null) receives the kernel's start time stamp.
 hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, bool adjoint, bool stream, const int* block_off_dev,
-                       const int* block_off_host, int parity, const Coefs& cf, hipStream_t s);
+                       const int* block_off_host, int parity, const Coefs& cf, hipStream_t s,
+                       hipEvent_t ev0 = nullptr);
 // acoustic_iso: one step is launch_iso_u (u^{n+1/2} from p^n = buf[parity])
 // then launch_iso_p (p^{n+1} into buf[parity ^ 1]), over the same tile
 // table as the stencil kernel; bc 0 none, 1 sponge.  Sources are added by
@@ -134,8 +136,8 @@ hipError_t launch_iso_step(int variant, int bc, bool stream, const TileEnt* tile
                            int parity, const Coefs& cf, hipStream_t s, hipEvent_t ev0 = nullptr,
                            hipEvent_t ev1 = nullptr);
 bool iso_variant_ok(int variant);
-// dt rho v^2 and dt / rho of one shot (n cells)
-hipError_t launch_iso_setup(const float* vel, const float* rho, long long n, double dt, float* kdt, float* bdt,
+// dt rho v^2 and rho / dt of one shot (n cells)
+hipError_t launch_iso_setup(const float* vel, const float* rho, long long n, double dt, float* kdt, float* rdt,
                             hipStream_t s);
 hipError_t launch_inject(const InjTab& tab, const ShotDev* shots, int parity, const float* vals, int ncols,
                          int mode, const StepAux& aux, hipStream_t s);

@@ -478,8 +478,9 @@ hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int 
 // LDS (x / y neighbours) and a register queue (z); in k_iso_p, u_x and u_y
 // are staged in LDS with their x / y halos and u_z in a register queue.
 // Sources are added to p^{n+1} by k_inject (dt rho v^2 s).  The face
-// buoyancy is formed on the fly from dt / rho of the two cells beside the
-// face (their mean; the inner cell's value on the last face of an axis).
+// buoyancy is formed on the fly from rho / dt of the two cells beside the
+// face: dt b = 2 / (rho_0 / dt + rho_1 / dt), one over their mean density
+// (the inner cell's dt / rho on the last face of an axis).
 
 template <int TX, int RY>
 struct IsoTile {
@@ -493,7 +494,7 @@ __global__ __launch_bounds__(256) void k_iso_u(const TileEnt* __restrict__ tiles
     constexpr int LW = TX + 8;
     constexpr bool SPONGE = BC == 1;
     __shared__ float lds[2][TY + 8][LW];  // p^n of the plane with halos
-    __shared__ float ldb[2][TY + 8][LW];  // dt / rho of the plane with halos (face buoyancy)
+    __shared__ float ldb[2][TY + 8][LW];  // rho / dt of the plane with halos (face buoyancy)
     const int b = blockIdx.x;
     const int t = (b & 7) * per_xcd + (b >> 3);
     if (t >= ntiles) return;
@@ -502,7 +503,7 @@ __global__ __launch_bounds__(256) void k_iso_u(const TileEnt* __restrict__ tiles
     const int nx = sd.nx, ny = sd.ny, nz = sd.nz;
     const long long plane = (long long)nx * ny;
     const float* __restrict__ pc = sd.buf[parity];
-    const float* __restrict__ bd = sd.bdt;
+    const float* __restrict__ bd = sd.rdt;
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int x = te.x0 + tx;
     const bool xin = x < nx;
@@ -561,7 +562,7 @@ __global__ __launch_bounds__(256) void k_iso_u(const TileEnt* __restrict__ tiles
             q[r][0] = 4 < nz ? -bload(r4, voc[r]) : 0.0f;
         }
     }
-    // stage for plane zn: p^n(zn+4), halos of p and dt/rho at zn, dt/rho(zn+1), u at zn
+    // stage for plane zn: p^n(zn+4), halos of p and rho/dt at zn, rho/dt(zn+1), u at zn
     float nq[RY], nxh[RY], nyh[YH], nbh[RY], nbx[RY], nby[YH], nu[3][RY];
     auto fetch = [&](int zn) {
         const bool hin = zn + 4 < nz, bin = zn + 1 < nz;
@@ -642,10 +643,12 @@ __global__ __launch_bounds__(256) void k_iso_u(const TileEnt* __restrict__ tiles
             if (in[r]) {
                 const long long o = zoff + (row[r] * nx + x);
                 const float G = SPONGE ? gx * gyv[r] * gz : 1.0f;
-                const float bc = b0[r];
-                const float fx = xlast ? bc : 0.5f * (bc + B[yy][xx + 1]);
-                const float fy = row[r] + 1 >= ny ? bc : 0.5f * (bc + B[yy + 1][xx]);
-                const float fz = zlast ? bc : 0.5f * (bc + b1[r]);
+                // dt times the face buoyancy: 2 / (rho_0 / dt + rho_1 / dt), the inner cell's
+                // dt / rho_0 on the last face of an axis
+                const float rc = b0[r];
+                const float fx = 2.0f / (rc + (xlast ? rc : B[yy][xx + 1]));
+                const float fy = 2.0f / (rc + (row[r] + 1 >= ny ? rc : B[yy + 1][xx]));
+                const float fz = 2.0f / (rc + (zlast ? rc : b1[r]));
                 ((gfloat*)sd.u[0])[o] = G * fmaf(fx, dx, cu[0][r]);
                 ((gfloat*)sd.u[1])[o] = G * fmaf(fy, dy, cu[1][r]);
                 ((gfloat*)sd.u[2])[o] = G * fmaf(fz, dz, cu[2][r]);
@@ -851,19 +854,19 @@ hipError_t launch_iso_step(int variant, int bc, bool stream, const TileEnt* tile
 
 __global__ __launch_bounds__(256) void k_iso_setup(const float* __restrict__ vel, const float* __restrict__ rho,
                                                    long long n, double dt, float* __restrict__ kdt,
-                                                   float* __restrict__ bdt) {
+                                                   float* __restrict__ rdt) {
     for (long long o = blockIdx.x * 256LL + threadIdx.x; o < n; o += (long long)gridDim.x * 256) {
         const double r0 = rho[o], v = vel[o];
         kdt[o] = (float)(dt * r0 * v * v);
-        bdt[o] = (float)(dt / r0);
+        rdt[o] = (float)(r0 / dt);
     }
 }
 
-hipError_t launch_iso_setup(const float* vel, const float* rho, long long n, double dt, float* kdt, float* bdt,
+hipError_t launch_iso_setup(const float* vel, const float* rho, long long n, double dt, float* kdt, float* rdt,
                             hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const long long blocks = std::min<long long>((n + 255) / 256, 65536);
-    k_iso_setup<<<dim3((unsigned)blocks), 256, 0, s>>>(vel, rho, n, dt, kdt, bdt);
+    k_iso_setup<<<dim3((unsigned)blocks), 256, 0, s>>>(vel, rho, n, dt, kdt, rdt);
     return hipGetLastError();
 }
 
@@ -1230,7 +1233,7 @@ void cpml_block_table(const int* nx, const int* ny, const int* nz, int nshots, i
 }
 
 hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, bool adjoint, bool stream, const int* block_off_dev,
-                       const int* block_off_host, int parity, const Coefs& cf, hipStream_t s) {
+                       const int* block_off_host, int parity, const Coefs& cf, hipStream_t s, hipEvent_t ev0) {
     if (nshots <= 0) return hipSuccess;
     if (nb < 1 || nb > (adjoint ? 64 : 128)) return hipErrorInvalidValue;
     const int width = adjoint ? nb + 4 : nb;
@@ -1243,12 +1246,14 @@ hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, bool adjoint, b
         (long long)block_off_host[S] + block_off_host[(S + 1) + S] + block_off_host[2 * (S + 1) + S];
     // forward: psi and D2 p of one end [nb][64] (x part: 256); adjoint: three [W][64] arrays (x part: 3 x 256)
     const size_t fl = adjoint ? 3 * (size_t)std::max(width * 64, 256) : (size_t)std::max(2 * nb * 64, 256);
+    const dim3 grid((unsigned)blocks), block(256);
+    const unsigned lds = (unsigned)(sizeof(float) * fl);
     if (adjoint)
-        k_cpml<true, false><<<dim3((unsigned)blocks), 256, sizeof(float) * fl, s>>>(shots, parity, cf, g);
+        hipExtLaunchKernelGGL(k_cpml<true, false>, grid, block, lds, s, ev0, nullptr, 0, shots, parity, cf, g);
     else if (stream)
-        k_cpml<false, true><<<dim3((unsigned)blocks), 256, sizeof(float) * fl, s>>>(shots, parity, cf, g);
+        hipExtLaunchKernelGGL(k_cpml<false, true>, grid, block, lds, s, ev0, nullptr, 0, shots, parity, cf, g);
     else
-        k_cpml<false, false><<<dim3((unsigned)blocks), 256, sizeof(float) * fl, s>>>(shots, parity, cf, g);
+        hipExtLaunchKernelGGL(k_cpml<false, false>, grid, block, lds, s, ev0, nullptr, 0, shots, parity, cf, g);
     return hipGetLastError();
 }
 

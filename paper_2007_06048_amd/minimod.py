@@ -285,10 +285,20 @@ def _make_traces_fn():
         forward builds a gradient-capable context from v = m^{-1/2}, runs the
         checkpointed forward and returns the receiver traces [nsteps][nrec];
         backward runs the library's adjoint with the incoming trace gradient as
-        the residual and returns dL/dm (the imaging condition)."""
+        the residual and returns dL/dm (the imaging condition).
+
+        The gradient is taken at a fixed time step and fixed boundary
+        profiles, so params.dt (> 0) and params.vmax (> 0, the velocity of the
+        CPML damping and of the stability check) must be set: were they
+        derived from max(m^{-1/2}), they would move with m under a wavelet
+        sampled at the old dt, and the returned gradient would not include
+        that dependence.  ValueError otherwise."""
 
         @staticmethod
         def forward(ctx, m, wavelet, params, src, rec):
+            if not (params.dt > 0.0 and params.vmax > 0.0):
+                raise ValueError("traces_from_slowness needs params.dt > 0 and params.vmax > 0: dt and the "
+                                 "CPML profiles are held fixed while m changes")
             vel = torch.rsqrt(m).contiguous()
             nsteps = wavelet.shape[0]
             p = Params.from_buffer_copy(params)

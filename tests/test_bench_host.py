@@ -32,26 +32,42 @@ def _counter_file(d, counter, rows):
 
 
 def test_pmc_summary_scales_by_the_calibration_kernels(tmp_path):
-    """With k_vcheck reading 2x and k_vdt2 writing 1x its true bytes, the
-    stencil's counters are scaled by 1/2 and 1, per dispatch."""
+    """With k_vcheck reading 2x and k_vdt2 writing 1x its true bytes, every
+    step kernel's counters are scaled by 1/2 and 1, averaged per dispatch and
+    summed over the kernels of a time step; other kernels are left out."""
     from paper_2007_06048_amd import workloads as W
-    n = W.smooth_240().nx ** 3
+    wl = W.smooth_240()
+    n = wl.nx ** 3
     kib = 4.0 * n / 1024.0  # 4 N bytes in KiB
     step = "void mm::k_step<32, 2, 1, 2, 0, 256, false>(args)"
     cpml = "void mm::k_cpml<false, false>(args)"
+    other = "void mm::k_fill(args)"
     _counter_file(tmp_path / "f", "FETCH_SIZE", [("mm::k_vcheck(args)", 2 * kib), (step, 6 * kib), (step, 8 * kib),
-                                                 (cpml, 2 * kib)])
+                                                 (cpml, 2 * kib), (cpml, 2 * kib), (other, 50 * kib)])
     _counter_file(tmp_path / "w", "WRITE_SIZE", [("mm::k_vdt2(args)", kib), (step, kib), (step, kib),
-                                                 (cpml, 3 * kib)])
+                                                 (cpml, 3 * kib), (cpml, 3 * kib), (other, 50 * kib)])
     out = tmp_path / "traffic.json"
     bench.pmc_summary(str(tmp_path / "f"), str(tmp_path / "w"), "smooth240", str(out))
-    e = json.load(open(out))["smooth_240^3_cpml20_1000steps"]
-    assert e["dispatches"] == 2 and e["kernel"] == step
+    e = json.load(open(out))[wl.name]
+    assert set(e["kernels"]) == {step, cpml}
+    assert e["kernels"][step]["dispatches"] == 2
     assert e["fetch_scale"] == pytest.approx(0.5) and e["write_scale"] == pytest.approx(1.0)
-    assert e["fetch_bytes_per_launch"] == pytest.approx(0.5 * 7 * 4 * n, rel=1e-9)
-    assert e["write_bytes_per_launch"] == pytest.approx(4 * n, rel=1e-9)
-    assert e["bytes_per_launch"] == e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
-    assert e["alg_bytes_per_launch"] == 16 * n
-    assert e["cpml"][cpml]["fetch_bytes"] == pytest.approx(4 * n, rel=1e-9)
-    assert e["cpml"][cpml]["write_bytes"] == pytest.approx(12 * n, rel=1e-9)
+    assert e["kernels"][step]["fetch_bytes"] == pytest.approx(0.5 * 7 * 4 * n, rel=1e-9)
+    assert e["kernels"][cpml]["write_bytes"] == pytest.approx(12 * n, rel=1e-9)
+    assert e["fetch_bytes_per_step"] == pytest.approx((14 + 4) * n, rel=1e-9)
+    assert e["write_bytes_per_step"] == pytest.approx((4 + 12) * n, rel=1e-9)
+    assert e["bytes_per_step"] == e["fetch_bytes_per_step"] + e["write_bytes_per_step"]
+    nb2 = 2 * wl.nb
+    assert e["alg_bytes_per_step"] == 16 * n + 16 * 3 * nb2 * wl.nx * wl.nx
     assert e["kernel_hash"] == bench.kernel_hash()
+
+
+def test_step_alg_bytes_at_the_1024_workload():
+    """20.0 bytes per point at 1024 x 1024 x 512 with a 32-cell CPML (16 B
+    per point and 16 B per point and damped axis), 24.0 at 240^3 with 20."""
+    from types import SimpleNamespace as NS
+    a = bench.step_alg_bytes(NS(nx=1024, ny=1024, nz=512, bc=2, nb=32), 16)
+    assert a / (1024 * 1024 * 512) == pytest.approx(20.0, abs=0.01)
+    b = bench.step_alg_bytes(NS(nx=240, ny=240, nz=240, bc=2, nb=20), 16)
+    assert b / 240 ** 3 == pytest.approx(24.0, abs=0.01)
+    assert bench.step_alg_bytes(NS(nx=64, ny=64, nz=64, bc=1, nb=12), 16) == 16 * 64 ** 3

@@ -173,6 +173,10 @@ def test_autograd_binding_matches_library_gradient():
     w = torch.from_numpy(mm.ricker(25.0, 0.06, dt, T).reshape(T, 1)).to(DEV)
     d_obs = torch.from_numpy(rng.standard_normal((T, len(rec))).astype(np.float32) * 1e-7).to(DEV)
     m = (1.0 / torch.from_numpy(vel).to(DEV) ** 2).requires_grad_(True)
+    with pytest.raises(ValueError):  # dt and vmax must be pinned
+        mm.traces_from_slowness(m, w, p, src, rec)
+    p.dt = dt
+    p.vmax = float(vel.max())
     tr = mm.traces_from_slowness(m, w, p, src, rec)
     loss = 0.5 * ((tr - d_obs) ** 2).sum()
     loss.backward()
@@ -234,3 +238,39 @@ def test_cpml_adjoint_limits():
     p.ckpt_every = 0
     p.nb = 10  # forward only: 2 nb + 4 suffices
     mm.Context.single(p, vt, [[8, 8, 8]], [[4, 4, 4]]).close()
+
+
+def test_graph_captured_without_checkpoints_is_not_reused_for_a_checkpointed_run():
+    """A graph captured for steps that store no checkpoints (a run starting
+    at step 2 that would overrun nsteps_max) is not replayed for a run from
+    step 0, which must store them: after reset, the graph run's checkpoints
+    give the same gradient as mm_gradient."""
+    rng = np.random.default_rng(41)
+    shape = (20, 22, 24)
+    vel = rng.uniform(1800.0, 2600.0, shape).astype(np.float32)
+    p = params(shape, bc=mm.BC_CPML, nb=4, f0=25.0)
+    p.ckpt_every = 8
+    T = 40
+    p.nsteps_max = T
+    src = np.array([[12, 11, 10]], np.int32)
+    rec = np.array([[i, 11, 3] for i in range(1, 23, 3)], np.int32)
+    vt = torch.from_numpy(vel).to(DEV)
+    ctx = mm.Context.single(p, vt, src, rec)
+    dt = ctx.dt
+    w = torch.from_numpy(mm.ricker(25.0, 0.06, dt, T + 2).reshape(T + 2, 1)).to(DEV)
+    d_obs = torch.from_numpy(rng.standard_normal((T, len(rec))).astype(np.float32) * 1e-6).to(DEV)
+    tr = torch.empty((T, len(rec)), device=DEV)
+    ctx.forward(2, w[:2])
+    ctx.forward(T, w[:T], tr, graph=True)  # steps 2 .. T + 1: past nsteps_max, no checkpoints
+    ctx.reset()
+    ctx.forward(T, w[:T], tr, graph=True)  # from step 0: checkpoints stored
+    g1 = torch.zeros(shape, device=DEV)
+    ctx.adjoint(T, (tr - d_obs).contiguous(), None, g1)
+    c2 = mm.Context.single(p, vt, src, rec)
+    g2 = torch.empty(shape, device=DEV)
+    tr2 = torch.empty_like(tr)
+    c2.gradient(T, w[:T].contiguous(), d_obs, g2, tr2)
+    torch.cuda.synchronize()
+    assert torch.equal(tr, tr2)
+    assert float(g2.abs().max()) > 0
+    assert rel(g1.cpu().numpy(), g2.cpu().numpy()) <= 1e-6
