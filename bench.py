@@ -158,9 +158,13 @@ def pmc_summary(fetch_dir, write_dir, workload, out_path):
     f_fac = 4.0 * n / one(fetch, "k_vcheck")
     w_fac = 4.0 * n / one(write, "k_vdt2")
     kernels = {}
-    for name in sorted(set(fetch) | set(write)):
-        if not any(k in name for k in STEP_KERNELS):
+    for fam in STEP_KERNELS:
+        # the instantiation the timed steps ran: the one with the most dispatches (the autotuner's
+        # trials of the other tile variants come first and are fewer)
+        names = [k for k in set(fetch) | set(write) if fam in k]
+        if not names:
             continue
+        name = max(names, key=lambda k: len(fetch.get(k, [])))
         kernels[name] = {"dispatches": len(fetch.get(name, [])),
                          "fetch_bytes": round(float(np.mean(fetch.get(name, [0.0]))) * f_fac),
                          "write_bytes": round(float(np.mean(write.get(name, [0.0]))) * w_fac)}

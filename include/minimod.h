@@ -103,7 +103,8 @@ typedef enum { MM_MODEL_ISO_CD = 0, MM_MODEL_ISO = 1 } mm_model;
 /* Snapshot storage of the gradient's checkpoints. */
 typedef enum {
     MM_SNAP_FP32 = 0, /* lossless */
-    MM_SNAP_BF16 = 1  /* bf16(x / s), s = max |x| of the field (1 if zero), round to nearest even */
+    MM_SNAP_BF16 = 1  /* p^k and the increment p^k - p^{k-1} in bfloat16, each scaled per block of
+                         4096 cells by its largest magnitude; see mm_snap_encode */
 } mm_snap;
 
 typedef struct {
@@ -224,6 +225,26 @@ mm_status mm_gradient(mm_ctx* ctx, int32_t nsteps, const float* wavelet, const f
 
 /* Zero the forward and adjoint state and the CPML memory; step = 0. */
 mm_status mm_reset(mm_ctx* ctx);
+
+/* BF16 snapshot codec of the gradient's checkpoints (MM_SNAP_BF16): the
+ * state (p^{k-1}, p^k) of the leapfrog of Eq. (minimod-semidisc) as
+ *   c0[i] = bf16(p^k[i] / s0[b]),   c1[i] = bf16((p^k[i] - p^{k-1}[i]) / s1[b]),
+ * b = i / 4096, with s0[b] (s1[b]) the largest magnitude of p^k (of the
+ * increment) over cells 4096 b .. 4096 b + 4095 (1 if all are zero); float
+ * division and subtraction rounded to nearest, bf16 = round to nearest even
+ * of the float.  Decoding writes p^k[i] = f(c0[i]) * s0[b] and
+ * p^{k-1}[i] = p^k[i] - f(c1[i]) * s1[b], f the exact bf16 -> float
+ * widening, each product and the difference rounded once.
+ * Arguments: prev, cur: device float [n]; c0, c1: device uint16 [n];
+ * s0, s1: device float [mm_snap_blocks(n)]; all caller-owned, not
+ * overlapping; enqueued on `stream` (hipStream_t, NULL = default stream).
+ * Errors: MM_ERR_ARG for n < 0 or a NULL array with n > 0, MM_ERR_DEVICE
+ * for a failed launch. */
+int64_t mm_snap_blocks(int64_t n);
+mm_status mm_snap_encode(const float* prev_dev, const float* cur_dev, int64_t n, uint16_t* c0_dev,
+                         uint16_t* c1_dev, float* s0_dev, float* s1_dev, void* stream);
+mm_status mm_snap_decode(const uint16_t* c0_dev, const uint16_t* c1_dev, const float* s0_dev, const float* s1_dev,
+                         int64_t n, float* prev_dev, float* cur_dev, void* stream);
 
 /* Size of the state blob of mm_get_state / mm_set_state, in bytes. */
 mm_status mm_state_size(const mm_ctx* ctx, size_t* bytes);

@@ -123,7 +123,7 @@ struct Layout {
     size_t cpml_off = 0;  // CPML block tables: per group (forward), then all shots (adjoint)
     bool adjoint = false, grad = false;
     int nseg = 0;
-    size_t seg = 0, ckpt = 0, ckpt_scale = 0, wav_store = 0, tr_store = 0, resid_store = 0;
+    size_t seg = 0, ckpt = 0, ckpt_scale = 0, ckpt_scale_n = 0, wav_store = 0, tr_store = 0, resid_store = 0;
     size_t ckpt_field_bytes = 0;
     size_t ckpt_mem = 0, ckpt_mem_bytes = 0;  // CPML memory of each checkpoint (FP32)
 };
@@ -150,8 +150,8 @@ void compute_layout(const mm_params& p, const std::vector<ShotGeom>& shots, int 
     }
     L.max_tiles = mt;
     L.tiles = take(L, sizeof(TileEnt) * mt);
-    // scratch: vcheck (2 u32), absmax partials + result, loss partials + loss
-    L.scratch = take(L, 64 + sizeof(float) * (kPartials + 2) + sizeof(double) * (kPartials + 2));
+    // scratch: vcheck (2 u32), loss partials + loss
+    L.scratch = take(L, 64 + sizeof(double) * (kPartials + 2));
     L.adjoint = p.ckpt_every > 0;
     L.grad = L.adjoint && S == 1;
     for (int s = 0; s < S; ++s) {
@@ -203,7 +203,9 @@ void compute_layout(const mm_params& p, const std::vector<ShotGeom>& shots, int 
         L.seg = take(L, sizeof(float) * (size_t)K * N);
         L.ckpt_field_bytes = align256((p.snap == MM_SNAP_BF16 ? 2 : 4) * (size_t)N);
         L.ckpt = take(L, (size_t)L.nseg * 2 * L.ckpt_field_bytes);
-        L.ckpt_scale = take(L, sizeof(float) * 2 * L.nseg);
+        // BF16: two scales per block of SNAP_BLOCK cells per checkpoint
+        L.ckpt_scale_n = p.snap == MM_SNAP_BF16 ? (size_t)snap_blocks(N) : 0;
+        L.ckpt_scale = take(L, sizeof(float) * 2 * L.ckpt_scale_n * L.nseg);
         if (p.bc == MM_BC_CPML) {
             const auto& g = shots[0];
             const size_t nb2 = 2 * (size_t)p.nb;
@@ -321,8 +323,6 @@ struct mm_ctx {
     int adj_T = 0, adj_j = 0, seg_loaded = -1;
     // scratch pointers
     unsigned* vcheck = nullptr;
-    float* absmax_part = nullptr;
-    float* absmax_res = nullptr;
     double* loss_part = nullptr;
     double* loss_dev = nullptr;
     // graph
@@ -670,17 +670,19 @@ mm_status ckpt_memory(mm_ctx* c, int seg, bool save, hipStream_t s) {
 mm_status save_ckpt(mm_ctx* c, int seg, int parity, hipStream_t s) {
     const long long N = c->geom[0].n();
     const ShotDev& sd = c->shots_h[0];
-    const float* f[2] = {sd.buf[parity ^ 1], sd.buf[parity]};  // p^{k-1}, p^k
-    float* scale = at<float>(c->ws, c->L.ckpt_scale) + 2 * seg;
-    for (int w = 0; w < 2; ++w) {
-        if (c->p.snap == MM_SNAP_FP32) {
-            MM_TRY(dev(c, hipMemcpyAsync(ckpt_field(c, seg, w), f[w], sizeof(float) * N, hipMemcpyDeviceToDevice, s),
-                       "checkpoint copy"));
-        } else {
-            MM_TRY(dev(c, launch_absmax(f[w], N, c->absmax_part, kPartials, scale + w, s), "absmax"));
-            MM_TRY(dev(c, launch_pack_bf16(f[w], N, scale + w, reinterpret_cast<uint16_t*>(ckpt_field(c, seg, w)), s),
-                       "pack"));
-        }
+    const float* prev = sd.buf[parity ^ 1];  // p^{k-1}
+    const float* cur = sd.buf[parity];       // p^k
+    if (c->p.snap == MM_SNAP_FP32) {
+        MM_TRY(dev(c, hipMemcpyAsync(ckpt_field(c, seg, 0), prev, sizeof(float) * N, hipMemcpyDeviceToDevice, s),
+                   "checkpoint copy"));
+        MM_TRY(dev(c, hipMemcpyAsync(ckpt_field(c, seg, 1), cur, sizeof(float) * N, hipMemcpyDeviceToDevice, s),
+                   "checkpoint copy"));
+    } else {
+        float* sc = at<float>(c->ws, c->L.ckpt_scale) + 2 * c->L.ckpt_scale_n * seg;
+        MM_TRY(dev(c, launch_snap_encode(prev, cur, N, reinterpret_cast<uint16_t*>(ckpt_field(c, seg, 0)),
+                                         reinterpret_cast<uint16_t*>(ckpt_field(c, seg, 1)), sc,
+                                         sc + c->L.ckpt_scale_n, s),
+                   "snapshot encode"));
     }
     return ckpt_memory(c, seg, true, s);
 }
@@ -688,17 +690,19 @@ mm_status save_ckpt(mm_ctx* c, int seg, int parity, hipStream_t s) {
 mm_status restore_ckpt(mm_ctx* c, int seg, int parity, hipStream_t s) {
     const long long N = c->geom[0].n();
     const ShotDev& sd = c->shots_h[0];
-    float* f[2] = {sd.buf[parity ^ 1], sd.buf[parity]};
-    const float* scale = at<float>(c->ws, c->L.ckpt_scale) + 2 * seg;
-    for (int w = 0; w < 2; ++w) {
-        if (c->p.snap == MM_SNAP_FP32) {
-            MM_TRY(dev(c, hipMemcpyAsync(f[w], ckpt_field(c, seg, w), sizeof(float) * N, hipMemcpyDeviceToDevice, s),
-                       "checkpoint copy"));
-        } else {
-            MM_TRY(dev(c, launch_unpack_bf16(reinterpret_cast<const uint16_t*>(ckpt_field(c, seg, w)), N, scale + w,
-                                             f[w], s),
-                       "unpack"));
-        }
+    float* prev = sd.buf[parity ^ 1];
+    float* cur = sd.buf[parity];
+    if (c->p.snap == MM_SNAP_FP32) {
+        MM_TRY(dev(c, hipMemcpyAsync(prev, ckpt_field(c, seg, 0), sizeof(float) * N, hipMemcpyDeviceToDevice, s),
+                   "checkpoint copy"));
+        MM_TRY(dev(c, hipMemcpyAsync(cur, ckpt_field(c, seg, 1), sizeof(float) * N, hipMemcpyDeviceToDevice, s),
+                   "checkpoint copy"));
+    } else {
+        const float* sc = at<float>(c->ws, c->L.ckpt_scale) + 2 * c->L.ckpt_scale_n * seg;
+        MM_TRY(dev(c, launch_snap_decode(reinterpret_cast<const uint16_t*>(ckpt_field(c, seg, 0)),
+                                         reinterpret_cast<const uint16_t*>(ckpt_field(c, seg, 1)), sc,
+                                         sc + c->L.ckpt_scale_n, N, prev, cur, s),
+                   "snapshot decode"));
     }
     return ckpt_memory(c, seg, false, s);
 }
@@ -942,9 +946,7 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
 
     char* scr = c->ws + L.scratch;
     c->vcheck = reinterpret_cast<unsigned*>(scr);
-    c->absmax_part = reinterpret_cast<float*>(scr + 64);
-    c->absmax_res = c->absmax_part + kPartials;
-    c->loss_part = reinterpret_cast<double*>(scr + 64 + sizeof(float) * (kPartials + 2));
+    c->loss_part = reinterpret_cast<double*>(scr + 64);
     c->loss_dev = c->loss_part + kPartials;
 
     // velocity check and maximum (one synchronisation)
@@ -1356,6 +1358,26 @@ mm_status mm_gradient(mm_ctx* c, int32_t nsteps, const float* wav, const float* 
             *loss_host = 0.0;
         }
     }
+    return MM_OK;
+}
+
+int64_t mm_snap_blocks(int64_t n) { return n > 0 ? (int64_t)snap_blocks(n) : 0; }
+
+mm_status mm_snap_encode(const float* prev, const float* cur, int64_t n, uint16_t* c0, uint16_t* c1, float* s0,
+                         float* s1, void* stream) {
+    if (n < 0) return fail(nullptr, MM_ERR_ARG, "n must be >= 0");
+    if (n > 0 && (!prev || !cur || !c0 || !c1 || !s0 || !s1)) return fail(nullptr, MM_ERR_ARG, "NULL array");
+    const hipError_t e = launch_snap_encode(prev, cur, n, c0, c1, s0, s1, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(nullptr, MM_ERR_DEVICE, std::string("snapshot encode: ") + hipGetErrorString(e));
+    return MM_OK;
+}
+
+mm_status mm_snap_decode(const uint16_t* c0, const uint16_t* c1, const float* s0, const float* s1, int64_t n,
+                         float* prev, float* cur, void* stream) {
+    if (n < 0) return fail(nullptr, MM_ERR_ARG, "n must be >= 0");
+    if (n > 0 && (!prev || !cur || !c0 || !c1 || !s0 || !s1)) return fail(nullptr, MM_ERR_ARG, "NULL array");
+    const hipError_t e = launch_snap_decode(c0, c1, s0, s1, n, prev, cur, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(nullptr, MM_ERR_DEVICE, std::string("snapshot decode: ") + hipGetErrorString(e));
     return MM_OK;
 }
 

@@ -146,10 +146,15 @@ hipError_t launch_vdt2(const float* vel, float* vdt2, long long n, double dt, hi
 hipError_t launch_vcheck(const float* vel, long long n, unsigned* result2, hipStream_t s);
 hipError_t launch_fill(float* p, long long n, float v, hipStream_t s);
 hipError_t launch_copy(float* dst, const float* src, long long n, hipStream_t s);
-hipError_t launch_absmax(const float* x, long long n, float* partial, int nparts, float* result,
-                         hipStream_t s);
-hipError_t launch_pack_bf16(const float* x, long long n, const float* scale, uint16_t* out, hipStream_t s);
-hipError_t launch_unpack_bf16(const uint16_t* in, long long n, const float* scale, float* x, hipStream_t s);
+// BF16 snapshot codec of a checkpoint (p^{k-1}, p^k): c0 = bf16(p^k / s0),
+// c1 = bf16((p^k - p^{k-1}) / s1), scales per block of SNAP_BLOCK cells
+// (snap_blocks(n) of each); decode writes both fields back.
+constexpr int SNAP_BLOCK = 4096;
+long long snap_blocks(long long n);
+hipError_t launch_snap_encode(const float* prev, const float* cur, long long n, uint16_t* c0, uint16_t* c1, float* s0,
+                              float* s1, hipStream_t s);
+hipError_t launch_snap_decode(const uint16_t* c0, const uint16_t* c1, const float* s0, const float* s1, long long n,
+                              float* prev, float* cur, hipStream_t s);
 hipError_t launch_residual_loss(const float* traces, const float* dobs, float* resid, long long n,
                                 double* partial, int nparts, double* loss, hipStream_t s);
 

@@ -380,7 +380,7 @@ template <int TX, int RY, int PD, int BC, int MODE, int NT, bool STREAM = false>
 static void launch_step_k(dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd, const ShotDev* shots, int parity,
                           const Coefs& cf, const StepAux& aux, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const dim3 block(TX, NT / TX);
-    if (ev0)
+    if (ev0 || ev1)  // either stamp alone is allowed (a CPML launch may have taken the start)
         hipExtLaunchKernelGGL(k_step<TX, RY, PD, BC, MODE, NT, STREAM>, grid, block, 0, s, ev0, ev1, 0, tiles,
                               ntiles, per_xcd, shots, parity, cf, aux);
     else
@@ -1378,45 +1378,15 @@ hipError_t launch_copy(float* dst, const float* src, long long n, hipStream_t s)
 }
 
 // ------------------------------------------------------- snapshot codec
-
-__global__ __launch_bounds__(256) void k_absmax_part(const float* __restrict__ x, long long n,
-                                                     float* __restrict__ part) {
-    __shared__ float sm[256];
-    float m = 0.0f;
-    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
-        m = fmaxf(m, fabsf(x[i]));
-    sm[threadIdx.x] = m;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) sm[threadIdx.x] = fmaxf(sm[threadIdx.x], sm[threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
-}
-
-__global__ __launch_bounds__(256) void k_absmax_final(const float* __restrict__ part, int nparts,
-                                                      float* __restrict__ result) {
-    __shared__ float sm[256];
-    float m = 0.0f;
-    for (int i = threadIdx.x; i < nparts; i += 256) m = fmaxf(m, part[i]);
-    sm[threadIdx.x] = m;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) sm[threadIdx.x] = fmaxf(sm[threadIdx.x], sm[threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) result[0] = sm[0] > 0.0f ? sm[0] : 1.0f;
-}
-
-hipError_t launch_absmax(const float* x, long long n, float* partial, int nparts, float* result, hipStream_t s) {
-    dim3 g = stride_grid(n);
-    if ((int)g.x > nparts) g.x = nparts;
-    k_absmax_part<<<g, 256, 0, s>>>(x, n, partial);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_absmax_final<<<1, 256, 0, s>>>(partial, (int)g.x, result);
-    return hipGetLastError();
-}
+//
+// A checkpoint (p^{k-1}, p^k) is stored as two bfloat16 arrays: c0 = bf16(p^k / s0)
+// and c1 = bf16((p^k - p^{k-1}) / s1), each scaled per block of SNAP_BLOCK cells
+// by the block's largest magnitude (1 for an all-zero block), rounded to nearest
+// even.  Keeping the increment instead of p^{k-1} itself stores the part of the
+// state the leapfrog amplifies most (the difference of two nearly equal fields)
+// with its own 8-bit relative precision.  Decoding gives p^k = f(c0) s0 and
+// p^{k-1} = p^k - f(c1) s1, each product and difference rounded once.
+// One pass each way: read 8 B and write 4 B per cell, or the reverse.
 
 // float -> bfloat16, round to nearest even (finite inputs)
 __device__ __forceinline__ uint16_t f2bf_rne(float f) {
@@ -1425,27 +1395,88 @@ __device__ __forceinline__ uint16_t f2bf_rne(float f) {
     return (uint16_t)((u + 0x7FFFu + lsb) >> 16);
 }
 
-__global__ __launch_bounds__(256) void k_pack_bf16(const float* __restrict__ x, long long n,
-                                                   const float* __restrict__ scale, uint16_t* __restrict__ out) {
-    const float s = scale[0];
-    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
-        out[i] = f2bf_rne(x[i] / s);
+__device__ __forceinline__ float block_absmax256(float m, float* sm) {
+    // wave reduction, then the 4 waves of the block through LDS
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    return fmaxf(fmaxf(sm[0], sm[1]), fmaxf(sm[2], sm[3]));
 }
 
-__global__ __launch_bounds__(256) void k_unpack_bf16(const uint16_t* __restrict__ in, long long n,
-                                                     const float* __restrict__ scale, float* __restrict__ x) {
-    const float s = scale[0];
-    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
-        x[i] = __uint_as_float((unsigned)in[i] << 16) * s;
+constexpr int SNAP_PER_THREAD = SNAP_BLOCK / 256;
+
+__global__ __launch_bounds__(256) void k_snap_encode(const float* __restrict__ prev, const float* __restrict__ cur,
+                                                     long long n, uint16_t* __restrict__ c0,
+                                                     uint16_t* __restrict__ c1, float* __restrict__ s0,
+                                                     float* __restrict__ s1) {
+    __shared__ float sm[2][4];
+    const long long base = (long long)blockIdx.x * SNAP_BLOCK;
+    float v[SNAP_PER_THREAD], d[SNAP_PER_THREAD];
+    float m0 = 0.0f, m1 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < SNAP_PER_THREAD; ++k) {
+        const long long i = base + k * 256 + threadIdx.x;
+        const bool ok = i < n;
+        const float c = ok ? __builtin_nontemporal_load(cur + i) : 0.0f;
+        const float p = ok ? __builtin_nontemporal_load(prev + i) : 0.0f;
+        v[k] = c;
+        d[k] = c - p;
+        m0 = fmaxf(m0, fabsf(v[k]));
+        m1 = fmaxf(m1, fabsf(d[k]));
+    }
+    m0 = block_absmax256(m0, sm[0]);
+    m1 = block_absmax256(m1, sm[1]);
+    const float a0 = m0 > 0.0f ? m0 : 1.0f, a1 = m1 > 0.0f ? m1 : 1.0f;
+    if (threadIdx.x == 0) {
+        s0[blockIdx.x] = a0;
+        s1[blockIdx.x] = a1;
+    }
+#pragma unroll
+    for (int k = 0; k < SNAP_PER_THREAD; ++k) {
+        const long long i = base + k * 256 + threadIdx.x;
+        if (i < n) {
+            c0[i] = f2bf_rne(v[k] / a0);
+            c1[i] = f2bf_rne(d[k] / a1);
+        }
+    }
 }
 
-hipError_t launch_pack_bf16(const float* x, long long n, const float* scale, uint16_t* out, hipStream_t s) {
-    k_pack_bf16<<<stride_grid(n), 256, 0, s>>>(x, n, scale, out);
+__global__ __launch_bounds__(256) void k_snap_decode(const uint16_t* __restrict__ c0, const uint16_t* __restrict__ c1,
+                                                     const float* __restrict__ s0, const float* __restrict__ s1,
+                                                     long long n, float* __restrict__ prev, float* __restrict__ cur) {
+#pragma clang fp contract(off)  // the product and the difference are rounded separately
+    const long long base = (long long)blockIdx.x * SNAP_BLOCK;
+    const float a0 = s0[blockIdx.x], a1 = s1[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < SNAP_PER_THREAD; ++k) {
+        const long long i = base + k * 256 + threadIdx.x;
+        if (i < n) {
+            const float v = __uint_as_float((unsigned)c0[i] << 16) * a0;
+            const float d = __uint_as_float((unsigned)c1[i] << 16) * a1;
+            cur[i] = v;
+            prev[i] = v - d;
+        }
+    }
+}
+
+long long snap_blocks(long long n) { return (n + SNAP_BLOCK - 1) / SNAP_BLOCK; }
+
+hipError_t launch_snap_encode(const float* prev, const float* cur, long long n, uint16_t* c0, uint16_t* c1, float* s0,
+                              float* s1, hipStream_t s) {
+    const long long nb = snap_blocks(n);
+    if (nb <= 0) return hipSuccess;
+    if (nb > 0x7FFFFFFFLL) return hipErrorInvalidValue;
+    k_snap_encode<<<dim3((unsigned)nb), 256, 0, s>>>(prev, cur, n, c0, c1, s0, s1);
     return hipGetLastError();
 }
 
-hipError_t launch_unpack_bf16(const uint16_t* in, long long n, const float* scale, float* x, hipStream_t s) {
-    k_unpack_bf16<<<stride_grid(n), 256, 0, s>>>(in, n, scale, x);
+hipError_t launch_snap_decode(const uint16_t* c0, const uint16_t* c1, const float* s0, const float* s1, long long n,
+                              float* prev, float* cur, hipStream_t s) {
+    const long long nb = snap_blocks(n);
+    if (nb <= 0) return hipSuccess;
+    if (nb > 0x7FFFFFFFLL) return hipErrorInvalidValue;
+    k_snap_decode<<<dim3((unsigned)nb), 256, 0, s>>>(c0, c1, s0, s1, n, prev, cur);
     return hipGetLastError();
 }
 

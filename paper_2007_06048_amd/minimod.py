@@ -24,7 +24,7 @@ SYMBOLS = [
     "mm_forward_steps", "mm_forward_steps_graph", "mm_adjoint_steps", "mm_gradient", "mm_reset",
     "mm_state_size", "mm_get_state", "mm_set_state", "mm_get_info", "mm_autotune", "mm_set_tile",
     "mm_num_tiles", "mm_tile_name", "mm_profile", "mm_profile_read", "mm_destroy", "mm_status_str",
-    "mm_last_error",
+    "mm_last_error", "mm_snap_blocks", "mm_snap_encode", "mm_snap_decode",
 ]
 
 
@@ -97,6 +97,9 @@ def load():
         "mm_destroy": (None, [vp]),
         "mm_status_str": (ctypes.c_char_p, [st]),
         "mm_last_error": (ctypes.c_char_p, [vp]),
+        "mm_snap_blocks": (ctypes.c_int64, [ctypes.c_int64]),
+        "mm_snap_encode": (st, [vp, vp, ctypes.c_int64, vp, vp, vp, vp, vp]),
+        "mm_snap_decode": (st, [vp, vp, vp, vp, ctypes.c_int64, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -275,6 +278,33 @@ def tile_name(t):
 
 
 # ----------------------------------------------------------------- autograd
+
+def snap_encode(prev, cur):
+    """BF16 snapshot codec (mm_snap_encode) of two float32 CUDA tensors of
+    the same size: returns (c0, c1) as int16 tensors holding the bfloat16
+    bit patterns and the block scales (s0, s1)."""
+    import torch
+    n = prev.numel()
+    nb = load().mm_snap_blocks(n)
+    c0 = torch.empty(n, dtype=torch.int16, device=prev.device)
+    c1 = torch.empty_like(c0)
+    s0 = torch.empty(max(nb, 1), dtype=torch.float32, device=prev.device)
+    s1 = torch.empty_like(s0)
+    st = ctypes.c_void_p(torch.cuda.current_stream(prev.device).cuda_stream)
+    _check(load().mm_snap_encode(_ptr(prev), _ptr(cur), n, _ptr(c0), _ptr(c1), _ptr(s0), _ptr(s1), st))
+    return c0, c1, s0[:nb], s1[:nb]
+
+
+def snap_decode(c0, c1, s0, s1):
+    """Inverse of snap_encode: returns (prev, cur) as float32 tensors."""
+    import torch
+    n = c0.numel()
+    prev = torch.empty(n, dtype=torch.float32, device=c0.device)
+    cur = torch.empty_like(prev)
+    st = ctypes.c_void_p(torch.cuda.current_stream(c0.device).cuda_stream)
+    _check(load().mm_snap_decode(_ptr(c0), _ptr(c1), _ptr(s0), _ptr(s1), n, _ptr(prev), _ptr(cur), st))
+    return prev, cur
+
 
 def _make_traces_fn():
     import torch

@@ -78,8 +78,8 @@ def test_adjoint_in_chunks_is_bitwise_one_call(bc):
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
-@pytest.mark.parametrize("bc,snap,tol,fs", [(mm.BC_SPONGE, mm.SNAP_FP32, 1e-4, 0), (mm.BC_SPONGE, mm.SNAP_BF16, 2e-2, 0),
-                                             (mm.BC_CPML, mm.SNAP_FP32, 1e-4, 0), (mm.BC_CPML, mm.SNAP_BF16, 2e-2, 0),
+@pytest.mark.parametrize("bc,snap,tol,fs", [(mm.BC_SPONGE, mm.SNAP_FP32, 1e-4, 0), (mm.BC_SPONGE, mm.SNAP_BF16, 1e-2, 0),
+                                             (mm.BC_CPML, mm.SNAP_FP32, 1e-4, 0), (mm.BC_CPML, mm.SNAP_BF16, 1e-2, 0),
                                              (mm.BC_CPML, mm.SNAP_FP32, 1e-4, 1)])
 def test_gradient_matches_oracle(bc, snap, tol, fs):
     """FWI gradient w.r.t. m = 1/v^2 with checkpoints every 16 steps (a partial
@@ -122,7 +122,7 @@ def test_gradient_matches_oracle(bc, snap, tol, fs):
     assert abs(J - ref_J) <= 1e-4 * ref_J
     assert e <= tol
     if snap == mm.SNAP_BF16:
-        assert cos >= 0.9995
+        assert cos >= 0.9999
 
 
 def test_gradient_is_independent_of_cache_hints():

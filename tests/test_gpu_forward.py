@@ -267,3 +267,21 @@ def test_autotune_then_forward_matches_default_tile():
     q.tile = -1  # autotune inside init
     b = gpu_forward(q, vel, src, rec, w, T)
     assert np.array_equal(b[0], a[0]) and np.array_equal(b[1], a[1])
+
+
+@pytest.mark.parametrize("bc", [mm.BC_NONE, mm.BC_SPONGE, mm.BC_CPML])
+def test_step_timing_stamps_every_bc(bc):
+    """mm_profile stamps whole time steps (the first launch's start, the last
+    launch's end) for every boundary kind, CPML included where the CPML
+    kernel takes the start stamp; timing leaves the results bitwise alone."""
+    p, vel, src, rec, w, T, dt = _ragged_case(bc, seed=6)
+    ref = gpu_forward(p, vel, src, rec, w, T)
+    ctx = mm.Context.single(p, torch.from_numpy(vel).to(DEV), src, rec)
+    tr = torch.zeros((T, len(rec)), dtype=torch.float32, device=DEV)
+    ctx.profile(3)
+    ctx.forward(T, torch.from_numpy(np.asarray(w, dtype=np.float32)).to(DEV), tr)
+    ms, n = ctx.profile_read()
+    ctx.profile(0)
+    assert n == (T + 2) // 3 and ms > 0.0, (n, ms)
+    assert np.array_equal(tr.cpu().numpy(), ref[0])
+    ctx.close()

@@ -1,0 +1,119 @@
+"""Whole-run parity at the sizes the benchmark uses, against the FP64 oracle
+run over every step (not a sampled last step).
+
+- The 240^3 CPML-20 workload, 1000 steps, in the launch configuration the
+  benchmark times (autotuned tile, cache hints by working set): the final
+  fields over the whole grid and all 57,600 traces of every step.
+- The FWI gradient workload at its real size (200^3, sponge 20, receivers on
+  the full plane z = 20, checkpoints every 32 steps, 1000 steps) for one of
+  its shots, with FP32 and BF16 checkpoints, against the oracle's exact
+  gradient (the run must be long enough for waves scattered by the
+  anomalies to reach the receivers; over the first few hundred steps the
+  residual is rounding noise only).
+
+Each takes one to three minutes of oracle time on the host; both print their
+progress and the measured errors.  Bars: 1e-4 relative L2 for the 1000-step
+forward run (error grows with the number of steps; 1e-5 is the bar at 200
+steps), 1e-4 for the gradient with FP32 checkpoints, 1e-2 with cosine
+>= 0.9999 for BF16 checkpoints."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import c_oracle as C
+from paper_2007_06048_amd import minimod as mm
+from paper_2007_06048_amd import workloads as W
+
+from .gpu_util import DEV, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(capsys, msg):
+    with capsys.disabled():
+        print(f"\n  [{time.strftime('%H:%M:%S')}] {msg}", flush=True)
+
+
+def test_smooth240_cpml_1000_steps_whole_run(capsys):
+    wl = W.smooth_240()
+    s = wl.shots[0]
+    T = wl.nsteps
+    p = mm.default_params(nx=wl.nx, ny=wl.ny, nz=wl.nz, dx=wl.h, dy=wl.h, dz=wl.h, cfl=wl.cfl, bc=wl.bc, nb=wl.nb,
+                          cpml_R=wl.cpml_R, cpml_f0=wl.f0, tile=-1)
+    ctx = mm.Context.single(p, torch.from_numpy(s.vel).to(DEV), s.src, s.rec)
+    dt = ctx.dt
+    w = mm.ricker(wl.f0, wl.t0, dt, T)
+    tr = torch.empty((T, len(s.rec)), dtype=torch.float32, device=DEV)
+    ctx.forward(T, torch.from_numpy(w).to(DEV).reshape(T, 1), tr)
+    st = ctx.get_state()
+    torch.cuda.synchronize()
+    n = s.vel.size
+    stv = st.cpu().numpy()
+    g_pm, g_pc = stv[:n].reshape(s.vel.shape), stv[n:2 * n].reshape(s.vel.shape)
+    g_tr = tr.cpu().numpy()
+    tile = mm.tile_name(ctx.info()["tile"])
+    ctx.close()
+    del st, tr
+    _say(capsys, f"GPU run done (tile {tile}); oracle 1000 steps in chunks of 100")
+    g = C.Grid(wl.nx, wl.ny, wl.nz, wl.h, wl.h, wl.h, dt, bc=wl.bc, nb=wl.nb, R=wl.cpml_R, f0=wl.f0,
+               vmax=float(s.vel.max()))
+    vel = s.vel.astype(np.float64)
+    w64 = w.astype(np.float64)[:, None]
+    pm = pc = mem = None
+    r_tr = np.empty((T, len(s.rec)))
+    for c0 in range(0, T, 100):
+        t0 = time.time()
+        r_tr[c0:c0 + 100], pm, pc, mem = C.forward(g, vel, s.src, w64[c0:c0 + 100], s.rec, 100, p_prev=pm,
+                                                   p_cur=pc, cpml_mem=mem)
+        _say(capsys, f"oracle steps {c0}..{c0 + 99} done ({time.time() - t0:.1f} s)")
+    e_tr, e_pc, e_pm = rel(g_tr, r_tr), rel(g_pc, pc), rel(g_pm, pm)
+    # error over time: the traces of each 100-step window
+    win = [rel(g_tr[a:a + 100], r_tr[a:a + 100]) for a in range(0, T, 100)]
+    _say(capsys, f"240^3 CPML 1000 steps: traces {e_tr:.3e}, p^T {e_pc:.3e}, p^(T-1) {e_pm:.3e}; "
+                 f"traces per 100-step window {', '.join(f'{x:.2e}' for x in win)}")
+    assert e_tr <= 1e-4 and e_pc <= 1e-4 and e_pm <= 1e-4
+
+
+def test_fwi200_gradient_fp32_and_bf16_checkpoints(capsys):
+    wl = W.fwi_200(nshots=1)
+    T = wl.nsteps
+    s = wl.shots[0]
+    p = mm.default_params(nx=wl.nx, ny=wl.ny, nz=wl.nz, dx=wl.h, dy=wl.h, dz=wl.h, cfl=wl.cfl, bc=wl.bc, nb=wl.nb,
+                          sponge_sigma=wl.sigma, vmax=wl.vmax, tile=-1)
+    dt = mm.dt_for(p, wl.vmax)
+    w = mm.ricker(wl.f0, wl.t0, dt, T)
+    g = C.Grid(wl.nx, wl.ny, wl.nz, wl.h, wl.h, wl.h, dt, bc=wl.bc, nb=wl.nb, sigma=wl.sigma, vmax=wl.vmax)
+    t0 = time.time()
+    d_obs, _, _, _ = C.forward(g, wl.vel_true.astype(np.float64), s.src, w.astype(np.float64)[:, None], s.rec, T)
+    d_obs32 = d_obs.astype(np.float32)
+    _say(capsys, f"oracle observed data on the true model done ({time.time() - t0:.1f} s)")
+    t0 = time.time()
+    ref, ref_tr, ref_J = C.gradient(g, s.vel.astype(np.float64), s.src, w.astype(np.float64)[:, None], s.rec,
+                                    d_obs32.astype(np.float64), T, ckpt=wl.ckpt_every)
+    _say(capsys, f"oracle gradient done ({time.time() - t0:.1f} s)")
+    # the residual carries the anomalies' scattered waves, far above float32 rounding of d_obs
+    assert ref_J > 1e-6 * 0.5 * float(np.sum(d_obs ** 2)), ref_J
+    res = {}
+    for name, snap in (("fp32", mm.SNAP_FP32), ("bf16", mm.SNAP_BF16)):
+        q = mm.default_params(nx=wl.nx, ny=wl.ny, nz=wl.nz, dx=wl.h, dy=wl.h, dz=wl.h, cfl=wl.cfl, bc=wl.bc,
+                              nb=wl.nb, sponge_sigma=wl.sigma, vmax=wl.vmax, tile=-1, ckpt_every=wl.ckpt_every,
+                              snap=snap, nsteps_max=T)
+        ctx = mm.Context.single(q, torch.from_numpy(s.vel).to(DEV), s.src, s.rec)
+        assert ctx.dt == dt
+        grad = torch.empty(s.vel.shape, dtype=torch.float32, device=DEV)
+        tr = torch.empty((T, len(s.rec)), dtype=torch.float32, device=DEV)
+        J = ctx.gradient(T, torch.from_numpy(w).to(DEV).reshape(T, 1), torch.from_numpy(d_obs32).to(DEV), grad, tr)
+        gg = grad.cpu().numpy().astype(np.float64)
+        e = rel(gg, ref)
+        cos = float(np.sum(gg * ref) / (np.linalg.norm(gg) * np.linalg.norm(ref)))
+        et = rel(tr.cpu().numpy(), ref_tr)
+        res[name] = (e, cos)
+        _say(capsys, f"200^3 gradient ({name} checkpoints): rel L2 {e:.3e}, cosine {cos:.8f}, traces {et:.2e}, "
+                     f"J {J:.6e} vs {ref_J:.6e}")
+        assert et <= 1e-5
+        assert abs(J - ref_J) <= 1e-4 * ref_J
+        ctx.close()
+    assert res["fp32"][0] <= 1e-4
+    assert res["bf16"][0] <= 1e-2 and res["bf16"][1] >= 0.9999
