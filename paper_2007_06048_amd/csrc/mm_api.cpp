@@ -90,22 +90,110 @@ void build_tiles_range(int variant, const std::vector<ShotGeom>& shots, int s0, 
         for (int z0 = 0; z0 < g.nz; z0 += zlen) {
             const int z1 = std::min(g.nz, z0 + zlen);
             for (int y0 = 0; y0 < g.ny; y0 += TY)
-                for (int x0 = 0; x0 < g.nx; x0 += TX) out.push_back(TileEnt{s, x0, y0, z0, z1, 0, 0, 0});
+                for (int x0 = 0; x0 < g.nx; x0 += TX)
+                    out.push_back(TileEnt{s, x0, y0, z0, z1, 0, std::min(g.nx, x0 + TX), std::min(g.ny, y0 + TY)});
         }
     }
 }
 
-// Tiles of every group, concatenated; tile_off[g] / count[g] locate group g.
-void build_tiles(int variant, const std::vector<ShotGeom>& shots, const std::vector<std::pair<int, int>>& groups,
-                 std::vector<TileEnt>& out, std::vector<int>* tile_off = nullptr, std::vector<int>* count = nullptr) {
+// The box [bx0, bx1) x [by0, by1) x [z0, z1) of shot s cut into tw x th
+// rectangles (the last ones clipped to the box) and z chunks of zlen planes.
+void tile_box(int s, int bx0, int bx1, int by0, int by1, int z0, int z1, int zlen, int tw, int th,
+              std::vector<TileEnt>& out) {
+    if (bx1 <= bx0 || by1 <= by0 || z1 <= z0) return;
+    for (int za = z0; za < z1; za += zlen) {
+        const int zb = std::min(z1, za + zlen);
+        for (int y = by0; y < by1; y += th)
+            for (int x = bx0; x < bx1; x += tw)
+                out.push_back(TileEnt{s, x, y, za, zb, 0, std::min(bx1, x + tw), std::min(by1, y + th)});
+    }
+}
+
+// Forward CPML regions of a shot: the interior box [bx0, bx1) x [by0, by1) x
+// [zlo, zhi) holds no layer cell and is a whole number of TX x TY tiles
+// (bx0 rounded up to 32 cells keeps its rows 128-byte aligned); the frame
+// around it in the middle z range [zlo, zhi) and the z-layer chunks [0, nb)
+// (none under a free surface) and [nz - nb, nz) belong to the fused CPML kernel.
+struct CpmlRegions {
+    int bx0, bx1, by0, by1, zlo, zhi;
+};
+
+CpmlRegions cpml_regions(const ShotGeom& g, int nb, bool fs, int TX, int TY) {
+    CpmlRegions r;
+    r.bx0 = std::min(g.nx, (nb + 31) / 32 * 32);
+    r.bx1 = r.bx0 + TX * (std::max(0, g.nx - nb - r.bx0) / TX);
+    r.by0 = std::min(g.ny, nb);
+    r.by1 = r.by0 + TY * (std::max(0, g.ny - nb - r.by0) / TY);
+    r.zlo = fs ? 0 : nb;
+    r.zhi = g.nz - nb;
+    return r;
+}
+
+constexpr int kStripTarget = 2048;  // blocks of a group's strip launch (z-chunking of the frame)
+
+// Where the tile lists of one shot group sit in the tile table.
+struct GroupTiles {
+    int full_off = 0, nfull = 0;  // variant tiles over the whole grid: every step without forward CPML
+    int in_off = 0, nin = 0;      // forward CPML: variant tiles of the interior boxes
+    int st_off = 0, nst = 0;      // forward CPML: fused tiles of the frames (middle z range)
+    int zl_off = 0, nzl = 0;      // forward CPML: fused tiles of the z-layer chunks
+};
+
+// Every tile list: the full lists of all groups first (so that one launch
+// over [0, sum of nfull) covers every shot), then for forward CPML the
+// interior, frame and z-layer lists of each group.
+void build_tiles(int variant, const mm_params& p, const std::vector<ShotGeom>& shots,
+                 const std::vector<std::pair<int, int>>& groups, std::vector<TileEnt>& out,
+                 std::vector<GroupTiles>& gt) {
     out.clear();
-    if (tile_off) tile_off->clear();
-    if (count) count->clear();
-    for (const auto& gr : groups) {
-        const size_t before = out.size();
-        build_tiles_range(variant, shots, gr.first, gr.second, out);
-        if (tile_off) tile_off->push_back((int)before);
-        if (count) count->push_back((int)(out.size() - before));
+    gt.assign(groups.size(), GroupTiles());
+    for (size_t k = 0; k < groups.size(); ++k) {
+        gt[k].full_off = (int)out.size();
+        build_tiles_range(variant, shots, groups[k].first, groups[k].second, out);
+        gt[k].nfull = (int)out.size() - gt[k].full_off;
+    }
+    if (p.bc != MM_BC_CPML || p.model != MM_MODEL_ISO_CD) return;
+    const int TX = tile_variant(variant).tx, TY = tile_rows(variant);
+    const int CW = cstep_tile_w(), CH = cstep_tile_h(), nb = p.nb;
+    const bool fs = p.free_surface != 0;
+    for (size_t k = 0; k < groups.size(); ++k) {
+        const int s0 = groups[k].first, s1 = groups[k].second;
+        // interior boxes, z-chunked towards the variant's block target
+        long long xy = 0, sxy = 0;
+        for (int s = s0; s < s1; ++s) {
+            const CpmlRegions r = cpml_regions(shots[s], nb, fs, TX, TY);
+            xy += (long long)((r.bx1 - r.bx0) / TX) * ((r.by1 - r.by0) / TY);
+            const int nx = shots[s].nx, ny = shots[s].ny;
+            sxy += (long long)((r.bx0 + CW - 1) / CW + (nx - r.bx1 + CW - 1) / CW) * ((ny + CH - 1) / CH) +
+                   (long long)((r.bx1 - r.bx0 + CW - 1) / CW) * ((r.by0 + CH - 1) / CH + (ny - r.by1 + CH - 1) / CH);
+        }
+        const long long nch = std::max(1LL, xy > 0 ? (tile_variant(variant).target + xy - 1) / xy : 1);
+        const long long sch = std::max(1LL, sxy > 0 ? (kStripTarget + sxy - 1) / sxy : 1);
+        gt[k].in_off = (int)out.size();
+        for (int s = s0; s < s1; ++s) {
+            const CpmlRegions r = cpml_regions(shots[s], nb, fs, TX, TY);
+            const int zlen = std::max(4, (int)((r.zhi - r.zlo + nch - 1) / nch));
+            tile_box(s, r.bx0, r.bx1, r.by0, r.by1, r.zlo, r.zhi, zlen, TX, TY, out);
+        }
+        gt[k].nin = (int)out.size() - gt[k].in_off;
+        gt[k].st_off = (int)out.size();
+        for (int s = s0; s < s1; ++s) {
+            const CpmlRegions r = cpml_regions(shots[s], nb, fs, TX, TY);
+            const int nx = shots[s].nx, ny = shots[s].ny;
+            const int zlen = std::max(16, (int)((r.zhi - r.zlo + sch - 1) / sch));
+            tile_box(s, 0, r.bx0, 0, ny, r.zlo, r.zhi, zlen, CW, CH, out);         // low x
+            tile_box(s, r.bx1, nx, 0, ny, r.zlo, r.zhi, zlen, CW, CH, out);        // high x
+            tile_box(s, r.bx0, r.bx1, 0, r.by0, r.zlo, r.zhi, zlen, CW, CH, out);  // low y
+            tile_box(s, r.bx0, r.bx1, r.by1, ny, r.zlo, r.zhi, zlen, CW, CH, out); // high y
+        }
+        gt[k].nst = (int)out.size() - gt[k].st_off;
+        gt[k].zl_off = (int)out.size();
+        for (int s = s0; s < s1; ++s) {
+            const int nx = shots[s].nx, ny = shots[s].ny, nz = shots[s].nz;
+            if (!fs) tile_box(s, 0, nx, 0, ny, 0, nb, nb, CW, CH, out);
+            tile_box(s, 0, nx, 0, ny, nz - nb, nz, nb, CW, CH, out);
+        }
+        gt[k].nzl = (int)out.size() - gt[k].zl_off;
     }
 }
 
@@ -143,9 +231,10 @@ void compute_layout(const mm_params& p, const std::vector<ShotGeom>& shots, int 
     L.shots_adj = take(L, sizeof(ShotDev) * S);
     int mt = 0;
     std::vector<TileEnt> tmp;
+    std::vector<GroupTiles> gt;
     const auto groups = make_groups(p, shots);
     for (int v = 0; v < num_tile_variants(); ++v) {
-        build_tiles(v, shots, groups, tmp);
+        build_tiles(v, p, shots, groups, tmp, gt);
         mt = std::max(mt, (int)tmp.size());
     }
     L.max_tiles = mt;
@@ -195,7 +284,7 @@ void compute_layout(const mm_params& p, const std::vector<ShotGeom>& shots, int 
     L.rg_off = take(L, sizeof(long long) * nrec);
     L.sg_shot = take(L, sizeof(int) * nsrc);
     L.sg_off = take(L, sizeof(long long) * nsrc);
-    L.cpml_off = take(L, sizeof(int) * 3 * (S + (int)groups.size() + S + 1));
+    L.cpml_off = take(L, sizeof(int) * 3 * (S + 1));  // block table of the adjoint CPML kernel
     if (L.grad) {
         const long long N = shots[0].n();
         const int K = p.ckpt_every;
@@ -291,18 +380,16 @@ struct mm_ctx {
     ShotDev* d_shots_adj = nullptr;
     TileEnt* d_tiles = nullptr;
     std::vector<TileEnt> tiles_h;
-    int ntiles = 0, variant = 0;
+    int nfull = 0, variant = 0;  // nfull: tiles of the full lists of all groups (the table's head)
     InjTab src_inj{}, rec_inj{};
     GatherTab rec_gather{}, src_gather{};
     int nsrc = 0, nrec = 0;
     struct Group {
         int s0, s1;            // shots [s0, s1)
-        int tile_off, ntiles;  // slice of the tile table
+        GroupTiles t;          // its slices of the tile table
         int rec0, rec1;        // receivers (columns of a trace row)
         int cell0, cell1;      // source cells of the injection table
-        std::vector<int> cpml_h;  // CPML block table of the group (host copy)
-        const int* cpml_d = nullptr;
-        bool stream = false;      // working set beyond the Infinity Cache (StepAux::stream_loads)
+        bool stream = false;   // working set beyond the Infinity Cache (StepAux::stream_loads)
     };
     std::vector<Group> groups;
     bool stream_all = false;      // the same for all shots together (adjoint steps)
@@ -491,24 +578,24 @@ mm_status upload(mm_ctx* c, void* dst, const void* src, size_t bytes) {
     return dev(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream), "upload");
 }
 
-void tile_flags(mm_ctx* c, int v) {
-    // correction slabs: nb cells per end, nb + 4 when the adjoint shares the table
-    const int TX = tile_variant(v).tx, TY = tile_rows(v), nb = c->p.nb + (c->L.adjoint ? 4 : 0);
-    auto meets = [nb](int a0, int a1, int n) { return a0 < nb || a1 > n - nb; };  // [a0, a1) vs the slabs
-    for (TileEnt& t : c->tiles_h) {
+// Flags of the tiles [a, b) of the table: the cells a tile writes meet the
+// damping layers of width w of an axis (CPML), or hold an inline source.
+void tile_flags(mm_ctx* c, int a, int b, int w, int zflag) {
+    auto meets = [w](int a0, int a1, int n) { return a0 < w || a1 > n - w; };  // [a0, a1) vs the layers
+    for (int i = a; i < b; ++i) {
+        TileEnt& t = c->tiles_h[i];
         const ShotGeom& g = c->geom[t.shot];
-        const int x1 = std::min(g.nx, t.x0 + TX), y1 = std::min(g.ny, t.y0 + TY);
-        int f = 0;
+        int f = zflag;
         if (c->cpml) {
-            if (meets(t.x0, x1, g.nx)) f |= TF_LX;
-            if (meets(t.y0, y1, g.ny)) f |= TF_LY;
-            if (meets(t.z0, t.z1, g.nz)) f |= TF_LZ;
+            if (meets(t.x0, t.x1, g.nx)) f |= TF_LX;
+            if (meets(t.y0, t.y1, g.ny)) f |= TF_LY;
+            if (!zflag && meets(t.z0, t.z1, g.nz)) f |= TF_LZ;
         }
         if (c->inline_src)
             for (long long o : c->src_cells[t.shot]) {
                 const int z = (int)(o / ((long long)g.nx * g.ny));
                 const int y = (int)((o / g.nx) % g.ny), x = (int)(o % g.nx);
-                if (x >= t.x0 && x < x1 && y >= t.y0 && y < y1 && z >= t.z0 && z < t.z1) f |= TF_SRC;
+                if (x >= t.x0 && x < t.x1 && y >= t.y0 && y < t.y1 && z >= t.z0 && z < t.z1) f |= TF_SRC;
             }
         t.flags = f;
     }
@@ -517,18 +604,23 @@ void tile_flags(mm_ctx* c, int v) {
 mm_status set_variant(mm_ctx* c, int v) {
     std::vector<std::pair<int, int>> gr;
     for (const auto& g : c->groups) gr.push_back({g.s0, g.s1});
-    std::vector<int> off, cnt;
-    build_tiles(v, c->geom, gr, c->tiles_h, &off, &cnt);
+    std::vector<GroupTiles> gt;
+    build_tiles(v, c->p, c->geom, gr, c->tiles_h, gt);
+    c->nfull = 0;
     for (size_t i = 0; i < c->groups.size(); ++i) {
-        c->groups[i].tile_off = off[i];
-        c->groups[i].ntiles = cnt[i];
+        const GroupTiles& t = gt[i];
+        c->groups[i].t = t;
+        c->nfull += t.nfull;
+        // full lists: the adjoint's correction slabs reach nb + 4 cells per end
+        tile_flags(c, t.full_off, t.full_off + t.nfull, c->p.nb + (c->L.adjoint ? 4 : 0), 0);
+        tile_flags(c, t.in_off, t.in_off + t.nin, c->p.nb, 0);
+        tile_flags(c, t.st_off, t.st_off + t.nst, c->p.nb, 0);
+        tile_flags(c, t.zl_off, t.zl_off + t.nzl, c->p.nb, TF_LZ);
     }
-    tile_flags(c, v);
     if ((int)c->tiles_h.size() > c->L.max_tiles) return fail(c, MM_ERR_WORKSPACE, "tile table overflow");
     MM_TRY(dev(c, hipStreamSynchronize(c->stream), "sync"));
     MM_TRY(upload(c, c->d_tiles, c->tiles_h.data(), sizeof(TileEnt) * c->tiles_h.size()));
     MM_TRY(dev(c, hipStreamSynchronize(c->stream), "sync"));
-    c->ntiles = (int)c->tiles_h.size();
     c->variant = v;
     return MM_OK;
 }
@@ -556,6 +648,7 @@ mm_status zero_state(mm_ctx* c, hipStream_t s) {
                                      nb2 * c->geom[i].ny * c->geom[i].nx};
             for (int a = 0; a < 3; ++a) {
                 MM_TRY(dev(c, launch_fill(sd.psi[a], sl[a], 0.0f, s), "fill"));
+                MM_TRY(dev(c, launch_fill(sd.corr[a], sl[a], 0.0f, s), "fill"));
                 MM_TRY(dev(c, launch_fill(sd.zeta[a], sl[a], 0.0f, s), "fill"));
             }
         }
@@ -598,21 +691,44 @@ mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, co
         ev1 = c->prof_ev[c->prof_used + 1];
         c->prof_used += 2;
     }
-    if (c->cpml) {
-        if (shots == c->d_shots) {
-            if (!g) return fail(c, MM_ERR_STATE, "forward CPML step without a shot group");
-            MM_TRY(dev(c, launch_cpml(shots + g->s0, g->s1 - g->s0, c->p.nb, false, g->stream, g->cpml_d,
-                                      g->cpml_h.data(), parity, c->cf, s, ev0),
-                       "cpml launch"));
-        } else {
-            MM_TRY(dev(c, launch_cpml(shots, (int)c->geom.size(), c->p.nb, true, false, c->cpml_adj_d,
-                                      c->cpml_adj_h.data(), parity, c->cf, s, ev0),
-                       "adjoint cpml launch"));
+    if (c->cpml && shots == c->d_shots) {
+        // forward CPML: the interior boxes (plain stencil), then the frames and the z-layer
+        // chunks (fused CPML kernel); the three write disjoint cells and read only p^n of the
+        // step, so their order is free; the receivers ride in the first launch that runs
+        if (!g) return fail(c, MM_ERR_STATE, "forward CPML step without a shot group");
+        const GroupTiles& t = g->t;
+        const int off[3] = {t.in_off, t.st_off, t.zl_off}, cnt[3] = {t.nin, t.nst, t.nzl};
+        int first = -1, last = -1;
+        for (int k = 0; k < 3; ++k)
+            if (cnt[k] > 0) {
+                if (first < 0) first = k;
+                last = k;
+            }
+        StepAux a = aux;
+        a.stream_loads = g->stream ? 1 : 0;
+        for (int k = 0; k < 3; ++k) {
+            if (cnt[k] <= 0) continue;
+            StepAux ak = a;
+            if (k != first) ak.gather_blocks = 0;
+            hipEvent_t e0 = k == first ? ev0 : nullptr, e1 = k == last ? ev1 : nullptr;
+            const TileEnt* tl = c->d_tiles + off[k];
+            if (k == 0)
+                MM_TRY(dev(c, launch_step(c->variant, MM_BC_NONE, mode, tl, cnt[k], shots, parity, c->cf, ak, s, e0, e1),
+                           "stencil launch"));
+            else
+                MM_TRY(dev(c, launch_cpml_step(k == 2, mode, tl, cnt[k], shots, parity, c->cf, ak, s, e0, e1),
+                           "cpml step launch"));
         }
+        return MM_OK;
+    }
+    if (c->cpml) {
+        MM_TRY(dev(c, launch_cpml_adjoint(shots, (int)c->geom.size(), c->p.nb, c->cpml_adj_d, c->cpml_adj_h.data(),
+                                          parity, c->cf, s, ev0),
+                   "adjoint cpml launch"));
         ev0 = nullptr;  // stamped by the CPML kernel
     }
-    const TileEnt* tiles = g ? c->d_tiles + g->tile_off : c->d_tiles;
-    const int nt = g ? g->ntiles : c->ntiles;
+    const TileEnt* tiles = c->d_tiles + (g ? g->t.full_off : 0);
+    const int nt = g ? g->t.nfull : c->nfull;
     if (c->iso) {
         MM_TRY(dev(c, launch_iso_step(c->variant, c->p.bc, g ? g->stream : c->stream_all, tiles, nt, shots, parity,
                                       c->cf, s, ev0, ev1),
@@ -648,8 +764,12 @@ float* ckpt_field(mm_ctx* c, int seg, int which) {
     return reinterpret_cast<float*>(c->ws + c->L.ckpt + ((size_t)seg * 2 + which) * c->L.ckpt_field_bytes);
 }
 
+// The buffer that holds psi^k of a forward shot after k steps (parity k & 1):
+// the step of parity q reads psi from psi (q = 0) or corr (q = 1) and writes the other.
+float* psi_now(const ShotDev& sd, int a, int parity) { return parity ? sd.corr[a] : sd.psi[a]; }
+
 // CPML memory (psi_x,y,z, zeta_x,y,z) of checkpoint seg, kept in FP32
-mm_status ckpt_memory(mm_ctx* c, int seg, bool save, hipStream_t s) {
+mm_status ckpt_memory(mm_ctx* c, int seg, bool save, int parity, hipStream_t s) {
     if (!c->cpml) return MM_OK;
     const auto& g = c->geom[0];
     const size_t nb2 = 2 * (size_t)c->p.nb;
@@ -657,7 +777,7 @@ mm_status ckpt_memory(mm_ctx* c, int seg, bool save, hipStream_t s) {
     char* base = c->ws + c->L.ckpt_mem + (size_t)seg * c->L.ckpt_mem_bytes;
     size_t o = 0;
     for (int k = 0; k < 6; ++k) {
-        float* f = k < 3 ? c->shots_h[0].psi[k] : c->shots_h[0].zeta[k - 3];
+        float* f = k < 3 ? psi_now(c->shots_h[0], k, parity) : c->shots_h[0].zeta[k - 3];
         const size_t bytes = sizeof(float) * sl[k % 3];
         float* dst = save ? reinterpret_cast<float*>(base + o) : f;
         const float* src = save ? f : reinterpret_cast<const float*>(base + o);
@@ -684,7 +804,7 @@ mm_status save_ckpt(mm_ctx* c, int seg, int parity, hipStream_t s) {
                                          sc + c->L.ckpt_scale_n, s),
                    "snapshot encode"));
     }
-    return ckpt_memory(c, seg, true, s);
+    return ckpt_memory(c, seg, true, parity, s);
 }
 
 mm_status restore_ckpt(mm_ctx* c, int seg, int parity, hipStream_t s) {
@@ -704,7 +824,7 @@ mm_status restore_ckpt(mm_ctx* c, int seg, int parity, hipStream_t s) {
                                          sc + c->L.ckpt_scale_n, N, prev, cur, s),
                    "snapshot decode"));
     }
-    return ckpt_memory(c, seg, false, s);
+    return ckpt_memory(c, seg, false, parity, s);
 }
 
 // Forward steps: each group of shots runs all nsteps steps before the next
@@ -1144,8 +1264,7 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
     up(L.sg_shot, s_shot.data(), sizeof(int) * s_shot.size());
     up(L.sg_off, s_off.data(), sizeof(long long) * s_off.size());
     {
-        // shot groups: receivers, source cells and the CPML block table of each
-        int cpml_pos = 0;
+        // shot groups: receivers and source cells of each; the adjoint CPML block table
         std::vector<int> rec_start(nshots + 1, 0);
         for (int i = 0; i < nshots; ++i) rec_start[i + 1] = rec_start[i] + shots[i].nrec;
         // auto: non-temporal hints only when every shot of a launch alone overflows the cache (a
@@ -1162,29 +1281,12 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
             g.s0 = gr.first;
             g.s1 = gr.second;
             g.stream = hinted(g.s0, g.s1);
-            g.tile_off = g.ntiles = 0;
             g.rec0 = rec_start[g.s0];
             g.rec1 = rec_start[g.s1];
             g.cell0 = (int)(std::lower_bound(cs.shot.begin(), cs.shot.end(), g.s0) - cs.shot.begin());
             g.cell1 = (int)(std::lower_bound(cs.shot.begin(), cs.shot.end(), g.s1) - cs.shot.begin());
-            if (c->cpml) {
-                std::vector<int> gx, gy, gz;
-                for (int i = g.s0; i < g.s1; ++i) {
-                    gx.push_back(geom[i].nx);
-                    gy.push_back(geom[i].ny);
-                    gz.push_back(geom[i].nz);
-                }
-                const int ng = g.s1 - g.s0;
-                g.cpml_h.assign(3 * (ng + 1), 0);
-                cpml_block_table(gx.data(), gy.data(), gz.data(), ng, p->nb, g.cpml_h.data());
-                g.cpml_d = at<int>(c->ws, L.cpml_off) + cpml_pos;
-                cpml_pos += 3 * (ng + 1);
-            }
             c->groups.push_back(std::move(g));
         }
-        for (const auto& g : c->groups)
-            if (c->cpml) up(L.cpml_off + sizeof(int) * (g.cpml_d - at<int>(c->ws, L.cpml_off)), g.cpml_h.data(),
-                            sizeof(int) * g.cpml_h.size());
         if (c->cpml && L.adjoint) {
             std::vector<int> gx, gy, gz;
             for (const auto& q : geom) {
@@ -1194,8 +1296,8 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
             }
             c->cpml_adj_h.assign(3 * (nshots + 1), 0);
             cpml_block_table(gx.data(), gy.data(), gz.data(), nshots, p->nb + 4, c->cpml_adj_h.data());
-            c->cpml_adj_d = at<int>(c->ws, L.cpml_off) + cpml_pos;
-            up(L.cpml_off + sizeof(int) * cpml_pos, c->cpml_adj_h.data(), sizeof(int) * c->cpml_adj_h.size());
+            c->cpml_adj_d = at<int>(c->ws, L.cpml_off);
+            up(L.cpml_off, c->cpml_adj_h.data(), sizeof(int) * c->cpml_adj_h.size());
         }
     }
     for (int i = 0; i < nshots && !st; ++i) {
@@ -1418,7 +1520,7 @@ static mm_status state_copy(mm_ctx* c, char* ext, bool to_ext) {
         if (c->cpml) {
             const size_t nb2 = 2 * (size_t)c->p.nb;
             const size_t sl[3] = {(size_t)g.nz * g.ny * nb2, (size_t)g.nz * nb2 * g.nx, nb2 * g.ny * g.nx};
-            for (int a = 0; a < 3; ++a) MM_TRY(cp(c->shots_h[i].psi[a], sizeof(float) * sl[a]));
+            for (int a = 0; a < 3; ++a) MM_TRY(cp(psi_now(c->shots_h[i], a, par), sizeof(float) * sl[a]));
             for (int a = 0; a < 3; ++a) MM_TRY(cp(c->shots_h[i].zeta[a], sizeof(float) * sl[a]));
         }
     }

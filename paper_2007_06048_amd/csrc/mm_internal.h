@@ -14,7 +14,9 @@ struct ShotDev {
     const float* prof;    // sponge: g_x[nx] g_y[ny] g_z[nz]; CPML: a_x b_x [nx], a_y b_y [ny], a_z b_z [nz]
     float* psi[3];        // CPML memory, slab layouts (see minimod.h); adjoint fields: its adjoint
     float* zeta[3];
-    float* corr[3];       // CPML correction added to the Laplacian this step, slabs of cw cells per end
+    // forward fields: the second buffer of psi (psi^k is in psi at even k, in corr at odd k);
+    // adjoint fields: the correction added to the Laplacian this step, slabs of cw cells per end
+    float* corr[3];
     int nx, ny, nz, nb;
     int cw;               // width of the correction slabs: nb (forward), nb + 4 (adjoint)
     int fs;               // free surface on plane z = 0 (p = 0 there, odd mirror above)
@@ -29,9 +31,11 @@ struct ShotDev {
 
 enum { MAX_INLINE_SRC = 4 };
 
-// One z-marching tile: an xy rectangle of one shot and a z range [z0, z1).
+// One z-marching tile of one shot: the kernel stages the xy rectangle of
+// its launch's tile shape at (x0, y0) and writes the cells [x0, x1) x
+// [y0, y1) x [z0, z1) (x1, y1 clip the rectangle to the tile's region).
 struct TileEnt {
-    int shot, x0, y0, z0, z1, flags, pad1, pad2;
+    int shot, x0, y0, z0, z1, flags, x1, y1;
 };
 
 // TileEnt::flags: the tile meets the x / y / z damping layer (CPML), or
@@ -105,26 +109,33 @@ int num_tile_variants();
 const TileShape& tile_variant(int t);
 int tile_rows(int t);  // TY of variant t
 
-// bc: 0 none, 1 sponge, 2 CPML (launch_cpml must have written the layer
-// corrections of the same step first)
+// bc: 0 none, 1 sponge, 2 CPML adjoint fields (launch_cpml must have written
+// the layer corrections of the same step first)
 // With ev0 / ev1 the launch records its own start and end time stamps into
 // them (hipExtLaunchKernel), for per-launch timing without extra packets.
 hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int ntiles,
                        const ShotDev* shots, int parity, const Coefs& cf, const StepAux& aux,
                        hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-// CPML memory update and corrections of every shot for this step, before the
-// stencil kernel (shared nb <= 128).  With adjoint set, the same for the
-// adjoint fields: the transposed memory recursions and a correction reaching
-// 4 cells past the layer (nb <= 64).  The block table (3 (nshots + 1) ints,
-// made by cpml_block_table with width nb, or nb + 4 for the adjoint) is
-// passed both as the device copy the kernel reads and as the host copy that
-// sizes the grid.  stream (forward only): psi and zeta are loaded with the
-// non-temporal hint (the step's working set exceeds the Infinity Cache).
+// Forward CPML step of the tiles that meet a layer, memory update included
+// (no launch_cpml before it): zlayer selects the launch over the z-layer
+// chunks [0, nb) and [nz - nb, nz) (every tile TF_LZ), else the tiles of the
+// middle z range flagged TF_LX / TF_LY.  mode MODE_PLAIN or MODE_D2P.  The
+// tiles are cstep_tile_w() x cstep_tile_h().
+hipError_t launch_cpml_step(bool zlayer, int mode, const TileEnt* tiles, int ntiles, const ShotDev* shots,
+                            int parity, const Coefs& cf, const StepAux& aux, hipStream_t s, hipEvent_t ev0 = nullptr,
+                            hipEvent_t ev1 = nullptr);
+int cstep_tile_w();
+int cstep_tile_h();
+// Adjoint CPML memory update and corrections of every shot for this step,
+// before the adjoint stencil kernel: the transposed memory recursions and a
+// correction reaching 4 cells past the layer (nb <= 64).  The block table
+// (3 (nshots + 1) ints, made by cpml_block_table with width nb + 4) is passed
+// both as the device copy the kernel reads and as the host copy that sizes
+// the grid.  ev0 (may be null) receives the kernel's start time stamp.
 void cpml_block_table(const int* nx, const int* ny, const int* nz, int nshots, int width, int* off);
-// ev0 (may be null) receives the kernel's start time stamp.
-hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, bool adjoint, bool stream, const int* block_off_dev,
-                       const int* block_off_host, int parity, const Coefs& cf, hipStream_t s,
-                       hipEvent_t ev0 = nullptr);
+hipError_t launch_cpml_adjoint(const ShotDev* shots, int nshots, int nb, const int* block_off_dev,
+                               const int* block_off_host, int parity, const Coefs& cf, hipStream_t s,
+                               hipEvent_t ev0 = nullptr);
 // acoustic_iso: one step is launch_iso_u (u^{n+1/2} from p^n = buf[parity])
 // then launch_iso_p (p^{n+1} into buf[parity ^ 1]), over the same tile
 // table as the stencil kernel; bc 0 none, 1 sponge.  Sources are added by

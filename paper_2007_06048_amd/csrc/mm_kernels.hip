@@ -92,9 +92,11 @@ int tile_rows(int t) { return (kTiles[t].nt / kTiles[t].tx) * kTiles[t].ry; }
 // ------------------------------------------------------------- stencil step
 
 // The small-tile, one-plane-prefetch shapes are held to 72 VGPRs (7 waves per
-// SIMD instead of 6 for the CPML forward and the imaging instantiations);
-// they fit without spilling, the larger shapes and the CPML replay / imaging
-// modes would not.
+// SIMD instead of 6 for the CPML adjoint and the imaging instantiations);
+// they fit without spilling, the larger shapes and the CPML imaging mode
+// would not.  BC == 2 is the adjoint fields' CPML (corrections written by
+// launch_cpml_adjoint); the forward CPML step of the cells near the faces is
+// k_cstep.
 template <int TX, int RY, int PD, int BC, int MODE, int NT, bool STREAM>
 __global__ __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu((PD == 1 && RY <= 2 && !(BC == 2 && MODE != MODE_PLAIN)) ? 7 : 1)))
@@ -136,11 +138,12 @@ void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const Sh
     const bool xin = x < nx;
 
     int row[RY];
-    bool in[RY];
+    bool in[RY], own[RY];  // in the grid (staged in LDS) / written by this tile
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         row[r] = te.y0 + ty + r * BY;
         in[r] = xin && row[r] < ny;
+        own[r] = x < te.x1 && row[r] < te.y1;
     }
     // x halo: lanes 0..7 of every thread row carry the 4 left and 4 right columns
     const int hcol = tx < 4 ? te.x0 - 4 + tx : te.x0 + TX + (tx - 4);
@@ -344,7 +347,7 @@ void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const Sh
             }
             float lap = (lx + ly) + lzv;
             if (CPML) lap += ccr[CPML ? r : 0];
-            if (in[r]) {
+            if (own[r]) {
                 const long long o = zoff + (row[r] * nx + x);
                 if ((te.flags & TF_SRC) && aux.wrow) {
 #pragma unroll
@@ -463,6 +466,470 @@ hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int 
     if (ts.ry == 2) MM_T(32, 2, 256);
     MM_T(32, 4, 256);
 #undef MM_T
+}
+
+// ------------------------------------------------------ CPML, fused step
+//
+// Time step of the tiles that meet a CPML layer, with the memory update of
+// every damped axis done in the same pass (no correction arrays written and
+// read back).  Per damped axis a and layer cell,
+//   psi_a^{n+1} = b_a psi_a^n + a_a D1_a p^n,
+//   zeta_a^{n+1} = b_a zeta_a^n + a_a (D2_a p^n + D1_a psi_a^{n+1}),
+// and the cell's Laplacian gains D1_a psi_a^{n+1} + zeta_a^{n+1}.  D1 of
+// psi^{n+1} reaches 8 cells of p^n, so:
+//  - x and y: the staged plane carries 8-cell halos (tiles flagged TF_LX /
+//    TF_LY), psi^{n+1} is formed over the tile and 4 cells around it into
+//    LDS (the outer ring redundantly with the neighbouring tile, from the
+//    same p^n and psi^n), and D1 psi is taken from there after a barrier;
+//  - z (LZ launches, whose z-chunks are exactly the layers [0, nb) and
+//    [nz - nb, nz)): the register queue holds planes z-4 .. z+8, psi_z^{n+1}
+//    of plane z+4 is formed as soon as plane z+8 arrives and kept in a
+//    second queue of planes z-4 .. z+4 (zero outside the chunk, which is
+//    outside the layer).
+// psi is double-buffered by step parity (current in ShotDev::psi at even
+// steps and in ShotDev::corr at odd ones, the next in the other), so the
+// ring of a tile reads psi^n while its owner writes psi^{n+1}; zeta is
+// updated in place by the owner only.  Cells owned by the tile are
+// [x0, x1) x [y0, y1) x [z0, z1); the plane is staged over the full TX x TY
+// so the ring around the owned cells holds real p^n values.
+template <int TX, int RY, int NT, bool LZ, int MODE, bool STREAM>
+__global__ __launch_bounds__(NT) void k_cstep(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd,
+                                              const ShotDev* __restrict__ shots, int parity, Coefs cf,
+                                              StepAux aux) {
+    constexpr int BY = NT / TX;  // thread rows
+    constexpr int TY = BY * RY;
+    constexpr int H = 8;  // halo of the staged plane
+    constexpr int LW = TX + 2 * H;
+    constexpr int QD = LZ ? 13 : 9;             // z queue: planes z-4 .. z+QD-5
+    constexpr int YH = BY >= 16 ? 1 : 16 / BY;  // plane halo rows per thread row (16 in all)
+    constexpr int PH = BY >= 8 ? 1 : 8 / BY;    // psi_y ring rows per thread row (8 in all)
+    static_assert(TX >= 16 && (BY >= 16 || 16 % BY == 0), "halo split");
+    __shared__ float lds[2][TY + 2 * H][LW];
+    __shared__ float psx[TY][TX + 8];  // psi_x^{n+1}: tile rows, columns x0-4 .. x0+TX+3
+    __shared__ float psy[TY + 8][TX];  // psi_y^{n+1}: tile columns, rows y0-4 .. y0+TY+3
+
+    if ((int)blockIdx.x < aux.gather_blocks) {
+        // record of the previous step: its output is this step's p^n (256 receivers per block)
+        const int tid = threadIdx.y * TX + threadIdx.x;
+        const int r = blockIdx.x * 256 + tid;
+        if (tid < 256 && r < aux.g_n) aux.gather_out[r] = shots[aux.g_shot[r]].buf[parity][aux.g_off[r]];
+        return;
+    }
+    const int b = blockIdx.x - aux.gather_blocks;
+    const int t = (b & 7) * per_xcd + (b >> 3);
+    if (t >= ntiles) return;
+    const TileEnt te = tiles[t];
+    const ShotDev& sd = shots[te.shot];
+    const int nx = sd.nx, ny = sd.ny, nz = sd.nz, nb = sd.nb, nb2 = 2 * nb;
+    const long long plane = (long long)nx * ny;
+    const float* __restrict__ pc = sd.buf[parity];
+    float* __restrict__ pn = sd.buf[parity ^ 1];
+    const float* __restrict__ vd = sd.vdt2;
+    const float* __restrict__ prof = sd.prof;  // a_x b_x [nx], a_y b_y [ny], a_z b_z [nz]
+    const float* __restrict__ rpx = parity ? sd.corr[0] : sd.psi[0];
+    const float* __restrict__ rpy = parity ? sd.corr[1] : sd.psi[1];
+    const float* __restrict__ rpz = parity ? sd.corr[2] : sd.psi[2];
+    float* __restrict__ wpx = parity ? sd.psi[0] : sd.corr[0];
+    float* __restrict__ wpy = parity ? sd.psi[1] : sd.corr[1];
+    float* __restrict__ wpz = parity ? sd.psi[2] : sd.corr[2];
+    const long long pxs = (long long)ny * nb2, pys = (long long)nb2 * nx;  // slab planes of x and y
+
+    const bool tlx = (te.flags & TF_LX) != 0, tly = (te.flags & TF_LY) != 0;
+    const bool wide = tlx || tly;  // block-uniform
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int x = te.x0 + tx;
+    const bool xin = x < nx;
+    int row[RY];
+    bool in[RY], own[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        row[r] = te.y0 + ty + r * BY;
+        in[r] = xin && row[r] < ny;
+        own[r] = x < te.x1 && row[r] < te.y1;
+    }
+    // plane halo: lanes 0..15 carry columns x0-8 .. x0-1 and x0+TX .. x0+TX+7, thread rows the
+    // 16 rows y0-8 .. y0-1 and y0+TY .. y0+TY+7 (the outer 4 of each side only on wide tiles)
+    const int hcol = tx < 8 ? te.x0 - 8 + tx : te.x0 + TX + (tx - 8);
+    const bool hx_lane = tx < 16 && (wide || (tx >= 4 && tx < 12)) && hcol >= 0 && hcol < nx;
+    const bool hy_row = BY <= 16 || ty < 16;  // wave-uniform
+    unsigned voc[RY], vox[RY], voy[YH];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        voc[r] = in[r] ? (unsigned)(row[r] * nx + x) * 4u : OOB;
+        vox[r] = (hx_lane && row[r] < ny) ? (unsigned)(row[r] * nx + hcol) * 4u : OOB;
+    }
+#pragma unroll
+    for (int h = 0; h < YH; ++h) {
+        const int hr = ty + h * BY;
+        const int y = hr < 8 ? te.y0 - 8 + hr : te.y0 + TY + (hr - 8);
+        const bool ok = hy_row && hr < 16 && (wide || (hr >= 4 && hr < 12)) && xin && y >= 0 && y < ny;
+        voy[h] = ok ? (unsigned)(y * nx + x) * 4u : OOB;
+    }
+    // x layer: this thread's column, and (lanes 0..7) the psi_x ring columns x0-4 .. x0-1, x0+TX .. x0+TX+3
+    const bool xl = tlx && xin && (x < nb || x >= nx - nb);
+    const float axc = xl ? prof[x] : 0.0f, bxc = xl ? prof[nx + x] : 0.0f;
+    const int pcol = tx < 4 ? te.x0 - 4 + tx : te.x0 + TX + (tx - 4);
+    const bool pxl = tlx && tx < 8 && pcol >= 0 && pcol < nx && (pcol < nb || pcol >= nx - nb);
+    const float apx = pxl ? prof[pcol] : 0.0f, bpx = pxl ? prof[nx + pcol] : 0.0f;
+    unsigned vsx[RY], vpx[RY], vsy[RY];
+    bool yl[RY];
+    float ayc[RY], byc[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int y = row[r];
+        vsx[r] = (xl && y < ny) ? (unsigned)(y * nb2 + (x < nb ? x : x - (nx - nb2))) * 4u : OOB;
+        vpx[r] = (pxl && y < ny) ? (unsigned)(y * nb2 + (pcol < nb ? pcol : pcol - (nx - nb2))) * 4u : OOB;
+        yl[r] = tly && in[r] && (y < nb || y >= ny - nb);
+        vsy[r] = yl[r] ? (unsigned)((y < nb ? y : y - (ny - nb2)) * nx + x) * 4u : OOB;
+        ayc[r] = yl[r] ? prof[2 * nx + y] : 0.0f;
+        byc[r] = yl[r] ? prof[2 * nx + ny + y] : 0.0f;
+    }
+    // y layer: the psi_y ring rows y0-4 .. y0-1 and y0+TY .. y0+TY+3 (thread row ty takes ty, ty + BY, ... < 8)
+    unsigned vpy[PH];
+    float apy[PH], bpy[PH];
+#pragma unroll
+    for (int h = 0; h < PH; ++h) {
+        const int hr = ty + h * BY;
+        const int y = hr < 4 ? te.y0 - 4 + hr : te.y0 + TY + (hr - 4);
+        const bool ok = tly && hr < 8 && xin && y >= 0 && y < ny && (y < nb || y >= ny - nb);
+        vpy[h] = ok ? (unsigned)((y < nb ? y : y - (ny - nb2)) * nx + x) * 4u : OOB;
+        apy[h] = ok ? prof[2 * nx + y] : 0.0f;
+        bpy[h] = ok ? prof[2 * nx + ny + y] : 0.0f;
+    }
+    const float* __restrict__ zprof = prof + 2 * nx + 2 * ny;  // a_z [nz], b_z [nz]
+
+    const int z0 = te.z0, z1 = te.z1;
+    float q[RY][QD];
+#pragma unroll
+    for (int m = 0; m < QD - 1; ++m) {
+        const int z = z0 - 4 + m;
+        const bool zin = z >= 0 && z < nz;  // block-uniform
+        const __amdgpu_buffer_rsrc_t rp = plane_rsrc(pc, zin ? z : 0, plane);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) q[r][m] = zin ? bload(rp, voc[r]) : 0.0f;
+    }
+    if (!LZ && z0 == 0 && sd.fs) {
+        // above a free surface on plane 0: the odd mirror, planes -1..-4 = -p(1..4)
+        const __amdgpu_buffer_rsrc_t r4 = plane_rsrc(pc, 4 < nz ? 4 : 0, plane);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            q[r][3] = -q[r][5];
+            q[r][2] = -q[r][6];
+            q[r][1] = -q[r][7];
+            q[r][0] = 4 < nz ? -bload(r4, voc[r]) : 0.0f;
+        }
+    }
+    auto zslab = [&](int z) { return z < nb ? z : z - (nz - nb2); };
+    // psi_z^{n+1} of planes z-4 .. z+4 (LZ): the planes before the chunk are outside the layer
+    float ps[LZ ? RY : 1][9];
+    if (LZ) {
+#pragma unroll
+        for (int r = 0; r < RY; ++r)
+#pragma unroll
+            for (int m = 0; m < 9; ++m) ps[r][m] = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int zz = z0 + j;
+            if (zz < z1) {
+                const __amdgpu_buffer_rsrc_t ro = plane_rsrc(rpz, zslab(zz), plane);
+                const float az = zprof[zz], bz = zprof[nz + zz];
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    float d1 = 0.0f;
+#pragma unroll
+                    for (int m = 1; m <= 4; ++m) d1 = fmaf(cf.bz[m - 1], q[r][4 + j + m] - q[r][4 + j - m], d1);
+                    const float v = fmaf(bz, bload(ro, voc[r]), az * d1);
+                    ps[r][4 + j] = v;
+                    if (own[r]) ((gfloat*)wpz)[(long long)zslab(zz) * plane + (row[r] * nx + x)] = v;
+                }
+            }
+        }
+    }
+
+    // prefetch stage for plane zn: queue head p^n(zn+QD-5), p^{n-1}, (dt v)^2, the plane halos,
+    // psi^n and zeta^n of the cell (x, y: plane zn; z: psi of plane zn+4, zeta of zn), psi^n of the rings
+    float nq[RY], npp[RY], nvd[RY], nxh[RY], nyh[YH];
+    float nsx[RY], nzx[RY], nhx[RY], nsy[RY], nzy[RY], nhy[PH], nsz[RY], nzz[RY];
+    auto fetch = [&](int zn) {
+        const int zq = zn + QD - 5;
+        const bool hin = zq < nz;
+        const __amdgpu_buffer_rsrc_t rh = plane_rsrc(pc, hin ? zq : 0, plane);
+        const __amdgpu_buffer_rsrc_t rc = plane_rsrc(pc, zn, plane);
+        const __amdgpu_buffer_rsrc_t rm = plane_rsrc(pn, zn, plane);
+        const __amdgpu_buffer_rsrc_t rv = plane_rsrc(vd, zn, plane);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            nq[r] = hin ? bload(rh, voc[r]) : 0.0f;
+            npp[r] = STREAM ? bload_nt(rm, voc[r]) : bload(rm, voc[r]);
+            nvd[r] = STREAM ? bload_nt(rv, voc[r]) : bload(rv, voc[r]);
+            nxh[r] = bload(rc, vox[r]);
+            nsx[r] = nzx[r] = nhx[r] = nsy[r] = nzy[r] = nsz[r] = nzz[r] = 0.0f;
+        }
+#pragma unroll
+        for (int h = 0; h < YH; ++h) nyh[h] = bload(rc, voy[h]);
+#pragma unroll
+        for (int h = 0; h < PH; ++h) nhy[h] = 0.0f;
+        if (tlx) {
+            const __amdgpu_buffer_rsrc_t rs = plane_rsrc(rpx, zn, pxs);
+            const __amdgpu_buffer_rsrc_t rz = plane_rsrc(sd.zeta[0], zn, pxs);
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                nsx[r] = STREAM ? bload_nt(rs, vsx[r]) : bload(rs, vsx[r]);
+                nzx[r] = STREAM ? bload_nt(rz, vsx[r]) : bload(rz, vsx[r]);
+                nhx[r] = bload(rs, vpx[r]);
+            }
+        }
+        if (tly) {
+            const __amdgpu_buffer_rsrc_t rs = plane_rsrc(rpy, zn, pys);
+            const __amdgpu_buffer_rsrc_t rz = plane_rsrc(sd.zeta[1], zn, pys);
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                nsy[r] = STREAM ? bload_nt(rs, vsy[r]) : bload(rs, vsy[r]);
+                nzy[r] = STREAM ? bload_nt(rz, vsy[r]) : bload(rz, vsy[r]);
+            }
+#pragma unroll
+            for (int h = 0; h < PH; ++h) nhy[h] = bload(rs, vpy[h]);
+        }
+        if (LZ) {
+            const bool pin = zn + 4 < z1;  // the chunk is the whole layer
+            const __amdgpu_buffer_rsrc_t rs = plane_rsrc(rpz, pin ? zslab(zn + 4) : 0, plane);
+            const __amdgpu_buffer_rsrc_t rz = plane_rsrc(sd.zeta[2], zslab(zn), plane);
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                nsz[r] = pin ? (STREAM ? bload_nt(rs, voc[r]) : bload(rs, voc[r])) : 0.0f;
+                nzz[r] = STREAM ? bload_nt(rz, voc[r]) : bload(rz, voc[r]);
+            }
+        }
+    };
+    if (z0 < z1) fetch(z0);
+
+    const int xx = H + tx;
+    gfloat* __restrict__ pn_g = (gfloat*)pn;
+    for (int z = z0; z < z1; ++z) {
+        float cpp[RY], cvd[RY], cxh[RY], cyh[YH], csx[RY], czx[RY], chx[RY], csy[RY], czy[RY], chy[PH], csz[RY],
+            czz[RY];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            q[r][QD - 1] = nq[r];
+            cpp[r] = npp[r];
+            cvd[r] = nvd[r];
+            cxh[r] = nxh[r];
+            csx[r] = nsx[r];
+            czx[r] = nzx[r];
+            chx[r] = nhx[r];
+            csy[r] = nsy[r];
+            czy[r] = nzy[r];
+            csz[r] = nsz[r];
+            czz[r] = nzz[r];
+        }
+#pragma unroll
+        for (int h = 0; h < YH; ++h) cyh[h] = nyh[h];
+#pragma unroll
+        for (int h = 0; h < PH; ++h) chy[h] = nhy[h];
+        if (z + 1 < z1) fetch(z + 1);
+
+        if (LZ) {
+            // psi_z^{n+1} of plane z+4: its D1 needs planes z .. z+8, now all in the queue
+            const int zp = z + 4;
+            if (zp < z1) {
+                const float az = zprof[zp], bz = zprof[nz + zp];
+                const long long so = (long long)zslab(zp) * plane;
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    float d1 = 0.0f;
+#pragma unroll
+                    for (int m = 1; m <= 4; ++m) d1 = fmaf(cf.bz[m - 1], q[r][8 + m] - q[r][8 - m], d1);
+                    const float v = fmaf(bz, csz[r], az * d1);
+                    ps[r][8] = v;
+                    if (own[r]) ((gfloat*)wpz)[so + (row[r] * nx + x)] = v;
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < RY; ++r) ps[r][8] = 0.0f;
+            }
+        }
+
+        float(*L)[LW] = lds[z & 1];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            L[H + ty + r * BY][xx] = q[r][4];
+            if (tx < 16) L[H + ty + r * BY][tx < 8 ? tx : TX + tx] = cxh[r];
+        }
+        if (hy_row) {
+#pragma unroll
+            for (int h = 0; h < YH; ++h) {
+                const int hr = ty + h * BY;
+                if (hr < 16) L[hr < 8 ? hr : TY + hr][xx] = cyh[h];
+            }
+        }
+        __syncthreads();
+
+        if (wide) {
+            if (tlx) {
+                const long long so = (long long)z * pxs;
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    const int yy = H + ty + r * BY;
+                    float v = 0.0f;
+                    if (xl && in[r]) {
+                        float d1 = 0.0f;
+#pragma unroll
+                        for (int m = 1; m <= 4; ++m) d1 = fmaf(cf.bx[m - 1], L[yy][xx + m] - L[yy][xx - m], d1);
+                        v = fmaf(bxc, csx[r], axc * d1);
+                        if (own[r]) ((gfloat*)wpx)[so + (vsx[r] >> 2)] = v;
+                    }
+                    psx[ty + r * BY][4 + tx] = v;
+                    if (tx < 8) {
+                        float w = 0.0f;
+                        if (pxl && row[r] < ny) {
+                            const int cc = tx < 4 ? H - 4 + tx : H + TX + (tx - 4);
+                            float d1 = 0.0f;
+#pragma unroll
+                            for (int m = 1; m <= 4; ++m) d1 = fmaf(cf.bx[m - 1], L[yy][cc + m] - L[yy][cc - m], d1);
+                            w = fmaf(bpx, chx[r], apx * d1);
+                        }
+                        psx[ty + r * BY][tx < 4 ? tx : TX + tx] = w;
+                    }
+                }
+            }
+            if (tly) {
+                const long long so = (long long)z * pys;
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    const int yy = H + ty + r * BY;
+                    float v = 0.0f;
+                    if (yl[r]) {
+                        float d1 = 0.0f;
+#pragma unroll
+                        for (int m = 1; m <= 4; ++m) d1 = fmaf(cf.by[m - 1], L[yy + m][xx] - L[yy - m][xx], d1);
+                        v = fmaf(byc[r], csy[r], ayc[r] * d1);
+                        if (own[r]) ((gfloat*)wpy)[so + (vsy[r] >> 2)] = v;
+                    }
+                    psy[4 + ty + r * BY][tx] = v;
+                }
+#pragma unroll
+                for (int h = 0; h < PH; ++h) {
+                    const int hr = ty + h * BY;
+                    if (hr < 8) {
+                        float w = 0.0f;
+                        if (vpy[h] != OOB) {
+                            const int lr = hr < 4 ? H - 4 + hr : H + TY + (hr - 4);
+                            float d1 = 0.0f;
+#pragma unroll
+                            for (int m = 1; m <= 4; ++m) d1 = fmaf(cf.by[m - 1], L[lr + m][xx] - L[lr - m][xx], d1);
+                            w = fmaf(bpy[h], chy[h], apy[h] * d1);
+                        }
+                        psy[hr < 4 ? hr : TY + hr][tx] = w;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+
+        const long long zoff = (long long)z * plane;
+        const float az = LZ ? zprof[z] : 0.0f, bz = LZ ? zprof[nz + z] : 0.0f;
+        const long long zso = LZ ? (long long)zslab(z) * plane : 0;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const int yy = H + ty + r * BY;
+            const float c = q[r][4];
+            float lx = 0.0f, ly = 0.0f, lzv = 0.0f;
+#pragma unroll
+            for (int m = 1; m <= 4; ++m) {
+                lx = fmaf(cf.cx[m - 1], (L[yy][xx + m] - c) + (L[yy][xx - m] - c), lx);
+                ly = fmaf(cf.cy[m - 1], (L[yy + m][xx] - c) + (L[yy - m][xx] - c), ly);
+                lzv = fmaf(cf.cz[m - 1], (q[r][4 + m] - c) + (q[r][4 - m] - c), lzv);
+            }
+            float lap = (lx + ly) + lzv;
+            float cx = 0.0f, cy = 0.0f, cz = 0.0f;
+            bool layer = false;
+            if (tlx && xl && in[r]) {
+                const int pr = ty + r * BY;
+                float d1 = 0.0f;
+#pragma unroll
+                for (int m = 1; m <= 4; ++m) d1 = fmaf(cf.bx[m - 1], psx[pr][4 + tx + m] - psx[pr][4 + tx - m], d1);
+                const float zn = fmaf(bxc, czx[r], axc * (lx + d1));
+                if (own[r]) ((gfloat*)sd.zeta[0])[(long long)z * pxs + (vsx[r] >> 2)] = zn;
+                cx = d1 + zn;
+                layer = true;
+            }
+            if (tly && yl[r]) {
+                const int pr = 4 + ty + r * BY;
+                float d1 = 0.0f;
+#pragma unroll
+                for (int m = 1; m <= 4; ++m) d1 = fmaf(cf.by[m - 1], psy[pr + m][tx] - psy[pr - m][tx], d1);
+                const float zn = fmaf(byc[r], czy[r], ayc[r] * (ly + d1));
+                if (own[r]) ((gfloat*)sd.zeta[1])[(long long)z * pys + (vsy[r] >> 2)] = zn;
+                cy = d1 + zn;
+                layer = true;
+            }
+            if (LZ && in[r]) {
+                float d1 = 0.0f;
+#pragma unroll
+                for (int m = 1; m <= 4; ++m) d1 = fmaf(cf.bz[m - 1], ps[r][4 + m] - ps[r][4 - m], d1);
+                const float zn = fmaf(bz, czz[r], az * (lzv + d1));
+                if (own[r]) ((gfloat*)sd.zeta[2])[zso + (row[r] * nx + x)] = zn;
+                cz = d1 + zn;
+                layer = true;
+            }
+            if (layer) lap += (cx + cy) + cz;
+            if (own[r]) {
+                const long long o = zoff + (row[r] * nx + x);
+                if ((te.flags & TF_SRC) && aux.wrow) {
+#pragma unroll
+                    for (int k = 0; k < MAX_INLINE_SRC; ++k)
+                        if (k < sd.nsrc_in && o == sd.src_off[k]) lap = fmaf(aux.src_scale, aux.wrow[sd.src_col[k]], lap);
+                }
+                const float out = c + fmaf(cvd[r], lap, c - cpp[r]);
+                pn_g[o] = out;
+                if (MODE == MODE_D2P) __builtin_nontemporal_store(cvd[r] * lap, &((gfloat*)aux.d2p_out)[o]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+#pragma unroll
+            for (int m = 0; m < QD - 1; ++m) q[r][m] = q[r][m + 1];
+            if (LZ) {
+#pragma unroll
+                for (int m = 0; m < 8; ++m) ps[r][m] = ps[r][m + 1];
+            }
+        }
+    }
+}
+
+// fixed shape of the fused CPML kernel: 32-wide, 16-row tiles of 512 threads (one row each)
+constexpr int CS_TX = 32, CS_RY = 1, CS_NT = 512;
+int cstep_tile_w() { return CS_TX; }
+int cstep_tile_h() { return (CS_NT / CS_TX) * CS_RY; }
+
+template <bool LZ, int MODE, bool STREAM>
+static void launch_cstep_k(dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd, const ShotDev* shots, int parity,
+                           const Coefs& cf, const StepAux& aux, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    const dim3 block(CS_TX, CS_NT / CS_TX);
+    hipExtLaunchKernelGGL(k_cstep<CS_TX, CS_RY, CS_NT, LZ, MODE, STREAM>, grid, block, 0, s, ev0, ev1, 0, tiles,
+                          ntiles, per_xcd, shots, parity, cf, aux);
+}
+
+hipError_t launch_cpml_step(bool zlayer, int mode, const TileEnt* tiles, int ntiles, const ShotDev* shots,
+                            int parity, const Coefs& cf, const StepAux& aux, hipStream_t s, hipEvent_t ev0,
+                            hipEvent_t ev1) {
+    if (ntiles <= 0) return hipSuccess;
+    if (mode != MODE_PLAIN && mode != MODE_D2P) return hipErrorInvalidValue;
+    const int per_xcd = (ntiles + 7) / 8;
+    const dim3 grid(8 * per_xcd + aux.gather_blocks);
+    const bool st = aux.stream_loads != 0 && mode == MODE_PLAIN;
+#define MM_CS(LZ_, M_, S_) launch_cstep_k<LZ_, M_, S_>(grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0, ev1)
+    if (zlayer) {
+        if (mode == MODE_D2P) MM_CS(true, MODE_D2P, false);
+        else if (st) MM_CS(true, MODE_PLAIN, true);
+        else MM_CS(true, MODE_PLAIN, false);
+    } else {
+        if (mode == MODE_D2P) MM_CS(false, MODE_D2P, false);
+        else if (st) MM_CS(false, MODE_PLAIN, true);
+        else MM_CS(false, MODE_PLAIN, false);
+    }
+#undef MM_CS
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------ acoustic_iso
@@ -870,24 +1337,19 @@ hipError_t launch_iso_setup(const float* vel, const float* rho, long long n, dou
     return hipGetLastError();
 }
 
-// -------------------------------------------------------------------- CPML
+// ------------------------------------------------------------ CPML adjoint
 //
-// One launch per step, before the stencil kernel, one thread per cell of the
-// damping layers of every axis (nb cells at each end).  Phase 1:
-//   psi <- b psi + a D1 p^n   (stored, and kept in LDS along the layer),
-// phase 2, after a barrier:
-//   zeta <- b zeta + a (D2 p^n + D1 psi)   (stored),   corr = D1 psi + zeta,
-// with D1, D2 the order-8 first / second differences along the axis.  The
-// stencil kernel of the same step adds corr_x + corr_y + corr_z to the
-// Laplacian of the cells inside the layers.  psi is zero outside its layer
-// and the two layers of an axis are at least 4 cells apart, so a block that
-// holds a whole layer segment along the axis has every psi it needs in LDS.
-// The axes write disjoint arrays, so they share one launch: the grid is the
-// x-layer blocks (whole 2 nb-cell rows, lanes along x), then the y-layer and
-// z-layer blocks (64 x-columns by the nb cells of one end).
+// The adjoint fields' CPML runs as one launch per step before their stencil
+// kernel, one thread per cell of the damping layers of every axis (nb + 4
+// cells at each end), writing a correction that the stencil kernel adds to
+// the Laplacian of those cells.  The axes write disjoint arrays, so they
+// share one launch: the grid is the x-layer blocks (whole 2 (nb + 4)-cell
+// rows, lanes along x), then the y-layer and z-layer blocks (64 x-columns by
+// the cells of one end).
 //
-// Slab arrays: x [nz][ny][2nb], y [nz][2nb][nx], z [2nb][ny][nx]; slab index
-// s < nb is grid index s, s >= nb is grid index n - 2nb + s.
+// Slab arrays: memory x [nz][ny][2nb], y [nz][2nb][nx], z [2nb][ny][nx]
+// (slab index s < nb is grid index s, s >= nb is grid index n - 2nb + s);
+// corrections the same with nb + 4 cells per end.
 
 // Compact block enumeration over the shots: part x has, per shot, one block
 // per CPML_XG * rows_per_block rows; parts y and z have 2 ends x 64-column
@@ -909,123 +1371,6 @@ __device__ __forceinline__ int find_shot(const int* off, int nshots, int b) {
         else hi = mid - 1;
     }
     return lo;
-}
-
-// NT: psi and zeta (read once per step) are loaded with the non-temporal hint
-template <bool NT>
-__device__ __forceinline__ float once(const float* p) {
-    if constexpr (NT) return __builtin_nontemporal_load(p);
-    else return *p;
-}
-
-template <bool NT>
-__device__ void cpml_x_block(const ShotDev& sd, int parity, const Coefs& cf, int blk, int rpb, float* lds) {
-    const int nx = sd.nx, ny = sd.ny, nz = sd.nz, nb = sd.nb, nb2 = 2 * nb;
-    const int e = threadIdx.x;
-    const int r = e / nb2, sl = e - r * nb2;
-    const int x = sl < nb ? sl : nx - nb2 + sl;
-    const int lo = sl < nb ? 0 : nb, hi = lo + nb;  // this end of the row (the other is >= 4 cells away)
-    const float* __restrict__ p = sd.buf[parity];
-    float* __restrict__ ps = sd.psi[0];
-    float* __restrict__ ze = sd.zeta[0];
-    float* __restrict__ co = sd.corr[0];
-    const float a = sd.prof[x], b = sd.prof[nx + x];
-    for (int g = 0; g < CPML_XG; ++g) {
-        const int row = (blk * CPML_XG + g) * rpb + r;
-        const bool active = r < rpb && row < ny * nz;
-        const long long o = (long long)row * nx + x;  // row = z * ny + y
-        const long long si = (long long)row * nb2 + sl;
-        float c = 0.0f, d1 = 0.0f, d2 = 0.0f;
-        if (active) {
-            c = p[o];
-#pragma unroll
-            for (int m = 1; m <= 4; ++m) {
-                const float fp = x + m < nx ? p[o + m] : 0.0f;
-                const float fm = x - m >= 0 ? p[o - m] : 0.0f;
-                d1 = fmaf(cf.bx[m - 1], fp - fm, d1);
-                d2 = fmaf(cf.cx[m - 1], (fp - c) + (fm - c), d2);
-            }
-            const float pv = fmaf(b, once<NT>(ps + si), a * d1);
-            ps[si] = pv;
-            lds[e] = pv;
-        }
-        __syncthreads();
-        if (active) {
-            float dpsi = 0.0f;
-#pragma unroll
-            for (int m = 1; m <= 4; ++m) {
-                const float vp = sl + m < hi ? lds[e + m] : 0.0f;
-                const float vm = sl - m >= lo ? lds[e - m] : 0.0f;
-                dpsi = fmaf(cf.bx[m - 1], vp - vm, dpsi);
-            }
-            const float zn = fmaf(b, once<NT>(ze + si), a * (d2 + dpsi));
-            ze[si] = zn;
-            co[si] = dpsi + zn;
-        }
-        __syncthreads();  // lds is rewritten by the next row group
-    }
-}
-
-// y (AX = 1) or z (AX = 2) layers of one end: block = 64 x-columns, thread row
-// ty takes cells ty, ty + 4, ... of the nb cells; w is z (AX = 1) or y (AX = 2).
-template <int AX, bool NT>
-__device__ void cpml_yz_block(const ShotDev& sd, int parity, const Coefs& cf, int xblk, int w, int side, float* lds) {
-    const int nx = sd.nx, ny = sd.ny, nz = sd.nz, nb = sd.nb, nb2 = 2 * nb;
-    if (w >= (AX == 2 ? ny : nz)) return;  // whole block
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const int x = xblk * 64 + tx;
-    const bool active = x < nx;
-    const long long plane = (long long)nx * ny;
-    const int n = AX == 2 ? nz : ny;
-    const long long stride = AX == 2 ? plane : (long long)nx;
-    const long long base = AX == 2 ? (long long)w * nx + x : (long long)w * plane + x;
-    const long long sbase = AX == 2 ? (long long)w * nx + x : (long long)w * nb2 * nx + x;
-    const long long sstride = AX == 2 ? plane : (long long)nx;
-    const float* prof = AX == 2 ? sd.prof + 2 * nx + 2 * ny : sd.prof + 2 * nx;
-    const int s0 = side ? n - nb : 0;
-    const int soff = side ? nb : 0;  // slab index of the first cell of this end
-    float* psl = lds;                // [nb][64]
-    float* d2l = lds + nb * 64;      // [nb][64]
-    const float* __restrict__ p = sd.buf[parity];
-    float* __restrict__ psi = sd.psi[AX];
-    if (active) {
-        for (int s = ty; s < nb; s += 4) {
-            const int z = s0 + s;
-            const long long o = base + z * stride;
-            const float c = p[o];
-            float d1 = 0.0f, d2 = 0.0f;
-#pragma unroll
-            for (int m = 1; m <= 4; ++m) {
-                const float fp = z + m < n ? p[o + m * stride] : 0.0f;
-                const float fm = z - m >= 0 ? p[o - m * stride] : 0.0f;
-                d1 = fmaf(AX == 2 ? cf.bz[m - 1] : cf.by[m - 1], fp - fm, d1);
-                d2 = fmaf(AX == 2 ? cf.cz[m - 1] : cf.cy[m - 1], (fp - c) + (fm - c), d2);
-            }
-            const long long si = sbase + (long long)(soff + s) * sstride;
-            const float ps = fmaf(prof[n + z], once<NT>(psi + si), prof[z] * d1);
-            psi[si] = ps;
-            psl[s * 64 + tx] = ps;
-            d2l[s * 64 + tx] = d2;
-        }
-    }
-    __syncthreads();
-    if (!active) return;
-    float* __restrict__ ze = sd.zeta[AX];
-    float* __restrict__ co = sd.corr[AX];
-    for (int s = ty; s < nb; s += 4) {
-        const int z = s0 + s;
-        float dpsi = 0.0f;
-#pragma unroll
-        for (int m = 1; m <= 4; ++m) {
-            const float vp = s + m < nb ? psl[(s + m) * 64 + tx] : 0.0f;
-            const float vm = s - m >= 0 ? psl[(s - m) * 64 + tx] : 0.0f;
-            dpsi = fmaf(AX == 2 ? cf.bz[m - 1] : cf.by[m - 1], vp - vm, dpsi);
-        }
-        const long long si = sbase + (long long)(soff + s) * sstride;
-        const float zn = fmaf(prof[n + z], once<NT>(ze + si), prof[z] * (d2l[s * 64 + tx] + dpsi));
-        ze[si] = zn;
-        co[si] = dpsi + zn;
-    }
 }
 
 // Adjoint of the CPML step, run on the adjoint fields before their stencil
@@ -1181,8 +1526,8 @@ __device__ void cpml_yz_block_adj(const ShotDev& sd, int parity, const Coefs& cf
     }
 }
 
-template <bool ADJ, bool NT>
-__global__ __launch_bounds__(256) void k_cpml(const ShotDev* __restrict__ shots, int parity, Coefs cf, CpmlGrid g) {
+__global__ __launch_bounds__(256) void k_cpml_adj(const ShotDev* __restrict__ shots, int parity, Coefs cf,
+                                                  CpmlGrid g) {
     extern __shared__ float lds[];
     const int S = g.nshots;
     const int* ox = g.off;
@@ -1191,8 +1536,7 @@ __global__ __launch_bounds__(256) void k_cpml(const ShotDev* __restrict__ shots,
     int b = blockIdx.x;
     if (b < ox[S]) {
         const int s = find_shot(ox, S, b);
-        if (ADJ) cpml_x_block_adj(shots[s], parity, cf, b - ox[s], g.rows_per_block, lds);
-        else cpml_x_block<NT>(shots[s], parity, cf, b - ox[s], g.rows_per_block, lds);
+        cpml_x_block_adj(shots[s], parity, cf, b - ox[s], g.rows_per_block, lds);
         return;
     }
     b -= ox[S];
@@ -1206,13 +1550,8 @@ __global__ __launch_bounds__(256) void k_cpml(const ShotDev* __restrict__ shots,
     const int W = ypart ? sd.nz : sd.ny;
     const int xblk = local % xb, rest = local / xb;
     const int w = rest % W, side = rest / W;
-    if (ADJ) {
-        if (ypart) cpml_yz_block_adj<1>(sd, parity, cf, xblk, w, side, lds);
-        else cpml_yz_block_adj<2>(sd, parity, cf, xblk, w, side, lds);
-    } else {
-        if (ypart) cpml_yz_block<1, NT>(sd, parity, cf, xblk, w, side, lds);
-        else cpml_yz_block<2, NT>(sd, parity, cf, xblk, w, side, lds);
-    }
+    if (ypart) cpml_yz_block_adj<1>(sd, parity, cf, xblk, w, side, lds);
+    else cpml_yz_block_adj<2>(sd, parity, cf, xblk, w, side, lds);
 }
 
 int cpml_rows_per_block(int width) { return 256 / (2 * width); }
@@ -1232,11 +1571,11 @@ void cpml_block_table(const int* nx, const int* ny, const int* nz, int nshots, i
     }
 }
 
-hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, bool adjoint, bool stream, const int* block_off_dev,
-                       const int* block_off_host, int parity, const Coefs& cf, hipStream_t s, hipEvent_t ev0) {
+hipError_t launch_cpml_adjoint(const ShotDev* shots, int nshots, int nb, const int* block_off_dev,
+                               const int* block_off_host, int parity, const Coefs& cf, hipStream_t s, hipEvent_t ev0) {
     if (nshots <= 0) return hipSuccess;
-    if (nb < 1 || nb > (adjoint ? 64 : 128)) return hipErrorInvalidValue;
-    const int width = adjoint ? nb + 4 : nb;
+    if (nb < 1 || nb > 64) return hipErrorInvalidValue;
+    const int width = nb + 4;
     CpmlGrid g;
     g.off = block_off_dev;
     g.nshots = nshots;
@@ -1244,16 +1583,11 @@ hipError_t launch_cpml(const ShotDev* shots, int nshots, int nb, bool adjoint, b
     const int S = nshots;
     const long long blocks =
         (long long)block_off_host[S] + block_off_host[(S + 1) + S] + block_off_host[2 * (S + 1) + S];
-    // forward: psi and D2 p of one end [nb][64] (x part: 256); adjoint: three [W][64] arrays (x part: 3 x 256)
-    const size_t fl = adjoint ? 3 * (size_t)std::max(width * 64, 256) : (size_t)std::max(2 * nb * 64, 256);
+    // three [W][64] arrays (x part: 3 x 256)
+    const size_t fl = 3 * (size_t)std::max(width * 64, 256);
     const dim3 grid((unsigned)blocks), block(256);
-    const unsigned lds = (unsigned)(sizeof(float) * fl);
-    if (adjoint)
-        hipExtLaunchKernelGGL(k_cpml<true, false>, grid, block, lds, s, ev0, nullptr, 0, shots, parity, cf, g);
-    else if (stream)
-        hipExtLaunchKernelGGL(k_cpml<false, true>, grid, block, lds, s, ev0, nullptr, 0, shots, parity, cf, g);
-    else
-        hipExtLaunchKernelGGL(k_cpml<false, false>, grid, block, lds, s, ev0, nullptr, 0, shots, parity, cf, g);
+    hipExtLaunchKernelGGL(k_cpml_adj, grid, block, (unsigned)(sizeof(float) * fl), s, ev0, nullptr, 0, shots,
+                          parity, cf, g);
     return hipGetLastError();
 }
 
@@ -1525,5 +1859,7 @@ hipError_t launch_residual_loss(const float* traces, const float* dobs, float* r
     k_sum_final<<<1, 256, 0, s>>>(partial, (int)g.x, loss);
     return hipGetLastError();
 }
+
+
 
 }  // namespace mm

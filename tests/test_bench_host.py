@@ -39,12 +39,14 @@ def test_pmc_summary_scales_by_the_calibration_kernels(tmp_path):
     wl = W.smooth_240()
     n = wl.nx ** 3
     kib = 4.0 * n / 1024.0  # 4 N bytes in KiB
-    step = "void mm::k_step<32, 2, 1, 2, 0, 256, false>(args)"
-    cpml = "void mm::k_cpml<false, false>(args)"
+    step = "void mm::k_step<32, 2, 1, 0, 0, 256, false>(args)"
+    trial = "void mm::k_step<64, 4, 1, 0, 0, 256, false>(args)"  # an autotuner trial: fewer dispatches
+    cpml = "void mm::k_cstep<32, 1, 512, true, 0, false>(args)"
     other = "void mm::k_fill(args)"
     _counter_file(tmp_path / "f", "FETCH_SIZE", [("mm::k_vcheck(args)", 2 * kib), (step, 6 * kib), (step, 8 * kib),
-                                                 (cpml, 2 * kib), (cpml, 2 * kib), (other, 50 * kib)])
-    _counter_file(tmp_path / "w", "WRITE_SIZE", [("mm::k_vdt2(args)", kib), (step, kib), (step, kib),
+                                                 (trial, 99 * kib), (cpml, 2 * kib), (cpml, 2 * kib),
+                                                 (other, 50 * kib)])
+    _counter_file(tmp_path / "w", "WRITE_SIZE", [("mm::k_vdt2(args)", kib), (step, kib), (step, kib), (trial, kib),
                                                  (cpml, 3 * kib), (cpml, 3 * kib), (other, 50 * kib)])
     out = tmp_path / "traffic.json"
     bench.pmc_summary(str(tmp_path / "f"), str(tmp_path / "w"), "smooth240", str(out))

