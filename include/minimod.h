@@ -183,6 +183,23 @@ mm_status mm_init(mm_ctx** out, const mm_params* p, const float* vel_dev, const 
                   int32_t nsrc, const int32_t* rec_ijk_host, int32_t nrec, void* workspace, size_t ws_bytes,
                   void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * as mm_init, with the context's device memory taken from a fixed array of
+ * 64 MiB that the library holds on every GPU it runs on until the process
+ * ends, instead of a caller workspace.  Calls no hipMalloc, hipFree or other
+ * allocating routine and runs no autotuning (p->tile == -1 runs the default
+ * tile variant).  The array is per GPU (the current device) and shared by
+ * every call on that GPU: a later mm_init_static on the same GPU takes it
+ * over, after which the earlier context fails every call except
+ * mm_destroy with MM_ERR_STATE; calls that overlap on one GPU (two threads,
+ * or work of the earlier context still in flight on its stream) race.
+ * Everything the run needs at zero is cleared by this call.  Errors as
+ * mm_init, and MM_ERR_WORKSPACE with the sizes in mm_last_error(NULL) when
+ * mm_workspace_size of the problem exceeds 64 MiB. */
+mm_status mm_init_static(mm_ctx** out, const mm_params* p, const float* vel_dev, const int32_t* src_ijk_host,
+                         int32_t nsrc, const int32_t* rec_ijk_host, int32_t nrec, void* hip_stream);
+
 /* Advance nsteps steps.  wavelet: device [nsteps][nsrc_total] raw samples
  * (may be NULL only if nsrc_total == 0).  traces: device
  * [nsteps][nrec_total] or NULL.  If the context was made with

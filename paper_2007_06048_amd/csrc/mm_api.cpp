@@ -420,6 +420,10 @@ struct mm_ctx {
     std::string err;
     // host tables kept alive until their uploads complete
     std::vector<char> host_tables;
+    // mm_init_static: the device whose static workspace holds the context, and the
+    // take-over count of that workspace when the context was made (0: caller's workspace)
+    int static_dev = -1;
+    unsigned long long static_gen = 0;
     // stencil timing
     int prof_stride = 0;
     long long prof_count = 0;
@@ -438,6 +442,19 @@ mm_status fail(mm_ctx* c, mm_status s, const std::string& msg) {
 mm_status dev(mm_ctx* c, hipError_t e, const char* what) {
     if (e == hipSuccess) return MM_OK;
     return fail(c, MM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Take-overs of each GPU's static workspace: a context made by mm_init_static
+// stays usable until the next mm_init_static on the same GPU.
+std::mutex g_static_mu;
+unsigned long long g_static_gen[64] = {};
+
+mm_status live(mm_ctx* c) {
+    if (!c || c->static_dev < 0) return MM_OK;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static_gen[c->static_dev] != c->static_gen)
+        return fail(c, MM_ERR_STATE, "the static workspace of this GPU was taken over by a later mm_init_static");
+    return MM_OK;
 }
 
 #define MM_TRY(expr)                 \
@@ -872,6 +889,7 @@ mm_status enqueue_forward(mm_ctx* c, int nsteps, const float* wav, float* traces
 
 mm_status check_forward(mm_ctx* c, int nsteps, const float* wav) {
     if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
+    MM_TRY(live(c));
     if (nsteps < 0) return fail(c, MM_ERR_ARG, "nsteps must be >= 0");
     if (c->nsrc > 0 && nsteps > 0 && !wav) return fail(c, MM_ERR_ARG, "wavelet is NULL");
     if (!c->fwd_valid)
@@ -1351,6 +1369,44 @@ mm_status mm_init(mm_ctx** out, const mm_params* p, const float* vel_dev, const 
     return mm_init_batch(out, p, 1, &s, workspace, ws_bytes, hip_stream);
 }
 
+mm_status mm_init_static(mm_ctx** out, const mm_params* p, const float* vel_dev, const int32_t* src, int32_t nsrc,
+                         const int32_t* rec, int32_t nrec, void* hip_stream) {
+    if (!out) return fail(nullptr, MM_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!p) return fail(nullptr, MM_ERR_ARG, "params is NULL");
+    mm_shot shot{p->nx, p->ny, p->nz, vel_dev, src, nsrc, rec, nrec, nullptr};
+    size_t need = 0;
+    MM_TRY(mm_workspace_size(p, 1, &shot, &need));
+    const size_t have = static_workspace_bytes();
+    if (need > have) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "the problem needs %zu bytes of device memory; the static workspace holds %zu", need,
+                 have);
+        return fail(nullptr, MM_ERR_WORKSPACE, buf);
+    }
+    int d = -1;
+    hipError_t e = hipGetDevice(&d);
+    if (e != hipSuccess) return fail(nullptr, MM_ERR_DEVICE, std::string("device: ") + hipGetErrorString(e));
+    if (d < 0 || d >= 64) return fail(nullptr, MM_ERR_DEVICE, "device index out of range");
+    void* ws = nullptr;
+    e = static_workspace(&ws);
+    if (e != hipSuccess) return fail(nullptr, MM_ERR_DEVICE, std::string("static workspace: ") + hipGetErrorString(e));
+    // no autotuning (its trials create HIP events): tile -1 runs the default variant
+    mm_params q = *p;
+    if (q.tile == -1) q.tile = 0;
+    unsigned long long gen;
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        gen = ++g_static_gen[d];  // earlier static contexts on this GPU stop here
+    }
+    mm_ctx* c = nullptr;
+    MM_TRY(mm_init_batch(&c, &q, 1, &shot, ws, have, hip_stream));
+    c->static_dev = d;
+    c->static_gen = gen;
+    *out = c;
+    return MM_OK;
+}
+
 mm_status mm_forward_steps(mm_ctx* c, int32_t nsteps, const float* wav, float* traces) {
     MM_TRY(check_forward(c, nsteps, wav));
     begin_forward(c, nsteps);
@@ -1399,6 +1455,7 @@ mm_status mm_forward_steps_graph(mm_ctx* c, int32_t nsteps, const float* wav, fl
 
 mm_status mm_adjoint_steps(mm_ctx* c, int32_t nsteps, const float* resid, float* adj_src, float* grad) {
     if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
+    MM_TRY(live(c));
     if (!c->L.adjoint) return fail(c, MM_ERR_STATE, "context was created with ckpt_every = 0 (no adjoint storage)");
     if (nsteps < 0) return fail(c, MM_ERR_ARG, "nsteps must be >= 0");
     if (c->nrec > 0 && nsteps > 0 && !resid) return fail(c, MM_ERR_ARG, "residual is NULL");
@@ -1425,6 +1482,7 @@ mm_status mm_adjoint_steps(mm_ctx* c, int32_t nsteps, const float* resid, float*
 
 mm_status mm_reset(mm_ctx* c) {
     if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
+    MM_TRY(live(c));
     MM_TRY(zero_state(c, c->stream));
     if (c->L.adjoint) MM_TRY(zero_adjoint(c, c->stream));
     c->step = 0;
@@ -1438,6 +1496,7 @@ mm_status mm_reset(mm_ctx* c) {
 mm_status mm_gradient(mm_ctx* c, int32_t nsteps, const float* wav, const float* d_obs, float* grad, float* traces,
                       double* loss_host) {
     if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
+    MM_TRY(live(c));
     if (!c->L.grad) return fail(c, MM_ERR_STATE, "gradients need a single-shot context with ckpt_every > 0");
     if (nsteps < 1 || nsteps > c->p.nsteps_max) return fail(c, MM_ERR_ARG, "nsteps must be in [1, nsteps_max]");
     if (!grad || (c->nrec > 0 && !d_obs) || (c->nsrc > 0 && !wav)) return fail(c, MM_ERR_ARG, "NULL operand");
@@ -1529,12 +1588,14 @@ static mm_status state_copy(mm_ctx* c, char* ext, bool to_ext) {
 
 mm_status mm_get_state(mm_ctx* c, void* dst) {
     if (!c || !dst) return fail(c, MM_ERR_ARG, "NULL argument");
+    MM_TRY(live(c));
     if (!c->fwd_valid) return fail(c, MM_ERR_STATE, "forward state was consumed by a gradient replay");
     return state_copy(c, reinterpret_cast<char*>(dst), true);
 }
 
 mm_status mm_set_state(mm_ctx* c, const void* src, int32_t step) {
     if (!c || !src) return fail(c, MM_ERR_ARG, "NULL argument");
+    MM_TRY(live(c));
     if (step < 0) return fail(c, MM_ERR_ARG, "step must be >= 0");
     c->step = step;
     c->fwd_valid = true;
@@ -1567,6 +1628,7 @@ const char* mm_tile_name(int32_t t) { return (t >= 0 && t < num_tile_variants())
 
 mm_status mm_set_tile(mm_ctx* c, int32_t t) {
     if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
+    MM_TRY(live(c));
     if (t < 0 || t >= num_tile_variants()) return fail(c, MM_ERR_ARG, "unknown tile variant");
     if (c->iso && !iso_variant_ok(t)) return fail(c, MM_ERR_ARG, "acoustic_iso runs the 256-thread tile variants only");
     drop_graph(c);
@@ -1575,6 +1637,7 @@ mm_status mm_set_tile(mm_ctx* c, int32_t t) {
 
 mm_status mm_autotune(mm_ctx* c, int32_t steps, int32_t* tile_out) {
     if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
+    MM_TRY(live(c));
     if (steps < 1) return fail(c, MM_ERR_ARG, "steps_per_trial must be >= 1");
     hipEvent_t e0, e1;
     MM_TRY(dev(c, hipEventCreate(&e0), "event"));

@@ -169,4 +169,8 @@ hipError_t launch_snap_decode(const uint16_t* c0, const uint16_t* c1, const floa
 hipError_t launch_residual_loss(const float* traces, const float* dobs, float* resid, long long n,
                                 double* partial, int nparts, double* loss, hipStream_t s);
 
+// Device address of this GPU's static workspace (mm_init_static) and its size.
+hipError_t static_workspace(void** out);
+size_t static_workspace_bytes();
+
 }  // namespace mm

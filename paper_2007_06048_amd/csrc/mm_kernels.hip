@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "mm_internal.h"
 
@@ -1861,5 +1862,38 @@ hipError_t launch_residual_loss(const float* traces, const float* dobs, float* r
 }
 
 
+
+// --------------------------------------------------------- static workspace
+//
+// Device memory of the contexts made by mm_init_static, for callers that
+// cannot allocate: one array per GPU, which that GPU holds until the process
+// ends.  Host code must not use the array's name as an address (on the host
+// it is a stand-in symbol); static_workspace looks up its device address
+// once per device, with that device current, and keeps it.
+constexpr size_t kStaticWorkspaceBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kStaticWorkspaceBytes];
+
+size_t static_workspace_bytes() { return kStaticWorkspaceBytes; }
+
+hipError_t static_workspace(void** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    *out = nullptr;
+    int d = -1;
+    hipError_t e = hipGetDevice(&d);
+    if (e != hipSuccess) return e;
+    if (d < 0 || d >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[d]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[d] = p;
+    }
+    *out = addr[d];
+    return hipSuccess;
+}
 
 }  // namespace mm

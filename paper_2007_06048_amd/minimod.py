@@ -24,7 +24,7 @@ SYMBOLS = [
     "mm_forward_steps", "mm_forward_steps_graph", "mm_adjoint_steps", "mm_gradient", "mm_reset",
     "mm_state_size", "mm_get_state", "mm_set_state", "mm_get_info", "mm_autotune", "mm_set_tile",
     "mm_num_tiles", "mm_tile_name", "mm_profile", "mm_profile_read", "mm_destroy", "mm_status_str",
-    "mm_last_error", "mm_snap_blocks", "mm_snap_encode", "mm_snap_decode",
+    "mm_last_error", "mm_snap_blocks", "mm_snap_encode", "mm_snap_decode", "mm_init_static",
 ]
 
 
@@ -98,6 +98,7 @@ def load():
         "mm_status_str": (ctypes.c_char_p, [st]),
         "mm_last_error": (ctypes.c_char_p, [vp]),
         "mm_snap_blocks": (ctypes.c_int64, [ctypes.c_int64]),
+        "mm_init_static": (st, [ctypes.POINTER(vp), pp, vp, ctypes.POINTER(i32), i32, ctypes.POINTER(i32), i32, vp]),
         "mm_snap_encode": (st, [vp, vp, ctypes.c_int64, vp, vp, vp, vp, vp]),
         "mm_snap_decode": (st, [vp, vp, vp, vp, ctypes.c_int64, vp, vp, vp]),
     }
@@ -201,6 +202,31 @@ class Context:
     @classmethod
     def single(cls, params, vel, src, rec, stream=None, rho=None):
         return cls(params, [(vel, src, rec) if rho is None else (vel, src, rec, rho)], stream)
+
+    @classmethod
+    def static(cls, params, vel, src, rec, stream=None):
+        """A single-shot context in the library's static per-GPU workspace
+        (mm_init_static): no device allocation here or in the library."""
+        import torch
+        self = cls.__new__(cls)
+        assert vel.is_cuda and vel.dtype == torch.float32 and vel.is_contiguous() and vel.dim() == 3
+        s, r = _pts(src), _pts(rec)
+        self.params = params
+        self._keep = [vel, s, r]
+        self.nsrc, self.nrec = len(s), len(r)
+        self.shapes = [tuple(vel.shape)]
+        self.device = vel.device
+        self.iso = params.model == MODEL_ISO
+        self.ws_bytes = 0
+        self.workspace = None
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(load().mm_init_static(ctypes.byref(h), ctypes.byref(params), ctypes.c_void_p(vel.data_ptr()),
+                                     s.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(s),
+                                     r.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(r),
+                                     ctypes.c_void_p(self.stream.cuda_stream)))
+        self.h = h
+        return self
 
     def __del__(self):
         h = getattr(self, "h", None)
