@@ -109,6 +109,8 @@ def lib():
         L.orc_iso_dplus.argtypes = [gp, dp, ctypes.c_int, dp]
         L.orc_iso_forward.restype = ctypes.c_int
         L.orc_iso_forward.argtypes = [gp, fp, dp, ctypes.c_int, ip, dp, ctypes.c_int, ip, ctypes.c_int, dp, dp]
+        L.orc_iso_cpml_coeffs.restype = None
+        L.orc_iso_cpml_coeffs.argtypes = [gp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
         L.orc_iso_energy.restype = ctypes.c_double
         L.orc_iso_energy.argtypes = [gp, fp, dp, dp, dp, dp]
         _lib = L
@@ -276,17 +278,29 @@ def iso_dplus(g: Grid, f, ax):
     return out
 
 
+def iso_cpml_coeffs(g: Grid, axis, k, face):
+    """acoustic_iso CPML (a, b) of axis `axis` at cell k (face=0) or at the
+    face k + 1/2 (face=1)."""
+    a = ctypes.c_double()
+    b = ctypes.c_double()
+    lib().orc_iso_cpml_coeffs(ctypes.byref(g._c()), axis, k, int(face), ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
 def iso_forward(g: Grid, vel, rho, src, wav, rec, T, state=None):
     """acoustic_iso run of T steps.  state = [4][nz][ny][nx] (p^n, u_x, u_y,
-    u_z at n-1/2; u_x[k][j][i] is the face i+1/2), zero if None.  Returns
-    (traces [T][nrec], end state)."""
+    u_z at n-1/2; u_x[k][j][i] is the face i+1/2), and with CPML six more
+    (psi_px, psi_py, psi_pz at the faces, psi_ux, psi_uy, psi_uz at the
+    cells), zero if None.  Returns (traces [T][nrec], end state)."""
     vel = _vel(g, vel)
     rho = _vel(g, rho)
     src = _pts(src)
     rec = _pts(rec)
     nsrc, nrec = len(src), len(rec)
     wav = np.ascontiguousarray(np.asarray(wav, dtype=np.float64).reshape(T, nsrc)) if nsrc else np.zeros((T, 0))
-    st = np.zeros((4,) + g.shape) if state is None else np.array(state, dtype=np.float64, order="C")
+    nst = 10 if g.bc == BC_CPML else 4
+    st = np.zeros((nst,) + g.shape) if state is None else np.array(state, dtype=np.float64, order="C")
+    assert st.shape == (nst,) + g.shape, st.shape
     traces = np.zeros((T, nrec))
     rc = lib().orc_iso_forward(ctypes.byref(g._c()), _f(vel), _d(rho), nsrc, _i(src), _d(wav), nrec, _i(rec), T,
                                _d(traces), _d(st))

@@ -768,8 +768,20 @@ void orc_set_num_threads(int n) {
  *  - free surface (as for acoustic_iso_cd): p = 0 on the plane k = 0, p odd
  *    about it above (so the p-derivative faces see -p(-k)), u_z even about
  *    it, no damping layer on the top face; sources and receivers on the
- *    plane inject and record nothing.
- * CPML is not defined for this propagator here.
+ *    plane inject and record nothing;
+ *  - CPML (section "Finite Differences": every propagator has CPML
+ *    boundaries): the first-order convolutional PML with kappa = 1.  Inside
+ *    the layers each first derivative gains a memory variable updated by
+ *    the recursive convolution psi <- b psi + a (that derivative):
+ *      u_a^{n+1/2} = u_a^{n-1/2} + dt b (D+_a p^n + psi_pa),
+ *        psi_pa <- bf psi_pa + af D+_a p^n          (at the faces),
+ *      p^{n+1} = p^n + dt K (sum_a (D-_a u_a^{n+1/2} + psi_ua) + s^n),
+ *        psi_ua <- bc psi_ua + ac D-_a u_a^{n+1/2}  (at the cells),
+ *    with d, alpha, b = exp(-(d + alpha) dt), a = d (b - 1)/(d + alpha) as
+ *    for acoustic_iso_cd, evaluated at the position of the quantity: a cell
+ *    at depth nb - k inside the low layer (k - (n - 1 - nb) inside the high
+ *    one), a face i + 1/2 at depth nb - i - 1/2 (i + 1/2 - (n - 1 - nb)),
+ *    q = depth / nb clamped to 1 (the face beyond the last cell).
  */
 static const double C8[5] = {0.0, 1225.0 / 1024.0, -245.0 / 3072.0, 49.0 / 5120.0, -5.0 / 7168.0};
 
@@ -833,20 +845,62 @@ void orc_iso_dplus(const orc_grid* g, const double* p, int ax, double* out) {
 
 static int iso_check(const orc_grid* g) {
     if (check_grid(g) || g->wnx > 0) return ORC_ERR_ARG;
-    if (g->bc == BC_CPML || (g->fs && g->bc == BC_PERIODIC)) return ORC_ERR_UNSUPPORTED;
+    if (g->fs && g->bc == BC_PERIODIC) return ORC_ERR_UNSUPPORTED;
     return ORC_OK;
 }
 
-/* acoustic_iso forward run for T steps.  state (4N: p^n, u_x, u_y, u_z at
- * n-1/2) is the start state and receives the end state; NULL starts from
- * zero.  wav [T][nsrc], traces [T][nrec] (may be NULL). */
+/* CPML coefficients at a position of the given depth (in cells) inside the
+ * layer of axis ax; depth 0: outside (a = 0, b = 1). */
+static int cpml_ab_depth(const orc_grid* g, int ax, double depth, double* a, double* b) {
+    if (depth <= 0.0) {
+        *a = 0.0;
+        *b = 1.0;
+        return 0;
+    }
+    const double pi = 3.14159265358979323846;
+    double h = axis_h(g, ax);
+    double q = depth / g->nb;
+    if (q > 1.0) q = 1.0;
+    double d0 = -3.0 * g->vmax * log(g->R) / (2.0 * g->nb * h);
+    double dq = d0 * q * q;
+    double al = pi * g->f0 * (1.0 - q);
+    double bb = exp(-(dq + al) * g->dt);
+    *b = bb;
+    *a = (dq + al) > 0.0 ? dq * (bb - 1.0) / (dq + al) : 0.0;
+    return 1;
+}
+
+/* Depth of the face i + 1/2 of axis ax inside its damping layers (0 outside);
+ * no layer on the top face under a free surface. */
+static double face_depth(const orc_grid* g, int ax, int i) {
+    int n = ax == 0 ? g->nx : (ax == 1 ? g->ny : g->nz);
+    double lo = g->nb - i - 0.5;
+    if (g->fs && ax == 2) lo = 0.0;
+    double hi = i + 0.5 - (n - 1 - g->nb);
+    double d = lo > hi ? lo : hi;
+    return d > 0.0 ? d : 0.0;
+}
+
+/* acoustic_iso CPML coefficients of axis ax at index k: cell (face = 0) or
+ * face k + 1/2 (face = 1) (test access to the profiles). */
+void orc_iso_cpml_coeffs(const orc_grid* g, int ax, int k, int face, double* a, double* b) {
+    double depth = face ? face_depth(g, ax, k) : (double)axis_depth(g, ax, k);
+    cpml_ab_depth(g, ax, depth, a, b);
+}
+
+/* acoustic_iso forward run for T steps.  state (p^n, u_x, u_y, u_z at
+ * n-1/2, then with CPML psi_px, psi_py, psi_pz at the faces and psi_ux,
+ * psi_uy, psi_uz at the cells: 4N, or 10N with CPML) is the start state and
+ * receives the end state; NULL starts from zero.  wav [T][nsrc], traces
+ * [T][nrec] (may be NULL). */
 int orc_iso_forward(const orc_grid* g, const double* vel, const double* rho, int nsrc, const int* src,
                     const double* wav, int nrec, const int* rec, int T, double* traces, double* state) {
     int rc = iso_check(g);
     if (rc) return rc;
     if (T < 0 || nsrc < 0 || nrec < 0 || check_pts(g, nsrc, src) || check_pts(g, nrec, rec)) return ORC_ERR_ARG;
     size_t N = npts(g);
-    double* st = state ? state : alloc_d(4 * N);
+    const int cpml = g->bc == BC_CPML;
+    double* st = state ? state : alloc_d((cpml ? 10 : 4) * N);
     double* pn = alloc_d(N);
     double* S = alloc_d(N);
     if (!st || !pn || !S) {
@@ -856,6 +910,8 @@ int orc_iso_forward(const orc_grid* g, const double* vel, const double* rho, int
     }
     double* p = st;
     double* u[3] = {st + N, st + 2 * N, st + 3 * N};
+    double* psi_p[3] = {st + 4 * N, st + 5 * N, st + 6 * N};  /* CPML only */
+    double* psi_u[3] = {st + 7 * N, st + 8 * N, st + 9 * N};
     double inv_vol = 1.0 / (g->hx * g->hy * g->hz);
     for (int n = 0; n < T; ++n) {
         /* u^{n+1/2} from p^n */
@@ -866,7 +922,16 @@ int orc_iso_forward(const orc_grid* g, const double* vel, const double* rho, int
                     for (int i = 0; i < g->nx; ++i) {
                         size_t id = lin(g, i, j, k);
                         double G = orc_sponge_G(g, i, j, k);
-                        u[ax][id] = G * (u[ax][id] + g->dt * face_b(g, rho, i, j, k, ax) * dplus(g, p, i, j, k, ax));
+                        double dp = dplus(g, p, i, j, k, ax);
+                        if (cpml) {
+                            double a, b;
+                            int pos = ax == 0 ? i : (ax == 1 ? j : k);
+                            if (cpml_ab_depth(g, ax, face_depth(g, ax, pos), &a, &b)) {
+                                psi_p[ax][id] = b * psi_p[ax][id] + a * dp;
+                                dp += psi_p[ax][id];
+                            }
+                        }
+                        u[ax][id] = G * (u[ax][id] + g->dt * face_b(g, rho, i, j, k, ax) * dp);
                     }
         }
         /* p^{n+1} from p^n, u^{n+1/2} and s^n */
@@ -880,7 +945,19 @@ int orc_iso_forward(const orc_grid* g, const double* vel, const double* rho, int
                     size_t id = lin(g, i, j, k);
                     double G = orc_sponge_G(g, i, j, k);
                     double K = rho[id] * vel[id] * vel[id];
-                    double div = dminus(g, u[0], i, j, k, 0) + dminus(g, u[1], i, j, k, 1) + dminus(g, u[2], i, j, k, 2);
+                    double du[3];
+                    for (int ax = 0; ax < 3; ++ax) {
+                        du[ax] = dminus(g, u[ax], i, j, k, ax);
+                        if (cpml) {
+                            double a, b;
+                            int pos = ax == 0 ? i : (ax == 1 ? j : k);
+                            if (cpml_ab_depth(g, ax, (double)axis_depth(g, ax, pos), &a, &b)) {
+                                psi_u[ax][id] = b * psi_u[ax][id] + a * du[ax];
+                                du[ax] += psi_u[ax][id];
+                            }
+                        }
+                    }
+                    double div = du[0] + du[1] + du[2];
                     pn[id] = G * (p[id] + g->dt * K * (div + S[id]));
                     if (g->fs && k == 0) pn[id] = 0.0; /* pressure release: p = 0 on the surface plane */
                 }

@@ -5,6 +5,7 @@ exact discrete energy conservation, the exact evolution of a Fourier mode, and
 the equivalence with a second-order scheme for constant density (an
 independent numpy restatement)."""
 import json
+import math
 import os
 
 import numpy as np
@@ -189,11 +190,113 @@ def test_iso_sponge_with_zero_strength_is_bc_none_and_sponge_absorbs():
     assert np.abs(sc[0]).max() < 0.2 * np.abs(sd[0]).max()
 
 
-def test_iso_rejects_cpml():
-    g = C.Grid(10, 10, 10, 10.0, 10.0, 10.0, 1e-4, bc=C.BC_CPML, nb=2)
-    with pytest.raises(RuntimeError):
-        C.iso_forward(g, np.full((10, 10, 10), 2000.0), np.full((10, 10, 10), 1000.0), [[5, 5, 5]],
-                      np.zeros((2, 1)), [[5, 5, 5]], 2)
+def test_iso_cpml_with_no_damping_is_bc_none():
+    """CPML with R = 1 (d0 = 0) and f0 = 0 (alpha = 0) has a = 0, b = 1: the
+    memory variables stay zero and the run equals bc none bitwise (pressure,
+    velocities, traces), with and without a free surface."""
+    rng = np.random.default_rng(81)
+    shape = (15, 16, 17)
+    v, rho = _model(rng, shape)
+    h = (10.0, 11.0, 9.0)
+    dt = 0.5 * C.iso_dt_stab(v.max(), *h)
+    T = 50
+    w = rng.standard_normal((T, 2))
+    src, rec = [[8, 7, 6], [2, 3, 1]], [[1, 1, 1], [15, 14, 13], [8, 8, 0]]
+    for fs in (0, 1):
+        g0 = C.Grid(shape[2], shape[1], shape[0], *h, dt, fs=fs)
+        gc = C.Grid(shape[2], shape[1], shape[0], *h, dt, bc=C.BC_CPML, nb=4, R=1.0, f0=0.0, vmax=v.max(), fs=fs)
+        a, sa = C.iso_forward(g0, v, rho, src, w, rec, T)
+        b, sb = C.iso_forward(gc, v, rho, src, w, rec, T)
+        assert np.array_equal(a, b) and np.array_equal(sa, sb[:4])
+        assert not np.any(sb[4:])
+
+
+def _iso_reflection(bc, nb):
+    """Largest difference, at receivers inside the undamped core, between a
+    40^3 run with the given boundary and a run on a 100^3 grid whose own
+    boundary is too far to be seen in the window, relative to the peak of
+    the direct wave there (constant v and rho)."""
+    n_small, margin = 40, 30
+    hh = 10.0
+    c = 2000.0
+    f0 = 25.0
+    dt = 0.5 * C.iso_dt_stab(c, hh, hh, hh)
+    T = int(0.3 / dt)  # 0.3 s: the reflection from the 40^3 boundary arrives, not the one from the 100^3 boundary
+    w = C.ricker(f0, 1.5 / f0, dt, T)[:, None]
+    ctr = n_small // 2
+    off = [(6, 0, 0), (0, -6, 0), (0, 0, 6), (4, 4, 4), (-5, 3, 0)]
+    rec = [[ctr + a, ctr + b, ctr + c_] for a, b, c_ in off]
+    g = C.Grid(n_small, n_small, n_small, hh, hh, hh, dt, bc=bc, nb=nb, R=1e-3, f0=f0, vmax=c)
+    shp = g.shape
+    small, _ = C.iso_forward(g, np.full(shp, c), np.full(shp, 1500.0), [[ctr] * 3], w, rec, T)
+    nbig = n_small + 2 * margin
+    gb = C.Grid(nbig, nbig, nbig, hh, hh, hh, dt)
+    rec_b = [[x + margin for x in r] for r in rec]
+    big, _ = C.iso_forward(gb, np.full(gb.shape, c), np.full(gb.shape, 1500.0), [[ctr + margin] * 3], w, rec_b, T)
+    return np.abs(small - big).max() / np.abs(big).max()
+
+
+@pytest.mark.slow
+def test_iso_cpml_absorbs():
+    """CPML leaves a reflection far below that of the zero-ghost boundary, and
+    a wider layer absorbs better (as for the constant-density propagator)."""
+    r_none = _iso_reflection(C.BC_NONE, 10)
+    r10 = _iso_reflection(C.BC_CPML, 10)
+    r5 = _iso_reflection(C.BC_CPML, 5)
+    assert r_none > 0.05, r_none
+    assert r10 < 2e-2 and r10 < 0.1 * r_none, (r10, r_none)
+    assert r10 < r5, (r10, r5)
+
+
+@pytest.mark.parametrize("nb,h,vmax,R", [(20, 10.0, 4500.0, 1e-3), (32, 12.5, 5000.0, 1e-4)])
+def test_iso_cpml_profiles_match_pml_reflection_theory(nb, h, vmax, R):
+    """The damping d recovered from (a, b) at the cells and at the faces (b =
+    exp(-(d + alpha) dt), a / (b - 1) = d / (d + alpha)) against PML theory:
+    R = exp(-(2 / c) * integral of d over the layer), so the layer sums of
+    d h over the cells (depths 1 .. nb) and over the faces (depths 1/2 ..
+    nb - 1/2) must give ln R within the quadrature errors of a quadratic
+    profile sampled at those points: the cell sum overshoots the integral by
+    (1 + 3/(2 nb) + 1/(2 nb^2)), the face (midpoint) sum undershoots it by
+    (1 - 1/(4 nb^2)).  alpha is pi f0 at the interface falling linearly to 0
+    at the outer edge, both ends agree at the same depth, the face beyond the
+    last cell takes the outermost value, and outside the layers a = 0, b = 1."""
+    f0 = 17.0
+    n = 2 * nb + 11
+    dt = 1e-4
+    hs = (h, 0.8 * h, 1.3 * h)
+    g = C.Grid(n, n + 1, n + 2, hs[0], hs[1], hs[2], dt, bc=C.BC_CPML, nb=nb, R=R, f0=f0, vmax=vmax)
+
+    def d_alpha(ab):
+        a, b = ab
+        sgm = -math.log(b) / dt
+        d = a / (b - 1.0) * sgm
+        return d, sgm - d
+
+    for ax in range(3):
+        na = (n, n + 1, n + 2)[ax]
+        sums = []
+        for face in (0, 1):
+            tot = 0.0
+            for j in range(1, nb + 1):
+                # depth j (cells) or j - 1/2 (faces): index nb - j from the low end
+                lo = C.iso_cpml_coeffs(g, ax, nb - j, face)
+                hi = C.iso_cpml_coeffs(g, ax, na - 1 - (nb - j) - face, face)
+                assert lo == pytest.approx(hi, rel=1e-12, abs=1e-15)
+                d, alpha = d_alpha(lo)
+                q = (j - 0.5 * face) / nb
+                assert alpha == pytest.approx(math.pi * f0 * (1.0 - q), rel=1e-9, abs=1e-9)
+                tot += d * hs[ax]
+            sums.append((-2.0 / vmax * tot) / math.log(R))
+            assert C.iso_cpml_coeffs(g, ax, nb + face * 0, 0) == (0.0, 1.0)
+        assert sums[0] == pytest.approx((nb + 1) * (2 * nb + 1) / (2.0 * nb * nb), rel=1e-9), (ax, sums)
+        assert sums[1] == pytest.approx(1.0 - 1.0 / (4.0 * nb * nb), rel=1e-9), (ax, sums)
+        # the face beyond the last cell and the last cell carry the outermost coefficients
+        assert C.iso_cpml_coeffs(g, ax, na - 1, 1) == pytest.approx(C.iso_cpml_coeffs(g, ax, na - 1, 0), rel=1e-12)
+        # the faces just inside the layers: depth 1/2
+        assert C.iso_cpml_coeffs(g, ax, nb, 1) == (0.0, 1.0)
+        assert C.iso_cpml_coeffs(g, ax, nb - 1, 1) != (0.0, 1.0)
+        assert C.iso_cpml_coeffs(g, ax, na - 1 - nb, 1) != (0.0, 1.0)
+        assert C.iso_cpml_coeffs(g, ax, na - 2 - nb, 1) == (0.0, 1.0)
 
 
 def _mirror_z(a, nz):
