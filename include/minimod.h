@@ -96,8 +96,12 @@ typedef enum { MM_BC_NONE = 0, MM_BC_SPONGE = 1, MM_BC_CPML = 2 } mm_bc;
  *    the two cells beside the face (1/rho of the inner cell on the last
  *    face), G the cell's sponge factor;
  *    dt = cfl / (C vmax sqrt(dx^-2 + dy^-2 + dz^-2)), C = 2161/1680.
- *    Forward modelling only, bc none or sponge, with or without the free
- *    surface (p = 0 on the top plane and odd above it, u_z even about it). */
+ *    Forward modelling only, bc none, sponge or CPML, with or without the
+ *    free surface (p = 0 on the top plane and odd above it, u_z even about
+ *    it).  CPML (section "Finite Differences"): inside the layers D+ p (at
+ *    the faces) and D- u (at the cells) each gain a memory psi <- b psi + a
+ *    (that derivative), with the coefficients of the constant-density CPML
+ *    evaluated at the face's or cell's own depth in the layer. */
 typedef enum { MM_MODEL_ISO_CD = 0, MM_MODEL_ISO = 1 } mm_model;
 
 /* Snapshot storage of the gradient's checkpoints. */
@@ -139,6 +143,11 @@ typedef struct {
                                 shot of a launch exceeds the 256 MiB Infinity Cache), 1 never,
                                 2 always.  Results are bitwise the same either way; only the speed
                                 differs. */
+    int32_t watch_every;     /* > 0: after every watch_every-th forward step (counted from step 0)
+                                the new wavefield of every shot is scanned for NaN or Inf on the
+                                device (one extra read of the field, no synchronisation); the first
+                                such step is kept and reported by mm_watch (and by mm_gradient) as
+                                MM_ERR_NONFINITE.  0 => off */
 } mm_params;
 
 /* One shot of a batched context. */
@@ -262,6 +271,13 @@ mm_status mm_snap_encode(const float* prev_dev, const float* cur_dev, int64_t n,
                          uint16_t* c1_dev, float* s0_dev, float* s1_dev, void* stream);
 mm_status mm_snap_decode(const uint16_t* c0_dev, const uint16_t* c1_dev, const float* s0_dev, const float* s1_dev,
                          int64_t n, float* prev_dev, float* cur_dev, void* stream);
+
+/* Result of the watchdog (mm_params.watch_every): synchronises the context's
+ * stream and returns MM_ERR_NONFINITE if a scanned wavefield held NaN or Inf
+ * (*bad_step, if not NULL, receives the first such step: the state after it),
+ * else MM_OK with *bad_step = -1.  The finding stays until mm_reset or
+ * mm_set_state.  MM_ERR_STATE if the context was made with watch_every = 0. */
+mm_status mm_watch(mm_ctx* ctx, int32_t* bad_step);
 
 /* Size of the state blob of mm_get_state / mm_set_state, in bytes. */
 mm_status mm_state_size(const mm_ctx* ctx, size_t* bytes);

@@ -37,14 +37,17 @@ struct ShotGeom {
     long long n() const { return (long long)nx * ny * nz; }
 };
 
+// Cells per end of the CPML memory slabs: the layer width, and one more for
+// acoustic_iso, whose high end has a layer face beyond the last cell.
+int mem_width(const mm_params& p) { return p.model == MM_MODEL_ISO ? p.nb + 1 : p.nb; }
+
 // Bytes one forward step of a shot touches: three fields, and for CPML the
 // memory (psi, zeta) and correction slabs; acoustic_iso: two pressure fields,
 // three face velocities, dt rho v^2 and rho / dt.
 double shot_set_bytes(const mm_params& p, const ShotGeom& q) {
-    if (p.model == MM_MODEL_ISO) return 28.0 * q.n();
-    double b = 12.0 * q.n();
+    double b = p.model == MM_MODEL_ISO ? 28.0 * q.n() : 12.0 * q.n();
     if (p.bc == MM_BC_CPML) {
-        const double nb2 = 2.0 * p.nb;
+        const double nb2 = 2.0 * mem_width(p);
         b += 12.0 * ((double)q.nz * q.ny * nb2 + (double)q.nz * nb2 * q.nx + nb2 * q.ny * q.nx);
     }
     return b;
@@ -249,17 +252,18 @@ void compute_layout(const mm_params& p, const std::vector<ShotGeom>& shots, int 
         L.buf0.push_back(take(L, fb));
         L.buf1.push_back(take(L, fb));
         L.vdt2.push_back(take(L, fb));
-        const int np = p.bc == MM_BC_CPML ? 2 * (g.nx + g.ny + g.nz) : (g.nx + g.ny + g.nz);
+        const int np = (p.bc == MM_BC_CPML ? (p.model == MM_MODEL_ISO ? 4 : 2) : 1) * (g.nx + g.ny + g.nz);
         L.prof.push_back(take(L, sizeof(float) * np));
-        const size_t nb2 = 2 * (size_t)std::max(p.nb, 0);
+        const size_t nb2 = 2 * (size_t)std::max(mem_width(p), 0);
         const size_t sl[3] = {(size_t)g.nz * g.ny * nb2, (size_t)g.nz * nb2 * g.nx, nb2 * g.ny * g.nx};
-        const size_t w2 = nb2 + 8;  // adjoint corrections: nb + 4 cells per end
+        const size_t w2 = 2 * (size_t)std::max(p.nb, 0) + 8;  // adjoint corrections: nb + 4 cells per end
         const size_t wl[3] = {(size_t)g.nz * g.ny * w2, (size_t)g.nz * w2 * g.nx, w2 * g.ny * g.nx};
         const bool c = p.bc == MM_BC_CPML, ca = c && L.adjoint;
         for (int a = 0; a < 3; ++a) {
             L.psi[a].push_back(c ? take(L, sizeof(float) * sl[a]) : 0);
             L.zeta[a].push_back(c ? take(L, sizeof(float) * sl[a]) : 0);
-            L.corr[a].push_back(c ? take(L, sizeof(float) * sl[a]) : 0);
+            // the second psi buffer of the forward CPML step (acoustic_iso updates its memory in place)
+            L.corr[a].push_back(c && p.model != MM_MODEL_ISO ? take(L, sizeof(float) * sl[a]) : 0);
             L.apsi[a].push_back(ca ? take(L, sizeof(float) * sl[a]) : 0);
             L.azeta[a].push_back(ca ? take(L, sizeof(float) * sl[a]) : 0);
             L.acorr[a].push_back(ca ? take(L, sizeof(float) * wl[a]) : 0);
@@ -340,6 +344,27 @@ void cpml_table(int n, int nb, double h, double dt, double vmax, double R, doubl
     }
 }
 
+// The same at the faces i + 1/2 of a staggered axis (acoustic_iso): depth
+// nb - i - 1/2 in the low layer, i + 1/2 - (n - 1 - nb) in the high one, q
+// clamped to 1 (the face beyond the last cell).
+void cpml_face_table(int n, int nb, double h, double dt, double vmax, double R, double f0, float* a, float* b) {
+    const double d0 = -3.0 * vmax * std::log(R) / (2.0 * nb * h);
+    for (int k = 0; k < n; ++k) {
+        const double dep = std::max(nb - k - 0.5, k + 0.5 - (n - 1 - nb));
+        if (dep <= 0.0) {
+            a[k] = 0.0f;
+            b[k] = 1.0f;
+            continue;
+        }
+        const double q = std::min(1.0, dep / nb);
+        const double d = d0 * q * q;
+        const double al = kPi * f0 * (1.0 - q);
+        const double bb = std::exp(-(d + al) * dt);
+        b[k] = (float)bb;
+        a[k] = (d + al) > 0.0 ? (float)(d * (bb - 1.0) / (d + al)) : 0.0f;
+    }
+}
+
 double dt_stab(const mm_params& p, double vmax) {
     const double sum = 1.0 / (p.dx * p.dx) + 1.0 / (p.dy * p.dy) + 1.0 / (p.dz * p.dz);
     if (p.model == MM_MODEL_ISO) {
@@ -410,6 +435,7 @@ struct mm_ctx {
     int adj_T = 0, adj_j = 0, seg_loaded = -1;
     // scratch pointers
     unsigned* vcheck = nullptr;
+    unsigned* watch = nullptr;  // watchdog flag and first bad step (scratch words 4, 5)
     double* loss_part = nullptr;
     double* loss_dev = nullptr;
     // graph
@@ -495,8 +521,8 @@ mm_status check_params(const mm_params* p, mm_ctx* c) {
     if (p->free_surface != 0 && p->free_surface != 1) return fail(c, MM_ERR_ARG, "free_surface must be 0 or 1");
     if (p->model != MM_MODEL_ISO_CD && p->model != MM_MODEL_ISO) return fail(c, MM_ERR_ARG, "unknown model");
     if (p->cache_hints < 0 || p->cache_hints > 2) return fail(c, MM_ERR_ARG, "cache_hints must be 0, 1 or 2");
+    if (p->watch_every < 0) return fail(c, MM_ERR_ARG, "watch_every must be >= 0");
     if (p->model == MM_MODEL_ISO) {
-        if (p->bc == MM_BC_CPML) return fail(c, MM_ERR_UNSUPPORTED, "acoustic_iso supports bc none and sponge");
         if (p->ckpt_every > 0) return fail(c, MM_ERR_UNSUPPORTED, "acoustic_iso has no adjoint (ckpt_every must be 0)");
         if (p->tile > 0 && !iso_variant_ok(p->tile))
             return fail(c, MM_ERR_ARG, "acoustic_iso runs the 256-thread tile variants only");
@@ -629,7 +655,9 @@ mm_status set_variant(mm_ctx* c, int v) {
         c->groups[i].t = t;
         c->nfull += t.nfull;
         // full lists: the adjoint's correction slabs reach nb + 4 cells per end
-        tile_flags(c, t.full_off, t.full_off + t.nfull, c->p.nb + (c->L.adjoint ? 4 : 0), 0);
+        // (acoustic_iso: its memory slabs, one cell wider than the layer)
+        tile_flags(c, t.full_off, t.full_off + t.nfull, c->iso ? mem_width(c->p) : c->p.nb + (c->L.adjoint ? 4 : 0),
+                   0);
         tile_flags(c, t.in_off, t.in_off + t.nin, c->p.nb, 0);
         tile_flags(c, t.st_off, t.st_off + t.nst, c->p.nb, 0);
         tile_flags(c, t.zl_off, t.zl_off + t.nzl, c->p.nb, TF_LZ);
@@ -651,6 +679,7 @@ void drop_graph(mm_ctx* c) {
 }
 
 mm_status zero_state(mm_ctx* c, hipStream_t s) {
+    MM_TRY(dev(c, launch_watch_reset(c->watch, s), "watch reset"));
     for (size_t i = 0; i < c->geom.size(); ++i) {
         const long long n = c->geom[i].n();
         const ShotDev& sd = c->shots_h[i];
@@ -659,13 +688,13 @@ mm_status zero_state(mm_ctx* c, hipStream_t s) {
         MM_TRY(dev(c, launch_fill(sd.buf[0], n, 0.0f, s), "fill"));
         MM_TRY(dev(c, launch_fill(sd.buf[1], n, 0.0f, s), "fill"));
         if (c->cpml) {
-            const long long nb2 = 2LL * c->p.nb;
+            const long long nb2 = 2LL * mem_width(c->p);
             const long long sl[3] = {(long long)c->geom[i].nz * c->geom[i].ny * nb2,
                                      (long long)c->geom[i].nz * nb2 * c->geom[i].nx,
                                      nb2 * c->geom[i].ny * c->geom[i].nx};
             for (int a = 0; a < 3; ++a) {
                 MM_TRY(dev(c, launch_fill(sd.psi[a], sl[a], 0.0f, s), "fill"));
-                MM_TRY(dev(c, launch_fill(sd.corr[a], sl[a], 0.0f, s), "fill"));
+                if (!c->iso) MM_TRY(dev(c, launch_fill(sd.corr[a], sl[a], 0.0f, s), "fill"));
                 MM_TRY(dev(c, launch_fill(sd.zeta[a], sl[a], 0.0f, s), "fill"));
             }
         }
@@ -691,6 +720,22 @@ mm_status zero_adjoint(mm_ctx* c, hipStream_t s) {
     return MM_OK;
 }
 
+// Watchdog schedule: the state after `steps_done` forward steps is scanned
+// when watch_every divides it.
+bool watch_due(int steps_done, int watch_every) { return watch_every > 0 && steps_done > 0 && steps_done % watch_every == 0; }
+
+// Watchdog result from its two device words {flag, first bad step}.
+mm_status watch_result(const unsigned w[2], int32_t* bad_step, std::string* msg) {
+    if (!(w[0] & 1u)) {
+        if (bad_step) *bad_step = -1;
+        return MM_OK;
+    }
+    const int32_t b = w[1] > 0x7FFFFFFFu ? -1 : (int32_t)w[1];
+    if (bad_step) *bad_step = b;
+    if (msg) *msg = "non-finite wavefield (NaN or Inf) first seen in the state after step " + std::to_string(b);
+    return MM_ERR_NONFINITE;
+}
+
 // One leapfrog step of the forward (or adjoint) field set, for the shots of
 // group g (nullptr: every shot in one launch; forward CPML needs a group).
 mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, const StepAux& aux, hipStream_t s,
@@ -708,7 +753,7 @@ mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, co
         ev1 = c->prof_ev[c->prof_used + 1];
         c->prof_used += 2;
     }
-    if (c->cpml && shots == c->d_shots) {
+    if (c->cpml && !c->iso && shots == c->d_shots) {
         // forward CPML: the interior boxes (plain stencil), then the frames and the z-layer
         // chunks (fused CPML kernel); the three write disjoint cells and read only p^n of the
         // step, so their order is free; the receivers ride in the first launch that runs
@@ -738,7 +783,7 @@ mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, co
         }
         return MM_OK;
     }
-    if (c->cpml) {
+    if (c->cpml && !c->iso) {
         MM_TRY(dev(c, launch_cpml_adjoint(shots, (int)c->geom.size(), c->p.nb, c->cpml_adj_d, c->cpml_adj_h.data(),
                                           parity, c->cf, s, ev0),
                    "adjoint cpml launch"));
@@ -878,6 +923,10 @@ mm_status enqueue_forward(mm_ctx* c, int nsteps, const float* wav, float* traces
             if (c->iso && traces && rg.n > 0 && j + 1 < nsteps)
                 MM_TRY(dev(c, launch_gather(rg, c->d_shots, parity, traces + (size_t)j * c->nrec + g.rec0, s),
                            "record"));
+            if (watch_due(k + 1, c->p.watch_every))
+                for (int i = g.s0; i < g.s1; ++i)
+                    MM_TRY(dev(c, launch_watch(c->shots_h[i].buf[parity ^ 1], c->geom[i].n(), k + 1, c->watch, s),
+                               "watch"));
         }
         if (nsteps > 0 && traces && rg.n > 0)
             MM_TRY(dev(c, launch_gather(rg, c->d_shots, (c->step + nsteps - 1) & 1,
@@ -1084,6 +1133,7 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
 
     char* scr = c->ws + L.scratch;
     c->vcheck = reinterpret_cast<unsigned*>(scr);
+    c->watch = c->vcheck + 4;
     c->loss_part = reinterpret_cast<double*>(scr + 64);
     c->loss_dev = c->loss_part + kPartials;
 
@@ -1149,7 +1199,7 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
         for (int a = 0; a < 3; ++a) {
             sd.psi[a] = c->cpml ? at<float>(c->ws, L.psi[a][i]) : nullptr;
             sd.zeta[a] = c->cpml ? at<float>(c->ws, L.zeta[a][i]) : nullptr;
-            sd.corr[a] = c->cpml ? at<float>(c->ws, L.corr[a][i]) : nullptr;
+            sd.corr[a] = c->cpml && !c->iso ? at<float>(c->ws, L.corr[a][i]) : nullptr;
         }
         sd.nx = g.nx;
         sd.ny = g.ny;
@@ -1178,16 +1228,21 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
         // coefficients a = b = 0 there, so the layer memory stays 0 and adds nothing
         const bool fs = p->free_surface != 0;
         if (c->cpml) {
-            pr.resize(2 * (g.nx + g.ny + g.nz));
+            // (a, b) per axis at the cells; acoustic_iso appends the same at its faces i + 1/2
+            pr.resize((c->iso ? 4 : 2) * (g.nx + g.ny + g.nz));
             float* q = pr.data();
-            for (int a = 0; a < 3; ++a) {
-                cpml_table(n[a], p->nb, h[a], c->dt, c->vmax, p->cpml_R, p->cpml_f0, q, q + n[a]);
-                if (fs && a == 2) {
-                    std::fill(q, q + p->nb, 0.0f);
-                    std::fill(q + n[a], q + n[a] + p->nb, 0.0f);
+            for (int face = 0; face <= (c->iso ? 1 : 0); ++face)
+                for (int a = 0; a < 3; ++a) {
+                    if (face)
+                        cpml_face_table(n[a], p->nb, h[a], c->dt, c->vmax, p->cpml_R, p->cpml_f0, q, q + n[a]);
+                    else
+                        cpml_table(n[a], p->nb, h[a], c->dt, c->vmax, p->cpml_R, p->cpml_f0, q, q + n[a]);
+                    if (fs && a == 2) {
+                        std::fill(q, q + p->nb, 0.0f);
+                        std::fill(q + n[a], q + n[a] + p->nb, 0.0f);
+                    }
+                    q += 2 * n[a];
                 }
-                q += 2 * n[a];
-            }
         } else {
             pr.resize(g.nx + g.ny + g.nz);
             float* q = pr.data();
@@ -1519,6 +1574,19 @@ mm_status mm_gradient(mm_ctx* c, int32_t nsteps, const float* wav, const float* 
             *loss_host = 0.0;
         }
     }
+    if (c->p.watch_every > 0) return mm_watch(c, nullptr);
+    return MM_OK;
+}
+
+mm_status mm_watch(mm_ctx* c, int32_t* bad_step) {
+    if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
+    if (c->p.watch_every <= 0) return fail(c, MM_ERR_STATE, "the context was made with watch_every = 0");
+    unsigned w[2] = {0u, 0u};
+    MM_TRY(dev(c, hipMemcpyAsync(w, c->watch, sizeof w, hipMemcpyDeviceToHost, c->stream), "readback"));
+    MM_TRY(dev(c, hipStreamSynchronize(c->stream), "sync"));
+    std::string msg;
+    const mm_status st = watch_result(w, bad_step, &msg);
+    if (st != MM_OK) return fail(c, st, msg);
     return MM_OK;
 }
 
@@ -1548,7 +1616,7 @@ mm_status mm_state_size(const mm_ctx* c, size_t* bytes) {
     for (const auto& g : c->geom) {
         b += (c->iso ? 4 : 2) * sizeof(float) * (size_t)g.n();
         if (c->cpml) {
-            const size_t nb2 = 2 * (size_t)c->p.nb;
+            const size_t nb2 = 2 * (size_t)mem_width(c->p);
             b += 2 * sizeof(float) * ((size_t)g.nz * g.ny * nb2 + (size_t)g.nz * nb2 * g.nx + nb2 * g.ny * g.nx);
         }
     }
@@ -1569,9 +1637,16 @@ static mm_status state_copy(mm_ctx* c, char* ext, bool to_ext) {
         const auto& g = c->geom[i];
         const size_t fb = sizeof(float) * (size_t)g.n();
         if (c->iso) {
-            // acoustic_iso: p^k, then u_x, u_y, u_z at k - 1/2
+            // acoustic_iso: p^k, then u_x, u_y, u_z at k - 1/2, then with CPML the memory of
+            // the face derivatives (psi) and of the cell derivatives (zeta)
             MM_TRY(cp(c->shots_h[i].buf[par], fb));
             for (int a = 0; a < 3; ++a) MM_TRY(cp(c->shots_h[i].u[a], fb));
+            if (c->cpml) {
+                const size_t w2 = 2 * (size_t)mem_width(c->p);
+                const size_t sl[3] = {(size_t)g.nz * g.ny * w2, (size_t)g.nz * w2 * g.nx, w2 * g.ny * g.nx};
+                for (int a = 0; a < 3; ++a) MM_TRY(cp(c->shots_h[i].psi[a], sizeof(float) * sl[a]));
+                for (int a = 0; a < 3; ++a) MM_TRY(cp(c->shots_h[i].zeta[a], sizeof(float) * sl[a]));
+            }
             continue;
         }
         MM_TRY(cp(c->shots_h[i].buf[par ^ 1], fb));
@@ -1602,6 +1677,7 @@ mm_status mm_set_state(mm_ctx* c, const void* src, int32_t step) {
     c->ckpt_active = false;
     c->adj_started = false;
     MM_TRY(state_copy(c, const_cast<char*>(reinterpret_cast<const char*>(src)), false));
+    MM_TRY(dev(c, launch_watch_reset(c->watch, c->stream), "watch reset"));
     if (c->p.free_surface) {
         // the surface plane holds p = 0 at every time level
         for (size_t i = 0; i < c->geom.size(); ++i)

@@ -156,6 +156,10 @@ hipError_t launch_gather(const GatherTab& tab, const ShotDev* shots, int parity,
 hipError_t launch_vdt2(const float* vel, float* vdt2, long long n, double dt, hipStream_t s);
 hipError_t launch_vcheck(const float* vel, long long n, unsigned* result2, hipStream_t s);
 hipError_t launch_fill(float* p, long long n, float v, hipStream_t s);
+// Watchdog: w[0] |= 1 and w[1] = min(w[1], step) if p[0 .. n) holds NaN or
+// Inf; launch_watch_reset sets w = {0, 0xFFFFFFFF}.
+hipError_t launch_watch(const float* p, long long n, int step, unsigned* w, hipStream_t s);
+hipError_t launch_watch_reset(unsigned* w, hipStream_t s);
 hipError_t launch_copy(float* dst, const float* src, long long n, hipStream_t s);
 // BF16 snapshot codec of a checkpoint (p^{k-1}, p^k): c0 = bf16(p^k / s0),
 // c1 = bf16((p^k - p^{k-1}) / s1), scales per block of SNAP_BLOCK cells

@@ -493,7 +493,7 @@ hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int 
 // updated in place by the owner only.  Cells owned by the tile are
 // [x0, x1) x [y0, y1) x [z0, z1); the plane is staged over the full TX x TY
 // so the ring around the owned cells holds real p^n values.
-template <int TX, int RY, int NT, bool LZ, int MODE, bool STREAM>
+template <int TX, int RY, int NT, int PD, bool LZ, int MODE, bool STREAM>
 __global__ __launch_bounds__(NT) void k_cstep(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd,
                                               const ShotDev* __restrict__ shots, int parity, Coefs cf,
                                               StepAux aux) {
@@ -647,11 +647,14 @@ __global__ __launch_bounds__(NT) void k_cstep(const TileEnt* __restrict__ tiles,
         }
     }
 
-    // prefetch stage for plane zn: queue head p^n(zn+QD-5), p^{n-1}, (dt v)^2, the plane halos,
-    // psi^n and zeta^n of the cell (x, y: plane zn; z: psi of plane zn+4, zeta of zn), psi^n of the rings
-    float nq[RY], npp[RY], nvd[RY], nxh[RY], nyh[YH];
-    float nsx[RY], nzx[RY], nhx[RY], nsy[RY], nzy[RY], nhy[PH], nsz[RY], nzz[RY];
-    auto fetch = [&](int zn) {
+    // prefetch stage for plane zn (PD planes in flight): queue head p^n(zn+QD-5), p^{n-1},
+    // (dt v)^2, the plane halos, psi^n and zeta^n of the cell (x, y: plane zn; z: psi of plane
+    // zn+4, zeta of zn), psi^n of the rings
+    struct Stage {
+        float q[RY], pp[RY], vd[RY], xh[RY], yh[YH];
+        float sx[RY], zx[RY], hx[RY], sy[RY], zy[RY], hy[PH], sz[RY], zz[RY];
+    };
+    auto fetch = [&](Stage& f, int zn) {
         const int zq = zn + QD - 5;
         const bool hin = zq < nz;
         const __amdgpu_buffer_rsrc_t rh = plane_rsrc(pc, hin ? zq : 0, plane);
@@ -660,24 +663,24 @@ __global__ __launch_bounds__(NT) void k_cstep(const TileEnt* __restrict__ tiles,
         const __amdgpu_buffer_rsrc_t rv = plane_rsrc(vd, zn, plane);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            nq[r] = hin ? bload(rh, voc[r]) : 0.0f;
-            npp[r] = STREAM ? bload_nt(rm, voc[r]) : bload(rm, voc[r]);
-            nvd[r] = STREAM ? bload_nt(rv, voc[r]) : bload(rv, voc[r]);
-            nxh[r] = bload(rc, vox[r]);
-            nsx[r] = nzx[r] = nhx[r] = nsy[r] = nzy[r] = nsz[r] = nzz[r] = 0.0f;
+            f.q[r] = hin ? bload(rh, voc[r]) : 0.0f;
+            f.pp[r] = STREAM ? bload_nt(rm, voc[r]) : bload(rm, voc[r]);
+            f.vd[r] = STREAM ? bload_nt(rv, voc[r]) : bload(rv, voc[r]);
+            f.xh[r] = bload(rc, vox[r]);
+            f.sx[r] = f.zx[r] = f.hx[r] = f.sy[r] = f.zy[r] = f.sz[r] = f.zz[r] = 0.0f;
         }
 #pragma unroll
-        for (int h = 0; h < YH; ++h) nyh[h] = bload(rc, voy[h]);
+        for (int h = 0; h < YH; ++h) f.yh[h] = bload(rc, voy[h]);
 #pragma unroll
-        for (int h = 0; h < PH; ++h) nhy[h] = 0.0f;
+        for (int h = 0; h < PH; ++h) f.hy[h] = 0.0f;
         if (tlx) {
             const __amdgpu_buffer_rsrc_t rs = plane_rsrc(rpx, zn, pxs);
             const __amdgpu_buffer_rsrc_t rz = plane_rsrc(sd.zeta[0], zn, pxs);
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
-                nsx[r] = STREAM ? bload_nt(rs, vsx[r]) : bload(rs, vsx[r]);
-                nzx[r] = STREAM ? bload_nt(rz, vsx[r]) : bload(rz, vsx[r]);
-                nhx[r] = bload(rs, vpx[r]);
+                f.sx[r] = STREAM ? bload_nt(rs, vsx[r]) : bload(rs, vsx[r]);
+                f.zx[r] = STREAM ? bload_nt(rz, vsx[r]) : bload(rz, vsx[r]);
+                f.hx[r] = bload(rs, vpx[r]);
             }
         }
         if (tly) {
@@ -685,11 +688,11 @@ __global__ __launch_bounds__(NT) void k_cstep(const TileEnt* __restrict__ tiles,
             const __amdgpu_buffer_rsrc_t rz = plane_rsrc(sd.zeta[1], zn, pys);
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
-                nsy[r] = STREAM ? bload_nt(rs, vsy[r]) : bload(rs, vsy[r]);
-                nzy[r] = STREAM ? bload_nt(rz, vsy[r]) : bload(rz, vsy[r]);
+                f.sy[r] = STREAM ? bload_nt(rs, vsy[r]) : bload(rs, vsy[r]);
+                f.zy[r] = STREAM ? bload_nt(rz, vsy[r]) : bload(rz, vsy[r]);
             }
 #pragma unroll
-            for (int h = 0; h < PH; ++h) nhy[h] = bload(rs, vpy[h]);
+            for (int h = 0; h < PH; ++h) f.hy[h] = bload(rs, vpy[h]);
         }
         if (LZ) {
             const bool pin = zn + 4 < z1;  // the chunk is the whole layer
@@ -697,37 +700,27 @@ __global__ __launch_bounds__(NT) void k_cstep(const TileEnt* __restrict__ tiles,
             const __amdgpu_buffer_rsrc_t rz = plane_rsrc(sd.zeta[2], zslab(zn), plane);
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
-                nsz[r] = pin ? (STREAM ? bload_nt(rs, voc[r]) : bload(rs, voc[r])) : 0.0f;
-                nzz[r] = STREAM ? bload_nt(rz, voc[r]) : bload(rz, voc[r]);
+                f.sz[r] = pin ? (STREAM ? bload_nt(rs, voc[r]) : bload(rs, voc[r])) : 0.0f;
+                f.zz[r] = STREAM ? bload_nt(rz, voc[r]) : bload(rz, voc[r]);
             }
         }
     };
-    if (z0 < z1) fetch(z0);
+    Stage stg[PD];
+#pragma unroll
+    for (int k = 0; k < PD; ++k)
+        if (z0 + k < z1) fetch(stg[k], z0 + k);
 
     const int xx = H + tx;
     gfloat* __restrict__ pn_g = (gfloat*)pn;
     for (int z = z0; z < z1; ++z) {
-        float cpp[RY], cvd[RY], cxh[RY], cyh[YH], csx[RY], czx[RY], chx[RY], csy[RY], czy[RY], chy[PH], csz[RY],
-            czz[RY];
+        const Stage cur = stg[0];
 #pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            q[r][QD - 1] = nq[r];
-            cpp[r] = npp[r];
-            cvd[r] = nvd[r];
-            cxh[r] = nxh[r];
-            csx[r] = nsx[r];
-            czx[r] = nzx[r];
-            chx[r] = nhx[r];
-            csy[r] = nsy[r];
-            czy[r] = nzy[r];
-            csz[r] = nsz[r];
-            czz[r] = nzz[r];
-        }
+        for (int k = 0; k + 1 < PD; ++k) stg[k] = stg[k + 1];
+        if (z + PD < z1) fetch(stg[PD - 1], z + PD);
 #pragma unroll
-        for (int h = 0; h < YH; ++h) cyh[h] = nyh[h];
-#pragma unroll
-        for (int h = 0; h < PH; ++h) chy[h] = nhy[h];
-        if (z + 1 < z1) fetch(z + 1);
+        for (int r = 0; r < RY; ++r) q[r][QD - 1] = cur.q[r];
+        const float *cpp = cur.pp, *cvd = cur.vd, *cxh = cur.xh, *cyh = cur.yh, *csx = cur.sx, *czx = cur.zx,
+                    *chx = cur.hx, *csy = cur.sy, *czy = cur.zy, *chy = cur.hy, *csz = cur.sz, *czz = cur.zz;
 
         if (LZ) {
             // psi_z^{n+1} of plane z+4: its D1 needs planes z .. z+8, now all in the queue
@@ -898,8 +891,9 @@ __global__ __launch_bounds__(NT) void k_cstep(const TileEnt* __restrict__ tiles,
     }
 }
 
-// fixed shape of the fused CPML kernel: 32-wide, 16-row tiles of 512 threads (one row each)
-constexpr int CS_TX = 32, CS_RY = 1, CS_NT = 512;
+// fixed shape of the fused CPML kernel: 32-wide, 16-row tiles of 512 threads (one row each), loads two
+// planes ahead
+constexpr int CS_TX = 32, CS_RY = 1, CS_NT = 512, CS_PD = 2;
 int cstep_tile_w() { return CS_TX; }
 int cstep_tile_h() { return (CS_NT / CS_TX) * CS_RY; }
 
@@ -907,7 +901,7 @@ template <bool LZ, int MODE, bool STREAM>
 static void launch_cstep_k(dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd, const ShotDev* shots, int parity,
                            const Coefs& cf, const StepAux& aux, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const dim3 block(CS_TX, CS_NT / CS_TX);
-    hipExtLaunchKernelGGL(k_cstep<CS_TX, CS_RY, CS_NT, LZ, MODE, STREAM>, grid, block, 0, s, ev0, ev1, 0, tiles,
+    hipExtLaunchKernelGGL(k_cstep<CS_TX, CS_RY, CS_NT, CS_PD, LZ, MODE, STREAM>, grid, block, 0, s, ev0, ev1, 0, tiles,
                           ntiles, per_xcd, shots, parity, cf, aux);
 }
 
@@ -950,6 +944,47 @@ hipError_t launch_cpml_step(bool zlayer, int mode, const TileEnt* tiles, int nti
 // face: dt b = 2 / (rho_0 / dt + rho_1 / dt), one over their mean density
 // (the inner cell's dt / rho on the last face of an axis).
 
+// acoustic_iso CPML memory of one thread's cells (FACE = 0: psi_u of D- u at the
+// cells, in ShotDev::zeta) or faces (FACE = 1: psi_p of D+ p at the faces,
+// in ShotDev::psi): slab arrays of W = nb + 1 cells per end (x [nz][ny][2W],
+// y [nz][2W][nx], z [2W][ny][nx], slab index s < W is grid index s, else
+// n - 2W + s); (a, b) per axis from the shot's tables (cells first, then
+// faces: 2 (nx + ny + nz) floats each).  Outside the layers a = 0, b = 1, so
+// the memory of the slab cells next to a layer stays zero.
+template <int RY, bool FACE>
+struct IsoPml {
+    bool xl, yl[RY];
+    float ax, bx, ay[RY], by[RY];
+    unsigned vx[RY], vy[RY];
+    const float* tab;  // the z columns of the tables: a_z [nz], b_z [nz]
+    int W;
+    __device__ void init(const ShotDev& sd, const TileEnt& te, int x, const int* row, const bool* in) {
+        const int nx = sd.nx, ny = sd.ny, nz = sd.nz;
+        W = sd.nb + 1;
+        const int W2 = 2 * W;
+        const float* t0 = sd.prof + (FACE ? 2 * (nx + ny + nz) : 0);
+        tab = t0 + 2 * nx + 2 * ny;
+        xl = (te.flags & TF_LX) && x < nx && (x < W || x >= nx - W);
+        ax = xl ? t0[x] : 0.0f;
+        bx = xl ? t0[nx + x] : 1.0f;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const int y = row[r];
+            vx[r] = (xl && in[r]) ? (unsigned)(y * W2 + (x < W ? x : x - (nx - W2))) * 4u : OOB;
+            yl[r] = (te.flags & TF_LY) && in[r] && (y < W || y >= ny - W);
+            vy[r] = yl[r] ? (unsigned)((y < W ? y : y - (ny - W2)) * nx + x) * 4u : OOB;
+            ay[r] = yl[r] ? t0[2 * nx + y] : 0.0f;
+            by[r] = yl[r] ? t0[2 * nx + ny + y] : 1.0f;
+        }
+        (void)nz;
+    }
+    // plane z of the z-axis memory holds layer cells (block-uniform)
+    __device__ bool zl(const ShotDev& sd, const TileEnt& te, int z) const {
+        return (te.flags & TF_LZ) && (z < W || z >= sd.nz - W);
+    }
+    __device__ int zs(const ShotDev& sd, int z) const { return z < W ? z : z - (sd.nz - 2 * W); }
+};
+
 template <int TX, int RY>
 struct IsoTile {
     static constexpr int BY = 256 / TX, TY = BY * RY, YH = 8 / BY;
@@ -961,6 +996,7 @@ __global__ __launch_bounds__(256) void k_iso_u(const TileEnt* __restrict__ tiles
     constexpr int BY = IsoTile<TX, RY>::BY, TY = IsoTile<TX, RY>::TY, YH = IsoTile<TX, RY>::YH;
     constexpr int LW = TX + 8;
     constexpr bool SPONGE = BC == 1;
+    constexpr bool CPML = BC == 2;
     __shared__ float lds[2][TY + 8][LW];  // p^n of the plane with halos
     __shared__ float ldb[2][TY + 8][LW];  // rho / dt of the plane with halos (face buoyancy)
     const int b = blockIdx.x;
@@ -1002,6 +1038,9 @@ __global__ __launch_bounds__(256) void k_iso_u(const TileEnt* __restrict__ tiles
 #pragma unroll
         for (int r = 0; r < RY; ++r) gyv[r] = in[r] ? sd.prof[nx + row[r]] : 1.0f;
     }
+    IsoPml<RY, true> pm;  // CPML: memory of D+ p at this thread's faces
+    if (CPML) pm.init(sd, te, x, row, in);
+    const long long pxs = CPML ? (long long)ny * 2 * pm.W : 0, pys = CPML ? (long long)2 * pm.W * nx : 0;
     const int z0 = te.z0, z1 = te.z1;
     // p queue: planes z-4 .. z+4 (D+ at the face z+1/2 uses z-3 .. z+4); buoyancy of planes z, z+1
     float q[RY][9], b0[RY], b1[RY];
@@ -1032,7 +1071,20 @@ __global__ __launch_bounds__(256) void k_iso_u(const TileEnt* __restrict__ tiles
     }
     // stage for plane zn: p^n(zn+4), halos of p and rho/dt at zn, rho/dt(zn+1), u at zn
     float nq[RY], nxh[RY], nyh[YH], nbh[RY], nbx[RY], nby[YH], nu[3][RY];
+    float nm[CPML ? 3 : 1][RY];  // CPML memory of the three face derivatives at plane zn
     auto fetch = [&](int zn) {
+        if (CPML) {
+            const __amdgpu_buffer_rsrc_t mx = plane_rsrc(sd.psi[0], zn, pxs);
+            const __amdgpu_buffer_rsrc_t my = plane_rsrc(sd.psi[1], zn, pys);
+            const bool zl = pm.zl(sd, te, zn);
+            const __amdgpu_buffer_rsrc_t mz = plane_rsrc(sd.psi[2], zl ? pm.zs(sd, zn) : 0, plane);
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                nm[0][r] = bload(mx, pm.vx[r]);
+                nm[CPML ? 1 : 0][r] = bload(my, pm.vy[r]);
+                nm[CPML ? 2 : 0][r] = zl ? bload(mz, voc[r]) : 0.0f;
+            }
+        }
         const bool hin = zn + 4 < nz, bin = zn + 1 < nz;
         const __amdgpu_buffer_rsrc_t rh = plane_rsrc(pc, hin ? zn + 4 : 0, plane);
         const __amdgpu_buffer_rsrc_t rc = plane_rsrc(pc, zn, plane);
@@ -1060,7 +1112,13 @@ __global__ __launch_bounds__(256) void k_iso_u(const TileEnt* __restrict__ tiles
     if (z0 < z1) fetch(z0);
     const int xx = 4 + tx;
     for (int z = z0; z < z1; ++z) {
-        float cu[3][RY], cxh[RY], cyh[YH], cbx[RY], cby[YH];
+        float cu[3][RY], cxh[RY], cyh[YH], cbx[RY], cby[YH], cm[CPML ? 3 : 1][RY];
+        if (CPML) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int r = 0; r < RY; ++r) cm[CPML ? a : 0][r] = nm[CPML ? a : 0][r];
+        }
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             q[r][8] = nq[r];
@@ -1117,6 +1175,24 @@ __global__ __launch_bounds__(256) void k_iso_u(const TileEnt* __restrict__ tiles
                 const float fx = 2.0f / (rc + (xlast ? rc : B[yy][xx + 1]));
                 const float fy = 2.0f / (rc + (row[r] + 1 >= ny ? rc : B[yy + 1][xx]));
                 const float fz = 2.0f / (rc + (zlast ? rc : b1[r]));
+                if (CPML) {
+                    // psi <- b psi + a D+ p, and D+ p gains psi (faces inside the layers)
+                    if (pm.xl) {
+                        const float v = fmaf(pm.bx, cm[0][r], pm.ax * dx);
+                        ((gfloat*)sd.psi[0])[(long long)z * pxs + (pm.vx[r] >> 2)] = v;
+                        dx += v;
+                    }
+                    if (pm.yl[r]) {
+                        const float v = fmaf(pm.by[r], cm[CPML ? 1 : 0][r], pm.ay[r] * dy);
+                        ((gfloat*)sd.psi[1])[(long long)z * pys + (pm.vy[r] >> 2)] = v;
+                        dy += v;
+                    }
+                    if (pm.zl(sd, te, z)) {
+                        const float v = fmaf(pm.tab[nz + z], cm[CPML ? 2 : 0][r], pm.tab[z] * dz);
+                        ((gfloat*)sd.psi[2])[(long long)pm.zs(sd, z) * plane + (row[r] * nx + x)] = v;
+                        dz += v;
+                    }
+                }
                 ((gfloat*)sd.u[0])[o] = G * fmaf(fx, dx, cu[0][r]);
                 ((gfloat*)sd.u[1])[o] = G * fmaf(fy, dy, cu[1][r]);
                 ((gfloat*)sd.u[2])[o] = G * fmaf(fz, dz, cu[2][r]);
@@ -1137,6 +1213,7 @@ __global__ __launch_bounds__(256) void k_iso_p(const TileEnt* __restrict__ tiles
     constexpr int BY = IsoTile<TX, RY>::BY, TY = IsoTile<TX, RY>::TY, YH = IsoTile<TX, RY>::YH;
     constexpr int LW = TX + 8;
     constexpr bool SPONGE = BC == 1;
+    constexpr bool CPML = BC == 2;
     __shared__ float lx[2][TY][LW];      // u_x of the plane with its x halo
     __shared__ float ly[2][TY + 8][TX];  // u_y of the plane with its y halo
     const int b = blockIdx.x;
@@ -1178,6 +1255,9 @@ __global__ __launch_bounds__(256) void k_iso_p(const TileEnt* __restrict__ tiles
 #pragma unroll
         for (int r = 0; r < RY; ++r) gyv[r] = in[r] ? sd.prof[nx + row[r]] : 1.0f;
     }
+    IsoPml<RY, false> pm;  // CPML: memory of D- u at this thread's cells
+    if (CPML) pm.init(sd, te, x, row, in);
+    const long long pxs = CPML ? (long long)ny * 2 * pm.W : 0, pys = CPML ? (long long)2 * pm.W * nx : 0;
     const int z0 = te.z0, z1 = te.z1;
     // u_z queue: planes z-4 .. z+3 (D- at cell z uses them all)
     float w[RY][8];
@@ -1202,7 +1282,20 @@ __global__ __launch_bounds__(256) void k_iso_p(const TileEnt* __restrict__ tiles
         }
     }
     float nw[RY], nux[RY], nuxh[RY], nuy[RY], nuyh[YH], np_[RY], nk[RY];
+    float nm[CPML ? 3 : 1][RY];  // CPML memory of the three cell derivatives at plane zn
     auto fetch = [&](int zn) {
+        if (CPML) {
+            const __amdgpu_buffer_rsrc_t mx = plane_rsrc(sd.zeta[0], zn, pxs);
+            const __amdgpu_buffer_rsrc_t my = plane_rsrc(sd.zeta[1], zn, pys);
+            const bool zl = pm.zl(sd, te, zn);
+            const __amdgpu_buffer_rsrc_t mz = plane_rsrc(sd.zeta[2], zl ? pm.zs(sd, zn) : 0, plane);
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                nm[0][r] = bload(mx, pm.vx[r]);
+                nm[CPML ? 1 : 0][r] = bload(my, pm.vy[r]);
+                nm[CPML ? 2 : 0][r] = zl ? bload(mz, voc[r]) : 0.0f;
+            }
+        }
         const bool hin = zn + 3 < nz;
         const __amdgpu_buffer_rsrc_t rw = plane_rsrc(sd.u[2], hin ? zn + 3 : 0, plane);
         const __amdgpu_buffer_rsrc_t rx = plane_rsrc(sd.u[0], zn, plane);
@@ -1224,7 +1317,13 @@ __global__ __launch_bounds__(256) void k_iso_p(const TileEnt* __restrict__ tiles
     if (z0 < z1) fetch(z0);
     const int xx = 4 + tx;
     for (int z = z0; z < z1; ++z) {
-        float cux[RY], cuxh[RY], cuy[RY], cuyh[YH], cp[RY], ck[RY];
+        float cux[RY], cuxh[RY], cuy[RY], cuyh[YH], cp[RY], ck[RY], cm[CPML ? 3 : 1][RY];
+        if (CPML) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int r = 0; r < RY; ++r) cm[CPML ? a : 0][r] = nm[CPML ? a : 0][r];
+        }
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             w[r][7] = nw[r];
@@ -1266,6 +1365,24 @@ __global__ __launch_bounds__(256) void k_iso_p(const TileEnt* __restrict__ tiles
             if (in[r]) {
                 const long long o = zoff + (row[r] * nx + x);
                 const float G = SPONGE ? gx * gyv[r] * gz : 1.0f;
+                if (CPML) {
+                    // psi <- b psi + a D- u, and D- u gains psi (cells inside the layers)
+                    if (pm.xl) {
+                        const float v = fmaf(pm.bx, cm[0][r], pm.ax * dx);
+                        ((gfloat*)sd.zeta[0])[(long long)z * pxs + (pm.vx[r] >> 2)] = v;
+                        dx += v;
+                    }
+                    if (pm.yl[r]) {
+                        const float v = fmaf(pm.by[r], cm[CPML ? 1 : 0][r], pm.ay[r] * dy);
+                        ((gfloat*)sd.zeta[1])[(long long)z * pys + (pm.vy[r] >> 2)] = v;
+                        dy += v;
+                    }
+                    if (pm.zl(sd, te, z)) {
+                        const float v = fmaf(pm.tab[nz + z], cm[CPML ? 2 : 0][r], pm.tab[z] * dz);
+                        ((gfloat*)sd.zeta[2])[(long long)pm.zs(sd, z) * plane + (row[r] * nx + x)] = v;
+                        dz += v;
+                    }
+                }
                 pn[o] = G * fmaf(ck[r], (dx + dy) + dz, cp[r]);
             }
         }
@@ -1296,6 +1413,8 @@ static hipError_t launch_iso_t(int bc, bool stream, dim3 grid, const TileEnt* ti
                                hipEvent_t ev1) {
     if (bc == 1)
         launch_iso_bc<TX, RY, 1>(stream, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
+    else if (bc == 2)
+        launch_iso_bc<TX, RY, 2>(stream, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
     else
         launch_iso_bc<TX, RY, 0>(stream, grid, tiles, ntiles, per_xcd, shots, parity, cf, s, ev0, ev1);
     return hipGetLastError();
@@ -1306,7 +1425,7 @@ bool iso_variant_ok(int variant) { return variant >= 0 && variant < num_tile_var
 hipError_t launch_iso_step(int variant, int bc, bool stream, const TileEnt* tiles, int ntiles, const ShotDev* shots,
                            int parity, const Coefs& cf, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (ntiles <= 0) return hipSuccess;
-    if (!iso_variant_ok(variant) || (bc != 0 && bc != 1)) return hipErrorInvalidValue;
+    if (!iso_variant_ok(variant) || bc < 0 || bc > 2) return hipErrorInvalidValue;
     const int per_xcd = (ntiles + 7) / 8;
     const dim3 grid(8 * per_xcd);
     const TileShape& ts = kTiles[variant];
@@ -1699,6 +1818,36 @@ __global__ __launch_bounds__(256) void k_fill(float* __restrict__ p, long long n
 hipError_t launch_fill(float* p, long long n, float v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     k_fill<<<stride_grid(n), 256, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+// Watchdog scan: one vector atomic per wave that saw a non-finite value.
+__global__ __launch_bounds__(256) void k_watch(const float* __restrict__ p, long long n, int step,
+                                               unsigned* __restrict__ w) {
+    bool bad = false;
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        bad = bad || !isfinite(p[i]);
+    if (__ballot(bad) && (threadIdx.x & 63) == __ffsll((long long)__ballot(bad)) - 1) {
+        atomicOr(&w[0], 1u);
+        atomicMin(&w[1], (unsigned)step);
+    }
+}
+
+__global__ void k_watch_reset(unsigned* __restrict__ w) {
+    if (threadIdx.x == 0) {
+        w[0] = 0u;
+        w[1] = 0xFFFFFFFFu;
+    }
+}
+
+hipError_t launch_watch(const float* p, long long n, int step, unsigned* w, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_watch<<<stride_grid(n), 256, 0, s>>>(p, n, step, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_watch_reset(unsigned* w, hipStream_t s) {
+    k_watch_reset<<<1, 64, 0, s>>>(w);
     return hipGetLastError();
 }
 

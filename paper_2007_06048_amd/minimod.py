@@ -24,7 +24,7 @@ SYMBOLS = [
     "mm_forward_steps", "mm_forward_steps_graph", "mm_adjoint_steps", "mm_gradient", "mm_reset",
     "mm_state_size", "mm_get_state", "mm_set_state", "mm_get_info", "mm_autotune", "mm_set_tile",
     "mm_num_tiles", "mm_tile_name", "mm_profile", "mm_profile_read", "mm_destroy", "mm_status_str",
-    "mm_last_error", "mm_snap_blocks", "mm_snap_encode", "mm_snap_decode", "mm_init_static",
+    "mm_last_error", "mm_snap_blocks", "mm_snap_encode", "mm_snap_decode", "mm_init_static", "mm_watch",
 ]
 
 
@@ -38,6 +38,7 @@ class Params(ctypes.Structure):
         ("ckpt_every", ctypes.c_int32), ("snap", ctypes.c_int32), ("nsteps_max", ctypes.c_int32),
         ("tile", ctypes.c_int32), ("group_kb", ctypes.c_int32),
         ("free_surface", ctypes.c_int32), ("model", ctypes.c_int32), ("cache_hints", ctypes.c_int32),
+        ("watch_every", ctypes.c_int32),
     ]
 
 
@@ -98,6 +99,7 @@ def load():
         "mm_status_str": (ctypes.c_char_p, [st]),
         "mm_last_error": (ctypes.c_char_p, [vp]),
         "mm_snap_blocks": (ctypes.c_int64, [ctypes.c_int64]),
+        "mm_watch": (st, [vp, ctypes.POINTER(i32)]),
         "mm_init_static": (st, [ctypes.POINTER(vp), pp, vp, ctypes.POINTER(i32), i32, ctypes.POINTER(i32), i32, vp]),
         "mm_snap_encode": (st, [vp, vp, ctypes.c_int64, vp, vp, vp, vp, vp]),
         "mm_snap_decode": (st, [vp, vp, vp, vp, ctypes.c_int64, vp, vp, vp]),
@@ -285,6 +287,16 @@ class Context:
 
     def set_tile(self, t):
         _check(load().mm_set_tile(self.h, t), self.h)
+
+    def watch(self):
+        """Watchdog result: the first step whose wavefield held NaN or Inf, or
+        None (mm_watch; synchronises)."""
+        bad = ctypes.c_int32()
+        st = load().mm_watch(self.h, ctypes.byref(bad))
+        if st == MM_ERR_NONFINITE:
+            return bad.value
+        _check(st, self.h)
+        return None
 
     def profile(self, stride):
         _check(load().mm_profile(self.h, stride), self.h)

@@ -1,8 +1,9 @@
 """acoustic_iso (first-order variable-density system on the staggered grid)
 on the GPU: parity with the FP64 oracle (traces, pressure and the three
-face-velocity fields), every supported tile variant bitwise equal, graph and
-chunked runs bitwise equal, state round trip, argument errors, and a larger
-grid against the oracle."""
+face-velocity fields) for bc none, sponge and CPML, with and without the free
+surface, every supported tile variant bitwise equal, graph and chunked runs
+bitwise equal, state round trip, argument errors, and larger grids against
+the oracle."""
 import numpy as np
 import pytest
 import torch
@@ -24,7 +25,7 @@ def _case(bc, shape=(23, 29, 37), seed=80, T=120):
     src = np.array([[nx // 2, ny // 2, nz // 2], [3, 4, 5], [nx // 2, ny // 2, nz // 2], [nx - 1, 0, 2]], np.int32)
     rec = np.concatenate([W.plane(nx, ny, 2, inc=3), [[nx // 2, ny // 2, nz // 2], [0, ny - 1, nz - 1]]]).astype(np.int32)
     p = mm.default_params(nx=nx, ny=ny, nz=nz, dx=10.0, dy=12.0, dz=9.0, bc=bc, nb=5, sponge_sigma=0.05,
-                          model=mm.MODEL_ISO, tile=0)
+                          cpml_f0=20.0, model=mm.MODEL_ISO, tile=0)
     w = rng.standard_normal((T, len(src))).astype(np.float32)
     return p, v, rho, src, rec, w, T
 
@@ -39,18 +40,22 @@ def _gpu(p, v, rho, src, rec, w, T, tile=None, graph=False, chunks=None):
     for c in (chunks or [T]):
         ctx.forward(c, wt[done:done + c], tr[done:done + c], graph=graph)
         done += c
-    st = ctx.get_state().cpu().numpy().reshape((4,) + v.shape)
+    # p and the three velocities (with CPML the blob goes on with the layer memory)
+    st = ctx.get_state().cpu().numpy()[:4 * v.size].reshape((4,) + v.shape)
     dt = ctx.dt
     ctx.close()
     return tr.cpu().numpy(), st, dt
 
 
 def _oracle(p, dt, v, rho, src, rec, w, T):
-    g = C.Grid(p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, dt, bc=p.bc, nb=p.nb, sigma=p.sponge_sigma, fs=p.free_surface)
-    return C.iso_forward(g, v.astype(np.float64), rho.astype(np.float64), src, w.astype(np.float64), rec, T)
+    g = C.Grid(p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, dt, bc=p.bc, nb=p.nb, sigma=p.sponge_sigma, R=p.cpml_R,
+               f0=p.cpml_f0, vmax=float(v.max()), fs=p.free_surface)
+    tr, st = C.iso_forward(g, v.astype(np.float64), rho.astype(np.float64), src, w.astype(np.float64), rec, T)
+    return tr, st[:4]
 
 
-@pytest.mark.parametrize("bc,fs", [(mm.BC_NONE, 0), (mm.BC_SPONGE, 0), (mm.BC_NONE, 1), (mm.BC_SPONGE, 1)])
+@pytest.mark.parametrize("bc,fs", [(mm.BC_NONE, 0), (mm.BC_SPONGE, 0), (mm.BC_CPML, 0), (mm.BC_NONE, 1),
+                                   (mm.BC_SPONGE, 1), (mm.BC_CPML, 1)])
 def test_iso_matches_oracle(bc, fs):
     """Ragged grid, duplicate sources, receivers on sources and corners; with a
     free surface a source and a receiver sit on the surface plane (which
@@ -123,9 +128,9 @@ def test_iso_cache_hints_do_not_change_results():
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
-@pytest.mark.parametrize("fs", [0, 1])
-def test_iso_every_tile_variant_bitwise(fs):
-    p, v, rho, src, rec, w, T = _case(mm.BC_SPONGE, seed=81, T=60)
+@pytest.mark.parametrize("bc,fs", [(mm.BC_SPONGE, 0), (mm.BC_SPONGE, 1), (mm.BC_CPML, 0), (mm.BC_CPML, 1)])
+def test_iso_every_tile_variant_bitwise(bc, fs):
+    p, v, rho, src, rec, w, T = _case(bc, seed=81, T=60)
     p.free_surface = fs
     first = None
     n = 0
@@ -151,9 +156,11 @@ def test_iso_graph_and_chunked_runs_are_bitwise_equal():
         assert np.array_equal(a[0], other[0]) and np.array_equal(a[1], other[1])
 
 
-@pytest.mark.parametrize("fs", [0, 1])
-def test_iso_state_round_trip_and_resume(fs):
-    p, v, rho, src, rec, w, T = _case(mm.BC_NONE, seed=83, T=40)
+@pytest.mark.parametrize("bc,fs", [(mm.BC_NONE, 0), (mm.BC_NONE, 1), (mm.BC_CPML, 0)])
+def test_iso_state_round_trip_and_resume(bc, fs):
+    """The state blob (with CPML, the layer memory too) restores a run
+    bitwise."""
+    p, v, rho, src, rec, w, T = _case(bc, seed=83, T=40)
     p.free_surface = fs
     whole = _gpu(p, v, rho, src, rec, w, T)
     ctx = mm.Context.single(p, torch.from_numpy(v).to(DEV), src, rec, rho=torch.from_numpy(rho).to(DEV))
@@ -165,14 +172,13 @@ def test_iso_state_round_trip_and_resume(fs):
     ctx.set_state(st, 25)
     ctx.forward(T - 25, wt[25:], tr[25:])
     assert np.array_equal(tr.cpu().numpy(), whole[0])
-    assert np.array_equal(ctx.get_state().cpu().numpy().reshape((4,) + v.shape), whole[1])
+    assert np.array_equal(ctx.get_state().cpu().numpy()[:4 * v.size].reshape((4,) + v.shape), whole[1])
 
 
 def test_iso_argument_errors():
     p, v, rho, src, rec, w, T = _case(mm.BC_SPONGE, shape=(16, 16, 16), T=4)
     vt, rt = torch.from_numpy(v).to(DEV), torch.from_numpy(rho).to(DEV)
-    for field, val, status in (("bc", mm.BC_CPML, mm.MM_ERR_UNSUPPORTED), ("ckpt_every", 8, mm.MM_ERR_UNSUPPORTED),
-                               ("model", 7, mm.MM_ERR_ARG)):
+    for field, val, status in (("ckpt_every", 8, mm.MM_ERR_UNSUPPORTED), ("model", 7, mm.MM_ERR_ARG)):
         q = mm.default_params(**{k: getattr(p, k) for k, _ in mm.Params._fields_})
         setattr(q, field, val)
         q.nsteps_max = 10
@@ -210,3 +216,22 @@ def test_iso_larger_grid_matches_oracle():
     rtr, rst = _oracle(p, ctx.dt, s.vel, s.rho, s.src, s.rec, w, T)
     print("traces", rel(tr.cpu().numpy(), rtr), "p", rel(st[0], rst[0]))
     assert rel(tr.cpu().numpy(), rtr) <= 1e-5 and rel(st[0], rst[0]) <= 1e-5
+
+
+def test_iso_cpml_larger_grid_matches_oracle():
+    """120^3 smooth model with Gardner density, 16-cell CPML, 150 steps,
+    autotuned tile: traces and pressure against the oracle."""
+    n = 120
+    wl = W.smooth_iso(n=n, nsteps=150)
+    s = wl.shots[0]
+    p = mm.default_params(nx=n, ny=n, nz=n, dx=wl.h, dy=wl.h, dz=wl.h, cfl=wl.cfl, bc=mm.BC_CPML, nb=16,
+                          cpml_f0=wl.f0, model=mm.MODEL_ISO, tile=-1)
+    ctx = mm.Context.single(p, torch.from_numpy(s.vel).to(DEV), s.src, s.rec, rho=torch.from_numpy(s.rho).to(DEV))
+    T = wl.nsteps
+    w = mm.ricker(wl.f0, wl.t0, ctx.dt, T).reshape(T, 1)
+    tr = torch.zeros((T, len(s.rec)), device=DEV)
+    ctx.forward(T, torch.from_numpy(w).to(DEV), tr)
+    st = ctx.get_state().cpu().numpy()[:s.vel.size].reshape(s.vel.shape)
+    rtr, rst = _oracle(p, ctx.dt, s.vel, s.rho, s.src, s.rec, w, T)
+    print("traces", rel(tr.cpu().numpy(), rtr), "p", rel(st, rst[0]))
+    assert rel(tr.cpu().numpy(), rtr) <= 1e-5 and rel(st, rst[0]) <= 1e-5

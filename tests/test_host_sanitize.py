@@ -61,3 +61,18 @@ def test_tile_plans_cover_every_cell_once(tmp_path):
           os.path.join(ROOT, "tests", "sanitize", "tiles_driver.cpp"), kobj, "-o", exe, f"-L{rocm}/lib", "-lamdhip64",
           f"-Wl,-rpath,{rocm}/lib"], timeout=600)
     assert "cases ok" in _run([exe], timeout=600)
+
+
+def test_host_logic_under_sanitizers(tmp_path):
+    """The watchdog's schedule and result decoding, the parameter check of
+    watch_every, and the CPML memory width per model."""
+    csrc = os.path.join(ROOT, "paper_2007_06048_amd", "csrc")
+    kobj = os.path.join(csrc, "mm_kernels.o")
+    if not os.path.exists(kobj):
+        _run(["make", "-C", csrc, "mm_kernels.o"], timeout=900)
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    exe = str(tmp_path / "logic")
+    _run(["g++", "-std=c++17", *SAN, "-D__HIP_PLATFORM_AMD__", f"-I{rocm}/include", f"-I{csrc}",
+          os.path.join(ROOT, "tests", "sanitize", "host_logic_driver.cpp"), kobj, "-o", exe, f"-L{rocm}/lib",
+          "-lamdhip64", f"-Wl,-rpath,{rocm}/lib"], timeout=600)
+    assert "ok" in _run([exe], env=ENV, timeout=300)
