@@ -130,8 +130,9 @@ def test_workspace_size_and_argument_checks():
 def test_acoustic_iso_dt_workspace_and_argument_checks():
     """acoustic_iso on the host side: its dt uses the staggered scheme's
     limit (the oracle's, not the constant-density one), its workspace holds
-    the ping-pong pressure, three face velocities, dt rho v^2 and dt / rho,
-    and CPML and adjoint storage are refused."""
+    the ping-pong pressure, three face velocities, dt rho v^2 and rho / dt,
+    with CPML also the memory of the face and cell derivatives (slabs one
+    cell wider than the layer), and adjoint storage is refused."""
     p = mm.default_params(dx=10.0, dy=12.0, dz=8.0, cfl=0.5, model=mm.MODEL_ISO, bc=mm.BC_SPONGE, nb=4)
     assert mm.dt_for(p, 3000.0) == pytest.approx(0.5 * C.iso_dt_stab(3000.0, 10.0, 12.0, 8.0), rel=1e-15)
     assert mm.dt_for(p, 3000.0) < mm.dt_for(mm.default_params(dx=10.0, dy=12.0, dz=8.0, cfl=0.5), 3000.0)
@@ -140,11 +141,14 @@ def test_acoustic_iso_dt_workspace_and_argument_checks():
     assert st == mm.MM_OK and n_iso >= 7 * 4 * 40 * 36 * 32
     st, n_cd = _ws(mm.default_params(dx=10.0, dy=12.0, dz=8.0, cfl=0.5, bc=mm.BC_SPONGE, nb=4), [s])
     assert st == mm.MM_OK and n_iso - n_cd >= 4 * 4 * 40 * 36 * 32
-    for field, val in (("bc", mm.BC_CPML), ("ckpt_every", 8)):
-        q = mm.default_params(model=mm.MODEL_ISO, bc=mm.BC_SPONGE, nb=4, nsteps_max=10)
-        setattr(q, field, val)
-        st, _ = _ws(q, [s])
-        assert st == mm.MM_ERR_UNSUPPORTED, field
+    q = mm.default_params(dx=10.0, dy=12.0, dz=8.0, cfl=0.5, model=mm.MODEL_ISO, bc=mm.BC_CPML, nb=4)
+    st, n_pml = _ws(q, [s])
+    w2 = 2 * (4 + 1)
+    slabs = 32 * 36 * w2 + 32 * w2 * 40 + w2 * 36 * 40
+    assert st == mm.MM_OK and n_pml - n_iso >= 2 * 4 * slabs
+    q = mm.default_params(model=mm.MODEL_ISO, bc=mm.BC_SPONGE, nb=4, nsteps_max=10, ckpt_every=8)
+    st, _ = _ws(q, [s])
+    assert st == mm.MM_ERR_UNSUPPORTED
     q = mm.default_params(model=2)
     assert _ws(q, [s])[0] == mm.MM_ERR_ARG
     for bad in (-1, 3):
