@@ -265,20 +265,22 @@ def gradient_leg(dev, reps=2):
     return res
 
 
-def iso_leg(dev, reps=2):
+def iso_leg(dev, reps=2, bc=1):
     """acoustic_iso (first-order variable-density system, staggered grid) on
-    the 240^3 smooth model with Gardner density, 20-cell sponge, 1000 steps.
-    Algorithmic bytes per point and step: 40 (read and write p and the three
-    face velocities, read rho v^2 and the buoyancy); the two kernels move 56
-    (p and u are each read by both kernels)."""
+    the 240^3 smooth model with Gardner density, 20-cell sponge (bc 1) or
+    CPML (bc 2), 1000 steps.  Algorithmic bytes per point and step: 40 (read
+    and write p and the three face velocities, read rho v^2 and the
+    buoyancy), with CPML 16 more per damped cell and axis (the memory of the
+    face and of the cell derivative, each read and written); the two kernels
+    move 56 + the memory (p and u are each read by both kernels)."""
     import torch
     from paper_2007_06048_amd import minimod as mm
     from paper_2007_06048_amd import workloads as W
     wl = W.smooth_iso(240, 1000)
     s = wl.shots[0]
     T = wl.nsteps
-    p = mm.default_params(nx=wl.nx, ny=wl.ny, nz=wl.nz, dx=wl.h, dy=wl.h, dz=wl.h, cfl=wl.cfl, bc=wl.bc, nb=wl.nb,
-                          sponge_sigma=wl.sigma, model=mm.MODEL_ISO, tile=-1)
+    p = mm.default_params(nx=wl.nx, ny=wl.ny, nz=wl.nz, dx=wl.h, dy=wl.h, dz=wl.h, cfl=wl.cfl, bc=bc, nb=wl.nb,
+                          sponge_sigma=wl.sigma, cpml_R=wl.cpml_R, cpml_f0=wl.f0, model=mm.MODEL_ISO, tile=-1)
     ctx = mm.Context.single(p, torch.from_numpy(s.vel).to(dev), s.src, s.rec, rho=torch.from_numpy(s.rho).to(dev))
     w = torch.from_numpy(mm.ricker(wl.f0, wl.t0, ctx.dt, T)).to(dev).reshape(T, 1)
     tr = torch.empty((T, len(s.rec)), dtype=torch.float32, device=dev)
@@ -295,13 +297,18 @@ def iso_leg(dev, reps=2):
     ctx.profile(0)
     pts = wl.nx * wl.ny * wl.nz
     step_s = t / T
-    ach = 40.0 * pts / step_s / 1e9
-    return {"workload": wl.name, "run_s": round(t, 4), "gpts": round(pts * T / t / 1e9, 2),
-            "us_per_step": round(step_s * 1e6, 2), "tile": mm.tile_name(ctx.info()["tile"]),
-            "kernels_us_per_step": round(k_ms / max(k_n, 1) * 1e3, 2),
-            "roofline": {"bound": "hbm", "alg_bytes_per_point": 40, "achieved": round(ach, 1),
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                         "kernel_bytes_per_point": 56}}
+    from types import SimpleNamespace as NS
+    bytes_step = step_alg_bytes(NS(nx=wl.nx, ny=wl.ny, nz=wl.nz, bc=bc, nb=wl.nb), ALG_BYTES_ISO)
+    ach = bytes_step / step_s / 1e9
+    return {"workload": wl.name.replace("sponge", "cpml") if bc == 2 else wl.name, "run_s": round(t, 4),
+            "gpts": round(pts * T / t / 1e9, 2), "us_per_step": round(step_s * 1e6, 2),
+            "tile": mm.tile_name(ctx.info()["tile"]), "kernels_us_per_step": round(k_ms / max(k_n, 1) * 1e3, 2),
+            "roofline": {"bound": "hbm", "alg_bytes_per_point": round(bytes_step / pts, 3), "achieved": round(ach, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4)}}
+
+
+def iso_cpml_leg(dev, reps=2):
+    return iso_leg(dev, reps, bc=2)
 
 
 def free_surface_leg(dev, reps=2):
@@ -477,6 +484,9 @@ def main():
     ap.add_argument("--graph", action="store_true", help="launch the step loop as one HIP graph")
     ap.add_argument("--calib", action="store_true", help="also run a 1 GiB copy (counter calibration)")
     ap.add_argument("--time-steps", type=int, default=0, help="override the workload's step count (profiling)")
+    ap.add_argument("--legs", default="",
+                    help="comma-separated subset of the extra legs to run (cache_resident_240, gradient, batched, "
+                         "free_surface, acoustic_iso, acoustic_iso_cpml); default all")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 240^3, gradient, batched, free-surface and acoustic_iso legs")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -526,7 +536,7 @@ def main():
                 "us_per_step": round(t_run / T * 1e6, 2)}
 
     out = {
-        "metric": "Gpoint-updates/s and % HBM roofline (fwd)",
+        "metric": "Gpoint-updates/s and % HBM roofline (fwd); FWI gradient s/shot vs plain",
         "value": round(value, 3),
         "unit": "Gpt/s",
         "n_gpus": 1,
@@ -544,16 +554,16 @@ def main():
         "roofline": roof,
         "run_roofline": run_roof,
     }
-    if not args.no_extras:
-        out["cache_resident_240"] = cache_resident_leg(dev)
-        torch.cuda.empty_cache()
-        out["gradient"] = gradient_leg(dev)
-        torch.cuda.empty_cache()
-        out["batched"] = batched_leg(dev)
-        torch.cuda.empty_cache()
-        out["free_surface"] = free_surface_leg(dev)
-        torch.cuda.empty_cache()
-        out["acoustic_iso"] = iso_leg(dev)
+    legs = {"cache_resident_240": cache_resident_leg, "gradient": gradient_leg, "batched": batched_leg,
+            "free_surface": free_surface_leg, "acoustic_iso": iso_leg, "acoustic_iso_cpml": iso_cpml_leg}
+    if args.legs:
+        unknown = set(args.legs.split(",")) - set(legs)
+        if unknown:
+            raise SystemExit(f"unknown legs {sorted(unknown)}; known: {sorted(legs)}")
+    for name, leg in legs.items():
+        if args.no_extras or (args.legs and name not in args.legs.split(",")):
+            continue
+        out[name] = leg(dev)
         torch.cuda.empty_cache()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)

@@ -139,7 +139,8 @@ struct GroupTiles {
     int full_off = 0, nfull = 0;  // variant tiles over the whole grid: every step without forward CPML
     int in_off = 0, nin = 0;      // forward CPML: variant tiles of the interior boxes
     int st_off = 0, nst = 0;      // forward CPML: fused tiles of the frames (middle z range)
-    int zl_off = 0, nzl = 0;      // forward CPML: fused tiles of the z-layer chunks
+    int zl_off = 0, nzl = 0;      // forward CPML: fused tiles of the z-layer chunks that meet no x / y layer
+    int zc_off = 0, nzc = 0;      // forward CPML: fused tiles of the z-layer chunks that meet one
 };
 
 // Every tile list: the full lists of all groups first (so that one launch
@@ -190,13 +191,25 @@ void build_tiles(int variant, const mm_params& p, const std::vector<ShotGeom>& s
             tile_box(s, r.bx0, r.bx1, r.by1, ny, r.zlo, r.zhi, zlen, CW, CH, out); // high y
         }
         gt[k].nst = (int)out.size() - gt[k].st_off;
-        gt[k].zl_off = (int)out.size();
+        // z-layer chunks, split into the tiles away from the x / y layers and the corner tiles
+        std::vector<TileEnt> zl;
         for (int s = s0; s < s1; ++s) {
             const int nx = shots[s].nx, ny = shots[s].ny, nz = shots[s].nz;
-            if (!fs) tile_box(s, 0, nx, 0, ny, 0, nb, nb, CW, CH, out);
-            tile_box(s, 0, nx, 0, ny, nz - nb, nz, nb, CW, CH, out);
+            if (!fs) tile_box(s, 0, nx, 0, ny, 0, nb, nb, CW, CH, zl);
+            tile_box(s, 0, nx, 0, ny, nz - nb, nz, nb, CW, CH, zl);
         }
+        auto corner = [&](const TileEnt& t) {
+            const ShotGeom& g = shots[t.shot];
+            return t.x0 < nb || t.x1 > g.nx - nb || t.y0 < nb || t.y1 > g.ny - nb;
+        };
+        gt[k].zl_off = (int)out.size();
+        for (const TileEnt& t : zl)
+            if (!corner(t)) out.push_back(t);
         gt[k].nzl = (int)out.size() - gt[k].zl_off;
+        gt[k].zc_off = (int)out.size();
+        for (const TileEnt& t : zl)
+            if (corner(t)) out.push_back(t);
+        gt[k].nzc = (int)out.size() - gt[k].zc_off;
     }
 }
 
@@ -661,6 +674,7 @@ mm_status set_variant(mm_ctx* c, int v) {
         tile_flags(c, t.in_off, t.in_off + t.nin, c->p.nb, 0);
         tile_flags(c, t.st_off, t.st_off + t.nst, c->p.nb, 0);
         tile_flags(c, t.zl_off, t.zl_off + t.nzl, c->p.nb, TF_LZ);
+        tile_flags(c, t.zc_off, t.zc_off + t.nzc, c->p.nb, TF_LZ);
     }
     if ((int)c->tiles_h.size() > c->L.max_tiles) return fail(c, MM_ERR_WORKSPACE, "tile table overflow");
     MM_TRY(dev(c, hipStreamSynchronize(c->stream), "sync"));
@@ -754,21 +768,23 @@ mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, co
         c->prof_used += 2;
     }
     if (c->cpml && !c->iso && shots == c->d_shots) {
-        // forward CPML: the interior boxes (plain stencil), then the frames and the z-layer
-        // chunks (fused CPML kernel); the three write disjoint cells and read only p^n of the
-        // step, so their order is free; the receivers ride in the first launch that runs
+        // forward CPML: the interior boxes (plain stencil), then the frames, the z-layer tiles
+        // and the z-layer corner tiles (fused CPML kernel); the four write disjoint cells and
+        // read only p^n of the step, so their order is free; the receivers ride in the first
+        // launch that runs
         if (!g) return fail(c, MM_ERR_STATE, "forward CPML step without a shot group");
         const GroupTiles& t = g->t;
-        const int off[3] = {t.in_off, t.st_off, t.zl_off}, cnt[3] = {t.nin, t.nst, t.nzl};
+        const int off[4] = {t.in_off, t.st_off, t.zl_off, t.zc_off}, cnt[4] = {t.nin, t.nst, t.nzl, t.nzc};
+        const int kind[4] = {-1, CS_FRAME, CS_ZLAYER, CS_ZCORNER};
         int first = -1, last = -1;
-        for (int k = 0; k < 3; ++k)
+        for (int k = 0; k < 4; ++k)
             if (cnt[k] > 0) {
                 if (first < 0) first = k;
                 last = k;
             }
         StepAux a = aux;
         a.stream_loads = g->stream ? 1 : 0;
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 4; ++k) {
             if (cnt[k] <= 0) continue;
             StepAux ak = a;
             if (k != first) ak.gather_blocks = 0;
@@ -778,7 +794,7 @@ mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, co
                 MM_TRY(dev(c, launch_step(c->variant, MM_BC_NONE, mode, tl, cnt[k], shots, parity, c->cf, ak, s, e0, e1),
                            "stencil launch"));
             else
-                MM_TRY(dev(c, launch_cpml_step(k == 2, mode, tl, cnt[k], shots, parity, c->cf, ak, s, e0, e1),
+                MM_TRY(dev(c, launch_cpml_step(kind[k], mode, tl, cnt[k], shots, parity, c->cf, ak, s, e0, e1),
                            "cpml step launch"));
         }
         return MM_OK;

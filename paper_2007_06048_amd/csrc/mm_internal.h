@@ -116,13 +116,14 @@ int tile_rows(int t);  // TY of variant t
 hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int ntiles,
                        const ShotDev* shots, int parity, const Coefs& cf, const StepAux& aux,
                        hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-// Forward CPML step of the tiles that meet a layer, memory update included
-// (no launch_cpml before it): zlayer selects the launch over the z-layer
-// chunks [0, nb) and [nz - nb, nz) (every tile TF_LZ), else the tiles of the
-// middle z range flagged TF_LX / TF_LY.  mode MODE_PLAIN or MODE_D2P.  The
-// tiles are cstep_tile_w() x cstep_tile_h().
-hipError_t launch_cpml_step(bool zlayer, int mode, const TileEnt* tiles, int ntiles, const ShotDev* shots,
-                            int parity, const Coefs& cf, const StepAux& aux, hipStream_t s, hipEvent_t ev0 = nullptr,
+// Forward CPML step of the tiles that meet a layer, memory update included.
+// kind: CS_FRAME, the tiles of the middle z range (flagged TF_LX / TF_LY);
+// CS_ZLAYER, the tiles of the z-layer chunks [0, nb) and [nz - nb, nz) that
+// meet no x or y layer; CS_ZCORNER, those that do.  mode MODE_PLAIN or
+// MODE_D2P.  The tiles are cstep_tile_w() x cstep_tile_h().
+enum { CS_FRAME = 0, CS_ZLAYER = 1, CS_ZCORNER = 2 };
+hipError_t launch_cpml_step(int kind, int mode, const TileEnt* tiles, int ntiles, const ShotDev* shots, int parity,
+                            const Coefs& cf, const StepAux& aux, hipStream_t s, hipEvent_t ev0 = nullptr,
                             hipEvent_t ev1 = nullptr);
 int cstep_tile_w();
 int cstep_tile_h();

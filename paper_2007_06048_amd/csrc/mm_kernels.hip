@@ -493,7 +493,7 @@ hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int 
 // updated in place by the owner only.  Cells owned by the tile are
 // [x0, x1) x [y0, y1) x [z0, z1); the plane is staged over the full TX x TY
 // so the ring around the owned cells holds real p^n values.
-template <int TX, int RY, int NT, int PD, bool LZ, int MODE, bool STREAM>
+template <int TX, int RY, int NT, int PD, bool XY, bool LZ, int MODE, bool STREAM>
 __global__ __launch_bounds__(NT) void k_cstep(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd,
                                               const ShotDev* __restrict__ shots, int parity, Coefs cf,
                                               StepAux aux) {
@@ -535,7 +535,9 @@ __global__ __launch_bounds__(NT) void k_cstep(const TileEnt* __restrict__ tiles,
     float* __restrict__ wpz = parity ? sd.psi[2] : sd.corr[2];
     const long long pxs = (long long)ny * nb2, pys = (long long)nb2 * nx;  // slab planes of x and y
 
-    const bool tlx = (te.flags & TF_LX) != 0, tly = (te.flags & TF_LY) != 0;
+    // x / y layers only in the XY instantiations (the z-layer tiles away from the x and y faces
+    // run without that machinery, and its registers)
+    const bool tlx = XY && (te.flags & TF_LX) != 0, tly = XY && (te.flags & TF_LY) != 0;
     const bool wide = tlx || tly;  // block-uniform
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int x = te.x0 + tx;
@@ -897,33 +899,41 @@ constexpr int CS_TX = 32, CS_RY = 1, CS_NT = 512, CS_PD = 2;
 int cstep_tile_w() { return CS_TX; }
 int cstep_tile_h() { return (CS_NT / CS_TX) * CS_RY; }
 
-template <bool LZ, int MODE, bool STREAM>
+template <bool XY, bool LZ, int MODE, bool STREAM>
 static void launch_cstep_k(dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd, const ShotDev* shots, int parity,
                            const Coefs& cf, const StepAux& aux, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const dim3 block(CS_TX, CS_NT / CS_TX);
-    hipExtLaunchKernelGGL(k_cstep<CS_TX, CS_RY, CS_NT, CS_PD, LZ, MODE, STREAM>, grid, block, 0, s, ev0, ev1, 0, tiles,
-                          ntiles, per_xcd, shots, parity, cf, aux);
+    hipExtLaunchKernelGGL(k_cstep<CS_TX, CS_RY, CS_NT, CS_PD, XY, LZ, MODE, STREAM>, grid, block, 0, s, ev0, ev1, 0,
+                          tiles, ntiles, per_xcd, shots, parity, cf, aux);
 }
 
-hipError_t launch_cpml_step(bool zlayer, int mode, const TileEnt* tiles, int ntiles, const ShotDev* shots,
-                            int parity, const Coefs& cf, const StepAux& aux, hipStream_t s, hipEvent_t ev0,
-                            hipEvent_t ev1) {
+template <bool XY, bool LZ>
+static void launch_cstep_m(int mode, bool st, dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd,
+                           const ShotDev* shots, int parity, const Coefs& cf, const StepAux& aux, hipStream_t s,
+                           hipEvent_t ev0, hipEvent_t ev1) {
+    if (mode == MODE_D2P)
+        launch_cstep_k<XY, LZ, MODE_D2P, false>(grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0, ev1);
+    else if (st)
+        launch_cstep_k<XY, LZ, MODE_PLAIN, true>(grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0, ev1);
+    else
+        launch_cstep_k<XY, LZ, MODE_PLAIN, false>(grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0, ev1);
+}
+
+hipError_t launch_cpml_step(int kind, int mode, const TileEnt* tiles, int ntiles, const ShotDev* shots, int parity,
+                            const Coefs& cf, const StepAux& aux, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (ntiles <= 0) return hipSuccess;
     if (mode != MODE_PLAIN && mode != MODE_D2P) return hipErrorInvalidValue;
     const int per_xcd = (ntiles + 7) / 8;
     const dim3 grid(8 * per_xcd + aux.gather_blocks);
     const bool st = aux.stream_loads != 0 && mode == MODE_PLAIN;
-#define MM_CS(LZ_, M_, S_) launch_cstep_k<LZ_, M_, S_>(grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0, ev1)
-    if (zlayer) {
-        if (mode == MODE_D2P) MM_CS(true, MODE_D2P, false);
-        else if (st) MM_CS(true, MODE_PLAIN, true);
-        else MM_CS(true, MODE_PLAIN, false);
-    } else {
-        if (mode == MODE_D2P) MM_CS(false, MODE_D2P, false);
-        else if (st) MM_CS(false, MODE_PLAIN, true);
-        else MM_CS(false, MODE_PLAIN, false);
-    }
-#undef MM_CS
+    if (kind == CS_FRAME)
+        launch_cstep_m<true, false>(mode, st, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0, ev1);
+    else if (kind == CS_ZLAYER)
+        launch_cstep_m<false, true>(mode, st, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0, ev1);
+    else if (kind == CS_ZCORNER)
+        launch_cstep_m<true, true>(mode, st, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0, ev1);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -4,7 +4,8 @@
 // grid shapes (ragged, minimal, one GPU's production share), each cell of a
 // shot is written by exactly one tile of the full list and exactly one tile
 // of the forward CPML lists; interior tiles hold no layer cell, frame tiles
-// no z-layer cell, z-layer tiles are exactly the layers; no tile is larger
+// no z-layer cell, z-layer tiles are exactly the layers (split into those
+// that meet an x or y layer and those that do not); no tile is larger
 // than its launch's shape or leaves the grid.  Run by
 // tests/test_host_sanitize.py (optimised, without the sanitizers: it visits
 // every cell of every plan).
@@ -71,6 +72,14 @@ int main() {
                     mark(fwd, gt[gi].in_off, gt[gi].nin, 1);
                     mark(fwd, gt[gi].st_off, gt[gi].nst, 2);
                     mark(fwd, gt[gi].zl_off, gt[gi].nzl, 3);
+                    mark(fwd, gt[gi].zc_off, gt[gi].nzc, 3);
+                    // z-layer tiles: the plain ones meet no x / y layer, the corner ones do
+                    for (int c = 0; c < 2; ++c)
+                        for (int i = 0; i < (c ? gt[gi].nzc : gt[gi].nzl); ++i) {
+                            const TileEnt& t = out[(c ? gt[gi].zc_off : gt[gi].zl_off) + i];
+                            const bool meets = t.x0 < p.nb || t.x1 > g.nx - p.nb || t.y0 < p.nb || t.y1 > g.ny - p.nb;
+                            if (meets != (c == 1)) err("z-layer tile in the wrong list", t.x0, t.y0, c);
+                        }
                     for (size_t i = 0; i < full.size(); ++i)
                         if (full[i] != 1 || fwd[i] != 1) err("cell not written once", (int)i, full[i], fwd[i]);
                     ++cases;
