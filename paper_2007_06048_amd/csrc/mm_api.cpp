@@ -158,7 +158,9 @@ void build_tiles(int variant, const mm_params& p, const std::vector<ShotGeom>& s
     }
     if (p.bc != MM_BC_CPML || p.model != MM_MODEL_ISO_CD) return;
     const int TX = tile_variant(variant).tx, TY = tile_rows(variant);
-    const int CW = cstep_tile_w(), CH = cstep_tile_h(), nb = p.nb;
+    const int CW = cstep_tile_w(CS_FRAME), CH = cstep_tile_h(CS_FRAME), nb = p.nb;
+    const int ZW = cstep_tile_w(CS_ZLAYER), ZH = cstep_tile_h(CS_ZLAYER);
+    const int CZW = cstep_tile_w(CS_ZCORNER), CZH = cstep_tile_h(CS_ZCORNER);
     const bool fs = p.free_surface != 0;
     for (size_t k = 0; k < groups.size(); ++k) {
         const int s0 = groups[k].first, s1 = groups[k].second;
@@ -191,24 +193,34 @@ void build_tiles(int variant, const mm_params& p, const std::vector<ShotGeom>& s
             tile_box(s, r.bx0, r.bx1, r.by1, ny, r.zlo, r.zhi, zlen, CW, CH, out); // high y
         }
         gt[k].nst = (int)out.size() - gt[k].st_off;
-        // z-layer chunks, split into the tiles away from the x / y layers and the corner tiles
-        std::vector<TileEnt> zl;
-        for (int s = s0; s < s1; ++s) {
-            const int nx = shots[s].nx, ny = shots[s].ny, nz = shots[s].nz;
-            if (!fs) tile_box(s, 0, nx, 0, ny, 0, nb, nb, CW, CH, zl);
-            tile_box(s, 0, nx, 0, ny, nz - nb, nz, nb, CW, CH, zl);
-        }
-        auto corner = [&](const TileEnt& t) {
-            const ShotGeom& g = shots[t.shot];
-            return t.x0 < nb || t.x1 > g.nx - nb || t.y0 < nb || t.y1 > g.ny - nb;
-        };
+        // z-layer chunks: the box away from the x / y layers (its x range on a 32-cell grid,
+        // like the interior box) in tiles of the z-layer kind, the frame around it in corner
+        // tiles
         gt[k].zl_off = (int)out.size();
-        for (const TileEnt& t : zl)
-            if (!corner(t)) out.push_back(t);
+        for (int s = s0; s < s1; ++s) {
+            const ShotGeom& g = shots[s];
+            const int zx0 = std::min(g.nx, (nb + 31) / 32 * 32);
+            const int zx1 = zx0 + ZW * (std::max(0, g.nx - nb - zx0) / ZW);
+            const int zy0 = std::min(g.ny, nb), zy1 = zy0 + ZH * (std::max(0, g.ny - nb - zy0) / ZH);
+            if (!fs) tile_box(s, zx0, zx1, zy0, zy1, 0, nb, nb, ZW, ZH, out);
+            tile_box(s, zx0, zx1, zy0, zy1, g.nz - nb, g.nz, nb, ZW, ZH, out);
+        }
         gt[k].nzl = (int)out.size() - gt[k].zl_off;
         gt[k].zc_off = (int)out.size();
-        for (const TileEnt& t : zl)
-            if (corner(t)) out.push_back(t);
+        for (int s = s0; s < s1; ++s) {
+            const ShotGeom& g = shots[s];
+            const int zx0 = std::min(g.nx, (nb + 31) / 32 * 32);
+            const int zx1 = zx0 + ZW * (std::max(0, g.nx - nb - zx0) / ZW);
+            const int zy0 = std::min(g.ny, nb), zy1 = zy0 + ZH * (std::max(0, g.ny - nb - zy0) / ZH);
+            for (int c = 0; c < 2; ++c) {
+                if (c == 0 && fs) continue;
+                const int za = c == 0 ? 0 : g.nz - nb, zb = c == 0 ? nb : g.nz;
+                tile_box(s, 0, zx0, 0, g.ny, za, zb, nb, CZW, CZH, out);         // low x
+                tile_box(s, zx1, g.nx, 0, g.ny, za, zb, nb, CZW, CZH, out);      // high x
+                tile_box(s, zx0, zx1, 0, zy0, za, zb, nb, CZW, CZH, out);        // low y
+                tile_box(s, zx0, zx1, zy1, g.ny, za, zb, nb, CZW, CZH, out);     // high y
+            }
+        }
         gt[k].nzc = (int)out.size() - gt[k].zc_off;
     }
 }

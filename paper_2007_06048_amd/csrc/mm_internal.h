@@ -120,13 +120,13 @@ hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int 
 // kind: CS_FRAME, the tiles of the middle z range (flagged TF_LX / TF_LY);
 // CS_ZLAYER, the tiles of the z-layer chunks [0, nb) and [nz - nb, nz) that
 // meet no x or y layer; CS_ZCORNER, those that do.  mode MODE_PLAIN or
-// MODE_D2P.  The tiles are cstep_tile_w() x cstep_tile_h().
+// MODE_D2P.  The tiles of each kind are cstep_tile_w(kind) x cstep_tile_h(kind).
 enum { CS_FRAME = 0, CS_ZLAYER = 1, CS_ZCORNER = 2 };
 hipError_t launch_cpml_step(int kind, int mode, const TileEnt* tiles, int ntiles, const ShotDev* shots, int parity,
                             const Coefs& cf, const StepAux& aux, hipStream_t s, hipEvent_t ev0 = nullptr,
                             hipEvent_t ev1 = nullptr);
-int cstep_tile_w();
-int cstep_tile_h();
+int cstep_tile_w(int kind);
+int cstep_tile_h(int kind);
 // Adjoint CPML memory update and corrections of every shot for this step,
 // before the adjoint stencil kernel: the transposed memory recursions and a
 // correction reaching 4 cells past the layer (nb <= 64).  The block table

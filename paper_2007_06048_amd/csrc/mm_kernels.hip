@@ -893,18 +893,25 @@ __global__ __launch_bounds__(NT) void k_cstep(const TileEnt* __restrict__ tiles,
     }
 }
 
-// fixed shape of the fused CPML kernel: 32-wide, 16-row tiles of 512 threads (one row each), loads two
-// planes ahead
-constexpr int CS_TX = 32, CS_RY = 1, CS_NT = 512, CS_PD = 2;
-int cstep_tile_w() { return CS_TX; }
-int cstep_tile_h() { return (CS_NT / CS_TX) * CS_RY; }
+// shape of the fused CPML kernel: 32-wide tiles, one row per thread, loads two planes ahead
+constexpr int CS_TX = 32, CS_RY = 1, CS_PD = 2;
+// threads per block of each launch kind (frame, z layer, z-layer corners)
+constexpr int CS_NT_FRAME = 512, CS_NT_ZLAYER = 512, CS_NT_ZCORNER = 512;
+template <bool XY, bool LZ>
+constexpr int cs_nt() { return !LZ ? CS_NT_FRAME : (XY ? CS_NT_ZCORNER : CS_NT_ZLAYER); }
+int cstep_tile_w(int kind) { return CS_TX; }
+int cstep_tile_h(int kind) {
+    const int nt = kind == CS_FRAME ? CS_NT_FRAME : (kind == CS_ZLAYER ? CS_NT_ZLAYER : CS_NT_ZCORNER);
+    return (nt / CS_TX) * CS_RY;
+}
 
 template <bool XY, bool LZ, int MODE, bool STREAM>
 static void launch_cstep_k(dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd, const ShotDev* shots, int parity,
                            const Coefs& cf, const StepAux& aux, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    const dim3 block(CS_TX, CS_NT / CS_TX);
-    hipExtLaunchKernelGGL(k_cstep<CS_TX, CS_RY, CS_NT, CS_PD, XY, LZ, MODE, STREAM>, grid, block, 0, s, ev0, ev1, 0,
-                          tiles, ntiles, per_xcd, shots, parity, cf, aux);
+    constexpr int NT = cs_nt<XY, LZ>();
+    const dim3 block(CS_TX, NT / CS_TX);
+    hipExtLaunchKernelGGL(k_cstep<CS_TX, CS_RY, NT, CS_PD, XY, LZ, MODE, STREAM>, grid, block, 0, s, ev0, ev1, 0, tiles,
+                          ntiles, per_xcd, shots, parity, cf, aux);
 }
 
 template <bool XY, bool LZ>

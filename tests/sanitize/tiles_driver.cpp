@@ -5,7 +5,7 @@
 // shot is written by exactly one tile of the full list and exactly one tile
 // of the forward CPML lists; interior tiles hold no layer cell, frame tiles
 // no z-layer cell, z-layer tiles are exactly the layers (split into those
-// that meet an x or y layer and those that do not); no tile is larger
+// that may meet an x or y layer and those that do not); no tile is larger
 // than its launch's shape or leaves the grid.  Run by
 // tests/test_host_sanitize.py (optimised, without the sanitizers: it visits
 // every cell of every plan).
@@ -24,7 +24,8 @@ int main() {
                                                   {37, 29, 23, 5},    {28, 28, 28, 12},   {100, 33, 41, 8},
                                                   {257, 75, 70, 33},  {16, 16, 16, 6},    {129, 65, 40, 16},
                                                   {45, 300, 30, 10}};
-    const int CW = cstep_tile_w(), CH = cstep_tile_h();
+    const int CW = cstep_tile_w(CS_FRAME), CH = cstep_tile_h(CS_FRAME);
+    const int ZW = cstep_tile_w(CS_ZLAYER), ZH = cstep_tile_h(CS_ZLAYER);
     for (const auto& d : dims)
         for (int fs = 0; fs < 2; ++fs)
             for (int v = 0; v < num_tile_variants(); ++v) {
@@ -52,7 +53,8 @@ int main() {
                                 t.x1 <= t.x0 || t.y1 <= t.y0 || t.z1 <= t.z0)
                                 err("tile outside the grid", t.x0, t.y0, t.z0);
                             const bool var = kind <= 1;
-                            if (t.x1 - t.x0 > (var ? TX : CW) || t.y1 - t.y0 > (var ? TY : CH))
+                            const int tw = var ? TX : std::max(CW, ZW), th = var ? TY : std::max(CH, ZH);
+                            if (t.x1 - t.x0 > tw || t.y1 - t.y0 > th)
                                 err("tile larger than its shape", t.x1 - t.x0, t.y1 - t.y0, kind);
                             if (kind == 3 && !((t.z0 == 0 && t.z1 == p.nb && !fs) || (t.z0 == g.nz - p.nb && t.z1 == g.nz)))
                                 err("z-layer chunk", t.z0, t.z1, fs);
@@ -73,13 +75,12 @@ int main() {
                     mark(fwd, gt[gi].st_off, gt[gi].nst, 2);
                     mark(fwd, gt[gi].zl_off, gt[gi].nzl, 3);
                     mark(fwd, gt[gi].zc_off, gt[gi].nzc, 3);
-                    // z-layer tiles: the plain ones meet no x / y layer, the corner ones do
-                    for (int c = 0; c < 2; ++c)
-                        for (int i = 0; i < (c ? gt[gi].nzc : gt[gi].nzl); ++i) {
-                            const TileEnt& t = out[(c ? gt[gi].zc_off : gt[gi].zl_off) + i];
-                            const bool meets = t.x0 < p.nb || t.x1 > g.nx - p.nb || t.y0 < p.nb || t.y1 > g.ny - p.nb;
-                            if (meets != (c == 1)) err("z-layer tile in the wrong list", t.x0, t.y0, c);
-                        }
+                    // z-layer tiles of the plain list (no x / y memory code) meet no x / y layer
+                    for (int i = 0; i < gt[gi].nzl; ++i) {
+                        const TileEnt& t = out[gt[gi].zl_off + i];
+                        if (t.x0 < p.nb || t.x1 > g.nx - p.nb || t.y0 < p.nb || t.y1 > g.ny - p.nb)
+                            err("z-layer tile with x / y layer cells in the plain list", t.x0, t.y0, t.z0);
+                    }
                     for (size_t i = 0; i < full.size(); ++i)
                         if (full[i] != 1 || fwd[i] != 1) err("cell not written once", (int)i, full[i], fwd[i]);
                     ++cases;
