@@ -34,6 +34,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# names of the forward CPML strategies (mm_get_cpml_kernel)
+CPML_NAMES = {0: None, 1: "layer pass + stencil", 2: "fused"}
 ALG_BYTES_STENCIL = 16  # read p^n, p^{n-1}, (dt v)^2; write p^{n+1}  (bytes per grid point)
 ALG_BYTES_ISO = 40      # acoustic_iso: read and write p and the three face velocities, read rho v^2 and buoyancy
 
@@ -361,6 +363,7 @@ def batched_leg(dev, reps=2):
 
     t_batch = _timed(batch, reps)
     tile = mm.tile_name(ctx.info()["tile"])
+    cpml = CPML_NAMES[ctx.cpml_kernel()]
     del ctx, tr
     torch.cuda.empty_cache()
     singles = []
@@ -377,6 +380,7 @@ def batched_leg(dev, reps=2):
 
     t_seq = _timed(seq, reps)
     return {"workload": wl.name, "shots": len(wl.shots), "points": pts, "time_steps": T, "tile": tile,
+            "cpml_kernel": cpml,
             "batched_graph_s": round(t_batch, 4), "batched_gpts": round(pts * T / t_batch / 1e9, 2),
             "sequential_single_s": round(t_seq, 4), "sequential_gpts": round(pts * T / t_seq / 1e9, 2),
             "speedup": round(t_seq / t_batch, 3)}
@@ -420,7 +424,8 @@ def run_forward_workload(dev, wl, tile=-1, graph=False, steps=1, warmup=1, prof_
     t1 = time.perf_counter()
     k_ms, k_n = (ctx.profile_read() if prof_stride > 0 and not graph else (0.0, 0))
     ctx.profile(0)
-    info = {"tile": mm.tile_name(ctx.info()["tile"]), "init_s": round(t_init, 3), "dt_s": dt}
+    info = {"tile": mm.tile_name(ctx.info()["tile"]), "cpml_kernel": CPML_NAMES[ctx.cpml_kernel()],
+            "init_s": round(t_init, 3), "dt_s": dt}
     del ctx, traces, vel
     torch.cuda.empty_cache()
     return info, (t1 - t0) / steps, k_ms, k_n
@@ -463,6 +468,7 @@ def cache_resident_leg(dev, reps=2):
     info, t, k_ms, k_n = run_forward_workload(dev, wl, steps=reps, warmup=1)
     out = {"workload": wl.name, "run_s": round(t, 4),
            "gpts": round(wl.nx * wl.ny * wl.nz * wl.nsteps / t / 1e9, 2), "tile": info["tile"],
+           "cpml_kernel": info["cpml_kernel"],
            "note": "working set about 250 MB: Infinity-Cache resident, not an HBM figure"}
     if k_n > 0:
         out["roofline"] = step_roofline(wl, ALG_BYTES_STENCIL, k_ms / k_n, k_n, 10, step_kernels_name(wl, False))
@@ -550,7 +556,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "grid": [wl.nx, wl.ny, wl.nz], "time_steps_per_run": T, "h_m": wl.h,
                    "bc": {0: "none", 1: "sponge", 2: "cpml"}[wl.bc], "nb": wl.nb, "receivers": len(s.rec),
-                   "tile": info["tile"], "graph": bool(args.graph), "init_s": info["init_s"], "dt_s": info["dt_s"]},
+                   "tile": info["tile"], "cpml_kernel": info["cpml_kernel"], "graph": bool(args.graph), "init_s": info["init_s"], "dt_s": info["dt_s"]},
         "roofline": roof,
         "run_roofline": run_roof,
     }

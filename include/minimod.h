@@ -104,6 +104,20 @@ typedef enum { MM_BC_NONE = 0, MM_BC_SPONGE = 1, MM_BC_CPML = 2 } mm_bc;
  *    evaluated at the face's or cell's own depth in the layer. */
 typedef enum { MM_MODEL_ISO_CD = 0, MM_MODEL_ISO = 1 } mm_model;
 
+/* Forward CPML strategy of acoustic_iso_cd (mm_params.cpml_kernel).  Both
+ * compute the same update (section "Finite Differences", CPML); they differ
+ * in the kernels and in the order the layer terms are summed, so results
+ * agree to rounding. */
+typedef enum {
+    MM_CPML_AUTO = 0,  /* tuned with the tile variant when tile == -1, else the layer pass when 30 % or
+                          more of the cells lie in a damping layer */
+    MM_CPML_LAYER = 1, /* a layer kernel updates the memory of every layer cell and writes a
+                          correction that the stencil kernel over the whole grid adds (best when the
+                          layers hold a large share of the cells) */
+    MM_CPML_FUSED = 2  /* the stencil kernel runs the interior, a fused kernel the cells near the faces
+                          with their memory update in the same pass (no correction array) */
+} mm_cpml_kernel;
+
 /* Snapshot storage of the gradient's checkpoints. */
 typedef enum {
     MM_SNAP_FP32 = 0, /* lossless */
@@ -148,6 +162,7 @@ typedef struct {
                                 device (one extra read of the field, no synchronisation); the first
                                 such step is kept and reported by mm_watch (and by mm_gradient) as
                                 MM_ERR_NONFINITE.  0 => off */
+    int32_t cpml_kernel;     /* mm_cpml_kernel; 0 => MM_CPML_AUTO */
 } mm_params;
 
 /* One shot of a batched context. */
@@ -297,13 +312,18 @@ mm_status mm_set_state(mm_ctx* ctx, const void* src_dev, int32_t step);
  * Any output pointer may be NULL. */
 mm_status mm_get_info(const mm_ctx* ctx, double* dt, int32_t* step, int32_t* tile, int32_t* ngroups);
 
+/* The forward CPML strategy in use (MM_CPML_LAYER or MM_CPML_FUSED; MM_CPML_AUTO
+ * for other boundaries and for acoustic_iso). */
+mm_status mm_get_cpml_kernel(const mm_ctx* ctx, int32_t* kernel);
+
 /* Pick the stencil tile variant by timing each candidate on this context
  * (state is zeroed afterwards; synchronises).  steps_per_trial (>= 1) is a
  * minimum: it is raised so that one trial lasts about 2 ms (at most 200
  * steps); every variant is timed once and the four fastest twice more,
- * interleaved, keeping each one's best time.  Results are cached per (grid,
- * boundary, model, grouping) for the life of the process.  *tile_out may be
- * NULL. */
+ * interleaved, keeping each one's best time; with MM_CPML_AUTO the four
+ * are also timed in the other forward CPML strategy, which is kept if it
+ * wins.  Results are cached per (grid, boundary, model, grouping) for the
+ * life of the process.  *tile_out may be NULL. */
 mm_status mm_autotune(mm_ctx* ctx, int32_t steps_per_trial, int32_t* tile_out);
 
 /* Force a tile variant (0 = default).  Returns MM_ERR_ARG if unknown. */

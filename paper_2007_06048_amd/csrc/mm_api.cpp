@@ -113,26 +113,30 @@ void tile_box(int s, int bx0, int bx1, int by0, int by1, int z0, int z1, int zle
 }
 
 // Forward CPML regions of a shot: the interior box [bx0, bx1) x [by0, by1) x
-// [zlo, zhi) holds no layer cell and is a whole number of TX x TY tiles
-// (bx0 rounded up to 32 cells keeps its rows 128-byte aligned); the frame
-// around it in the middle z range [zlo, zhi) and the z-layer chunks [0, nb)
-// (none under a free surface) and [nz - nb, nz) belong to the fused CPML kernel.
+// [zlo, zhi) is exactly the cells outside every layer (its last tiles are
+// clipped to it); the frame around it in the middle z range [zlo, zhi) and
+// the z-layer chunks [0, nb) (none under a free surface) and [nz - nb, nz)
+// belong to the fused CPML kernel.
 struct CpmlRegions {
     int bx0, bx1, by0, by1, zlo, zhi;
 };
 
-CpmlRegions cpml_regions(const ShotGeom& g, int nb, bool fs, int TX, int TY) {
+CpmlRegions cpml_regions(const ShotGeom& g, int nb, bool fs) {
     CpmlRegions r;
-    r.bx0 = std::min(g.nx, (nb + 31) / 32 * 32);
-    r.bx1 = r.bx0 + TX * (std::max(0, g.nx - nb - r.bx0) / TX);
+    r.bx0 = std::min(g.nx, nb);
+    r.bx1 = std::max(r.bx0, g.nx - nb);
     r.by0 = std::min(g.ny, nb);
-    r.by1 = r.by0 + TY * (std::max(0, g.ny - nb - r.by0) / TY);
+    r.by1 = std::max(r.by0, g.ny - nb);
     r.zlo = fs ? 0 : nb;
     r.zhi = g.nz - nb;
     return r;
 }
 
 constexpr int kStripTarget = 2048;  // blocks of a group's strip launch (z-chunking of the frame)
+// Below this many fused-kernel tiles in a group, its frame, z-layer and corner tiles go in one
+// launch: each kind alone leaves most of the chip idle while its blocks march through z, and
+// one launch lets the three overlap.
+constexpr int kMergeTiles = 4096;
 
 // Where the tile lists of one shot group sit in the tile table.
 struct GroupTiles {
@@ -141,6 +145,7 @@ struct GroupTiles {
     int st_off = 0, nst = 0;      // forward CPML: fused tiles of the frames (middle z range)
     int zl_off = 0, nzl = 0;      // forward CPML: fused tiles of the z-layer chunks that meet no x / y layer
     int zc_off = 0, nzc = 0;      // forward CPML: fused tiles of the z-layer chunks that meet one
+    bool merged() const { return nst + nzl + nzc < kMergeTiles; }  // the three lists are consecutive
 };
 
 // Every tile list: the full lists of all groups first (so that one launch
@@ -167,8 +172,8 @@ void build_tiles(int variant, const mm_params& p, const std::vector<ShotGeom>& s
         // interior boxes, z-chunked towards the variant's block target
         long long xy = 0, sxy = 0;
         for (int s = s0; s < s1; ++s) {
-            const CpmlRegions r = cpml_regions(shots[s], nb, fs, TX, TY);
-            xy += (long long)((r.bx1 - r.bx0) / TX) * ((r.by1 - r.by0) / TY);
+            const CpmlRegions r = cpml_regions(shots[s], nb, fs);
+            xy += (long long)((r.bx1 - r.bx0 + TX - 1) / TX) * ((r.by1 - r.by0 + TY - 1) / TY);
             const int nx = shots[s].nx, ny = shots[s].ny;
             sxy += (long long)((r.bx0 + CW - 1) / CW + (nx - r.bx1 + CW - 1) / CW) * ((ny + CH - 1) / CH) +
                    (long long)((r.bx1 - r.bx0 + CW - 1) / CW) * ((r.by0 + CH - 1) / CH + (ny - r.by1 + CH - 1) / CH);
@@ -177,14 +182,14 @@ void build_tiles(int variant, const mm_params& p, const std::vector<ShotGeom>& s
         const long long sch = std::max(1LL, sxy > 0 ? (kStripTarget + sxy - 1) / sxy : 1);
         gt[k].in_off = (int)out.size();
         for (int s = s0; s < s1; ++s) {
-            const CpmlRegions r = cpml_regions(shots[s], nb, fs, TX, TY);
+            const CpmlRegions r = cpml_regions(shots[s], nb, fs);
             const int zlen = std::max(4, (int)((r.zhi - r.zlo + nch - 1) / nch));
             tile_box(s, r.bx0, r.bx1, r.by0, r.by1, r.zlo, r.zhi, zlen, TX, TY, out);
         }
         gt[k].nin = (int)out.size() - gt[k].in_off;
         gt[k].st_off = (int)out.size();
         for (int s = s0; s < s1; ++s) {
-            const CpmlRegions r = cpml_regions(shots[s], nb, fs, TX, TY);
+            const CpmlRegions r = cpml_regions(shots[s], nb, fs);
             const int nx = shots[s].nx, ny = shots[s].ny;
             const int zlen = std::max(16, (int)((r.zhi - r.zlo + sch - 1) / sch));
             tile_box(s, 0, r.bx0, 0, ny, r.zlo, r.zhi, zlen, CW, CH, out);         // low x
@@ -193,32 +198,27 @@ void build_tiles(int variant, const mm_params& p, const std::vector<ShotGeom>& s
             tile_box(s, r.bx0, r.bx1, r.by1, ny, r.zlo, r.zhi, zlen, CW, CH, out); // high y
         }
         gt[k].nst = (int)out.size() - gt[k].st_off;
-        // z-layer chunks: the box away from the x / y layers (its x range on a 32-cell grid,
-        // like the interior box) in tiles of the z-layer kind, the frame around it in corner
-        // tiles
+        // z-layer chunks: the box away from the x / y layers (the interior box's xy range) in
+        // tiles of the z-layer kind, the frame around it in corner tiles
         gt[k].zl_off = (int)out.size();
         for (int s = s0; s < s1; ++s) {
             const ShotGeom& g = shots[s];
-            const int zx0 = std::min(g.nx, (nb + 31) / 32 * 32);
-            const int zx1 = zx0 + ZW * (std::max(0, g.nx - nb - zx0) / ZW);
-            const int zy0 = std::min(g.ny, nb), zy1 = zy0 + ZH * (std::max(0, g.ny - nb - zy0) / ZH);
-            if (!fs) tile_box(s, zx0, zx1, zy0, zy1, 0, nb, nb, ZW, ZH, out);
-            tile_box(s, zx0, zx1, zy0, zy1, g.nz - nb, g.nz, nb, ZW, ZH, out);
+            const CpmlRegions r = cpml_regions(g, nb, fs);
+            if (!fs) tile_box(s, r.bx0, r.bx1, r.by0, r.by1, 0, nb, nb, ZW, ZH, out);
+            tile_box(s, r.bx0, r.bx1, r.by0, r.by1, g.nz - nb, g.nz, nb, ZW, ZH, out);
         }
         gt[k].nzl = (int)out.size() - gt[k].zl_off;
         gt[k].zc_off = (int)out.size();
         for (int s = s0; s < s1; ++s) {
             const ShotGeom& g = shots[s];
-            const int zx0 = std::min(g.nx, (nb + 31) / 32 * 32);
-            const int zx1 = zx0 + ZW * (std::max(0, g.nx - nb - zx0) / ZW);
-            const int zy0 = std::min(g.ny, nb), zy1 = zy0 + ZH * (std::max(0, g.ny - nb - zy0) / ZH);
+            const CpmlRegions r = cpml_regions(g, nb, fs);
             for (int c = 0; c < 2; ++c) {
                 if (c == 0 && fs) continue;
                 const int za = c == 0 ? 0 : g.nz - nb, zb = c == 0 ? nb : g.nz;
-                tile_box(s, 0, zx0, 0, g.ny, za, zb, nb, CZW, CZH, out);         // low x
-                tile_box(s, zx1, g.nx, 0, g.ny, za, zb, nb, CZW, CZH, out);      // high x
-                tile_box(s, zx0, zx1, 0, zy0, za, zb, nb, CZW, CZH, out);        // low y
-                tile_box(s, zx0, zx1, zy1, g.ny, za, zb, nb, CZW, CZH, out);     // high y
+                tile_box(s, 0, r.bx0, 0, g.ny, za, zb, nb, CZW, CZH, out);         // low x
+                tile_box(s, r.bx1, g.nx, 0, g.ny, za, zb, nb, CZW, CZH, out);      // high x
+                tile_box(s, r.bx0, r.bx1, 0, r.by0, za, zb, nb, CZW, CZH, out);    // low y
+                tile_box(s, r.bx0, r.bx1, r.by1, g.ny, za, zb, nb, CZW, CZH, out); // high y
             }
         }
         gt[k].nzc = (int)out.size() - gt[k].zc_off;
@@ -230,7 +230,7 @@ struct Layout {
     size_t shots_dev = 0, shots_adj = 0, tiles = 0, scratch = 0;
     int max_tiles = 0;
     std::vector<size_t> buf0, buf1, vdt2, prof, ebuf0, ebuf1;
-    std::vector<size_t> psi[3], zeta[3], corr[3];
+    std::vector<size_t> psi[3], psi2[3], zeta[3], corr[3];
     std::vector<size_t> apsi[3], azeta[3], acorr[3];  // CPML adjoint memory and corrections
     std::vector<size_t> iso_u[3], iso_b;              // acoustic_iso face velocities, rho / dt
     size_t src_shot = 0, src_off = 0, src_start = 0, src_col = 0, src_g = 0;
@@ -287,7 +287,9 @@ void compute_layout(const mm_params& p, const std::vector<ShotGeom>& shots, int 
         for (int a = 0; a < 3; ++a) {
             L.psi[a].push_back(c ? take(L, sizeof(float) * sl[a]) : 0);
             L.zeta[a].push_back(c ? take(L, sizeof(float) * sl[a]) : 0);
-            // the second psi buffer of the forward CPML step (acoustic_iso updates its memory in place)
+            // the second psi buffer of the forward CPML step and the layer pass's corrections
+            // (acoustic_iso updates its memory in place and needs neither)
+            L.psi2[a].push_back(c && p.model != MM_MODEL_ISO ? take(L, sizeof(float) * sl[a]) : 0);
             L.corr[a].push_back(c && p.model != MM_MODEL_ISO ? take(L, sizeof(float) * sl[a]) : 0);
             L.apsi[a].push_back(ca ? take(L, sizeof(float) * sl[a]) : 0);
             L.azeta[a].push_back(ca ? take(L, sizeof(float) * sl[a]) : 0);
@@ -313,7 +315,8 @@ void compute_layout(const mm_params& p, const std::vector<ShotGeom>& shots, int 
     L.rg_off = take(L, sizeof(long long) * nrec);
     L.sg_shot = take(L, sizeof(int) * nsrc);
     L.sg_off = take(L, sizeof(long long) * nsrc);
-    L.cpml_off = take(L, sizeof(int) * 3 * (S + 1));  // block table of the adjoint CPML kernel
+    // block tables of the CPML layer kernels: the adjoint's (every shot), then one per group (forward)
+    L.cpml_off = take(L, sizeof(int) * 3 * (2 * S + 1 + (int)groups.size()));
     if (L.grad) {
         const long long N = shots[0].n();
         const int K = p.ckpt_every;
@@ -440,8 +443,14 @@ struct mm_ctx {
         int rec0, rec1;        // receivers (columns of a trace row)
         int cell0, cell1;      // source cells of the injection table
         bool stream = false;   // working set beyond the Infinity Cache (StepAux::stream_loads)
+        std::vector<int> cpml_h;   // block table of the layer pass over the group's shots (host copy)
+        const int* cpml_d = nullptr;
     };
     std::vector<Group> groups;
+    // forward CPML strategy (acoustic_iso_cd): the layer pass, then the stencil over the whole
+    // grid adding its corrections (true); or the interior stencil and the fused kernel over the
+    // cells near the faces (false)
+    bool layer_pass = false;
     bool stream_all = false;      // the same for all shots together (adjoint steps)
     std::vector<int> cpml_adj_h;  // CPML block table of the adjoint (all shots, width nb + 4)
     const int* cpml_adj_d = nullptr;
@@ -547,6 +556,7 @@ mm_status check_params(const mm_params* p, mm_ctx* c) {
     if (p->model != MM_MODEL_ISO_CD && p->model != MM_MODEL_ISO) return fail(c, MM_ERR_ARG, "unknown model");
     if (p->cache_hints < 0 || p->cache_hints > 2) return fail(c, MM_ERR_ARG, "cache_hints must be 0, 1 or 2");
     if (p->watch_every < 0) return fail(c, MM_ERR_ARG, "watch_every must be >= 0");
+    if (p->cpml_kernel < 0 || p->cpml_kernel > 2) return fail(c, MM_ERR_ARG, "cpml_kernel must be 0, 1 or 2");
     if (p->model == MM_MODEL_ISO) {
         if (p->ckpt_every > 0) return fail(c, MM_ERR_UNSUPPORTED, "acoustic_iso has no adjoint (ckpt_every must be 0)");
         if (p->tile > 0 && !iso_variant_ok(p->tile))
@@ -648,16 +658,18 @@ mm_status upload(mm_ctx* c, void* dst, const void* src, size_t bytes) {
 
 // Flags of the tiles [a, b) of the table: the cells a tile writes meet the
 // damping layers of width w of an axis (CPML), or hold an inline source.
+// zflag: TF_LZ (every tile of the list is a z-layer chunk), 0 (from the
+// tile's z range) or -1 (never: the frame and interior lists).
 void tile_flags(mm_ctx* c, int a, int b, int w, int zflag) {
     auto meets = [w](int a0, int a1, int n) { return a0 < w || a1 > n - w; };  // [a0, a1) vs the layers
     for (int i = a; i < b; ++i) {
         TileEnt& t = c->tiles_h[i];
         const ShotGeom& g = c->geom[t.shot];
-        int f = zflag;
+        int f = zflag > 0 ? zflag : 0;
         if (c->cpml) {
             if (meets(t.x0, t.x1, g.nx)) f |= TF_LX;
             if (meets(t.y0, t.y1, g.ny)) f |= TF_LY;
-            if (!zflag && meets(t.z0, t.z1, g.nz)) f |= TF_LZ;
+            if (zflag == 0 && meets(t.z0, t.z1, g.nz)) f |= TF_LZ;
         }
         if (c->inline_src)
             for (long long o : c->src_cells[t.shot]) {
@@ -683,8 +695,8 @@ mm_status set_variant(mm_ctx* c, int v) {
         // (acoustic_iso: its memory slabs, one cell wider than the layer)
         tile_flags(c, t.full_off, t.full_off + t.nfull, c->iso ? mem_width(c->p) : c->p.nb + (c->L.adjoint ? 4 : 0),
                    0);
-        tile_flags(c, t.in_off, t.in_off + t.nin, c->p.nb, 0);
-        tile_flags(c, t.st_off, t.st_off + t.nst, c->p.nb, 0);
+        tile_flags(c, t.in_off, t.in_off + t.nin, c->p.nb, -1);
+        tile_flags(c, t.st_off, t.st_off + t.nst, c->p.nb, -1);
         tile_flags(c, t.zl_off, t.zl_off + t.nzl, c->p.nb, TF_LZ);
         tile_flags(c, t.zc_off, t.zc_off + t.nzc, c->p.nb, TF_LZ);
     }
@@ -720,7 +732,7 @@ mm_status zero_state(mm_ctx* c, hipStream_t s) {
                                      nb2 * c->geom[i].ny * c->geom[i].nx};
             for (int a = 0; a < 3; ++a) {
                 MM_TRY(dev(c, launch_fill(sd.psi[a], sl[a], 0.0f, s), "fill"));
-                if (!c->iso) MM_TRY(dev(c, launch_fill(sd.corr[a], sl[a], 0.0f, s), "fill"));
+                if (!c->iso) MM_TRY(dev(c, launch_fill(sd.psi2[a], sl[a], 0.0f, s), "fill"));
                 MM_TRY(dev(c, launch_fill(sd.zeta[a], sl[a], 0.0f, s), "fill"));
             }
         }
@@ -779,15 +791,31 @@ mm_status enqueue_step(mm_ctx* c, const ShotDev* shots, int parity, int mode, co
         ev1 = c->prof_ev[c->prof_used + 1];
         c->prof_used += 2;
     }
+    if (c->cpml && !c->iso && shots == c->d_shots && c->layer_pass) {
+        // forward CPML, layer pass: psi^{n+1}, zeta^{n+1} and the corrections of the group's
+        // layer cells, then the stencil over the group's whole grids adds the corrections
+        if (!g) return fail(c, MM_ERR_STATE, "forward CPML step without a shot group");
+        MM_TRY(dev(c, launch_cpml_forward(shots + g->s0, g->s1 - g->s0, c->p.nb, g->stream, g->cpml_d,
+                                          g->cpml_h.data(), parity, c->cf, s, ev0),
+                   "cpml layer launch"));
+        StepAux a = aux;
+        a.stream_loads = g->stream ? 1 : 0;
+        MM_TRY(dev(c, launch_step(c->variant, MM_BC_CPML, mode, c->d_tiles + g->t.full_off, g->t.nfull, shots,
+                                  parity, c->cf, a, s, nullptr, ev1),
+                   "stencil launch"));
+        return MM_OK;
+    }
     if (c->cpml && !c->iso && shots == c->d_shots) {
         // forward CPML: the interior boxes (plain stencil), then the frames, the z-layer tiles
-        // and the z-layer corner tiles (fused CPML kernel); the four write disjoint cells and
-        // read only p^n of the step, so their order is free; the receivers ride in the first
-        // launch that runs
+        // and the z-layer corner tiles (fused CPML kernel; one launch for the three when the
+        // group has few of them); the launches write disjoint cells and read only p^n of the
+        // step, so their order is free; the receivers ride in the first launch that runs
         if (!g) return fail(c, MM_ERR_STATE, "forward CPML step without a shot group");
         const GroupTiles& t = g->t;
-        const int off[4] = {t.in_off, t.st_off, t.zl_off, t.zc_off}, cnt[4] = {t.nin, t.nst, t.nzl, t.nzc};
-        const int kind[4] = {-1, CS_FRAME, CS_ZLAYER, CS_ZCORNER};
+        const bool one = t.merged();
+        const int off[4] = {t.in_off, t.st_off, t.zl_off, t.zc_off};
+        const int cnt[4] = {t.nin, one ? t.nst + t.nzl + t.nzc : t.nst, one ? 0 : t.nzl, one ? 0 : t.nzc};
+        const int kind[4] = {-1, one ? CS_ALL : CS_FRAME, CS_ZLAYER, CS_ZCORNER};
         int first = -1, last = -1;
         for (int k = 0; k < 4; ++k)
             if (cnt[k] > 0) {
@@ -855,8 +883,11 @@ float* ckpt_field(mm_ctx* c, int seg, int which) {
 }
 
 // The buffer that holds psi^k of a forward shot after k steps (parity k & 1):
-// the step of parity q reads psi from psi (q = 0) or corr (q = 1) and writes the other.
-float* psi_now(const ShotDev& sd, int a, int parity) { return parity ? sd.corr[a] : sd.psi[a]; }
+// with the fused kernel the step of parity q reads psi from psi (q = 0) or psi2
+// (q = 1) and writes the other; the layer pass keeps it in psi.
+float* psi_now(const mm_ctx* c, const ShotDev& sd, int a, int parity) {
+    return parity && !c->layer_pass ? sd.psi2[a] : sd.psi[a];
+}
 
 // CPML memory (psi_x,y,z, zeta_x,y,z) of checkpoint seg, kept in FP32
 mm_status ckpt_memory(mm_ctx* c, int seg, bool save, int parity, hipStream_t s) {
@@ -867,7 +898,7 @@ mm_status ckpt_memory(mm_ctx* c, int seg, bool save, int parity, hipStream_t s) 
     char* base = c->ws + c->L.ckpt_mem + (size_t)seg * c->L.ckpt_mem_bytes;
     size_t o = 0;
     for (int k = 0; k < 6; ++k) {
-        float* f = k < 3 ? psi_now(c->shots_h[0], k, parity) : c->shots_h[0].zeta[k - 3];
+        float* f = k < 3 ? psi_now(c, c->shots_h[0], k, parity) : c->shots_h[0].zeta[k - 3];
         const size_t bytes = sizeof(float) * sl[k % 3];
         float* dst = save ? reinterpret_cast<float*>(base + o) : f;
         const float* src = save ? f : reinterpret_cast<const float*>(base + o);
@@ -1040,14 +1071,34 @@ mm_status enqueue_adjoint(mm_ctx* c, int nsteps, const float* resid, float* adj_
 
 std::string tune_key(const mm_ctx* c) {
     std::string k = std::to_string(c->p.model) + "/" + std::to_string(c->p.bc) + "/" + std::to_string(c->p.nb) + "/" +
-                    std::to_string(c->p.cache_hints);
+                    std::to_string(c->p.cache_hints) + "/" + std::to_string(c->p.cpml_kernel) + "/" +
+                    std::to_string(c->p.free_surface);
     for (const auto& g : c->groups) k += "/" + std::to_string(g.s1 - g.s0);
     for (const auto& g : c->geom) k += ":" + std::to_string(g.nx) + "x" + std::to_string(g.ny) + "x" + std::to_string(g.nz);
     return k;
 }
 
+// tuned (tile variant, forward CPML layer pass) per problem
 std::mutex g_tune_mu;
-std::map<std::string, int> g_tune_cache;
+std::map<std::string, std::pair<int, bool>> g_tune_cache;
+
+// The forward CPML strategy (acoustic_iso_cd) before or without tuning: the
+// layer pass when the cells outside the interior boxes are 30 % or more of
+// the context's cells.  The fused kernel's z-marching strips then hold too
+// few blocks to fill the chip (measured per step: 79 against 142 us at 240^3
+// with 20-cell layers; 2.82 against 2.42 ms the other way at 1024^2 x 512
+// with 32-cell layers).
+bool layer_pass_default(const mm_params& p, const std::vector<ShotGeom>& shots) {
+    if (p.cpml_kernel == MM_CPML_LAYER) return true;
+    if (p.cpml_kernel == MM_CPML_FUSED) return false;
+    double all = 0.0, inner = 0.0;
+    const int zl = p.free_surface ? 1 : 2;
+    for (const auto& g : shots) {
+        all += (double)g.n();
+        inner += (double)std::max(0, g.nx - 2 * p.nb) * std::max(0, g.ny - 2 * p.nb) * std::max(0, g.nz - zl * p.nb);
+    }
+    return inner < 0.7 * all;
+}
 
 }  // namespace
 
@@ -1227,6 +1278,7 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
         for (int a = 0; a < 3; ++a) {
             sd.psi[a] = c->cpml ? at<float>(c->ws, L.psi[a][i]) : nullptr;
             sd.zeta[a] = c->cpml ? at<float>(c->ws, L.zeta[a][i]) : nullptr;
+            sd.psi2[a] = c->cpml && !c->iso ? at<float>(c->ws, L.psi2[a][i]) : nullptr;
             sd.corr[a] = c->cpml && !c->iso ? at<float>(c->ws, L.corr[a][i]) : nullptr;
         }
         sd.nx = g.nx;
@@ -1246,6 +1298,7 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
             const bool ca = c->cpml && L.adjoint;
             sa.psi[a] = ca ? at<float>(c->ws, L.apsi[a][i]) : nullptr;
             sa.zeta[a] = ca ? at<float>(c->ws, L.azeta[a][i]) : nullptr;
+            sa.psi2[a] = nullptr;
             sa.corr[a] = ca ? at<float>(c->ws, L.acorr[a][i]) : nullptr;
         }
         sa.cw = p->nb + 4;
@@ -1388,6 +1441,22 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
             g.cell1 = (int)(std::lower_bound(cs.shot.begin(), cs.shot.end(), g.s1) - cs.shot.begin());
             c->groups.push_back(std::move(g));
         }
+        size_t cpml_pos = 3 * (size_t)(nshots + 1);  // after the adjoint's table
+        if (c->cpml && !c->iso)
+            for (auto& g : c->groups) {
+                std::vector<int> gx, gy, gz;
+                for (int i = g.s0; i < g.s1; ++i) {
+                    gx.push_back(geom[i].nx);
+                    gy.push_back(geom[i].ny);
+                    gz.push_back(geom[i].nz);
+                }
+                const int ng = g.s1 - g.s0;
+                g.cpml_h.assign(3 * (ng + 1), 0);
+                cpml_block_table(gx.data(), gy.data(), gz.data(), ng, p->nb, g.cpml_h.data());
+                g.cpml_d = at<int>(c->ws, L.cpml_off) + cpml_pos;
+                up(L.cpml_off + sizeof(int) * cpml_pos, g.cpml_h.data(), sizeof(int) * g.cpml_h.size());
+                cpml_pos += g.cpml_h.size();
+            }
         if (c->cpml && L.adjoint) {
             std::vector<int> gx, gy, gz;
             for (const auto& q : geom) {
@@ -1430,10 +1499,14 @@ mm_status mm_init_batch(mm_ctx** out, const mm_params* p, int32_t nshots, const 
     if (st) return bail(st);
 
     int v = p->tile > 0 ? p->tile : 0;
+    c->layer_pass = c->cpml && !c->iso && layer_pass_default(*p, geom);
     if (p->tile == -1) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(tune_key(c));
-        if (it != g_tune_cache.end()) v = it->second;
+        if (it != g_tune_cache.end()) {
+            v = it->second.first;
+            c->layer_pass = it->second.second;
+        }
     }
     st = set_variant(c, v);
     if (st) return bail(st);
@@ -1682,7 +1755,7 @@ static mm_status state_copy(mm_ctx* c, char* ext, bool to_ext) {
         if (c->cpml) {
             const size_t nb2 = 2 * (size_t)c->p.nb;
             const size_t sl[3] = {(size_t)g.nz * g.ny * nb2, (size_t)g.nz * nb2 * g.nx, nb2 * g.ny * g.nx};
-            for (int a = 0; a < 3; ++a) MM_TRY(cp(psi_now(c->shots_h[i], a, par), sizeof(float) * sl[a]));
+            for (int a = 0; a < 3; ++a) MM_TRY(cp(psi_now(c, c->shots_h[i], a, par), sizeof(float) * sl[a]));
             for (int a = 0; a < 3; ++a) MM_TRY(cp(c->shots_h[i].zeta[a], sizeof(float) * sl[a]));
         }
     }
@@ -1726,6 +1799,12 @@ mm_status mm_get_info(const mm_ctx* c, double* dt, int32_t* step, int32_t* tile,
     return MM_OK;
 }
 
+mm_status mm_get_cpml_kernel(const mm_ctx* c, int32_t* kernel) {
+    if (!c) return fail(nullptr, MM_ERR_ARG, "context is NULL");
+    if (kernel) *kernel = !c->cpml || c->iso ? MM_CPML_AUTO : (c->layer_pass ? MM_CPML_LAYER : MM_CPML_FUSED);
+    return MM_OK;
+}
+
 int32_t mm_num_tiles(void) { return num_tile_variants(); }
 
 const char* mm_tile_name(int32_t t) { return (t >= 0 && t < num_tile_variants()) ? tile_variant(t).name : "?"; }
@@ -1749,7 +1828,10 @@ mm_status mm_autotune(mm_ctx* c, int32_t steps, int32_t* tile_out) {
     const StepAux none{};  // trial steps inject nothing (no wavelet row)
     // one trial: 2 untimed steps, then `steps` steps timed with HIP events
     // (raised after the first trial so that a trial lasts about 2 ms)
-    auto trial = [&](int v, float* ms) -> mm_status {
+    // the forward CPML strategy is tuned too unless the parameters fix it
+    const bool both = c->cpml && !c->iso && c->p.cpml_kernel == MM_CPML_AUTO;
+    auto trial = [&](int v, bool lp, float* ms) -> mm_status {
+        c->layer_pass = lp;
         MM_TRY(set_variant(c, v));
         for (const auto& g : c->groups)
             for (int j = 0; j < 2; ++j) MM_TRY(enqueue_step(c, c->d_shots, j & 1, MODE_PLAIN, none, c->stream, &g));
@@ -1760,40 +1842,59 @@ mm_status mm_autotune(mm_ctx* c, int32_t steps, int32_t* tile_out) {
         MM_TRY(dev(c, hipEventSynchronize(e1), "event"));
         return dev(c, hipEventElapsedTime(ms, e0, e1), "event");
     };
-    // every variant once, then the fastest few twice more, interleaved, each
-    // keeping its best time (near-ties are otherwise decided by run-to-run noise)
+    // every variant once (in the default CPML strategy), then the fastest few
+    // twice more, interleaved, in each strategy, each keeping its best time
+    // (near-ties are otherwise decided by run-to-run noise)
+    const bool lp0 = c->layer_pass;
     std::vector<std::pair<float, int>> res;
     mm_status st = MM_OK;
     for (int v = 0; v < num_tile_variants() && !st; ++v) {
         if (c->iso && !iso_variant_ok(v)) continue;
         float ms = 0.0f;
-        st = trial(v, &ms);
+        st = trial(v, lp0, &ms);
         if (st) break;
         if (res.empty() && ms > 0.0f && ms < 2.0f) {
             steps = std::min(200, std::max(steps, (int)std::ceil(2.0f * steps / ms)));
-            st = trial(v, &ms);
+            st = trial(v, lp0, &ms);
         }
         if (!st) res.push_back({ms, v});
     }
     std::sort(res.begin(), res.end());
     const size_t top = std::min<size_t>(res.size(), 4);
+    struct Cand {
+        float ms;
+        int v;
+        bool lp;
+    };
+    std::vector<Cand> cand;
+    for (size_t k = 0; k < top; ++k) {
+        cand.push_back({res[k].first, res[k].second, lp0});
+        if (both) cand.push_back({1e30f, res[k].second, !lp0});
+    }
     for (int round = 0; round < 2 && !st; ++round)
-        for (size_t k = 0; k < top && !st; ++k) {
+        for (size_t k = 0; k < cand.size() && !st; ++k) {
             float ms = 0.0f;
-            st = trial(res[k].second, &ms);
-            if (!st) res[k].first = std::min(res[k].first, ms);
+            st = trial(cand[k].v, cand[k].lp, &ms);
+            if (!st) cand[k].ms = std::min(cand[k].ms, ms);
         }
     int best = c->variant;
-    if (!st && top > 0) best = std::min_element(res.begin(), res.begin() + top)->second;
+    bool best_lp = lp0;
+    if (!st && !cand.empty()) {
+        const Cand& b = *std::min_element(cand.begin(), cand.end(),
+                                          [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+        best = b.v;
+        best_lp = b.lp;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st) return st;
     drop_graph(c);
+    c->layer_pass = best_lp;
     MM_TRY(set_variant(c, best));
     MM_TRY(mm_reset(c));
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune_cache[tune_key(c)] = best;
+        g_tune_cache[tune_key(c)] = {best, best_lp};
     }
     if (tile_out) *tile_out = best;
     return MM_OK;

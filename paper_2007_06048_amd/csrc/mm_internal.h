@@ -13,9 +13,11 @@ struct ShotDev {
     float* vdt2;          // (dt v)^2
     const float* prof;    // sponge: g_x[nx] g_y[ny] g_z[nz]; CPML: a_x b_x [nx], a_y b_y [ny], a_z b_z [nz]
     float* psi[3];        // CPML memory, slab layouts (see minimod.h); adjoint fields: its adjoint
+    float* psi2[3];       // forward fields, fused CPML kernel: the second buffer of psi (psi^k in psi at even k,
+                          // in psi2 at odd k; the layer pass keeps psi in place in psi)
     float* zeta[3];
-    // forward fields: the second buffer of psi (psi^k is in psi at even k, in corr at odd k);
-    // adjoint fields: the correction added to the Laplacian this step, slabs of cw cells per end
+    // the correction added to the Laplacian this step by the stencil kernel (bc 2), slabs of cw
+    // cells per end, written by the layer pass of the step (forward) or the adjoint CPML kernel
     float* corr[3];
     int nx, ny, nz, nb;
     int cw;               // width of the correction slabs: nb (forward), nb + 4 (adjoint)
@@ -109,8 +111,8 @@ int num_tile_variants();
 const TileShape& tile_variant(int t);
 int tile_rows(int t);  // TY of variant t
 
-// bc: 0 none, 1 sponge, 2 CPML adjoint fields (launch_cpml must have written
-// the layer corrections of the same step first)
+// bc: 0 none, 1 sponge, 2 CPML (launch_cpml_forward or launch_cpml_adjoint
+// must have written the layer corrections of the same step first)
 // With ev0 / ev1 the launch records its own start and end time stamps into
 // them (hipExtLaunchKernel), for per-launch timing without extra packets.
 hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int ntiles,
@@ -119,14 +121,25 @@ hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int 
 // Forward CPML step of the tiles that meet a layer, memory update included.
 // kind: CS_FRAME, the tiles of the middle z range (flagged TF_LX / TF_LY);
 // CS_ZLAYER, the tiles of the z-layer chunks [0, nb) and [nz - nb, nz) that
-// meet no x or y layer; CS_ZCORNER, those that do.  mode MODE_PLAIN or
-// MODE_D2P.  The tiles of each kind are cstep_tile_w(kind) x cstep_tile_h(kind).
-enum { CS_FRAME = 0, CS_ZLAYER = 1, CS_ZCORNER = 2 };
+// meet no x or y layer; CS_ZCORNER, those that do; CS_ALL, any mix of the
+// three in one launch (z-layer tiles flagged TF_LZ, frame tiles not).  mode
+// MODE_PLAIN or MODE_D2P.  The tiles of each kind are cstep_tile_w(kind) x
+// cstep_tile_h(kind).
+enum { CS_FRAME = 0, CS_ZLAYER = 1, CS_ZCORNER = 2, CS_ALL = 3 };
 hipError_t launch_cpml_step(int kind, int mode, const TileEnt* tiles, int ntiles, const ShotDev* shots, int parity,
                             const Coefs& cf, const StepAux& aux, hipStream_t s, hipEvent_t ev0 = nullptr,
                             hipEvent_t ev1 = nullptr);
 int cstep_tile_w(int kind);
 int cstep_tile_h(int kind);
+// Forward CPML layer pass of the shots [0, nshots) of `shots` for this step,
+// before the stencil kernel with bc 2: psi^{n+1} and zeta^{n+1} (in place in
+// ShotDev::psi and zeta) and the correction D1 psi^{n+1} + zeta^{n+1} of
+// every layer cell (slabs of nb cells per end, nb <= 128).  The block table
+// (cpml_block_table with width nb) and ev0 as for launch_cpml_adjoint;
+// stream: non-temporal loads of psi and zeta.
+hipError_t launch_cpml_forward(const ShotDev* shots, int nshots, int nb, bool stream, const int* block_off_dev,
+                               const int* block_off_host, int parity, const Coefs& cf, hipStream_t s,
+                               hipEvent_t ev0 = nullptr);
 // Adjoint CPML memory update and corrections of every shot for this step,
 // before the adjoint stencil kernel: the transposed memory recursions and a
 // correction reaching 4 cells past the layer (nb <= 64).  The block table

@@ -95,9 +95,10 @@ int tile_rows(int t) { return (kTiles[t].nt / kTiles[t].tx) * kTiles[t].ry; }
 // The small-tile, one-plane-prefetch shapes are held to 72 VGPRs (7 waves per
 // SIMD instead of 6 for the CPML adjoint and the imaging instantiations);
 // they fit without spilling, the larger shapes and the CPML imaging mode
-// would not.  BC == 2 is the adjoint fields' CPML (corrections written by
-// launch_cpml_adjoint); the forward CPML step of the cells near the faces is
-// k_cstep.
+// would not.  BC == 2 adds the CPML corrections of the step's layer pass
+// (launch_cpml_forward, or launch_cpml_adjoint for the adjoint fields); the
+// other forward CPML strategy runs the interior with BC == 0 and the cells
+// near the faces in k_cstep.
 template <int TX, int RY, int PD, int BC, int MODE, int NT, bool STREAM>
 __global__ __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu((PD == 1 && RY <= 2 && !(BC == 2 && MODE != MODE_PLAIN)) ? 7 : 1)))
@@ -482,13 +483,15 @@ hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int 
 //    TF_LY), psi^{n+1} is formed over the tile and 4 cells around it into
 //    LDS (the outer ring redundantly with the neighbouring tile, from the
 //    same p^n and psi^n), and D1 psi is taken from there after a barrier;
-//  - z (LZ launches, whose z-chunks are exactly the layers [0, nb) and
-//    [nz - nb, nz)): the register queue holds planes z-4 .. z+8, psi_z^{n+1}
-//    of plane z+4 is formed as soon as plane z+8 arrives and kept in a
-//    second queue of planes z-4 .. z+4 (zero outside the chunk, which is
-//    outside the layer).
+//  - z (tiles flagged TF_LZ in LZ launches, whose z-chunks are exactly the
+//    layers [0, nb) and [nz - nb, nz)): the register queue holds planes
+//    z-4 .. z+8, psi_z^{n+1} of plane z+4 is formed as soon as plane z+8
+//    arrives and kept in a second queue of planes z-4 .. z+4 (zero outside
+//    the chunk, which is outside the layer).  Other tiles of an LZ launch
+//    (the frame, when one launch takes every kind) use the same deeper
+//    queue without the z memory.
 // psi is double-buffered by step parity (current in ShotDev::psi at even
-// steps and in ShotDev::corr at odd ones, the next in the other), so the
+// steps and in ShotDev::psi2 at odd ones, the next in the other), so the
 // ring of a tile reads psi^n while its owner writes psi^{n+1}; zeta is
 // updated in place by the owner only.  Cells owned by the tile are
 // [x0, x1) x [y0, y1) x [z0, z1); the plane is staged over the full TX x TY
@@ -527,17 +530,19 @@ __global__ __launch_bounds__(NT) void k_cstep(const TileEnt* __restrict__ tiles,
     float* __restrict__ pn = sd.buf[parity ^ 1];
     const float* __restrict__ vd = sd.vdt2;
     const float* __restrict__ prof = sd.prof;  // a_x b_x [nx], a_y b_y [ny], a_z b_z [nz]
-    const float* __restrict__ rpx = parity ? sd.corr[0] : sd.psi[0];
-    const float* __restrict__ rpy = parity ? sd.corr[1] : sd.psi[1];
-    const float* __restrict__ rpz = parity ? sd.corr[2] : sd.psi[2];
-    float* __restrict__ wpx = parity ? sd.psi[0] : sd.corr[0];
-    float* __restrict__ wpy = parity ? sd.psi[1] : sd.corr[1];
-    float* __restrict__ wpz = parity ? sd.psi[2] : sd.corr[2];
+    const float* __restrict__ rpx = parity ? sd.psi2[0] : sd.psi[0];
+    const float* __restrict__ rpy = parity ? sd.psi2[1] : sd.psi[1];
+    const float* __restrict__ rpz = parity ? sd.psi2[2] : sd.psi[2];
+    float* __restrict__ wpx = parity ? sd.psi[0] : sd.psi2[0];
+    float* __restrict__ wpy = parity ? sd.psi[1] : sd.psi2[1];
+    float* __restrict__ wpz = parity ? sd.psi[2] : sd.psi2[2];
     const long long pxs = (long long)ny * nb2, pys = (long long)nb2 * nx;  // slab planes of x and y
 
     // x / y layers only in the XY instantiations (the z-layer tiles away from the x and y faces
-    // run without that machinery, and its registers)
+    // run without that machinery, and its registers), the z layer only in the LZ ones; within an
+    // instantiation the tile's flags decide (a launch may mix frame and z-layer tiles)
     const bool tlx = XY && (te.flags & TF_LX) != 0, tly = XY && (te.flags & TF_LY) != 0;
+    const bool lz = LZ && (te.flags & TF_LZ) != 0;
     const bool wide = tlx || tly;  // block-uniform
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int x = te.x0 + tx;
@@ -611,7 +616,7 @@ __global__ __launch_bounds__(NT) void k_cstep(const TileEnt* __restrict__ tiles,
 #pragma unroll
         for (int r = 0; r < RY; ++r) q[r][m] = zin ? bload(rp, voc[r]) : 0.0f;
     }
-    if (!LZ && z0 == 0 && sd.fs) {
+    if (!lz && z0 == 0 && sd.fs) {
         // above a free surface on plane 0: the odd mirror, planes -1..-4 = -p(1..4)
         const __amdgpu_buffer_rsrc_t r4 = plane_rsrc(pc, 4 < nz ? 4 : 0, plane);
 #pragma unroll
@@ -625,7 +630,7 @@ __global__ __launch_bounds__(NT) void k_cstep(const TileEnt* __restrict__ tiles,
     auto zslab = [&](int z) { return z < nb ? z : z - (nz - nb2); };
     // psi_z^{n+1} of planes z-4 .. z+4 (LZ): the planes before the chunk are outside the layer
     float ps[LZ ? RY : 1][9];
-    if (LZ) {
+    if (lz) {
 #pragma unroll
         for (int r = 0; r < RY; ++r)
 #pragma unroll
@@ -696,7 +701,7 @@ __global__ __launch_bounds__(NT) void k_cstep(const TileEnt* __restrict__ tiles,
 #pragma unroll
             for (int h = 0; h < PH; ++h) f.hy[h] = bload(rs, vpy[h]);
         }
-        if (LZ) {
+        if (lz) {
             const bool pin = zn + 4 < z1;  // the chunk is the whole layer
             const __amdgpu_buffer_rsrc_t rs = plane_rsrc(rpz, pin ? zslab(zn + 4) : 0, plane);
             const __amdgpu_buffer_rsrc_t rz = plane_rsrc(sd.zeta[2], zslab(zn), plane);
@@ -724,7 +729,7 @@ __global__ __launch_bounds__(NT) void k_cstep(const TileEnt* __restrict__ tiles,
         const float *cpp = cur.pp, *cvd = cur.vd, *cxh = cur.xh, *cyh = cur.yh, *csx = cur.sx, *czx = cur.zx,
                     *chx = cur.hx, *csy = cur.sy, *czy = cur.zy, *chy = cur.hy, *csz = cur.sz, *czz = cur.zz;
 
-        if (LZ) {
+        if (lz) {
             // psi_z^{n+1} of plane z+4: its D1 needs planes z .. z+8, now all in the queue
             const int zp = z + 4;
             if (zp < z1) {
@@ -823,8 +828,8 @@ __global__ __launch_bounds__(NT) void k_cstep(const TileEnt* __restrict__ tiles,
         }
 
         const long long zoff = (long long)z * plane;
-        const float az = LZ ? zprof[z] : 0.0f, bz = LZ ? zprof[nz + z] : 0.0f;
-        const long long zso = LZ ? (long long)zslab(z) * plane : 0;
+        const float az = lz ? zprof[z] : 0.0f, bz = lz ? zprof[nz + z] : 0.0f;
+        const long long zso = lz ? (long long)zslab(z) * plane : 0;
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             const int yy = H + ty + r * BY;
@@ -859,7 +864,7 @@ __global__ __launch_bounds__(NT) void k_cstep(const TileEnt* __restrict__ tiles,
                 cy = d1 + zn;
                 layer = true;
             }
-            if (LZ && in[r]) {
+            if (lz && in[r]) {
                 float d1 = 0.0f;
 #pragma unroll
                 for (int m = 1; m <= 4; ++m) d1 = fmaf(cf.bz[m - 1], ps[r][4 + m] - ps[r][4 - m], d1);
@@ -885,7 +890,7 @@ __global__ __launch_bounds__(NT) void k_cstep(const TileEnt* __restrict__ tiles,
         for (int r = 0; r < RY; ++r) {
 #pragma unroll
             for (int m = 0; m < QD - 1; ++m) q[r][m] = q[r][m + 1];
-            if (LZ) {
+            if (lz) {
 #pragma unroll
                 for (int m = 0; m < 8; ++m) ps[r][m] = ps[r][m + 1];
             }
@@ -904,6 +909,8 @@ int cstep_tile_h(int kind) {
     const int nt = kind == CS_FRAME ? CS_NT_FRAME : (kind == CS_ZLAYER ? CS_NT_ZLAYER : CS_NT_ZCORNER);
     return (nt / CS_TX) * CS_RY;
 }
+// one launch over every kind runs the corner instantiation on tiles of one shape
+static_assert(CS_NT_FRAME == CS_NT_ZCORNER && CS_NT_ZLAYER == CS_NT_ZCORNER, "CS_ALL needs one tile shape");
 
 template <bool XY, bool LZ, int MODE, bool STREAM>
 static void launch_cstep_k(dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd, const ShotDev* shots, int parity,
@@ -937,7 +944,7 @@ hipError_t launch_cpml_step(int kind, int mode, const TileEnt* tiles, int ntiles
         launch_cstep_m<true, false>(mode, st, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0, ev1);
     else if (kind == CS_ZLAYER)
         launch_cstep_m<false, true>(mode, st, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0, ev1);
-    else if (kind == CS_ZCORNER)
+    else if (kind == CS_ZCORNER || kind == CS_ALL)
         launch_cstep_m<true, true>(mode, st, grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0, ev1);
     else
         return hipErrorInvalidValue;
@@ -1691,6 +1698,170 @@ __global__ __launch_bounds__(256) void k_cpml_adj(const ShotDev* __restrict__ sh
     else cpml_yz_block_adj<2>(sd, parity, cf, xblk, w, side, lds);
 }
 
+// ------------------------------------------------------ CPML, layer pass
+//
+// The other forward CPML strategy (for grids whose layers hold a large share
+// of the cells, where the fused kernel's z-marching strips leave the chip
+// idle): one launch per step before the stencil kernel (BC == 2), one thread
+// per layer cell of every axis, in the block enumeration of the adjoint with
+// nb cells per end.  Per damped axis and layer cell
+//   psi^{n+1} = b psi^n + a D1 p^n,   zeta^{n+1} = b zeta^n + a (D2 p^n + D1 psi^{n+1}),
+// and the correction D1 psi^{n+1} + zeta^{n+1} goes to the slabs (corr) that
+// the stencil kernel adds to the Laplacian.  psi is zero outside its layer
+// and the two layers of an axis are at least 4 cells apart, so a block that
+// holds a whole layer segment along the axis has every psi^{n+1} it needs in
+// LDS, and psi and zeta are updated in place (ShotDev::psi; the second psi
+// buffer of k_cstep stays untouched, which keeps the step's working set at
+// that of the three slab arrays).
+
+// NT: psi and zeta (read once per step) are loaded with the non-temporal hint
+template <bool NT>
+__device__ __forceinline__ float once(const float* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <bool NT>
+__device__ void cpml_x_block_fwd(const ShotDev& sd, int parity, const Coefs& cf, int blk, int rpb, float* lds) {
+    const int nx = sd.nx, ny = sd.ny, nz = sd.nz, nb = sd.nb, nb2 = 2 * nb;
+    const int e = threadIdx.x;
+    const int r = e / nb2, sl = e - r * nb2;
+    const int x = sl < nb ? sl : nx - nb2 + sl;
+    const int lo = sl < nb ? 0 : nb, hi = lo + nb;  // this end of the row (the other is >= 4 cells away)
+    const float* __restrict__ p = sd.buf[parity];
+    float* __restrict__ ps = sd.psi[0];
+    float* __restrict__ ze = sd.zeta[0];
+    float* __restrict__ co = sd.corr[0];
+    const float a = sd.prof[x], b = sd.prof[nx + x];
+    for (int g = 0; g < CPML_XG; ++g) {
+        const int row = (blk * CPML_XG + g) * rpb + r;
+        const bool active = r < rpb && row < ny * nz;
+        const long long o = (long long)row * nx + x;  // row = z * ny + y
+        const long long si = (long long)row * nb2 + sl;
+        float d2 = 0.0f;
+        if (active) {
+            const float c = p[o];
+            float d1 = 0.0f;
+#pragma unroll
+            for (int m = 1; m <= 4; ++m) {
+                const float fp = x + m < nx ? p[o + m] : 0.0f;
+                const float fm = x - m >= 0 ? p[o - m] : 0.0f;
+                d1 = fmaf(cf.bx[m - 1], fp - fm, d1);
+                d2 = fmaf(cf.cx[m - 1], (fp - c) + (fm - c), d2);
+            }
+            const float pv = fmaf(b, once<NT>(ps + si), a * d1);
+            ps[si] = pv;
+            lds[e] = pv;
+        }
+        __syncthreads();
+        if (active) {
+            float dpsi = 0.0f;
+#pragma unroll
+            for (int m = 1; m <= 4; ++m) {
+                const float vp = sl + m < hi ? lds[e + m] : 0.0f;
+                const float vm = sl - m >= lo ? lds[e - m] : 0.0f;
+                dpsi = fmaf(cf.bx[m - 1], vp - vm, dpsi);
+            }
+            const float zn = fmaf(b, once<NT>(ze + si), a * (d2 + dpsi));
+            ze[si] = zn;
+            co[si] = dpsi + zn;
+        }
+        __syncthreads();  // lds is rewritten by the next row group
+    }
+}
+
+// y (AX = 1) or z (AX = 2) layers of one end: block = 64 x-columns, thread row
+// ty takes cells ty, ty + 4, ... of the nb cells; w is z (AX = 1) or y (AX = 2).
+template <int AX, bool NT>
+__device__ void cpml_yz_block_fwd(const ShotDev& sd, int parity, const Coefs& cf, int xblk, int w, int side,
+                                  float* lds) {
+    const int nx = sd.nx, ny = sd.ny, nz = sd.nz, nb = sd.nb, nb2 = 2 * nb;
+    if (w >= (AX == 2 ? ny : nz)) return;  // whole block
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int x = xblk * 64 + tx;
+    const bool active = x < nx;
+    const long long plane = (long long)nx * ny;
+    const int n = AX == 2 ? nz : ny;
+    const long long stride = AX == 2 ? plane : (long long)nx;
+    const long long base = AX == 2 ? (long long)w * nx + x : (long long)w * plane + x;
+    const long long sbase = AX == 2 ? (long long)w * nx + x : (long long)w * nb2 * nx + x;
+    const long long sstride = AX == 2 ? plane : (long long)nx;
+    const float* prof = AX == 2 ? sd.prof + 2 * nx + 2 * ny : sd.prof + 2 * nx;
+    const int s0 = side ? n - nb : 0;
+    const int soff = side ? nb : 0;  // slab index of the first cell of this end
+    float* psl = lds;                // [nb][64]: psi^{n+1}
+    float* d2l = lds + nb * 64;      // [nb][64]: D2 p^n
+    const float* __restrict__ p = sd.buf[parity];
+    float* __restrict__ psi = sd.psi[AX];
+    if (active) {
+        for (int s = ty; s < nb; s += 4) {
+            const int z = s0 + s;
+            const long long o = base + z * stride;
+            const float c = p[o];
+            float d1 = 0.0f, d2 = 0.0f;
+#pragma unroll
+            for (int m = 1; m <= 4; ++m) {
+                const float fp = z + m < n ? p[o + m * stride] : 0.0f;
+                const float fm = z - m >= 0 ? p[o - m * stride] : 0.0f;
+                d1 = fmaf(AX == 2 ? cf.bz[m - 1] : cf.by[m - 1], fp - fm, d1);
+                d2 = fmaf(AX == 2 ? cf.cz[m - 1] : cf.cy[m - 1], (fp - c) + (fm - c), d2);
+            }
+            const long long si = sbase + (long long)(soff + s) * sstride;
+            const float ps = fmaf(prof[n + z], once<NT>(psi + si), prof[z] * d1);
+            psi[si] = ps;
+            psl[s * 64 + tx] = ps;
+            d2l[s * 64 + tx] = d2;
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    float* __restrict__ ze = sd.zeta[AX];
+    float* __restrict__ co = sd.corr[AX];
+    for (int s = ty; s < nb; s += 4) {
+        const int z = s0 + s;
+        float dpsi = 0.0f;
+#pragma unroll
+        for (int m = 1; m <= 4; ++m) {
+            const float vp = s + m < nb ? psl[(s + m) * 64 + tx] : 0.0f;
+            const float vm = s - m >= 0 ? psl[(s - m) * 64 + tx] : 0.0f;
+            dpsi = fmaf(AX == 2 ? cf.bz[m - 1] : cf.by[m - 1], vp - vm, dpsi);
+        }
+        const long long si = sbase + (long long)(soff + s) * sstride;
+        const float zn = fmaf(prof[n + z], once<NT>(ze + si), prof[z] * (d2l[s * 64 + tx] + dpsi));
+        ze[si] = zn;
+        co[si] = dpsi + zn;
+    }
+}
+
+template <bool NT>
+__global__ __launch_bounds__(256) void k_cpml_fwd(const ShotDev* __restrict__ shots, int parity, Coefs cf,
+                                                  CpmlGrid g) {
+    extern __shared__ float lds[];
+    const int S = g.nshots;
+    const int* ox = g.off;
+    const int* oy = g.off + (S + 1);
+    const int* oz = g.off + 2 * (S + 1);
+    int b = blockIdx.x;
+    if (b < ox[S]) {
+        const int s = find_shot(ox, S, b);
+        cpml_x_block_fwd<NT>(shots[s], parity, cf, b - ox[s], g.rows_per_block, lds);
+        return;
+    }
+    b -= ox[S];
+    const bool ypart = b < oy[S];
+    if (!ypart) b -= oy[S];
+    const int* o = ypart ? oy : oz;
+    const int s = find_shot(o, S, b);
+    const ShotDev& sd = shots[s];
+    const int local = b - o[s];
+    const int xb = (sd.nx + 63) / 64;
+    const int W = ypart ? sd.nz : sd.ny;
+    const int xblk = local % xb, rest = local / xb;
+    const int w = rest % W, side = rest / W;
+    if (ypart) cpml_yz_block_fwd<1, NT>(sd, parity, cf, xblk, w, side, lds);
+    else cpml_yz_block_fwd<2, NT>(sd, parity, cf, xblk, w, side, lds);
+}
+
 int cpml_rows_per_block(int width) { return 256 / (2 * width); }
 
 void cpml_block_table(const int* nx, const int* ny, const int* nz, int nshots, int width, int* off) {
@@ -1706,6 +1877,28 @@ void cpml_block_table(const int* nx, const int* ny, const int* nz, int nshots, i
         oy[i + 1] = oy[i] + 2 * xb * nz[i];
         oz[i + 1] = oz[i] + 2 * xb * ny[i];
     }
+}
+
+hipError_t launch_cpml_forward(const ShotDev* shots, int nshots, int nb, bool stream, const int* block_off_dev,
+                               const int* block_off_host, int parity, const Coefs& cf, hipStream_t s, hipEvent_t ev0) {
+    if (nshots <= 0) return hipSuccess;
+    if (nb < 1 || nb > 128) return hipErrorInvalidValue;
+    CpmlGrid g;
+    g.off = block_off_dev;
+    g.nshots = nshots;
+    g.rows_per_block = cpml_rows_per_block(nb);
+    const int S = nshots;
+    const long long blocks =
+        (long long)block_off_host[S] + block_off_host[(S + 1) + S] + block_off_host[2 * (S + 1) + S];
+    // psi and D2 p of one end, [nb][64] each (x part: 256)
+    const size_t fl = std::max((size_t)2 * nb * 64, (size_t)256);
+    const dim3 grid((unsigned)blocks), block(256);
+    const unsigned lds = (unsigned)(sizeof(float) * fl);
+    if (stream)
+        hipExtLaunchKernelGGL(k_cpml_fwd<true>, grid, block, lds, s, ev0, nullptr, 0, shots, parity, cf, g);
+    else
+        hipExtLaunchKernelGGL(k_cpml_fwd<false>, grid, block, lds, s, ev0, nullptr, 0, shots, parity, cf, g);
+    return hipGetLastError();
 }
 
 hipError_t launch_cpml_adjoint(const ShotDev* shots, int nshots, int nb, const int* block_off_dev,

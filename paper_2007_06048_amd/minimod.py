@@ -17,6 +17,7 @@ MM_OK, MM_ERR_ARG, MM_ERR_UNSTABLE, MM_ERR_WORKSPACE, MM_ERR_DEVICE, MM_ERR_STAT
 BC_NONE, BC_SPONGE, BC_CPML = 0, 1, 2
 MODEL_ISO_CD, MODEL_ISO = 0, 1
 SNAP_FP32, SNAP_BF16 = 0, 1
+CPML_AUTO, CPML_LAYER, CPML_FUSED = 0, 1, 2
 
 # every symbol declared in include/minimod.h
 SYMBOLS = [
@@ -25,6 +26,7 @@ SYMBOLS = [
     "mm_state_size", "mm_get_state", "mm_set_state", "mm_get_info", "mm_autotune", "mm_set_tile",
     "mm_num_tiles", "mm_tile_name", "mm_profile", "mm_profile_read", "mm_destroy", "mm_status_str",
     "mm_last_error", "mm_snap_blocks", "mm_snap_encode", "mm_snap_decode", "mm_init_static", "mm_watch",
+    "mm_get_cpml_kernel",
 ]
 
 
@@ -38,7 +40,7 @@ class Params(ctypes.Structure):
         ("ckpt_every", ctypes.c_int32), ("snap", ctypes.c_int32), ("nsteps_max", ctypes.c_int32),
         ("tile", ctypes.c_int32), ("group_kb", ctypes.c_int32),
         ("free_surface", ctypes.c_int32), ("model", ctypes.c_int32), ("cache_hints", ctypes.c_int32),
-        ("watch_every", ctypes.c_int32),
+        ("watch_every", ctypes.c_int32), ("cpml_kernel", ctypes.c_int32),
     ]
 
 
@@ -89,6 +91,7 @@ def load():
         "mm_get_state": (st, [vp, vp]),
         "mm_set_state": (st, [vp, vp, i32]),
         "mm_get_info": (st, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "mm_get_cpml_kernel": (st, [vp, ctypes.POINTER(i32)]),
         "mm_autotune": (st, [vp, i32, ctypes.POINTER(i32)]),
         "mm_set_tile": (st, [vp, i32]),
         "mm_profile": (st, [vp, i32]),
@@ -279,6 +282,13 @@ class Context:
     @property
     def dt(self):
         return self.info()["dt"]
+
+    def cpml_kernel(self):
+        """The forward CPML strategy in use: CPML_LAYER or CPML_FUSED (CPML_AUTO
+        for other boundaries and acoustic_iso)."""
+        k = ctypes.c_int32()
+        _check(load().mm_get_cpml_kernel(self.h, ctypes.byref(k)), self.h)
+        return k.value
 
     def autotune(self, steps=3):
         t = ctypes.c_int32()

@@ -70,6 +70,9 @@ int main() {
                                     }
                         }
                     };
+                    // the fused lists are consecutive (one launch may take all three)
+                    if (gt[gi].st_off + gt[gi].nst != gt[gi].zl_off || gt[gi].zl_off + gt[gi].nzl != gt[gi].zc_off)
+                        err("fused lists not consecutive", gt[gi].st_off, gt[gi].zl_off, gt[gi].zc_off);
                     mark(full, gt[gi].full_off, gt[gi].nfull, 0);
                     mark(fwd, gt[gi].in_off, gt[gi].nin, 1);
                     mark(fwd, gt[gi].st_off, gt[gi].nst, 2);

@@ -78,14 +78,20 @@ def test_adjoint_in_chunks_is_bitwise_one_call(bc):
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
-@pytest.mark.parametrize("bc,snap,tol,fs", [(mm.BC_SPONGE, mm.SNAP_FP32, 1e-4, 0), (mm.BC_SPONGE, mm.SNAP_BF16, 1e-2, 0),
-                                             (mm.BC_CPML, mm.SNAP_FP32, 1e-4, 0), (mm.BC_CPML, mm.SNAP_BF16, 1e-2, 0),
-                                             (mm.BC_CPML, mm.SNAP_FP32, 1e-4, 1)])
-def test_gradient_matches_oracle(bc, snap, tol, fs):
+@pytest.mark.parametrize("bc,snap,tol,fs,kern", [(mm.BC_SPONGE, mm.SNAP_FP32, 1e-4, 0, 0),
+                                                  (mm.BC_SPONGE, mm.SNAP_BF16, 1e-2, 0, 0),
+                                                  (mm.BC_CPML, mm.SNAP_FP32, 1e-4, 0, mm.CPML_LAYER),
+                                                  (mm.BC_CPML, mm.SNAP_FP32, 1e-4, 0, mm.CPML_FUSED),
+                                                  (mm.BC_CPML, mm.SNAP_BF16, 1e-2, 0, mm.CPML_LAYER),
+                                                  (mm.BC_CPML, mm.SNAP_BF16, 1e-2, 0, mm.CPML_FUSED),
+                                                  (mm.BC_CPML, mm.SNAP_FP32, 1e-4, 1, mm.CPML_LAYER),
+                                                  (mm.BC_CPML, mm.SNAP_FP32, 1e-4, 1, mm.CPML_FUSED)])
+def test_gradient_matches_oracle(bc, snap, tol, fs, kern):
     """FWI gradient w.r.t. m = 1/v^2 with checkpoints every 16 steps (a partial
     last segment included) against the oracle's exact FP64 gradient; CPML
-    checkpoints carry the layer memory; with a free surface the receivers sit
-    just below it."""
+    checkpoints carry the layer memory, with either forward strategy in the
+    forward run and the replays; with a free surface the receivers sit just
+    below it."""
     rng = np.random.default_rng(30)
     shape = (28, 32, 36)
     nz, ny, nx = shape
@@ -98,6 +104,7 @@ def test_gradient_matches_oracle(bc, snap, tol, fs):
     p.ckpt_every = 16
     p.snap = snap
     p.free_surface = fs
+    p.cpml_kernel = kern
     T = 140
     p.nsteps_max = T
     dt = mm.dt_for(p, p.vmax)

@@ -21,13 +21,15 @@ def _ricker_rows(f0, t0, dt, T, nsrc=1):
     return np.repeat(w[:, None], nsrc, axis=1)
 
 
-@pytest.mark.parametrize("bc", [mm.BC_SPONGE, mm.BC_CPML, mm.BC_NONE])
-def test_two_layer_64_full_run(bc):
+@pytest.mark.parametrize("bc,kern", [(mm.BC_SPONGE, 0), (mm.BC_CPML, mm.CPML_LAYER), (mm.BC_CPML, mm.CPML_FUSED),
+                                     (mm.BC_NONE, 0)])
+def test_two_layer_64_full_run(bc, kern):
     """64^3 two-layer model, Ricker 15 Hz at the centre, 200 steps at cfl 0.5:
-    final field and the 64 x 64 receiver plane within 1e-5 of the oracle."""
+    final field and the 64 x 64 receiver plane within 1e-5 of the oracle
+    (CPML: either forward strategy)."""
     wl = W.two_layer_64()
     s = wl.shots[0]
-    p = params(s.vel.shape, bc=bc, nb=wl.nb, cfl=wl.cfl, f0=wl.f0, sigma=wl.sigma)
+    p = params(s.vel.shape, bc=bc, nb=wl.nb, cfl=wl.cfl, f0=wl.f0, sigma=wl.sigma, cpml_kernel=kern)
     T = wl.nsteps
     dt = mm.dt_for(p, float(s.vel.max()))
     w = _ricker_rows(wl.f0, wl.t0, dt, T)
@@ -55,15 +57,21 @@ def _ragged_case(bc, seed=3):
     return p, vel, src, rec, w, T, dt
 
 
-@pytest.mark.parametrize("bc,fs", [(mm.BC_NONE, 0), (mm.BC_SPONGE, 0), (mm.BC_CPML, 0), (mm.BC_NONE, 1),
-                                   (mm.BC_SPONGE, 1), (mm.BC_CPML, 1)])
-def test_ragged_every_tile_variant(bc, fs):
+_CPML_BOTH = [mm.CPML_LAYER, mm.CPML_FUSED]
+
+
+@pytest.mark.parametrize("bc,fs,kern", [(mm.BC_NONE, 0, 0), (mm.BC_SPONGE, 0, 0), (mm.BC_CPML, 0, mm.CPML_LAYER),
+                                        (mm.BC_CPML, 0, mm.CPML_FUSED), (mm.BC_NONE, 1, 0), (mm.BC_SPONGE, 1, 0),
+                                        (mm.BC_CPML, 1, mm.CPML_LAYER), (mm.BC_CPML, 1, mm.CPML_FUSED)])
+def test_ragged_every_tile_variant(bc, fs, kern):
     """A ragged grid (partial tiles in x, y and z), duplicate sources,
     receivers on sources and on corners: every tile variant matches the oracle
-    and all variants agree bitwise (tiling does not change the arithmetic).
-    With a free surface a source and a receiver sit on the surface plane."""
+    and all variants agree bitwise (tiling does not change the arithmetic),
+    in either forward CPML strategy.  With a free surface a source and a
+    receiver sit on the surface plane."""
     p, vel, src, rec, w, T, dt = _ragged_case(bc)
     p.free_surface = fs
+    p.cpml_kernel = kern
     rtr, rpc, _ = oracle_forward(p, dt, vel, src, rec, w, T)
     first = None
     for t in range(mm.num_tiles()):
@@ -76,10 +84,13 @@ def test_ragged_every_tile_variant(bc, fs):
             assert np.array_equal(first[0], tr) and np.array_equal(first[1], pc) and np.array_equal(first[2], pm), t
 
 
-@pytest.mark.parametrize("bc,fs", [(mm.BC_NONE, 0), (mm.BC_SPONGE, 0), (mm.BC_CPML, 0), (mm.BC_CPML, 1)])
-def test_graph_and_chunked_runs_are_bitwise_equal(bc, fs):
+@pytest.mark.parametrize("bc,fs,kern", [(mm.BC_NONE, 0, 0), (mm.BC_SPONGE, 0, 0), (mm.BC_CPML, 0, mm.CPML_LAYER),
+                                        (mm.BC_CPML, 0, mm.CPML_FUSED), (mm.BC_CPML, 1, mm.CPML_LAYER),
+                                        (mm.BC_CPML, 1, mm.CPML_FUSED)])
+def test_graph_and_chunked_runs_are_bitwise_equal(bc, fs, kern):
     p, vel, src, rec, w, T, dt = _ragged_case(bc, seed=4)
     p.free_surface = fs
+    p.cpml_kernel = kern
     a = gpu_forward(p, vel, src, rec, w, T)
     b = gpu_forward(p, vel, src, rec, w, T, graph=True)
     c = gpu_forward(p, vel, src, rec, w, T, chunks=[1, 20, 0, 33, 16])
@@ -89,12 +100,14 @@ def test_graph_and_chunked_runs_are_bitwise_equal(bc, fs):
             assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("bc,fs", [(mm.BC_NONE, 0), (mm.BC_SPONGE, 0), (mm.BC_CPML, 0), (mm.BC_CPML, 1)])
-def test_cache_hints_do_not_change_results(bc, fs):
+@pytest.mark.parametrize("bc,fs,kern", [(mm.BC_NONE, 0, 0), (mm.BC_SPONGE, 0, 0), (mm.BC_CPML, 0, mm.CPML_LAYER),
+                                        (mm.BC_CPML, 0, mm.CPML_FUSED), (mm.BC_CPML, 1, mm.CPML_FUSED)])
+def test_cache_hints_do_not_change_results(bc, fs, kern):
     """Non-temporal loads (forced on, forced off) change only where data is
     cached: traces and fields are bitwise the same, and the same as auto."""
     p, vel, src, rec, w, T, dt = _ragged_case(bc, seed=5)
     p.free_surface = fs
+    p.cpml_kernel = kern
     out = []
     for h in (0, 1, 2):
         p.cache_hints = h
@@ -175,18 +188,22 @@ def _batch_traces(p, vels, srcs, recs, ws, T, graph):
     return out, ng
 
 
-@pytest.mark.parametrize("group_kb,graph,many_src", [(-1, False, False), (1, False, False), (1, True, False),
-                                                     (0, True, False), (1, False, True), (700, True, True)])
-def test_batched_shots_equal_single_shot_runs(group_kb, graph, many_src):
+@pytest.mark.parametrize("group_kb,graph,many_src,kern",
+                         [(-1, False, False, mm.CPML_LAYER), (1, False, False, mm.CPML_LAYER),
+                          (1, True, False, mm.CPML_LAYER), (0, True, False, mm.CPML_LAYER),
+                          (1, False, True, mm.CPML_LAYER), (700, True, True, mm.CPML_LAYER),
+                          (-1, False, False, mm.CPML_FUSED), (1, True, False, mm.CPML_FUSED),
+                          (700, True, True, mm.CPML_FUSED)])
+def test_batched_shots_equal_single_shot_runs(group_kb, graph, many_src, kern):
     """Three uneven sub-volumes in one context give bitwise the single-shot
     results, whether all shots advance together (group_kb -1 or the default
     budget), one shot at a time (1 KiB budget) or two and one (700 KiB),
-    eagerly or from captured graphs.  With a shot of six sources every source
-    goes through the injection kernel; then the reference is the same batch
-    advanced as one group."""
+    eagerly or from captured graphs, in either forward CPML strategy.  With a
+    shot of six sources every source goes through the injection kernel; then
+    the reference is the same batch advanced as one group."""
     rng = np.random.default_rng(9)
     shapes = [(20, 26, 33), (31, 17, 22), (18, 18, 41)]
-    p = params(shapes[0], bc=mm.BC_CPML, nb=4, f0=25.0)
+    p = params(shapes[0], bc=mm.BC_CPML, nb=4, f0=25.0, cpml_kernel=kern)
     vels = [rng.uniform(1500, 3000, s).astype(np.float32) for s in shapes]
     p.vmax = float(max(v.max() for v in vels))
     T = 40
@@ -249,8 +266,10 @@ def test_errors_leave_context_usable():
 
 def test_autotune_then_forward_matches_default_tile():
     """The autotuner's trial steps (no wavelet) leave a zero state; the tuned
-    context then reproduces the default-tile run bitwise."""
+    context then reproduces the default-tile run bitwise (the CPML strategy
+    held fixed: the two sum the layer terms in different orders)."""
     p, vel, src, rec, w, T, dt = _ragged_case(mm.BC_CPML, seed=12)
+    p.cpml_kernel = mm.CPML_LAYER
     src, w = src[:3], w[:, :3]  # few enough sources to be added inside the stencil kernel
     a = gpu_forward(p, vel, src, rec, w, T)
     ctx = mm.Context.single(p, torch.from_numpy(vel).to(DEV), src, rec)
@@ -267,6 +286,35 @@ def test_autotune_then_forward_matches_default_tile():
     q.tile = -1  # autotune inside init
     b = gpu_forward(q, vel, src, rec, w, T)
     assert np.array_equal(b[0], a[0]) and np.array_equal(b[1], a[1])
+
+
+def test_cpml_strategy_choice_and_tuning():
+    """The forward CPML strategy: the layer pass by default on a grid whose
+    layers hold most of the cells, each strategy when forced, none reported
+    for a sponge; the autotuner settles on one of the two, and the tuned
+    context reproduces a fresh run forced to that strategy bitwise."""
+    p, vel, src, rec, w, T, dt = _ragged_case(mm.BC_CPML, seed=13)
+    src, w = src[:3], w[:, :3]
+    v = torch.from_numpy(vel).to(DEV)
+
+    def with_(**kw):
+        q = mm.default_params(**{k: getattr(p, k) for k, _ in mm.Params._fields_})
+        for k, x in kw.items():
+            setattr(q, k, x)
+        return q
+
+    assert mm.Context.single(p, v, src, rec).cpml_kernel() == mm.CPML_LAYER
+    for k in (mm.CPML_LAYER, mm.CPML_FUSED):
+        assert mm.Context.single(with_(cpml_kernel=k), v, src, rec).cpml_kernel() == k
+    assert mm.Context.single(with_(bc=mm.BC_SPONGE), v, src, rec).cpml_kernel() == mm.CPML_AUTO
+    ctx = mm.Context.single(p, v, src, rec)
+    t = ctx.autotune(2)
+    k = ctx.cpml_kernel()
+    assert k in (mm.CPML_LAYER, mm.CPML_FUSED)
+    tr = torch.zeros((T, len(rec)), dtype=torch.float32, device=DEV)
+    ctx.forward(T, torch.from_numpy(np.asarray(w, dtype=np.float32)).to(DEV), tr)
+    ref = gpu_forward(with_(cpml_kernel=k), vel, src, rec, w, T, tile=t)
+    assert np.array_equal(tr.cpu().numpy(), ref[0])
 
 
 @pytest.mark.parametrize("bc", [mm.BC_NONE, mm.BC_SPONGE, mm.BC_CPML])
