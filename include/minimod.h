@@ -122,7 +122,10 @@ typedef enum {
 typedef enum {
     MM_SNAP_FP32 = 0, /* lossless */
     MM_SNAP_BF16 = 1  /* p^k and the increment p^k - p^{k-1} in bfloat16, each scaled per block of
-                         4096 cells by its largest magnitude; see mm_snap_encode */
+                         4096 cells by its largest magnitude; see mm_snap_encode.  The replay's
+                         per-step d2p fields (the imaging condition's second time difference of
+                         the forward field) are kept in bfloat16 too, rounded to nearest even
+                         (no scale: bfloat16 has the exponent range of float) */
 } mm_snap;
 
 typedef struct {

@@ -321,7 +321,8 @@ void compute_layout(const mm_params& p, const std::vector<ShotGeom>& shots, int 
         const long long N = shots[0].n();
         const int K = p.ckpt_every;
         L.nseg = (p.nsteps_max + K - 1) / K;
-        L.seg = take(L, sizeof(float) * (size_t)K * N);
+        // the replay's d2p fields: bfloat16 with BF16 snapshots, float otherwise
+        L.seg = take(L, (p.snap == MM_SNAP_BF16 ? 2 : 4) * (size_t)K * N);
         L.ckpt_field_bytes = align256((p.snap == MM_SNAP_BF16 ? 2 : 4) * (size_t)N);
         L.ckpt = take(L, (size_t)L.nseg * 2 * L.ckpt_field_bytes);
         // BF16: two scales per block of SNAP_BLOCK cells per checkpoint
@@ -1020,11 +1021,13 @@ mm_status replay_segment(mm_ctx* c, int sg, hipStream_t s) {
     const int n0 = sg * K, n1 = std::min(n0 + K, c->adj_T);
     const long long N = c->geom[0].n();
     MM_TRY(restore_ckpt(c, sg, n0 & 1, s));
-    float* seg = at<float>(c->ws, c->L.seg);
+    char* seg = c->ws + c->L.seg;
+    const size_t esz = c->p.snap == MM_SNAP_BF16 ? 2 : 4;
     const float* wav = at<float>(c->ws, c->L.wav_store);
     for (int n = n0; n < n1; ++n) {
         StepAux aux{};
-        aux.d2p_out = seg + (size_t)(n - n0) * N;
+        aux.d2p_out = seg + (size_t)(n - n0) * N * esz;
+        aux.d2p_bf16 = c->p.snap == MM_SNAP_BF16;
         aux.src_scale = c->src_inj.scale;
         aux.wrow = c->nsrc > 0 ? wav + (size_t)n * c->nsrc : nullptr;
         MM_TRY(enqueue_step(c, c->d_shots, n & 1, MODE_D2P, aux, s, &c->groups[0]));
@@ -1051,7 +1054,8 @@ mm_status enqueue_adjoint(mm_ctx* c, int nsteps, const float* resid, float* adj_
             const int K = c->p.ckpt_every;
             const int sg = (m - 1) / K;
             if (c->seg_loaded != sg) MM_TRY(replay_segment(c, sg, s));
-            aux.d2p_in = at<float>(c->ws, c->L.seg) + (size_t)((m - 1) - sg * K) * N;
+            aux.d2p_in = c->ws + c->L.seg + (size_t)((m - 1) - sg * K) * N * (c->p.snap == MM_SNAP_BF16 ? 2 : 4);
+            aux.d2p_bf16 = c->p.snap == MM_SNAP_BF16;
             aux.grad = grad;
             aux.neg_inv_dt2 = (float)(-1.0 / (c->dt * c->dt));
             mode = MODE_IMAGE;

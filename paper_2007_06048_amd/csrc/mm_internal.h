@@ -72,15 +72,16 @@ struct GatherTab {
 };
 
 // Extra per-step operands.
-//  mode 1: d2p[x] = G (dt v)^2 Lap p^n  (= p^{n+1} - 2G p^n + G^2 p^{n-1}
-//          before the source term; single shot)
+//  mode 1: d2p[x] = G (dt v)^2 Lap p^n + the source term (= p^{n+1} - 2G p^n
+//          + G^2 p^{n-1}; single shot)
 //  mode 2: grad[x] += neg_inv_dt2 / G * p^{n+1}[x] * d2p[x]  (imaging)
 //  inline sources: lap += src_scale * wrow[col] at a shot's source cells
 //  folded record: the first gather_blocks blocks copy p^n (the previous
 //  step's output) at the receivers into gather_out
 struct StepAux {
-    float* d2p_out;
-    const float* d2p_in;
+    void* d2p_out;
+    const void* d2p_in;
+    int d2p_bf16;  // the d2p segment holds bfloat16 (round to nearest even) instead of float
     float* grad;
     float neg_inv_dt2;
     float src_scale;

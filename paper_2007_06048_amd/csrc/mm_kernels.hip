@@ -40,7 +40,29 @@ namespace mm {
 // per-lane byte offset, hardware range check returning 0 past the end, so
 // ghost cells need no branch), stores through address-space-1 pointers.
 typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) uint16_t gu16;
 constexpr unsigned OOB = 0xFFFFFFFFu;  // byte offset that is always out of range
+
+// float -> bfloat16, round to nearest even (finite inputs)
+__device__ __forceinline__ uint16_t f2bf_rne(float f) {
+    const unsigned u = __float_as_uint(f);
+    const unsigned lsb = (u >> 16) & 1u;
+    return (uint16_t)((u + 0x7FFFu + lsb) >> 16);
+}
+
+// The replay's d2p segment holds float or (BF, StepAux::d2p_bf16) bfloat16
+// elements.  It is written once in the replay and read once in the imaging:
+// non-temporal both ways, so it does not push the wavefields out of the caches.
+template <bool BF>
+__device__ __forceinline__ void d2p_put(void* seg, long long o, float v) {
+    if constexpr (BF) __builtin_nontemporal_store(f2bf_rne(v), &((gu16*)seg)[o]);
+    else __builtin_nontemporal_store(v, &((gfloat*)seg)[o]);
+}
+template <bool BF>
+__device__ __forceinline__ float d2p_get(const void* seg, long long o) {
+    if constexpr (BF) return __uint_as_float((unsigned)__builtin_nontemporal_load(&((const gu16*)seg)[o]) << 16);
+    else return __builtin_nontemporal_load(&((const gfloat*)seg)[o]);
+}
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float* base, int z, long long plane) {
     return __builtin_amdgcn_make_buffer_rsrc((void*)(base + (long long)z * plane), (short)0, (int)(plane * 4),
@@ -99,7 +121,7 @@ int tile_rows(int t) { return (kTiles[t].nt / kTiles[t].tx) * kTiles[t].ry; }
 // (launch_cpml_forward, or launch_cpml_adjoint for the adjoint fields); the
 // other forward CPML strategy runs the interior with BC == 0 and the cells
 // near the faces in k_cstep.
-template <int TX, int RY, int PD, int BC, int MODE, int NT, bool STREAM>
+template <int TX, int RY, int PD, int BC, int MODE, int NT, bool STREAM, bool BF>
 __global__ __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu((PD == 1 && RY <= 2 && !(BC == 2 && MODE != MODE_PLAIN)) ? 7 : 1)))
 void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const ShotDev* __restrict__ shots,
@@ -364,13 +386,10 @@ void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const Sh
                     out = c + fmaf(cvd[r], lap, c - cpp[r]);
                 }
                 pn_g[o] = out;
-                // the segment of d2p fields is written once in the replay and read once in the
-                // imaging: non-temporal, so it does not push the wavefields out of the caches
-                if (MODE == MODE_D2P) __builtin_nontemporal_store(G * (cvd[r] * lap), &((gfloat*)aux.d2p_out)[o]);
+                if (MODE == MODE_D2P) d2p_put<BF>(aux.d2p_out, o, G * (cvd[r] * lap));
                 if (MODE == MODE_IMAGE) {
                     gfloat* gr = (gfloat*)aux.grad;
-                    gr[o] = fmaf(aux.neg_inv_dt2 / G * out, __builtin_nontemporal_load(&((const gfloat*)aux.d2p_in)[o]),
-                                 gr[o]);
+                    gr[o] = fmaf(aux.neg_inv_dt2 / G * out, d2p_get<BF>(aux.d2p_in, o), gr[o]);
                 }
             }
         }
@@ -381,16 +400,16 @@ void k_step(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd, const Sh
     }
 }
 
-template <int TX, int RY, int PD, int BC, int MODE, int NT, bool STREAM = false>
+template <int TX, int RY, int PD, int BC, int MODE, int NT, bool STREAM = false, bool BF = false>
 static void launch_step_k(dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd, const ShotDev* shots, int parity,
                           const Coefs& cf, const StepAux& aux, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const dim3 block(TX, NT / TX);
     if (ev0 || ev1)  // either stamp alone is allowed (a CPML launch may have taken the start)
-        hipExtLaunchKernelGGL(k_step<TX, RY, PD, BC, MODE, NT, STREAM>, grid, block, 0, s, ev0, ev1, 0, tiles,
+        hipExtLaunchKernelGGL(k_step<TX, RY, PD, BC, MODE, NT, STREAM, BF>, grid, block, 0, s, ev0, ev1, 0, tiles,
                               ntiles, per_xcd, shots, parity, cf, aux);
     else
-        k_step<TX, RY, PD, BC, MODE, NT, STREAM><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity, cf,
-                                                                      aux);
+        k_step<TX, RY, PD, BC, MODE, NT, STREAM, BF><<<grid, block, 0, s>>>(tiles, ntiles, per_xcd, shots, parity,
+                                                                         cf, aux);
 }
 
 template <int TX, int RY, int PD, int BC, int NT>
@@ -403,8 +422,14 @@ static hipError_t launch_step_bc(int mode, dim3 grid, const TileEnt* tiles, int 
     else if (mode == MODE_PLAIN)
         launch_step_k<TX, RY, PD, BC, MODE_PLAIN, NT>(grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0,
                                                       ev1);
+    else if (mode == MODE_D2P && aux.d2p_bf16)
+        launch_step_k<TX, RY, PD, BC, MODE_D2P, NT, false, true>(grid, tiles, ntiles, per_xcd, shots, parity, cf, aux,
+                                                                 s, ev0, ev1);
     else if (mode == MODE_D2P)
         launch_step_k<TX, RY, PD, BC, MODE_D2P, NT>(grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0, ev1);
+    else if (aux.d2p_bf16)
+        launch_step_k<TX, RY, PD, BC, MODE_IMAGE, NT, false, true>(grid, tiles, ntiles, per_xcd, shots, parity, cf,
+                                                                   aux, s, ev0, ev1);
     else
         launch_step_k<TX, RY, PD, BC, MODE_IMAGE, NT>(grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0,
                                                       ev1);
@@ -496,7 +521,7 @@ hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int 
 // updated in place by the owner only.  Cells owned by the tile are
 // [x0, x1) x [y0, y1) x [z0, z1); the plane is staged over the full TX x TY
 // so the ring around the owned cells holds real p^n values.
-template <int TX, int RY, int NT, int PD, bool XY, bool LZ, int MODE, bool STREAM>
+template <int TX, int RY, int NT, int PD, bool XY, bool LZ, int MODE, bool STREAM, bool BF>
 __global__ __launch_bounds__(NT) void k_cstep(const TileEnt* __restrict__ tiles, int ntiles, int per_xcd,
                                               const ShotDev* __restrict__ shots, int parity, Coefs cf,
                                               StepAux aux) {
@@ -883,7 +908,7 @@ __global__ __launch_bounds__(NT) void k_cstep(const TileEnt* __restrict__ tiles,
                 }
                 const float out = c + fmaf(cvd[r], lap, c - cpp[r]);
                 pn_g[o] = out;
-                if (MODE == MODE_D2P) __builtin_nontemporal_store(cvd[r] * lap, &((gfloat*)aux.d2p_out)[o]);
+                if (MODE == MODE_D2P) d2p_put<BF>(aux.d2p_out, o, cvd[r] * lap);
             }
         }
 #pragma unroll
@@ -912,20 +937,23 @@ int cstep_tile_h(int kind) {
 // one launch over every kind runs the corner instantiation on tiles of one shape
 static_assert(CS_NT_FRAME == CS_NT_ZCORNER && CS_NT_ZLAYER == CS_NT_ZCORNER, "CS_ALL needs one tile shape");
 
-template <bool XY, bool LZ, int MODE, bool STREAM>
+template <bool XY, bool LZ, int MODE, bool STREAM, bool BF = false>
 static void launch_cstep_k(dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd, const ShotDev* shots, int parity,
                            const Coefs& cf, const StepAux& aux, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     constexpr int NT = cs_nt<XY, LZ>();
     const dim3 block(CS_TX, NT / CS_TX);
-    hipExtLaunchKernelGGL(k_cstep<CS_TX, CS_RY, NT, CS_PD, XY, LZ, MODE, STREAM>, grid, block, 0, s, ev0, ev1, 0, tiles,
-                          ntiles, per_xcd, shots, parity, cf, aux);
+    hipExtLaunchKernelGGL(k_cstep<CS_TX, CS_RY, NT, CS_PD, XY, LZ, MODE, STREAM, BF>, grid, block, 0, s, ev0, ev1, 0,
+                          tiles, ntiles, per_xcd, shots, parity, cf, aux);
 }
 
 template <bool XY, bool LZ>
 static void launch_cstep_m(int mode, bool st, dim3 grid, const TileEnt* tiles, int ntiles, int per_xcd,
                            const ShotDev* shots, int parity, const Coefs& cf, const StepAux& aux, hipStream_t s,
                            hipEvent_t ev0, hipEvent_t ev1) {
-    if (mode == MODE_D2P)
+    if (mode == MODE_D2P && aux.d2p_bf16)
+        launch_cstep_k<XY, LZ, MODE_D2P, false, true>(grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0,
+                                                      ev1);
+    else if (mode == MODE_D2P)
         launch_cstep_k<XY, LZ, MODE_D2P, false>(grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0, ev1);
     else if (st)
         launch_cstep_k<XY, LZ, MODE_PLAIN, true>(grid, tiles, ntiles, per_xcd, shots, parity, cf, aux, s, ev0, ev1);
@@ -1923,7 +1951,7 @@ hipError_t launch_cpml_adjoint(const ShotDev* shots, int nshots, int nb, const i
 
 // ------------------------------------------------------- inject and gather
 
-template <int MODE>
+template <int MODE, bool BF>
 __global__ __launch_bounds__(256) void k_inject(InjTab tab, const ShotDev* __restrict__ shots, int parity,
                                                 const float* __restrict__ vals, StepAux aux) {
     const int u = blockIdx.x * 256 + threadIdx.x;
@@ -1937,8 +1965,8 @@ __global__ __launch_bounds__(256) void k_inject(InjTab tab, const ShotDev* __res
     const float term = g * (sd.vdt2[o] * (tab.scale * acc));
     float* pn = sd.buf[parity ^ 1];
     pn[o] += term;
-    if (MODE == MODE_D2P) aux.d2p_out[o] += term;
-    if (MODE == MODE_IMAGE) aux.grad[o] = fmaf(aux.neg_inv_dt2 / g * term, aux.d2p_in[o], aux.grad[o]);
+    if (MODE == MODE_D2P) d2p_put<BF>(aux.d2p_out, o, d2p_get<BF>(aux.d2p_out, o) + term);
+    if (MODE == MODE_IMAGE) aux.grad[o] = fmaf(aux.neg_inv_dt2 / g * term, d2p_get<BF>(aux.d2p_in, o), aux.grad[o]);
 }
 
 hipError_t launch_inject(const InjTab& tab, const ShotDev* shots, int parity, const float* vals, int ncols, int mode,
@@ -1946,12 +1974,17 @@ hipError_t launch_inject(const InjTab& tab, const ShotDev* shots, int parity, co
     (void)ncols;
     if (tab.ncell <= 0) return hipSuccess;
     dim3 grid((tab.ncell + 255) / 256);
+    const bool h = aux.d2p_bf16 != 0;
     if (mode == MODE_PLAIN)
-        k_inject<MODE_PLAIN><<<grid, 256, 0, s>>>(tab, shots, parity, vals, aux);
+        k_inject<MODE_PLAIN, false><<<grid, 256, 0, s>>>(tab, shots, parity, vals, aux);
+    else if (mode == MODE_D2P && h)
+        k_inject<MODE_D2P, true><<<grid, 256, 0, s>>>(tab, shots, parity, vals, aux);
     else if (mode == MODE_D2P)
-        k_inject<MODE_D2P><<<grid, 256, 0, s>>>(tab, shots, parity, vals, aux);
+        k_inject<MODE_D2P, false><<<grid, 256, 0, s>>>(tab, shots, parity, vals, aux);
+    else if (h)
+        k_inject<MODE_IMAGE, true><<<grid, 256, 0, s>>>(tab, shots, parity, vals, aux);
     else
-        k_inject<MODE_IMAGE><<<grid, 256, 0, s>>>(tab, shots, parity, vals, aux);
+        k_inject<MODE_IMAGE, false><<<grid, 256, 0, s>>>(tab, shots, parity, vals, aux);
     return hipGetLastError();
 }
 
@@ -2081,13 +2114,6 @@ hipError_t launch_copy(float* dst, const float* src, long long n, hipStream_t s)
 // with its own 8-bit relative precision.  Decoding gives p^k = f(c0) s0 and
 // p^{k-1} = p^k - f(c1) s1, each product and difference rounded once.
 // One pass each way: read 8 B and write 4 B per cell, or the reverse.
-
-// float -> bfloat16, round to nearest even (finite inputs)
-__device__ __forceinline__ uint16_t f2bf_rne(float f) {
-    const unsigned u = __float_as_uint(f);
-    const unsigned lsb = (u >> 16) & 1u;
-    return (uint16_t)((u + 0x7FFFu + lsb) >> 16);
-}
 
 __device__ __forceinline__ float block_absmax256(float m, float* sm) {
     // wave reduction, then the 4 waves of the block through LDS
