@@ -61,9 +61,9 @@ def load_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def traffic_for(workload_name):
-    """HBM bytes per time step (all kernels of the step) from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
+def traffic_entry(workload_name):
+    """The committed rocprofv3 summary of a workload's time step (counters and
+    per-kernel durations), if it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "step_traffic.json")
     try:
         with open(path) as f:
@@ -73,7 +73,51 @@ def traffic_for(workload_name):
     e = d.get(workload_name)
     if not e or e.get("kernel_hash") != kernel_hash():
         return None
-    return e.get("bytes_per_step")
+    return e
+
+
+def traffic_for(workload_name):
+    """HBM bytes per time step (all kernels of the step) from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    e = traffic_entry(workload_name)
+    return e.get("bytes_per_step") if e else None
+
+
+def launch_kind(name):
+    """Which part of a forward CPML step (fused strategy) a kernel
+    instantiation runs: the plain stencil over the interior box, or the fused
+    kernel over the frame (template XY, not LZ), the z-layer chunks away from
+    the x / y faces (LZ, not XY) or the z-layer corners (both)."""
+    if name.startswith("void mm::k_step<") or name.startswith("mm::k_step<"):
+        return "interior"
+    if "k_cstep<" in name:
+        args = [a.strip() for a in name.split("<", 1)[1].split(">", 1)[0].split(",")]
+        xy, lz = args[4] == "true", args[5] == "true"
+        return {(True, False): "frame", (False, True): "z_layer", (True, True): "z_corners"}.get((xy, lz))
+    return None
+
+
+def region_alg_bytes(wl):
+    """Algorithmic bytes of each part of a forward CPML step (fused strategy):
+    16 B per point (p^n, p^{n-1}, (dt v)^2 read, p^{n+1} written) plus 16 B
+    per point and damped axis (psi and zeta, read and written).  The parts
+    are the interior box (no layer), the frame of the x / y layers in the
+    middle z range, the z-layer chunks away from the x / y layers, and the
+    z-layer corners; they sum to step_alg_bytes."""
+    nx, ny, nz, nb = wl.nx, wl.ny, wl.nz, wl.nb
+    fs = getattr(wl, "free_surface", 0)
+    zlo, zhi = (0 if fs else nb), nz - nb
+    mid = zhi - zlo
+    zl = nz - mid  # planes of the z layers
+    ix, iy = nx - 2 * nb, ny - 2 * nb
+    xy_all, xy_in = nx * ny, ix * iy
+    xl_cells = 2 * nb * ny     # xy cells in an x layer
+    yl_cells = 2 * nb * nx     # in a y layer
+    ring = xy_all - xy_in
+    return {"interior": 16 * xy_in * mid,
+            "frame": 16 * ring * mid + 16 * (xl_cells + yl_cells) * mid,
+            "z_layer": 32 * xy_in * zl,
+            "z_corners": 32 * ring * zl + 16 * (xl_cells + yl_cells) * zl}
 
 
 def step_alg_bytes(wl, alg_pt):
@@ -125,21 +169,25 @@ def _cpu_baseline(wl, budget_s, C, mm, np):
                       f"after 1 warm-up step"}
 
 
-# kernels that advance the forward wavefields by one time level (one launch each per step; the fused
-# CPML kernel runs twice, once over the frame of the faces and once over the z-layer chunks)
-STEP_KERNELS = ("k_step<", "k_cstep<", "k_iso_u<", "k_iso_p<")
+# kernels that advance the forward wavefields by one time level (one launch each per step; with CPML
+# either the fused kernel over the frame of the faces and the z-layer chunks beside the interior
+# stencil, or the layer pass before the stencil over the whole grid)
+STEP_KERNELS = ("k_step<", "k_cstep<", "k_cpml_fwd<", "k_iso_u<", "k_iso_p<")
 
 
-def pmc_summary(fetch_dir, write_dir, workload, out_path):
+def pmc_summary(fetch_dir, write_dir, workload, out_path, stats_dir=None):
     """HBM traffic of one time step from two rocprofv3 --pmc passes
     (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch): the mean per dispatch of
     every kernel of the step, summed, each counter scaled by what it reads
     for kernels of known size in the same program: k_vcheck reads exactly
-    4 N bytes (the velocity model), k_vdt2 writes exactly 4 N bytes."""
+    4 N bytes (the velocity model), k_vdt2 writes exactly 4 N bytes.  With
+    stats_dir (a rocprofv3 --kernel-trace --stats run of the same command)
+    each kernel's average duration is kept beside its bytes."""
     import csv
     import numpy as np
     from paper_2007_06048_amd import workloads as W
-    wl = {"smooth240": W.smooth_240, "layered1024": W.layered_1024}[workload]()
+    # a workload name, or an object with its name and geometry
+    wl = workload if hasattr(workload, "nx") else {"smooth240": W.smooth_240, "layered1024": W.layered_1024}[workload]()
     n = wl.nx * wl.ny * wl.nz
 
     def per_kernel(d, counter):
@@ -174,6 +222,12 @@ def pmc_summary(fetch_dir, write_dir, workload, out_path):
             kernels[name] = {"dispatches": len(fetch.get(name, [])),
                              "fetch_bytes": round(float(np.mean(fetch.get(name, [0.0]))) * f_fac),
                              "write_bytes": round(float(np.mean(write.get(name, [0.0]))) * w_fac)}
+    if stats_dir:
+        with open(os.path.join(stats_dir, "run_kernel_stats.csv")) as f:
+            for r in csv.DictReader(f):
+                if r["Name"] in kernels:
+                    kernels[r["Name"]]["avg_ns"] = round(float(r["AverageNs"]), 1)
+                    kernels[r["Name"]]["calls"] = int(r["Calls"])
     fb = sum(k["fetch_bytes"] for k in kernels.values())
     wb = sum(k["write_bytes"] for k in kernels.values())
     entry = {"kernels": kernels, "kernel_hash": kernel_hash(), "points": n,
@@ -431,6 +485,27 @@ def run_forward_workload(dev, wl, tile=-1, graph=False, steps=1, warmup=1, prof_
     return info, (t1 - t0) / steps, k_ms, k_n
 
 
+def kernel_breakdown(wl):
+    """Per-launch fractions of a forward CPML step (fused strategy) from the
+    committed profile of the current kernels: each part's algorithmic bytes
+    over its average rocprofv3 duration, and its counter-measured bytes."""
+    e = traffic_entry(wl.name)
+    if not e or wl.bc != 2:
+        return None
+    alg = region_alg_bytes(wl)
+    out = {}
+    for name, k in e["kernels"].items():
+        kind = launch_kind(name)
+        if kind is None or "avg_ns" not in k:
+            continue
+        ach = alg[kind] / (k["avg_ns"] * 1e-9) / 1e9
+        out[kind] = {"kernel": name.split("(")[0].replace("void ", ""), "avg_launch_us": round(k["avg_ns"] / 1e3, 1),
+                     "alg_bytes": alg[kind], "achieved": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": k["fetch_bytes"] + k["write_bytes"],
+                     "traffic_per_alg": round((k["fetch_bytes"] + k["write_bytes"]) / alg[kind], 3)}
+    return out or None
+
+
 def step_roofline(wl, alg_pt, step_ms, n_timed, stride, kernels):
     """Roofline of one time step: its algorithmic bytes over the average
     duration of the timed steps."""
@@ -446,6 +521,10 @@ def step_roofline(wl, alg_pt, step_ms, n_timed, stride, kernels):
         # the bytes the step's kernels actually move below L2, at the measured step time
         roof["traffic_GBs"] = round(roof["traffic"] / (step_ms / 1e3) / 1e9, 1)
         roof["traffic_per_alg"] = round(roof["traffic"] / bytes_step, 3)
+        parts = kernel_breakdown(wl)
+        if parts:
+            # per launch, from the profile summary committed with the counters (same kernel source)
+            roof["kernels"] = parts
     return roof
 
 
@@ -495,12 +574,17 @@ def main():
                          "free_surface, acoustic_iso, acoustic_iso_cpml); default all")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 240^3, gradient, batched, free-surface and acoustic_iso legs")
-    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="summarise two rocprofv3 --pmc runs into profiles/step_traffic.json and exit")
+    ap.add_argument("--pmc-summary", nargs="+", metavar="DIR",
+                    help="FETCH_DIR WRITE_DIR [STATS_DIR]: summarise two rocprofv3 --pmc runs (and a "
+                         "--kernel-trace --stats run of the same command) into profiles/step_traffic.json "
+                         "and exit")
     args = ap.parse_args()
     if args.pmc_summary:
+        if len(args.pmc_summary) not in (2, 3):
+            raise SystemExit("--pmc-summary takes FETCH_DIR WRITE_DIR [STATS_DIR]")
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.workload,
-                    os.path.join(ROOT, "profiles", "step_traffic.json"))
+                    os.path.join(ROOT, "profiles", "step_traffic.json"),
+                    args.pmc_summary[2] if len(args.pmc_summary) == 3 else None)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (shots and z-slabs would shard "

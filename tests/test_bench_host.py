@@ -64,6 +64,53 @@ def test_pmc_summary_scales_by_the_calibration_kernels(tmp_path):
     assert e["kernel_hash"] == bench.kernel_hash()
 
 
+def test_pmc_summary_keeps_kernel_durations_and_per_launch_fractions(tmp_path, monkeypatch):
+    """With a --stats run beside the counters each kernel keeps its average
+    duration; the bench line's per-launch breakdown then divides each part's
+    algorithmic bytes by it (and is dropped once the kernel source changes)."""
+    from types import SimpleNamespace as NS
+    wl = NS(name="t", nx=128, ny=96, nz=80, bc=2, nb=8, free_surface=0)
+    n = wl.nx * wl.ny * wl.nz
+    kib = 4.0 * n / 1024.0
+    names = {"interior": "void mm::k_step<64, 2, 1, 0, 0, 512, true, false>(a)",
+             "frame": "void mm::k_cstep<32, 1, 512, 2, true, false, 0, true, false>(a)",
+             "z_layer": "void mm::k_cstep<32, 1, 512, 2, false, true, 0, true, false>(a)",
+             "z_corners": "void mm::k_cstep<32, 1, 512, 2, true, true, 0, true, false>(a)"}
+    _counter_file(tmp_path / "f", "FETCH_SIZE", [("mm::k_vcheck(args)", kib)] + [(k, kib) for k in names.values()])
+    _counter_file(tmp_path / "w", "WRITE_SIZE", [("mm::k_vdt2(args)", kib)] + [(k, kib) for k in names.values()])
+    os.makedirs(tmp_path / "s")
+    with open(tmp_path / "s" / "run_kernel_stats.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Name", "Calls", "AverageNs"])
+        w.writeheader()
+        for i, k in enumerate(names.values()):
+            w.writerow({"Name": k, "Calls": 20, "AverageNs": 1000.0 * (i + 1)})
+    out = tmp_path / "traffic.json"
+    bench.pmc_summary(str(tmp_path / "f"), str(tmp_path / "w"), wl, str(out), str(tmp_path / "s"))
+    e = json.load(open(out))["t"]
+    assert e["kernels"][names["frame"]]["avg_ns"] == 2000.0 and e["kernels"][names["frame"]]["calls"] == 20
+    monkeypatch.setattr(bench, "traffic_entry", lambda name: e)
+    parts = bench.kernel_breakdown(wl)
+    alg = bench.region_alg_bytes(wl)
+    assert set(parts) == set(names)
+    for i, kind in enumerate(names):
+        assert parts[kind]["alg_bytes"] == alg[kind]
+        assert parts[kind]["achieved"] == pytest.approx(alg[kind] / (1e-6 * (i + 1)) / 1e9, rel=1e-3)
+        assert parts[kind]["traffic"] == round(4 * n) + round(4 * n)
+
+
+def test_region_alg_bytes_sum_to_the_step():
+    """The four parts of a fused CPML step (interior, frame, z-layer chunks,
+    z-layer corners) add up to the whole step's algorithmic bytes."""
+    from types import SimpleNamespace as NS
+    for nx, ny, nz, nb in ((1024, 1024, 512, 32), (240, 240, 240, 20), (37, 29, 23, 5)):
+        wl = NS(nx=nx, ny=ny, nz=nz, bc=2, nb=nb, free_surface=0)
+        assert sum(bench.region_alg_bytes(wl).values()) == bench.step_alg_bytes(wl, 16)
+    assert bench.launch_kind("void mm::k_cstep<32, 1, 512, 2, true, false, 0, true, false>(x)") == "frame"
+    assert bench.launch_kind("void mm::k_cstep<32, 1, 512, 2, false, true, 1, false, true>(x)") == "z_layer"
+    assert bench.launch_kind("void mm::k_cstep<32, 1, 512, 2, true, true, 0, false, false>(x)") == "z_corners"
+    assert bench.launch_kind("void mm::k_step<64, 2, 1, 0, 0, 512, true, false>(x)") == "interior"
+
+
 def test_step_alg_bytes_at_the_1024_workload():
     """20.0 bytes per point at 1024 x 1024 x 512 with a 32-cell CPML (16 B
     per point and 16 B per point and damped axis), 24.0 at 240^3 with 20."""
