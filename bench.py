@@ -528,9 +528,12 @@ def step_roofline(wl, alg_pt, step_ms, n_timed, stride, kernels):
     return roof
 
 
-def step_kernels_name(wl, iso):
+def step_kernels_name(wl, iso, cpml=None):
     if iso:
         return "time step: k_iso_u + k_iso_p (face velocities, then pressure)"
+    if wl.bc == 2 and cpml == CPML_NAMES[1]:
+        return ("time step: k_cpml_fwd over the damping layers (CPML memory update and correction) + k_step over "
+                "the whole grid (stencil adding the correction, leapfrog, record)")
     if wl.bc == 2:
         return ("time step: k_step over the interior box (stencil, leapfrog, record) + k_cstep over the frame of "
                 "the x / y faces and k_cstep over the z-layer chunks (stencil with the CPML memory update fused)")
@@ -550,7 +553,8 @@ def cache_resident_leg(dev, reps=2):
            "cpml_kernel": info["cpml_kernel"],
            "note": "working set about 250 MB: Infinity-Cache resident, not an HBM figure"}
     if k_n > 0:
-        out["roofline"] = step_roofline(wl, ALG_BYTES_STENCIL, k_ms / k_n, k_n, 10, step_kernels_name(wl, False))
+        out["roofline"] = step_roofline(wl, ALG_BYTES_STENCIL, k_ms / k_n, k_n, 10,
+                                        step_kernels_name(wl, False, info["cpml_kernel"]))
     return out
 
 
@@ -618,7 +622,8 @@ def main():
     alg_pt = ALG_BYTES_ISO if iso else ALG_BYTES_STENCIL
     roof = None
     if k_n > 0:
-        roof = step_roofline(wl, alg_pt, k_ms / k_n, k_n, args.prof_stride, step_kernels_name(wl, iso))
+        roof = step_roofline(wl, alg_pt, k_ms / k_n, k_n, args.prof_stride,
+                             step_kernels_name(wl, iso, info["cpml_kernel"]))
     # the same over the whole run (wall clock of a run / T): launch gaps, the trace record and reset included
     bytes_step = step_alg_bytes(wl, alg_pt)
     run_ach = bytes_step / (t_run / T) / 1e9
