@@ -145,7 +145,10 @@ struct GroupTiles {
     int st_off = 0, nst = 0;      // forward CPML: fused tiles of the frames (middle z range)
     int zl_off = 0, nzl = 0;      // forward CPML: fused tiles of the z-layer chunks that meet no x / y layer
     int zc_off = 0, nzc = 0;      // forward CPML: fused tiles of the z-layer chunks that meet one
-    bool merged() const { return nst + nzl + nzc < kMergeTiles; }  // the three lists are consecutive
+    // the frame, z-layer and corner lists (consecutive) run as one launch: fewer than kMergeTiles
+    // tiles, all in the corner shape
+    bool one = false;
+    bool merged() const { return one; }
 };
 
 // Every tile list: the full lists of all groups first (so that one launch
@@ -199,29 +202,39 @@ void build_tiles(int variant, const mm_params& p, const std::vector<ShotGeom>& s
         }
         gt[k].nst = (int)out.size() - gt[k].st_off;
         // z-layer chunks: the box away from the x / y layers (the interior box's xy range) in
-        // tiles of the z-layer kind, the frame around it in corner tiles
-        gt[k].zl_off = (int)out.size();
-        for (int s = s0; s < s1; ++s) {
-            const ShotGeom& g = shots[s];
-            const CpmlRegions r = cpml_regions(g, nb, fs);
-            if (!fs) tile_box(s, r.bx0, r.bx1, r.by0, r.by1, 0, nb, nb, ZW, ZH, out);
-            tile_box(s, r.bx0, r.bx1, r.by0, r.by1, g.nz - nb, g.nz, nb, ZW, ZH, out);
-        }
-        gt[k].nzl = (int)out.size() - gt[k].zl_off;
-        gt[k].zc_off = (int)out.size();
-        for (int s = s0; s < s1; ++s) {
-            const ShotGeom& g = shots[s];
-            const CpmlRegions r = cpml_regions(g, nb, fs);
-            for (int c = 0; c < 2; ++c) {
-                if (c == 0 && fs) continue;
-                const int za = c == 0 ? 0 : g.nz - nb, zb = c == 0 ? nb : g.nz;
-                tile_box(s, 0, r.bx0, 0, g.ny, za, zb, nb, CZW, CZH, out);         // low x
-                tile_box(s, r.bx1, g.nx, 0, g.ny, za, zb, nb, CZW, CZH, out);      // high x
-                tile_box(s, r.bx0, r.bx1, 0, r.by0, za, zb, nb, CZW, CZH, out);    // low y
-                tile_box(s, r.bx0, r.bx1, r.by1, g.ny, za, zb, nb, CZW, CZH, out); // high y
+        // tiles of the z-layer kind, the frame around it in corner tiles; a group with few fused
+        // tiles runs all of them in one launch of the corner instantiation, so then its z-layer
+        // box takes the corner shape too
+        auto zlayer = [&](int w, int h) {
+            gt[k].zl_off = (int)out.size();
+            for (int s = s0; s < s1; ++s) {
+                const ShotGeom& g = shots[s];
+                const CpmlRegions r = cpml_regions(g, nb, fs);
+                if (!fs) tile_box(s, r.bx0, r.bx1, r.by0, r.by1, 0, nb, nb, w, h, out);
+                tile_box(s, r.bx0, r.bx1, r.by0, r.by1, g.nz - nb, g.nz, nb, w, h, out);
             }
+            gt[k].nzl = (int)out.size() - gt[k].zl_off;
+            gt[k].zc_off = (int)out.size();
+            for (int s = s0; s < s1; ++s) {
+                const ShotGeom& g = shots[s];
+                const CpmlRegions r = cpml_regions(g, nb, fs);
+                for (int c = 0; c < 2; ++c) {
+                    if (c == 0 && fs) continue;
+                    const int za = c == 0 ? 0 : g.nz - nb, zb = c == 0 ? nb : g.nz;
+                    tile_box(s, 0, r.bx0, 0, g.ny, za, zb, nb, CZW, CZH, out);         // low x
+                    tile_box(s, r.bx1, g.nx, 0, g.ny, za, zb, nb, CZW, CZH, out);      // high x
+                    tile_box(s, r.bx0, r.bx1, 0, r.by0, za, zb, nb, CZW, CZH, out);    // low y
+                    tile_box(s, r.bx0, r.bx1, r.by1, g.ny, za, zb, nb, CZW, CZH, out); // high y
+                }
+            }
+            gt[k].nzc = (int)out.size() - gt[k].zc_off;
+        };
+        zlayer(CZW, CZH);
+        gt[k].one = gt[k].nst + gt[k].nzl + gt[k].nzc < kMergeTiles && CW == CZW && CH == CZH;
+        if (!gt[k].one && (ZW != CZW || ZH != CZH)) {
+            out.resize(gt[k].zl_off);
+            zlayer(ZW, ZH);
         }
-        gt[k].nzc = (int)out.size() - gt[k].zc_off;
     }
 }
 

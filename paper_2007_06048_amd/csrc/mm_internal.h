@@ -123,9 +123,9 @@ hipError_t launch_step(int variant, int bc, int mode, const TileEnt* tiles, int 
 // kind: CS_FRAME, the tiles of the middle z range (flagged TF_LX / TF_LY);
 // CS_ZLAYER, the tiles of the z-layer chunks [0, nb) and [nz - nb, nz) that
 // meet no x or y layer; CS_ZCORNER, those that do; CS_ALL, any mix of the
-// three in one launch (z-layer tiles flagged TF_LZ, frame tiles not).  mode
-// MODE_PLAIN or MODE_D2P.  The tiles of each kind are cstep_tile_w(kind) x
-// cstep_tile_h(kind).
+// three in one launch (z-layer tiles flagged TF_LZ, frame tiles not; all of
+// the corner shape).  mode MODE_PLAIN or MODE_D2P.  The tiles of each kind
+// are cstep_tile_w(kind) x cstep_tile_h(kind).
 enum { CS_FRAME = 0, CS_ZLAYER = 1, CS_ZCORNER = 2, CS_ALL = 3 };
 hipError_t launch_cpml_step(int kind, int mode, const TileEnt* tiles, int ntiles, const ShotDev* shots, int parity,
                             const Coefs& cf, const StepAux& aux, hipStream_t s, hipEvent_t ev0 = nullptr,

@@ -70,9 +70,15 @@ int main() {
                                     }
                         }
                     };
-                    // the fused lists are consecutive (one launch may take all three)
+                    // the fused lists are consecutive (one launch may take all three), and a group
+                    // run as one launch has all of them in the corner shape
                     if (gt[gi].st_off + gt[gi].nst != gt[gi].zl_off || gt[gi].zl_off + gt[gi].nzl != gt[gi].zc_off)
                         err("fused lists not consecutive", gt[gi].st_off, gt[gi].zl_off, gt[gi].zc_off);
+                    if (gt[gi].merged())
+                        for (int i = gt[gi].st_off; i < gt[gi].zc_off + gt[gi].nzc; ++i)
+                            if (out[i].x1 - out[i].x0 > cstep_tile_w(CS_ZCORNER) ||
+                                out[i].y1 - out[i].y0 > cstep_tile_h(CS_ZCORNER))
+                                err("tile of a one-launch group larger than the corner shape", i, out[i].x0, out[i].y0);
                     mark(full, gt[gi].full_off, gt[gi].nfull, 0);
                     mark(fwd, gt[gi].in_off, gt[gi].nin, 1);
                     mark(fwd, gt[gi].st_off, gt[gi].nst, 2);

@@ -232,6 +232,50 @@ def test_fullsize_layered_1024x1024x512_cpml_500_steps():
                      np.random.default_rng(1024), mm.BC_CPML)
 
 
+def test_fused_cpml_per_kind_launches_match_layer_pass_and_oracle():
+    """A grid large enough (over 4096 fused tiles) that the fused CPML
+    strategy runs its frame, z-layer (64-wide tiles) and corner tiles as
+    separate launches, as at the benchmark size, with sources near two
+    opposite corners so that the wavefield crosses every kind of layer region
+    within the run: the whole field and the traces after 160 steps equal the
+    layer-pass strategy's (an independent kernel pair, held to the oracle on
+    every small case) to rounding, and the last step matches the oracle at
+    sampled cells, the layers around the sources included."""
+    shape = (64, 1024, 1024)
+    nz, ny, nx = shape
+    vel = W.smooth_random_coarse(shape, 6.0, 1800.0, 3200.0, 77, factor=8).astype(np.float32)
+    src = np.array([[20, 24, 16], [1000, 990, 48]], np.int32)
+    rec = np.array([[i, j, 6] for i in range(0, nx, 16) for j in range(0, ny, 16)], np.int32)
+    T = 160
+    out = {}
+    for kern in (mm.CPML_FUSED, mm.CPML_LAYER):
+        p = mm.default_params(nx=nx, ny=ny, nz=nz, dx=10.0, dy=10.0, dz=10.0, cfl=0.5, bc=mm.BC_CPML, nb=12,
+                              cpml_f0=15.0, vmax=float(vel.max()), cpml_kernel=kern)
+        ctx = mm.Context.single(p, torch.from_numpy(vel).to(DEV), src, rec)
+        assert ctx.cpml_kernel() == kern
+        w = np.repeat(mm.ricker(15.0, 0.08, ctx.dt, T)[:, None], 2, axis=1).astype(np.float32)
+        wt = torch.from_numpy(w).to(DEV)
+        tr = torch.empty((T, len(rec)), dtype=torch.float32, device=DEV)
+        ctx.forward(T - 1, wt[:T - 1], tr[:T - 1])
+        before = _split_state(ctx.get_state(), shape, mm.BC_CPML, 12)
+        ctx.forward(1, wt[T - 1:], tr[T - 1:])
+        after = _split_state(ctx.get_state(), shape, mm.BC_CPML, 12)
+        torch.cuda.synchronize()
+        out[kern] = (ctx, p, before, after, float(w[-1, 0]), tr)
+    (cf, pf, bf, af, wl_, trf), (_, _, _, al, _, trl) = out[mm.CPML_FUSED], out[mm.CPML_LAYER]
+    # the layers carry the wave: CPML memory is nonzero on every axis
+    for a in range(3):
+        assert float(af["mem"][a].abs().max()) > 0.0
+    e_p = float(torch.linalg.norm((af["pc"] - al["pc"]).double()) / torch.linalg.norm(al["pc"].double()))
+    e_tr = float(torch.linalg.norm((trf - trl).double()) / torch.linalg.norm(trl.double()))
+    e_m = max(float(torch.linalg.norm((af["mem"][a] - al["mem"][a]).double()) /
+                    torch.linalg.norm(al["mem"][a].double())) for a in range(6))
+    print(f"fused vs layer pass after {T} steps: p {e_p:.2e}, traces {e_tr:.2e}, memory {e_m:.2e}")
+    assert e_p <= 1e-5 and e_tr <= 1e-5 and e_m <= 1e-5
+    _check_last_step(cf, 0, [shape], vel.astype(np.float64), pf, float(vel.max()), src, wl_, bf, af,
+                     np.random.default_rng(1044), mm.BC_CPML)
+
+
 def test_fullsize_two_layer_64_graph_matches_plain():
     """The 64^3 case is compared whole against the oracle elsewhere; here its
     HIP-graph launch reproduces the plain launch bitwise at full length."""
