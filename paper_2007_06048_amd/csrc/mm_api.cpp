@@ -113,17 +113,19 @@ void tile_box(int s, int bx0, int bx1, int by0, int by1, int z0, int z1, int zle
 }
 
 // Forward CPML regions of a shot: the interior box [bx0, bx1) x [by0, by1) x
-// [zlo, zhi) is exactly the cells outside every layer (its last tiles are
-// clipped to it); the frame around it in the middle z range [zlo, zhi) and
-// the z-layer chunks [0, nb) (none under a free surface) and [nz - nb, nz)
-// belong to the fused CPML kernel.
+// [zlo, zhi) holds no layer cell (its last tiles are clipped to it; bx0 is nb
+// rounded up to 32 cells, which keeps every row of its tiles on 128-byte
+// lines: the stencil fetches 16.5 B per point with the box at x = 32 and
+// 20.8 with it at x = 16); the frame around it in the middle z range
+// [zlo, zhi) and the z-layer chunks [0, nb) (none under a free surface) and
+// [nz - nb, nz) belong to the fused CPML kernel.
 struct CpmlRegions {
     int bx0, bx1, by0, by1, zlo, zhi;
 };
 
 CpmlRegions cpml_regions(const ShotGeom& g, int nb, bool fs) {
     CpmlRegions r;
-    r.bx0 = std::min(g.nx, nb);
+    r.bx0 = std::min(g.nx, (nb + 31) / 32 * 32);
     r.bx1 = std::max(r.bx0, g.nx - nb);
     r.by0 = std::min(g.ny, nb);
     r.by1 = std::max(r.by0, g.ny - nb);
