@@ -1,7 +1,7 @@
 // Host-side logic of the runtime that needs no GPU, compiled together with
 // mm_api.cpp (run by tests/test_host_sanitize.py under the sanitizers): the
-// watchdog's schedule and its decoding of the device words, and the CPML
-// memory width per model.
+// watchdog's schedule and its decoding of the device words, the CPML
+// memory width per model, and the default forward CPML strategy.
 #include "../../paper_2007_06048_amd/csrc/mm_api.cpp"
 
 static int fails = 0;
@@ -41,6 +41,23 @@ int main() {
     CHECK(mem_width(p) == 9);
     p.model = MM_MODEL_ISO;
     CHECK(mem_width(p) == 10);
+    // forward CPML strategy without tuning: the layer pass when 30 % or more of the cells lie in a
+    // layer (240^3 with 20 cells: 42 %; 1024^2 x 512 with 32 cells: 23 %), or as forced
+    p.model = MM_MODEL_ISO_CD;
+    p.bc = MM_BC_CPML;
+    p.nb = 20;
+    p.cpml_kernel = MM_CPML_AUTO;
+    CHECK(layer_pass_default(p, {{240, 240, 240}}));
+    p.nb = 32;
+    CHECK(!layer_pass_default(p, {{1024, 1024, 512}}));
+    CHECK(layer_pass_default(p, {{1024, 1024, 512}, {128, 128, 128}}) == false);
+    CHECK(layer_pass_default(p, {{128, 128, 128}}));
+    p.cpml_kernel = MM_CPML_LAYER;
+    CHECK(layer_pass_default(p, {{1024, 1024, 512}}));
+    p.cpml_kernel = MM_CPML_FUSED;
+    CHECK(!layer_pass_default(p, {{240, 240, 240}}));
+    p.cpml_kernel = 3;
+    CHECK(check_params(&p, nullptr) == MM_ERR_ARG);
     if (fails) return 1;
     std::printf("host logic: ok\n");
     return 0;
