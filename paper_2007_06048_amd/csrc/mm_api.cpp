@@ -1865,6 +1865,7 @@ mm_status mm_autotune(mm_ctx* c, int32_t steps, int32_t* tile_out) {
     // twice more, interleaved, in each strategy, each keeping its best time
     // (near-ties are otherwise decided by run-to-run noise)
     const bool lp0 = c->layer_pass;
+    const int v_in = c->variant;
     std::vector<std::pair<float, int>> res;
     mm_status st = MM_OK;
     for (int v = 0; v < num_tile_variants() && !st; ++v) {
@@ -1906,7 +1907,16 @@ mm_status mm_autotune(mm_ctx* c, int32_t steps, int32_t* tile_out) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (st) return st;
+    if (st) {
+        // a failed trial: back to the tile variant and strategy the context had (its state, which
+        // the trials overwrote, needs mm_reset or mm_set_state as after any failed launch)
+        const std::string err = c->err;
+        c->layer_pass = lp0;
+        (void)set_variant(c, v_in);
+        c->fwd_valid = false;
+        c->err = err;
+        return st;
+    }
     drop_graph(c);
     c->layer_pass = best_lp;
     MM_TRY(set_variant(c, best));
