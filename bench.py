@@ -41,8 +41,10 @@ ALG_BYTES_ISO = 40      # acoustic_iso: read and write p and the three face velo
 
 
 def kernel_hash():
+    """Hash of the kernel source and of the host runtime that plans their launches (tile tables,
+    z-chunking, strategy choice), which the counter and duration summaries depend on."""
     h = hashlib.sha256()
-    for f in ("mm_kernels.hip", "mm_internal.h"):
+    for f in ("mm_kernels.hip", "mm_internal.h", "mm_api.cpp"):
         with open(os.path.join(ROOT, "paper_2007_06048_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
