@@ -390,7 +390,8 @@ def free_surface_leg(dev, reps=2):
 
     t = _timed(run, reps)
     return {"workload": wl.name + "_free_surface", "run_s": round(t, 4),
-            "gpts": round(wl.nx * wl.ny * wl.nz * T / t / 1e9, 2)}
+            "gpts": round(wl.nx * wl.ny * wl.nz * T / t / 1e9, 2), "tile": mm.tile_name(ctx.info()["tile"]),
+            "cpml_kernel": CPML_NAMES[ctx.cpml_kernel()]}
 
 
 def batched_leg(dev, reps=2):
