@@ -325,7 +325,7 @@ mm_status mm_get_cpml_kernel(const mm_ctx* ctx, int32_t* kernel);
  * steps); every variant is timed once and the four fastest twice more,
  * interleaved, keeping each one's best time; with MM_CPML_AUTO the four
  * are also timed in the other forward CPML strategy, which is kept if it
- * wins.  Results are cached per (grid, boundary, model, grouping) for the
+ * wins by 3% or more.  Results are cached per (grid, boundary, model, grouping) for the
  * life of the process.  *tile_out may be NULL. */
 mm_status mm_autotune(mm_ctx* ctx, int32_t steps_per_trial, int32_t* tile_out);
 
