@@ -594,7 +594,7 @@ def main():
                     args.pmc_summary[2] if len(args.pmc_summary) == 3 else None)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (shots and z-slabs would shard "
+        print("bench.py measures one GPU: the library has no multi-GPU path (shots and z-slabs would shard "
               "across GPUs; see the design notes). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 

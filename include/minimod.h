@@ -76,7 +76,7 @@ typedef enum {
     MM_ERR_DEVICE = 4,      /* a HIP call failed */
     MM_ERR_STATE = 5,       /* call not valid in the context's current state */
     MM_ERR_NONFINITE = 6,   /* NaN/Inf or non-positive velocity */
-    MM_ERR_UNSUPPORTED = 7  /* valid request this build does not implement */
+    MM_ERR_UNSUPPORTED = 7  /* valid request the library does not implement */
 } mm_status;
 
 typedef enum { MM_BC_NONE = 0, MM_BC_SPONGE = 1, MM_BC_CPML = 2 } mm_bc;
